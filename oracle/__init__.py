@@ -1,0 +1,264 @@
+"""CPU FP64 oracle for the noisy quantum-circuit method of arXiv:1412.2293.
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the CPU-baseline
+leg of the benchmark, never by the HIP library or its Python binding.  It shares no code
+with the HIP path; both sides read the same seeded circuit description from ``workloads``.
+
+Parts:
+  * ``qsim_oracle.c`` (plain C loops, built into ``liboracle.so``): Philox4x32-10, the
+    Box-Muller normal deviate, Monte Carlo state-vector trajectories (Section 2, eq. 1-2),
+    the exact density matrix with Kraus channels (Section 3, eq. 3, 6, 9).
+  * ``fixed_rank.py`` (numpy): the fixed-rank density-matrix approximation (Section 3.2).
+
+Parity pinned by the not-gpu tests: Philox words against rocRAND's Philox4x32-10, the
+normal transform against libm and its moments, gates against Kronecker-product matrices,
+Grover and QFT closed forms, the noisy-QFT product closed form per trajectory, trace and
+norm preservation, the Kraus channel against the Monte Carlo mean, eq. (10) for rank 1.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qsim_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+GCC_FLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def build(force: bool = True) -> str:
+    """Compile qsim_oracle.c with gcc into liboracle.so (next to the source)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *GCC_FLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, u64, u32, i32, dbl = (ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
+                                   ctypes.c_int, ctypes.c_double)
+        L.or_philox_batch.argtypes = [i64, P, P, P]
+        L.or_log.argtypes = [dbl]
+        L.or_log.restype = dbl
+        L.or_cos2pi.argtypes = [dbl]
+        L.or_cos2pi.restype = dbl
+        L.or_normal.argtypes = [u64, u32, u32, u32, u32]
+        L.or_normal.restype = dbl
+        L.or_normals.argtypes = [u64, u32, u32, i64, P, i64, P, P]
+        circ = [i64, P, P, P, P, P, P, P, P, P]
+        L.or_sv_apply_circuit.argtypes = [i32] + circ + [dbl, u64, u32, u32, P]
+        L.or_sv_apply_circuit.restype = i32
+        L.or_sv_run.argtypes = [i32] + circ + [dbl, u64, u32, u32, u64, P]
+        L.or_sv_run.restype = i32
+        L.or_inner.argtypes = [i64, P, P, P, P, P, P]
+        L.or_dm_apply_kraus.argtypes = [i32, P, i32, P, i32, P]
+        L.or_dm_apply_kraus.restype = i32
+        L.or_dm_run.argtypes = [i32, i64, P, P, P, P, P, P, P, P, dbl, u64, P]
+        L.or_dm_run.restype = i32
+        L.or_dm_expect.argtypes = [i32, P, P, P, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class FlatCircuit:
+    """The oracle's own flat-array view of a ``workloads.Circuit``."""
+
+    def __init__(self, circuit):
+        G = len(circuit.gates)
+        self.n = circuit.n
+        self.kind = np.zeros(G, np.int32)
+        self.q0 = np.zeros(G, np.int32)
+        self.q1 = np.zeros(G, np.int32)
+        self.noise = np.zeros(G, np.int32)
+        self.site = np.zeros(G, np.uint32)
+        self.mats = np.zeros((G, 32), np.float64)
+        self.theta = np.zeros(G, np.float64)
+        self.mask = np.zeros(G, np.uint64)
+        self.value = np.zeros(G, np.uint64)
+        for i, g in enumerate(circuit.gates):
+            self.kind[i], self.q0[i], self.q1[i] = g.kind, g.q0, g.q1
+            self.noise[i], self.site[i], self.theta[i] = g.noise, g.site, g.theta
+            self.mask[i], self.value[i] = g.mask, g.value
+            if g.m is not None:
+                m = np.asarray(g.m, np.complex128).reshape(-1)
+                self.mats[i, : 2 * m.size : 2] = m.real
+                self.mats[i, 1 : 2 * m.size : 2] = m.imag
+        self.n_gates = G
+
+    def args(self):
+        return [ctypes.c_int64(self.n_gates), _ptr(self.kind), _ptr(self.q0), _ptr(self.q1),
+                _ptr(self.noise), _ptr(self.site), _ptr(self.mats), _ptr(self.theta),
+                _ptr(self.mask), _ptr(self.value)]
+
+
+# ------------------------------------------------------------------------------------------
+# Noise draws
+# ------------------------------------------------------------------------------------------
+def philox(ctrs: np.ndarray, keys: np.ndarray) -> np.ndarray:
+    """Philox4x32-10 words for each row of ctrs (k x 4 uint32) under keys (k x 2 uint32)."""
+    ctrs = np.ascontiguousarray(ctrs, np.uint32).reshape(-1, 4)
+    keys = np.ascontiguousarray(keys, np.uint32).reshape(-1, 2)
+    assert ctrs.shape[0] == keys.shape[0]
+    out = np.zeros_like(ctrs)
+    lib().or_philox_batch(ctrs.shape[0], _ptr(ctrs), _ptr(keys), _ptr(out))
+    return out
+
+
+def normals(seed: int, sites, trajs, request: int = 0, stream: int = 0) -> np.ndarray:
+    """xi[t, s] for the given trajectory ids and site ids (float64)."""
+    sites = np.ascontiguousarray(sites, np.uint32)
+    trajs = np.ascontiguousarray(trajs, np.uint32)
+    out = np.zeros((trajs.size, sites.size), np.float64)
+    lib().or_normals(ctypes.c_uint64(seed), request, stream, sites.size, _ptr(sites),
+                     trajs.size, _ptr(trajs), _ptr(out))
+    return out
+
+
+def log(x: float) -> float:
+    return lib().or_log(x)
+
+
+def cos2pi(u: float) -> float:
+    return lib().or_cos2pi(u)
+
+
+# ------------------------------------------------------------------------------------------
+# State-vector level
+# ------------------------------------------------------------------------------------------
+def sv_run(circuit, e: float = 0.0, seed: int = 0, traj: int = 0, request: int = 0,
+           init_index=None, flat: FlatCircuit = None) -> np.ndarray:
+    """Final state of one Monte Carlo trajectory (e = 0: the ideal circuit)."""
+    flat = flat or FlatCircuit(circuit)
+    init = circuit.init_index if init_index is None else init_index
+    psi = np.zeros(1 << circuit.n, np.complex128)
+    st = lib().or_sv_run(circuit.n, *flat.args(), ctypes.c_double(e), ctypes.c_uint64(seed),
+                         request, traj, ctypes.c_uint64(init), _ptr(psi))
+    if st != 0:
+        raise ValueError("oracle sv_run rejected its arguments")
+    return psi
+
+
+def sv_apply(circuit, psi: np.ndarray, e: float = 0.0, seed: int = 0, traj: int = 0,
+             request: int = 0) -> np.ndarray:
+    """Apply the circuit to a copy of psi."""
+    flat = FlatCircuit(circuit)
+    out = np.array(psi, np.complex128, copy=True)
+    st = lib().or_sv_apply_circuit(circuit.n, *flat.args(), ctypes.c_double(e),
+                                   ctypes.c_uint64(seed), request, traj, _ptr(out))
+    if st != 0:
+        raise ValueError("oracle sv_apply rejected its arguments")
+    return out
+
+
+def inner(a: np.ndarray, b: np.ndarray):
+    """(<a|b>, <a|a>, <b|b>) summed in index order."""
+    a = np.ascontiguousarray(a, np.complex128)
+    b = np.ascontiguousarray(b, np.complex128)
+    re, im, na, nb = (ctypes.c_double() for _ in range(4))
+    lib().or_inner(a.size, _ptr(a), _ptr(b), ctypes.byref(re), ctypes.byref(im),
+                   ctypes.byref(na), ctypes.byref(nb))
+    return complex(re.value, im.value), na.value, nb.value
+
+
+def fidelity(ideal: np.ndarray, psi: np.ndarray) -> float:
+    """|<ideal|psi>|^2 / (<ideal|ideal> <psi|psi>)."""
+    z, na, nb = inner(ideal, psi)
+    return (z.real * z.real + z.imag * z.imag) / (na * nb)
+
+
+def run_trajectories(circuit, e, seed: int, trajs, request: int = 0, keep_states: bool = False):
+    """Fidelity to the ideal state and marked-index probability for each trajectory id.
+
+    ``e`` is a scalar or one noise strength per trajectory.
+    """
+    flat = FlatCircuit(circuit)
+    ideal = sv_run(circuit, 0.0, flat=flat)
+    trajs = list(trajs)
+    es = np.broadcast_to(np.asarray(e, np.float64), (len(trajs),))
+    F = np.zeros(len(trajs))
+    p = np.zeros(len(trajs))
+    states = []
+    for k, t in enumerate(trajs):
+        psi = sv_run(circuit, float(es[k]), seed, t, request, flat=flat)
+        F[k] = fidelity(ideal, psi)
+        if circuit.marked is not None:
+            a = psi[circuit.marked]
+            p[k] = a.real * a.real + a.imag * a.imag
+        if keep_states:
+            states.append(psi)
+    return (F, p, ideal, states) if keep_states else (F, p)
+
+
+# ------------------------------------------------------------------------------------------
+# Density-matrix level
+# ------------------------------------------------------------------------------------------
+def dm_run(circuit, e: float, init_index=None) -> np.ndarray:
+    """Exact rho (2^n x 2^n) after the circuit with every noisy gate as its Kraus channel."""
+    n = circuit.n
+    flat = FlatCircuit(circuit)
+    init = circuit.init_index if init_index is None else init_index
+    rho = np.zeros((1 << n) * (1 << n), np.complex128)
+    st = lib().or_dm_run(n, ctypes.c_int64(flat.n_gates), _ptr(flat.kind), _ptr(flat.q0),
+                         _ptr(flat.q1), _ptr(flat.noise), _ptr(flat.mats), _ptr(flat.theta),
+                         _ptr(flat.mask), _ptr(flat.value), ctypes.c_double(e),
+                         ctypes.c_uint64(init), _ptr(rho))
+    if st != 0:
+        raise ValueError("oracle dm_run rejected its arguments")
+    return rho.reshape(1 << n, 1 << n)
+
+
+def dm_apply_kraus(rho: np.ndarray, n: int, qubits, ops) -> np.ndarray:
+    """sum_k E_k rho E_k^dagger for a Kraus set on one or two qubits (eq. 3)."""
+    out = np.array(rho, np.complex128, copy=True).reshape(-1)
+    qs = np.ascontiguousarray(qubits, np.int32)
+    ops = np.ascontiguousarray(np.asarray(ops, np.complex128))
+    st = lib().or_dm_apply_kraus(n, _ptr(out), qs.size, _ptr(qs), ops.shape[0], _ptr(ops))
+    if st != 0:
+        raise ValueError("oracle dm_apply_kraus rejected its arguments")
+    return out.reshape(rho.shape)
+
+
+def dm_expect(rho: np.ndarray, psi: np.ndarray):
+    """(<psi|rho|psi>, Tr rho) as complex numbers."""
+    n = int(np.log2(psi.size))
+    r = np.ascontiguousarray(rho, np.complex128).reshape(-1)
+    p = np.ascontiguousarray(psi, np.complex128)
+    vals = [ctypes.c_double() for _ in range(4)]
+    lib().or_dm_expect(n, _ptr(r), _ptr(p), *[ctypes.byref(v) for v in vals])
+    return complex(vals[0].value, vals[1].value), complex(vals[2].value, vals[3].value)
+
+
+def kraus_rot(u: np.ndarray, e: float) -> np.ndarray:
+    """Kraus set of the eq. (1) noisy one-qubit gate u: {u E1, u E2} with E1, E2 of eq. (6)."""
+    l1 = 0.5 * (1.0 + np.exp(-2.0 * e * e))
+    l2 = 0.5 * (1.0 - np.exp(-2.0 * e * e))
+    E1 = np.sqrt(l1) * np.eye(2)
+    E2 = np.sqrt(l2) * np.array([[0.0, 1.0], [-1.0, 0.0]])
+    return np.stack([u @ E1, u @ E2]).astype(np.complex128)
+
+
+def kraus_phase(theta: float, e: float) -> np.ndarray:
+    """Kraus set of the noisy controlled phase: {U_theta E1, U_theta E2} with eq. (9)."""
+    P = np.exp(-e * e)
+    ph = np.exp(-1j * theta)
+    E1 = np.diag([1.0, 1.0, 1.0, ph * np.sqrt(P)])
+    E2 = np.diag([0.0, 0.0, 0.0, ph * np.sqrt(1.0 - P)])
+    return np.stack([E1, E2]).astype(np.complex128)
