@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Benchmark of the noisy state-vector hot path on one MI355X.
+
+Workload (one "step"): QFT on n = 26 qubits from a seeded basis state, 128 Monte Carlo
+trajectories in one batch (64 with e = 0.001 and 64 with e = 0.01; Hadamards carry the eq. (1)
+rotation noise, controlled phases the theta -> theta + e xi noise), plus the ideal circuit,
+complex<float> amplitudes with FP64 fidelity reductions, fused passes.  The step ends when the
+128 fidelities are on the host.
+
+Reported: amplitude-updates/s (dense one-qubit gate: 2^n, controlled phase: 2^n / 4,
+SWAP: 2^n / 2 per trajectory), trajectories/s, the roofline of the dominant kernel from HIP
+events recorded on its stream during the timed steps, the same workload as plain per-gate
+sweeps in complex<double>, the unfused sweep kernels at n = 28, and the CPU oracle on a
+bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "amplitude-updates/s & %HBM peak; MC trajectories/s; p50/p99 request latency"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused_qft26.json")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("fused.hip", "planner.cpp"):
+        with open(os.path.join(ROOT, "paper_1412_2293_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=26)
+    ap.add_argument("--traj-per-e", type=int, default=64)
+    ap.add_argument("--no-extras", action="store_true", help="headline only (profiling runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain copy of 1 GiB (for HBM counter calibration)")
+    ap.add_argument("--plan", default="", help="tile_bits,reg_bits,run_bits of the fused plan")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported in this build "
+              "(trajectories shard trivially across GPUs, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1412_2293_amd as q
+    from workloads import qft
+
+    torch.cuda.set_device(0)
+    n, Te = a.n, a.traj_per_e
+    T = 2 * Te
+    es = np.array([0.001] * Te + [0.01] * Te)
+    seed = 1
+    c = qft(n, seed=seed)
+    ga = q.gate_array(c.gates)
+    plan = {"fuse": 1}
+    if a.plan:
+        kb, rb, runb = (int(x) for x in a.plan.split(","))
+        plan.update(tile_bits=kb, reg_bits=rb, run_bits=runb)
+    need = q.traj_bytes_required(ga, n, q.C64, T, plan)
+    buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    updates_per_traj = c.amplitude_updates()
+
+    def step():
+        return q.run_trajectories(ga, n, c.init_index, q.C64, T, e=es, seed=seed, plan=plan, buf=buf,
+                                  stream=stream)
+
+    log(f"[bench] qft{n} T={T} c64 fused: warmup {a.warmup}")
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    q.timing_reset()
+    q.timing_enable(True)
+    log(f"[bench] timed {a.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        res = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    q.timing_enable(False)
+    ms_step = (t1 - t0) * 1e3 / a.steps
+    fused = q.timing_read("fused")
+    kernels = {k: q.timing_read(k) for k in ("fused", "noise", "init", "reduce")}
+    value = updates_per_traj * T / (ms_step / 1e3)
+    F_c64 = res["F"].copy()
+    launch_ms = fused["ms"] / max(fused["launches"], 1)
+    launch_bytes = fused["alg_bytes"] / max(fused["launches"], 1)
+    achieved = launch_bytes / (launch_ms / 1e3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("source_hash") == source_hash() and tr.get("n") == n and tr.get("T") == T:
+            traffic = tr.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_fused<float,RB>", "launches_per_step": fused["launches"] / a.steps,
+                "avg_launch_ms": round(launch_ms, 4), "alg_bytes_per_launch": launch_bytes}
+    out = {
+        "metric": METRIC, "value": value, "unit": "amplitude-updates/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"qft{n}: {T} noisy trajectories (64 at e=0.001, 64 at e=0.01) + ideal, "
+                               "complex64 amplitudes, FP64 fidelities, fused passes",
+                   "n_qubits": n, "trajectories": T, "gates": len(c.gates), "seed": seed,
+                   "plan": plan},
+        "trajectories_per_s": T / (ms_step / 1e3),
+        "hbm_frac_step": None,
+        "roofline": roofline,
+        "kernels_ms_per_step": {k: v["ms"] / a.steps for k, v in kernels.items()},
+    }
+    # whole-step HBM fraction: algorithmic bytes of every kernel over the step time
+    step_bytes = sum(v["alg_bytes"] for v in kernels.values()) / a.steps
+    out["hbm_frac_step"] = round(step_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    del res
+    if a.copy_calibration:
+        nb = 1 << 30
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        q.copy(dst, src, nb, stream)
+        torch.cuda.synchronize()
+        del src, dst
+
+    if not a.no_extras:
+        del buf
+        torch.cuda.empty_cache()
+        out["fp64_unfused"] = fp64_unfused(q, c, ga, n, T, es, seed, F_c64, value)
+        torch.cuda.empty_cache()
+        out["sweeps_n28"] = sweeps(q)
+        torch.cuda.empty_cache()
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(c)
+    print(json.dumps(out), flush=True)
+
+
+def fp64_unfused(q, c, ga, n, T, es, seed, F_c64, fused_value):
+    """The same step as plain per-gate sweeps in complex<double> (one timed run)."""
+    import numpy as np
+    import torch
+    log("[bench] fp64 unfused per-gate comparison (1 run)")
+    plan = {"fuse": 0}
+    need = q.traj_bytes_required(ga, n, q.C128, T, plan)
+    buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    q.timing_reset()
+    q.timing_enable(True)
+    t0 = time.perf_counter()
+    res = q.run_trajectories(ga, n, c.init_index, q.C128, T, e=es, seed=seed, plan=plan, buf=buf)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    q.timing_enable(False)
+    ms = (t1 - t0) * 1e3
+    per = {k: q.timing_read(k) for k in ("sweep_u1", "sweep_cp", "sweep_swap")}
+    v = c.amplitude_updates() * T / (ms / 1e3)
+    dF = float(np.max(np.abs(res["F"] - F_c64)))
+    del res, buf
+    sweeps_ = {}
+    for k, d in per.items():
+        if d["launches"]:
+            sweeps_[k] = {"launches": d["launches"], "avg_ms": d["ms"] / d["launches"],
+                          "GB/s": d["alg_bytes"] / (d["ms"] / 1e3) / 1e9,
+                          "frac": d["alg_bytes"] / (d["ms"] / 1e3) / 1e9 / HBM_PEAK_GBS}
+    return {"dtype": "f64", "ms_per_step": ms, "value": v, "unit": "amplitude-updates/s",
+            "speedup_fused_f32_over_unfused_f64": fused_value / v,
+            "max_abs_dF_f32_fused_vs_f64_unfused": dF, "kernels": sweeps_}
+
+
+def sweeps(q):
+    """Unfused sweep kernels on n = 28 (one state + 1 more trajectory), every regime."""
+    import torch
+    from workloads import CP, Gate, SWAP, U1, haar_2x2
+    import numpy as np
+    log("[bench] unfused sweeps at n=28")
+    rng = np.random.default_rng(0)
+    out = {}
+    n, T = 28, 2
+    for dt, name in ((q.C64, "c64"), (q.C128, "c128")):
+        sv = q.StateVector(n, dt, T)
+        sv.init_basis(0)
+        res = {}
+        cases = [("u1_q0", Gate(U1, q0=0, m=haar_2x2(rng))), ("u1_q1", Gate(U1, q0=1, m=haar_2x2(rng))),
+                 ("u1_q6", Gate(U1, q0=6, m=haar_2x2(rng))), ("u1_q14", Gate(U1, q0=14, m=haar_2x2(rng))),
+                 ("u1_q27", Gate(U1, q0=27, m=haar_2x2(rng))), ("cp_3_20", Gate(CP, q0=3, q1=20, theta=0.3)),
+                 ("swap_2_25", Gate(SWAP, q0=2, q1=25))]
+        for label, g in cases:
+            kname = {U1: "sweep_u1", CP: "sweep_cp", SWAP: "sweep_swap"}[g.kind]
+            q.apply_gate(sv, g)
+            torch.cuda.synchronize()
+            q.timing_reset()
+            q.timing_enable(True)
+            for _ in range(5):
+                q.apply_gate(sv, g)
+            torch.cuda.synchronize()
+            q.timing_enable(False)
+            d = q.timing_read(kname)
+            gbs = d["alg_bytes"] / (d["ms"] / 1e3) / 1e9
+            res[label] = {"avg_ms": round(d["ms"] / d["launches"], 4), "GB/s": round(gbs, 1),
+                          "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        out[name] = res
+        sv.close()
+        del sv
+        torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(c, prefix=40):
+    """The CPU oracle, single thread, on a bounded sample of the workload: the first `prefix`
+    gates of one noisy trajectory (e = 0.01) of the same circuit, run as one oracle call."""
+    import oracle
+    from workloads import Circuit
+    log("[bench] cpu baseline (oracle, 1 thread)")
+    oracle.lib()
+    n = c.n
+    N = 1 << n
+    part = Circuit(n, c.gates[:prefix], init_index=c.init_index)
+    updates = sum({0: N, 1: N // 4, 2: N // 2}.get(g.kind, N) for g in part.gates)
+    t0 = time.perf_counter()
+    oracle.sv_run(part, 0.01, seed=1, traj=64)
+    dt = time.perf_counter() - t0
+    return {"value": updates / dt, "unit": "amplitude-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"qft{n} trajectory 64 (e=0.01): first {prefix} of {len(c.gates)} gates "
+                      f"({part.count(0)} H, {part.count(1)} controlled phases), complex128 plain "
+                      f"loops, {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

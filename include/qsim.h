@@ -1,0 +1,241 @@
+/*
+ * qsim.h -- C ABI of the MI355X (gfx950) noisy quantum-circuit library.
+ *
+ * The method is that of Bogdanov, Chernyavskiy et al., "Numerical and analytical research of
+ * the impact of decoherence on quantum circuits" (arXiv:1412.2293):
+ *   - Section 2: a circuit is the product U_s ... U_1 |psi0>; a one-qubit gate updates every
+ *     amplitude pair that differs only in the target bit; Monte Carlo noise replaces a
+ *     one-qubit gate U by U * V(e*xi) (eq. 1) and a controlled phase theta by theta + e*xi
+ *     (eq. 2 and the sentence after it), xi ~ N(0,1).
+ *   - Section 3: rho as the vector sum rho_ij |i>|j>, gates as U (x) U*, noise as Kraus sums
+ *     sum_k E_k rho E_k^dagger (eq. 3), Kraus sets of eq. (6) and eq. (9).
+ *   - Section 3.2: the fixed-rank approximation of rho, truncated by spectral decomposition
+ *     after every noisy step and renormalised.
+ *
+ * Conventions for every entry point:
+ *   - Qubit q is bit q of the amplitude index (qubit 0 is the least significant bit).
+ *   - A state buffer holds n_traj state vectors one after the other, each 2^n complex
+ *     amplitudes, interleaved (re, im), in float (QS_C64) or double (QS_C128).
+ *   - A density matrix of n qubits is a state of 2n qubits holding vec(rho), entry rho_ij at
+ *     index i * 2^n + j (ket bits high, bra bits low).
+ *   - Device buffers are BORROWED: the caller allocates them (for example as torch tensors),
+ *     keeps them alive while the library uses them and frees them; the library never frees
+ *     a caller buffer.  Handles own only their metadata and small device scratch that the
+ *     matching *_destroy frees.
+ *   - Streams are the caller's (hipStream_t passed as void*; NULL = the default stream).
+ *     Calls enqueue asynchronously on the handle's stream unless they return host values
+ *     (fidelities, ranks), which synchronise that stream before returning.
+ *   - Every call validates all arguments before enqueueing anything: on error nothing has
+ *     been enqueued, the call returns a negative qs_status and qs_last_error() (thread-local)
+ *     describes the problem.  Nothing throws or aborts across this boundary.
+ *   - One host thread per handle at a time.  Indices are 64-bit.
+ *   - Results depend only on the circuit, the seed, the request id, the trajectory counter,
+ *     the dtype and the plan; not on batch composition or timing.
+ */
+#ifndef QSIM_H
+#define QSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QS_OK = 0,
+    QS_EINVAL = -1,       /* invalid argument (range, size, null pointer, buffer too small) */
+    QS_ENOMEM = -2,       /* the library could not allocate its own small scratch            */
+    QS_EDEVICE = -3,      /* a HIP runtime call failed                                       */
+    QS_EUNSUPPORTED = -4, /* valid request this build does not implement                     */
+    QS_EBUSY = -5         /* serving: admission refused (no free memory or slot)             */
+} qs_status;
+
+typedef enum { QS_C64 = 0, QS_C128 = 1 } qs_dtype;
+
+/* Gate kinds. */
+typedef enum {
+    QS_G_U1 = 0,   /* dense one-qubit gate m (2x2) on q0                                    */
+    QS_G_CP = 1,   /* controlled phase, eq. (2): |11> of (q0, q1) times exp(-i theta); CZ = pi */
+    QS_G_SWAP = 2, /* exchange qubits q0, q1                                                  */
+    QS_G_CNOT = 3, /* control q0, target q1                                                   */
+    QS_G_U2 = 4,   /* dense two-qubit gate m (4x4), local index bit(q0) + 2 bit(q1)           */
+    QS_G_FLIP = 5  /* negate every amplitude i with (i & mask) == value                       */
+} qs_gate_kind;
+
+/* Noise tags (Section 2). */
+typedef enum {
+    QS_NOISE_NONE = 0,
+    QS_NOISE_ROT = 1,   /* one-qubit gate U becomes U * V(e xi), V = [[c, s], [-s, c]], eq. (1) */
+    QS_NOISE_PHASE = 2  /* controlled phase theta becomes theta + e xi                         */
+} qs_noise_kind;
+
+/* One gate.  m holds a row-major complex matrix, (re, im) interleaved: 2x2 in m[0..7] for
+ * U1, 4x4 in m[0..31] for U2; unused otherwise.  `site` is the first Philox counter word of
+ * this gate's noise draw (normally the gate's position in its circuit). */
+typedef struct {
+    int32_t kind;
+    int32_t q0;
+    int32_t q1;
+    int32_t noise;
+    uint32_t site;
+    uint32_t reserved;
+    double theta;
+    uint64_t mask;
+    uint64_t value;
+    double m[32];
+} qs_gate;
+
+/* Noise parameters.  Trajectory t of a batch draws xi from Philox4x32-10 with counter
+ * (site, traj_base + t, 0, request) and key (seed & 0xffffffff, seed >> 32); the two first
+ * words give u1 = (top 53 bits + 1) 2^-53, the two last u2 = (top 53 bits) 2^-53 and
+ * xi = sqrt(-2 ln u1) cos(2 pi u2).  e_per_traj (host array, n_traj entries) overrides e. */
+typedef struct {
+    double e;
+    uint64_t seed;
+    uint32_t request;
+    uint32_t traj_base;
+    const double *e_per_traj;
+} qs_noise;
+
+/* Execution plan for run_trajectories. */
+typedef struct {
+    int32_t fuse;      /* 0: one sweep kernel per gate; 1: fused passes; -1: library picks */
+    int32_t tile_bits; /* fused: amplitudes per tile = 2^tile_bits (0 = library picks)      */
+    int32_t reg_bits;  /* fused: amplitudes per thread = 2^reg_bits (0 = library picks)     */
+    int32_t run_bits;  /* fused: the 2^run_bits lowest-index amplitudes of a tile are one
+                          contiguous row (coalescing); 0 = library picks                   */
+} qs_plan;
+
+typedef struct qs_state_s *qs_state;
+typedef struct qs_fr_s *qs_fr;
+
+/* Thread-local description of the last error (empty string if none). */
+const char *qs_last_error(void);
+const char *qs_version(void);
+
+/* ------------------------------------------------------------------------------------------
+ * State vectors (Section 2).
+ * ---------------------------------------------------------------------------------------- */
+
+/* Bytes of a buffer holding n_traj states of n qubits (n in 1..34). */
+size_t qs_sv_bytes_required(int n_qubits, qs_dtype dt, int n_traj);
+
+/* Wrap a caller buffer (>= qs_sv_bytes_required bytes, 256-byte aligned device memory) as
+ * n_traj state vectors of n qubits.  The contents are left as they are. */
+qs_status qs_sv_create(int n_qubits, qs_dtype dt, int n_traj, void *dev_buf, size_t buf_bytes,
+                       void *hip_stream, qs_state *out);
+qs_status qs_sv_destroy(qs_state s);
+
+/* Every trajectory <- the basis state |index>. */
+qs_status qs_sv_init_basis(qs_state s, uint64_t index);
+
+/* Apply one gate to every trajectory of s as one sweep over the state buffer (Section 2:
+ * the amplitude-pair update of a one-qubit gate, its 4-tuple analogue for two qubits).
+ * nz == NULL or nz->e == 0 applies the ideal gate; otherwise trajectory t is noisy with the
+ * counter of qs_noise (nz->e_per_traj must be NULL here; run_trajectories takes it).
+ * Qubits must be distinct and < n.  Asynchronous. */
+qs_status qs_apply_gate(qs_state s, const qs_gate *g, const qs_noise *nz);
+
+/* Kraus channel on vec(rho) (eq. 3), asynchronous: rho <- sum_k E_k rho E_k^dagger.  `rho` is a state of 2n
+ * qubits (n_traj == 1) holding vec(rho) of an n-qubit density matrix; k = 1 or 2 target
+ * qubits `qubits` (< n); ops: n_ops host matrices of 2^k x 2^k complex doubles, row-major,
+ * (re, im) interleaved, local index bit(qubits[0]) + 2 bit(qubits[1]).  The library forms the
+ * superoperator sum_k E_k (x) conj(E_k) in FP64 and applies it in one sweep over the ket
+ * bits qubits + n and the bra bits qubits. */
+qs_status qs_apply_kraus(qs_state rho, int k, const int32_t *qubits, int n_ops, const double *ops);
+
+/* One circuit gate on vec(rho) (Section 3): a ROT-tagged one-qubit gate U with e > 0 becomes
+ * its Kraus channel {U E1, U E2} with E1, E2 of eq. (6) (lambda_1,2 = (1 +- exp(-2 e^2)) / 2),
+ * applied as one superoperator sweep; other one-qubit gates as U (x) U*; SWAP, CNOT, U2 and
+ * noiseless CP as U on the ket bits then U* on the bra bits; FLIP as the sign flip of the
+ * selected rows and columns.  A PHASE-tagged CP with e > 0 returns QS_EUNSUPPORTED.
+ * Asynchronous. */
+qs_status qs_dm_apply_gate(qs_state rho, const qs_gate *g, double e);
+
+/* F = |<a_ta|b_tb>|^2 / (<a|a><b|b>) in FP64 (Section 2, Fig. 1 uses 1 - F); both states must
+ * have the same n and dtype.  overlap (nullable) receives <a|b> as two doubles.  Blocks. */
+qs_status qs_fidelity(qs_state a, int ta, qs_state b, int tb, double *f, double *overlap);
+
+/* <psi|rho|psi> = sum_ij conj(psi_i) rho_ij psi_j and Tr rho, FP64 (Section 3).  rho as in
+ * qs_apply_kraus, psi trajectory tpsi of an n-qubit state of the same dtype.  Blocks. */
+qs_status qs_dm_fidelity(qs_state rho, qs_state psi, int tpsi, double *f, double *trace);
+
+/* Device noise draws for testing: out_dev[t * n_sites + s] = xi for (sites_dev[s],
+ * traj_base + t) on Philox stream `stream` (FP64, device memory).  Asynchronous. */
+qs_status qs_noise_draw(uint64_t seed, uint32_t request, uint32_t stream,
+                        const uint32_t *sites_dev, int n_sites, uint32_t traj_base, int n_traj,
+                        double *out_dev, void *hip_stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Monte Carlo trajectories (Section 2, Fig. 1): the ideal circuit and n_traj noisy copies,
+ * run as one batch, with the fidelity of each noisy state to the ideal one.
+ * ---------------------------------------------------------------------------------------- */
+
+/* Bytes of dev_buf needed by qs_run_trajectories for this circuit and plan. */
+size_t qs_traj_bytes_required(const qs_gate *gates, int n_gates, int n_qubits, qs_dtype dt,
+                              int n_traj, const qs_plan *plan);
+
+/* Run the circuit from |init_index> on n_traj + 1 states held in dev_buf: slot 0 is the ideal
+ * circuit, slot t + 1 trajectory t.  fid_out[t] (host, FP64) = |<ideal|psi_t>|^2 /
+ * (<ideal|ideal><psi_t|psi_t>); p_out[t] (nullable) = |psi_t[marked]|^2 when marked >= 0;
+ * norm_out[t] (nullable) = <psi_t|psi_t>.  The final states stay in dev_buf (slot s at byte
+ * offset s * 2^n * amplitude size), in the physical qubit order layout_out[q] (nullable,
+ * n entries): logical qubit q sits at bit layout_out[q] (fused plans turn SWAP gates into a
+ * relabelling instead of moving data).  Blocks until the results are on the host. */
+qs_status qs_run_trajectories(const qs_gate *gates, int n_gates, int n_qubits,
+                              uint64_t init_index, qs_dtype dt, const qs_noise *nz, int n_traj,
+                              int64_t marked, const qs_plan *plan, void *dev_buf,
+                              size_t buf_bytes, void *hip_stream, double *fid_out,
+                              double *p_out, double *norm_out, int32_t *layout_out);
+
+/* Per-kernel timing of the calling thread's launches, measured with HIP events on the stream
+ * each kernel is launched on.  While enabled, every launch is bracketed by two events;
+ * qs_timing_read synchronises and returns, for kernel class `name` ("sweep_u1", "sweep_cp",
+ * "sweep_swap", "sweep_2q", "flip", "fused", "reduce", "noise", "init", "fr_gram",
+ * "fr_recombine", "copy"), the number of launches, their summed duration in ms and their
+ * summed algorithmic bytes (what the method must move: read + write of the touched
+ * amplitudes). */
+qs_status qs_timing_enable(int on);
+qs_status qs_timing_read(const char *name, int64_t *launches, double *ms, double *alg_bytes);
+qs_status qs_timing_reset(void);
+
+/* Plain device copy of `bytes` (multiple of 16) from src to dst, for bandwidth calibration. */
+qs_status qs_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Fixed-rank density matrix (Section 3.2): rho = exp(log_trace) sum_{j<rank} |v_j><v_j|,
+ * columns v_j stored as `r` state vectors of n qubits, orthogonal, sum <v_j|v_j> = 1.
+ * ---------------------------------------------------------------------------------------- */
+size_t qs_fr_bytes_required(int n_qubits, int r, qs_dtype dt);
+qs_status qs_fr_create(int n_qubits, int r, qs_dtype dt, void *dev_buf, size_t buf_bytes,
+                       void *hip_stream, qs_fr *out);
+qs_status qs_fr_destroy(qs_fr fr);
+/* rho <- |index><index| (rank 1, log_trace 0). */
+qs_status qs_fr_init_basis(qs_fr fr, uint64_t index);
+/* A unitary gate (noise ignored) on every column; never truncates. */
+qs_status qs_fr_apply_gate(qs_fr fr, const qs_gate *g);
+/* One-qubit Kraus set (n_ops <= 4 host 2x2 complex matrices as in qs_apply_kraus) on qubit q:
+ * W = [E_k v_j], Gram G = W^dagger W (FP64, one pass over the columns), eigen-decomposition
+ * of G in FP64, keep the leading eigenvectors (at most r; eigenvalues <= zero_tol * max are
+ * dropped; if the r-th and (r+1)-th are within tau * max the whole tied cluster at the cut is
+ * dropped), columns <- W Q / sqrt(kept trace), log_trace += ln(kept trace).  rank_out gets
+ * the new rank.  Blocks (the eigen-decomposition runs on the host). */
+qs_status qs_fr_apply_kraus(qs_fr fr, int q, int n_ops, const double *ops, double tau,
+                            double zero_tol, int *rank_out);
+/* One circuit gate in the fixed-rank form: a ROT-tagged one-qubit gate U with e > 0 is the
+ * Kraus step of qs_fr_apply_kraus with {U E1, U E2} of eq. (6); any other gate (noise
+ * ignored) is qs_fr_apply_gate.  rank_out (nullable) gets the rank afterwards. */
+qs_status qs_fr_apply_noisy_gate(qs_fr fr, const qs_gate *g, double e, double tau,
+                                 double zero_tol, int *rank_out);
+/* <psi|rho|psi>: f_unnorm = exp(log_trace) f_norm, f_norm with the stored unit-trace rho. */
+qs_status qs_fr_fidelity(qs_fr fr, qs_state psi, int tpsi, double *f_unnorm, double *f_norm,
+                         double *log_trace);
+/* Current rank; columns (device pointer of column 0, columns 2^n amplitudes apart). */
+qs_status qs_fr_info(qs_fr fr, int *rank, double *log_trace, void **columns_dev);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSIM_H */

@@ -1,0 +1,951 @@
+// C ABI of libqsim: argument validation, buffer layout, launch orchestration, kernel timing,
+// and the host side of the fixed-rank step (FP64 Jacobi eigen-decomposition).
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace qs {
+
+// ---------------------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+qs_status fail(qs_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+qs_status hip_fail(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return QS_EDEVICE;
+}
+
+void clear_error() { g_err.clear(); }
+
+// ---------------------------------------------------------------------------------------
+// Timing
+// ---------------------------------------------------------------------------------------
+struct TimingRecord {
+    const char *name;
+    double bytes;
+    hipEvent_t a, b;
+};
+
+static std::mutex g_tmu;
+static bool g_timing = false;
+static std::vector<TimingRecord> g_pending;
+struct Acc {
+    int64_t n = 0;
+    double ms = 0, bytes = 0;
+};
+static std::vector<std::pair<std::string, Acc>> g_acc;
+
+TimedLaunch::TimedLaunch(const char *nm, double bytes, hipStream_t s) : name(nm), alg_bytes(bytes), st(s)
+{
+    if (!g_timing) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+    if (hipEventRecord(a, st) != hipSuccess) return;
+    on = true;
+}
+
+TimedLaunch::~TimedLaunch()
+{
+    if (!on) return;
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_pending.push_back({name, alg_bytes, a, b});
+}
+
+static void timing_flush()
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (auto &r : g_pending) {
+        (void)hipEventSynchronize(r.b);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, r.a, r.b);
+        auto it = std::find_if(g_acc.begin(), g_acc.end(), [&](auto &p) { return p.first == r.name; });
+        if (it == g_acc.end()) {
+            g_acc.push_back({r.name, Acc()});
+            it = g_acc.end() - 1;
+        }
+        it->second.n += 1;
+        it->second.ms += ms;
+        it->second.bytes += r.bytes;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_pending.clear();
+}
+
+}  // namespace qs
+
+using namespace qs;
+
+// ---------------------------------------------------------------------------------------
+// Handles
+// ---------------------------------------------------------------------------------------
+struct qs_state_s {
+    int n;
+    qs_dtype dt;
+    int T;
+    void *buf;
+    size_t bytes;
+    hipStream_t st;
+    double *scratch;     // device: table rows, reduction partials, outputs
+    size_t scratch_doubles;
+};
+
+struct qs_fr_s {
+    int n, r, rank;
+    qs_dtype dt;
+    void *V;
+    hipStream_t st;
+    double log_trace;
+    double *scratch;     // device: gram partials | gram out | coef | overlap partials | out | table
+    size_t off_gram, off_coef, off_ovp, off_ovo, off_tab;
+    double *host;        // pinned staging: gram (512) + coef (512)
+};
+
+static size_t state_bytes(int n, qs_dtype dt, int T) { return ((size_t)T << n) * amp_bytes(dt); }
+
+static bool aligned256(const void *p) { return ((uintptr_t)p & 255u) == 0; }
+
+extern "C" {
+
+const char *qs_last_error(void) { return g_err.c_str(); }
+const char *qs_version(void) { return "qsim-gfx950 1.0"; }
+
+size_t qs_sv_bytes_required(int n, qs_dtype dt, int T)
+{
+    if (n < 1 || n > 34 || T < 1 || (dt != QS_C64 && dt != QS_C128)) return 0;
+    return state_bytes(n, dt, T);
+}
+
+qs_status qs_sv_create(int n, qs_dtype dt, int T, void *buf, size_t bytes, void *stream, qs_state *out)
+{
+    clear_error();
+    if (!out) return fail(QS_EINVAL, "sv_create: out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > 34) return fail(QS_EINVAL, "sv_create: n_qubits must be in 1..34");
+    if (dt != QS_C64 && dt != QS_C128) return fail(QS_EINVAL, "sv_create: unknown dtype");
+    if (T < 1) return fail(QS_EINVAL, "sv_create: n_traj must be >= 1");
+    if (!buf || !aligned256(buf)) return fail(QS_EINVAL, "sv_create: buffer must be non-NULL and 256-byte aligned");
+    if (bytes < state_bytes(n, dt, T)) return fail(QS_EINVAL, "sv_create: buffer too small");
+    auto *s = new (std::nothrow) qs_state_s();
+    if (!s) return fail(QS_ENOMEM, "sv_create: out of host memory");
+    s->n = n;
+    s->dt = dt;
+    s->T = T;
+    s->buf = buf;
+    s->bytes = bytes;
+    s->st = (hipStream_t)stream;
+    s->scratch_doubles = (size_t)T * 8 + reduce_partials_doubles(n, T) + 2 * reduce_partials_doubles(n, 1) + 64 +
+                         (size_t)T * 5 + 64;
+    hipError_t e = hipMalloc(&s->scratch, s->scratch_doubles * sizeof(double));
+    if (e != hipSuccess) {
+        delete s;
+        return hip_fail(e, "sv_create: hipMalloc scratch");
+    }
+    *out = s;
+    return QS_OK;
+}
+
+qs_status qs_sv_destroy(qs_state s)
+{
+    clear_error();
+    if (!s) return QS_OK;
+    (void)hipStreamSynchronize(s->st);
+    (void)hipFree(s->scratch);
+    delete s;
+    return QS_OK;
+}
+
+qs_status qs_sv_init_basis(qs_state s, uint64_t index)
+{
+    clear_error();
+    if (!s) return fail(QS_EINVAL, "sv_init_basis: NULL state");
+    if (index >= (1ull << s->n)) return fail(QS_EINVAL, "sv_init_basis: index out of range");
+    QS_HIP(launch_init_basis(s->buf, s->dt, s->n, s->T, index, s->st));
+    return QS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// Gate validation and the single-gate sweep
+// ---------------------------------------------------------------------------------------
+static qs_status check_gate(const qs_gate &g, int n, int idx)
+{
+    auto bad = [&](const char *why) {
+        return fail(QS_EINVAL, "gate " + std::to_string(idx) + ": " + why);
+    };
+    const uint64_t nmask = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+    switch (g.kind) {
+    case QS_G_U1:
+        if (g.q0 < 0 || g.q0 >= n) return bad("qubit out of range");
+        if (g.noise != QS_NOISE_NONE && g.noise != QS_NOISE_ROT) return bad("U1 takes no or ROT noise");
+        break;
+    case QS_G_CP:
+    case QS_G_SWAP:
+    case QS_G_CNOT:
+    case QS_G_U2:
+        if (g.q0 < 0 || g.q0 >= n || g.q1 < 0 || g.q1 >= n) return bad("qubit out of range");
+        if (g.q0 == g.q1) return bad("two-qubit gate on one qubit");
+        if (g.kind == QS_G_CP && g.noise != QS_NOISE_NONE && g.noise != QS_NOISE_PHASE)
+            return bad("CP takes no or PHASE noise");
+        if (g.kind != QS_G_CP && g.noise != QS_NOISE_NONE) return bad("noise only on U1 and CP");
+        break;
+    case QS_G_FLIP:
+        if (g.mask & ~nmask) return bad("FLIP mask beyond n bits");
+        if (g.value & ~g.mask) return bad("FLIP value outside its mask");
+        break;
+    default:
+        return bad("unknown gate kind");
+    }
+    if (!std::isfinite(g.theta)) return bad("non-finite theta");
+    for (double v : g.m)
+        if (!std::isfinite(v)) return bad("non-finite matrix entry");
+    return QS_OK;
+}
+
+static qs_status check_noise(const qs_noise *nz, int T)
+{
+    if (!nz) return QS_OK;
+    if (!std::isfinite(nz->e) || nz->e < 0) return fail(QS_EINVAL, "noise: e must be finite and >= 0");
+    if (nz->e_per_traj)
+        for (int t = 0; t < T; ++t)
+            if (!std::isfinite(nz->e_per_traj[t]) || nz->e_per_traj[t] < 0)
+                return fail(QS_EINVAL, "noise: e_per_traj entries must be finite and >= 0");
+    return QS_OK;
+}
+
+static const double kCnot4[32] = {1, 0, 0, 0, 0, 0, 0, 0,  0, 0, 0, 0, 0, 0, 1, 0,
+                                  0, 0, 0, 0, 1, 0, 0, 0,  0, 0, 1, 0, 0, 0, 0, 0};
+
+// Apply gate g to S slots of psi; tab_scratch holds S * 8 doubles.
+static qs_status sweep_gate(void *psi, qs_dtype dt, int n, int S, const qs_gate &g,
+                            const qs_noise *nz, double *tab_scratch, hipStream_t st)
+{
+    if (g.kind == QS_G_U1 || g.kind == QS_G_CP) {
+        NoiseArgs na{};
+        na.e = nz ? nz->e : 0.0;
+        na.e_dev = nullptr;
+        na.seed = nz ? nz->seed : 0;
+        na.request = nz ? nz->request : 0;
+        na.traj_base = nz ? nz->traj_base : 0;
+        na.first_noisy_slot = 0;
+        QS_HIP(launch_noise_one(g, S, na, tab_scratch, st));
+        if (g.kind == QS_G_U1) QS_HIP(launch_sweep_u1(psi, dt, n, S, g.q0, tab_scratch, st));
+        else QS_HIP(launch_sweep_cp(psi, dt, n, S, g.q0, g.q1, tab_scratch, st));
+    } else if (g.kind == QS_G_SWAP || g.kind == QS_G_CNOT) {
+        QS_HIP(launch_sweep_perm(psi, dt, n, S, g.kind, g.q0, g.q1, st));
+    } else if (g.kind == QS_G_U2) {
+        QS_HIP(launch_sweep_2q(psi, dt, n, S, g.q0, g.q1, g.m, st));
+    } else if (g.kind == QS_G_FLIP) {
+        QS_HIP(launch_flip(psi, dt, n, S, g.mask, g.value, st));
+    }
+    return QS_OK;
+}
+
+// Kraus set of the eq. (1) noisy one-qubit gate U: {U E1, U E2}, E1 = sqrt(l1) I,
+// E2 = sqrt(l2) [[0, 1], [-1, 0]], l1,2 = (1 +- exp(-2 e^2)) / 2 (eq. 6).  out: 2 x 8 doubles.
+static void kraus_rot_ops(const double *u, double e, double *out)
+{
+    const double l1 = 0.5 * (1.0 + std::exp(-2.0 * e * e));
+    const double l2 = 0.5 * (1.0 - std::exp(-2.0 * e * e));
+    const double s1 = std::sqrt(l1), s2 = std::sqrt(l2);
+    for (int r = 0; r < 2; ++r) {
+        std::complex<double> a(u[4 * r], u[4 * r + 1]), b(u[4 * r + 2], u[4 * r + 3]);
+        std::complex<double> k1c0 = a * s1, k1c1 = b * s1;      // U E1
+        std::complex<double> k2c0 = -b * s2, k2c1 = a * s2;     // U E2: columns (-U_r1, U_r0) sqrt(l2)
+        out[4 * r] = k1c0.real(); out[4 * r + 1] = k1c0.imag();
+        out[4 * r + 2] = k1c1.real(); out[4 * r + 3] = k1c1.imag();
+        out[8 + 4 * r] = k2c0.real(); out[8 + 4 * r + 1] = k2c0.imag();
+        out[8 + 4 * r + 2] = k2c1.real(); out[8 + 4 * r + 3] = k2c1.imag();
+    }
+}
+
+extern "C" {
+
+qs_status qs_apply_gate(qs_state s, const qs_gate *g, const qs_noise *nz)
+{
+    clear_error();
+    if (!s || !g) return fail(QS_EINVAL, "apply_gate: NULL argument");
+    qs_status v = check_gate(*g, s->n, 0);
+    if (v != QS_OK) return v;
+    if ((v = check_noise(nz, s->T)) != QS_OK) return v;
+    if (nz && nz->e_per_traj) return fail(QS_EUNSUPPORTED, "apply_gate: e_per_traj is for run_trajectories");
+    return sweep_gate(s->buf, s->dt, s->n, s->T, *g, nz, s->scratch, s->st);
+}
+
+qs_status qs_apply_kraus(qs_state rho, int k, const int32_t *qubits, int n_ops, const double *ops)
+{
+    clear_error();
+    if (!rho || !qubits || !ops) return fail(QS_EINVAL, "apply_kraus: NULL argument");
+    if (rho->n % 2 != 0) return fail(QS_EINVAL, "apply_kraus: state must have 2n qubits (vec rho)");
+    if (rho->T != 1) return fail(QS_EINVAL, "apply_kraus: density matrix state must hold one vector");
+    const int n = rho->n / 2;
+    if (k != 1) return fail(QS_EUNSUPPORTED, "apply_kraus: one-qubit Kraus sets (k = 1) only");
+    if (qubits[0] < 0 || qubits[0] >= n) return fail(QS_EINVAL, "apply_kraus: qubit out of range");
+    if (n_ops < 1 || n_ops > 64) return fail(QS_EINVAL, "apply_kraus: n_ops must be in 1..64");
+    for (int i = 0; i < n_ops * 8; ++i)
+        if (!std::isfinite(ops[i])) return fail(QS_EINVAL, "apply_kraus: non-finite operator entry");
+    // Superoperator S = sum_k E_k (x) conj(E_k) on (bra bit q, ket bit q + n): local index
+    // bit(q) + 2 bit(q + n) = b + 2 a for ket bit a, bra bit b;
+    // S[(a, b), (c, d)] = sum_k E_k[a][c] conj(E_k[b][d]).
+    qs_gate g{};
+    g.kind = QS_G_U2;
+    g.q0 = qubits[0];
+    g.q1 = qubits[0] + n;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c)
+                for (int d = 0; d < 2; ++d) {
+                    std::complex<double> s = 0;
+                    for (int o = 0; o < n_ops; ++o) {
+                        const double *E = ops + 8 * o;
+                        std::complex<double> eac(E[2 * (2 * a + c)], E[2 * (2 * a + c) + 1]);
+                        std::complex<double> ebd(E[2 * (2 * b + d)], E[2 * (2 * b + d) + 1]);
+                        s += eac * std::conj(ebd);
+                    }
+                    int row = b + 2 * a, col = d + 2 * c;
+                    g.m[2 * (4 * row + col)] = s.real();
+                    g.m[2 * (4 * row + col) + 1] = s.imag();
+                }
+    return sweep_gate(rho->buf, rho->dt, rho->n, 1, g, nullptr, rho->scratch, rho->st);
+}
+
+qs_status qs_dm_apply_gate(qs_state rho, const qs_gate *g, double e)
+{
+    clear_error();
+    if (!rho || !g) return fail(QS_EINVAL, "dm_apply_gate: NULL argument");
+    if (rho->n % 2 != 0 || rho->T != 1) return fail(QS_EINVAL, "dm_apply_gate: rho must be one vector of 2n qubits");
+    if (!std::isfinite(e) || e < 0) return fail(QS_EINVAL, "dm_apply_gate: e must be finite and >= 0");
+    const int n = rho->n / 2;
+    qs_status v = check_gate(*g, n, 0);
+    if (v != QS_OK) return v;
+    if (g->kind == QS_G_U1) {
+        double ops[16];
+        int nops = 1;
+        if (e > 0 && g->noise == QS_NOISE_ROT) {
+            kraus_rot_ops(g->m, e, ops);
+            nops = 2;
+        } else {
+            std::memcpy(ops, g->m, 8 * sizeof(double));
+        }
+        int32_t q = g->q0;
+        return qs_apply_kraus(rho, 1, &q, nops, ops);
+    }
+    if (g->kind == QS_G_FLIP) {
+        QS_HIP(launch_flip(rho->buf, rho->dt, rho->n, 1, g->mask << n, g->value << n, rho->st));
+        QS_HIP(launch_flip(rho->buf, rho->dt, rho->n, 1, g->mask, g->value, rho->st));
+        return QS_OK;
+    }
+    if (g->kind == QS_G_CP && e > 0 && g->noise == QS_NOISE_PHASE)
+        return fail(QS_EUNSUPPORTED, "dm_apply_gate: the noisy controlled phase (eq. 9) is not implemented on vec(rho)");
+    // two-qubit unitary: U on the ket bits, conj(U) on the bra bits
+    qs_gate ket = *g, bra = *g;
+    ket.q0 += n;
+    ket.q1 += n;
+    ket.noise = bra.noise = QS_NOISE_NONE;
+    if (g->kind == QS_G_CP) bra.theta = -g->theta;
+    if (g->kind == QS_G_U2)
+        for (int k = 0; k < 16; ++k) bra.m[2 * k + 1] = -g->m[2 * k + 1];
+    v = sweep_gate(rho->buf, rho->dt, rho->n, 1, ket, nullptr, rho->scratch, rho->st);
+    if (v != QS_OK) return v;
+    return sweep_gate(rho->buf, rho->dt, rho->n, 1, bra, nullptr, rho->scratch + 8, rho->st);
+}
+
+qs_status qs_fidelity(qs_state a, int ta, qs_state b, int tb, double *f, double *overlap)
+{
+    clear_error();
+    if (!a || !b || !f) return fail(QS_EINVAL, "fidelity: NULL argument");
+    if (a->n != b->n || a->dt != b->dt) return fail(QS_EINVAL, "fidelity: states differ in n or dtype");
+    if (ta < 0 || ta >= a->T || tb < 0 || tb >= b->T) return fail(QS_EINVAL, "fidelity: trajectory out of range");
+    const int n = a->n;
+    const size_t sb = amp_bytes(a->dt) << n;
+    double *part = a->scratch + (size_t)a->T * 8;
+    double *out = a->scratch + a->scratch_doubles - 64 - 16;
+    const char *pa = (const char *)a->buf + sb * ta;
+    const char *pb = (const char *)b->buf + sb * tb;
+    if (a->st != b->st) QS_HIP(hipStreamSynchronize(b->st));
+    QS_HIP(launch_overlaps(pa, 0, pb, a->dt, n, 1, -1, part, out, a->st));
+    QS_HIP(launch_overlaps(pa, 0, pa, a->dt, n, 1, -1, part, out + 5, a->st));
+    double h[10];
+    QS_HIP(hipMemcpyAsync(h, out, sizeof h, hipMemcpyDeviceToHost, a->st));
+    QS_HIP(hipStreamSynchronize(a->st));
+    double nb = h[2], na = h[7];
+    *f = (h[0] * h[0] + h[1] * h[1]) / (na * nb);
+    if (overlap) {
+        overlap[0] = h[0];
+        overlap[1] = h[1];
+    }
+    return QS_OK;
+}
+
+qs_status qs_dm_fidelity(qs_state rho, qs_state psi, int tpsi, double *f, double *trace)
+{
+    clear_error();
+    if (!rho || !psi || !f) return fail(QS_EINVAL, "dm_fidelity: NULL argument");
+    if (rho->T != 1 || rho->n != 2 * psi->n || rho->dt != psi->dt)
+        return fail(QS_EINVAL, "dm_fidelity: rho must be one vector of 2n qubits with psi's dtype");
+    if (tpsi < 0 || tpsi >= psi->T) return fail(QS_EINVAL, "dm_fidelity: trajectory out of range");
+    const int n = psi->n;
+    const char *pp = (const char *)psi->buf + (amp_bytes(psi->dt) << n) * tpsi;
+    double *part = rho->scratch + 8;
+    double *out = rho->scratch + rho->scratch_doubles - 64 - 16;
+    if (rho->st != psi->st) QS_HIP(hipStreamSynchronize(psi->st));
+    QS_HIP(launch_dm_expect(rho->buf, pp, rho->dt, n, part, out, rho->st));
+    double h[4];
+    QS_HIP(hipMemcpyAsync(h, out, sizeof h, hipMemcpyDeviceToHost, rho->st));
+    QS_HIP(hipStreamSynchronize(rho->st));
+    *f = h[0];
+    if (trace) *trace = h[2];
+    return QS_OK;
+}
+
+qs_status qs_noise_draw(uint64_t seed, uint32_t request, uint32_t stream, const uint32_t *sites_dev,
+                        int n_sites, uint32_t traj_base, int n_traj, double *out_dev, void *hip_stream)
+{
+    clear_error();
+    if (!sites_dev || !out_dev) return fail(QS_EINVAL, "noise_draw: NULL argument");
+    if (n_sites < 0 || n_traj < 0) return fail(QS_EINVAL, "noise_draw: negative size");
+    QS_HIP(launch_noise_draw(seed, request, stream, sites_dev, n_sites, traj_base, n_traj, out_dev,
+                             (hipStream_t)hip_stream));
+    return QS_OK;
+}
+
+qs_status qs_copy(void *dst, const void *src, size_t bytes, void *hip_stream)
+{
+    clear_error();
+    if (!dst || !src || bytes % 16) return fail(QS_EINVAL, "copy: NULL pointer or size not a multiple of 16");
+    QS_HIP(launch_copy(dst, src, bytes, (hipStream_t)hip_stream));
+    return QS_OK;
+}
+
+qs_status qs_timing_enable(int on)
+{
+    clear_error();
+    timing_flush();
+    g_timing = on != 0;
+    return QS_OK;
+}
+
+qs_status qs_timing_read(const char *name, int64_t *launches, double *ms, double *alg_bytes)
+{
+    clear_error();
+    if (!name) return fail(QS_EINVAL, "timing_read: NULL name");
+    timing_flush();
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (auto &p : g_acc)
+        if (p.first == name) {
+            if (launches) *launches = p.second.n;
+            if (ms) *ms = p.second.ms;
+            if (alg_bytes) *alg_bytes = p.second.bytes;
+            return QS_OK;
+        }
+    if (launches) *launches = 0;
+    if (ms) *ms = 0;
+    if (alg_bytes) *alg_bytes = 0;
+    return QS_OK;
+}
+
+qs_status qs_timing_reset(void)
+{
+    clear_error();
+    timing_flush();
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_acc.clear();
+    return QS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// run_trajectories
+// ---------------------------------------------------------------------------------------
+namespace {
+
+struct TrajLayout {
+    size_t states, tab, gates, edev, passes, rounds, ops, prefs, partials, out, total;
+};
+
+struct Plan {
+    bool fused = false;
+    int K = 0, RB = 0, run_bits = 0;
+    qs::Program prog;
+};
+
+qs_status resolve_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, int T, const qs_plan *p,
+                       Plan &out)
+{
+    int fuse = p ? p->fuse : -1;
+    if (fuse < -1 || fuse > 1) return fail(QS_EINVAL, "plan: fuse must be -1, 0 or 1");
+    if (fuse == -1) fuse = 1;
+    out.fused = fuse == 1;
+    if (!out.fused) return QS_OK;
+    int maxK = dt == QS_C64 ? 13 : 12;
+    int K = (p && p->tile_bits > 0) ? p->tile_bits : maxK;
+    int RB = (p && p->reg_bits > 0) ? p->reg_bits : 4;
+    int run = (p && p->run_bits > 0) ? p->run_bits : (dt == QS_C64 ? 4 : 3);
+    if (K > kMaxTileBits) return fail(QS_EINVAL, "plan: tile_bits too large");
+    if ((size_t(1) << std::min(K, n)) * amp_bytes(dt) > 160 * 1024)
+        return fail(QS_EINVAL, "plan: tile does not fit the 160 KiB LDS of a gfx950 CU");
+    if (RB > kMaxRegBits) return fail(QS_EINVAL, "plan: reg_bits must be <= 4");
+    if (n <= K) {
+        K = n;   // the whole state is one tile: the circuit runs as one launch
+        if (RB > K) RB = K;
+    }
+    out.K = K;
+    out.RB = RB;
+    out.run_bits = run;
+    (void)T;
+    return plan_fused(gates, n_gates, n, K, RB, run, out.prog);
+}
+
+TrajLayout traj_layout(int n, qs_dtype dt, int T, int n_gates, const Plan &pl)
+{
+    TrajLayout L{};
+    const int S = T + 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    L.states = take(state_bytes(n, dt, S));
+    L.tab = take((size_t)n_gates * S * 8 * sizeof(double));
+    L.gates = take((size_t)std::max(n_gates, 1) * sizeof(qs_gate));
+    L.edev = take((size_t)S * sizeof(double));
+    L.passes = take(std::max<size_t>(pl.prog.passes.size(), 1) * sizeof(PassDesc));
+    L.rounds = take(std::max<size_t>(pl.prog.rounds.size(), 1) * sizeof(RoundDesc));
+    L.ops = take(std::max<size_t>(pl.prog.ops.size(), 1) * sizeof(OpDesc));
+    L.prefs = take(std::max<size_t>(pl.prog.prefs.size(), 1) * sizeof(PhaseRef));
+    L.partials = take(reduce_partials_doubles(n, S) * sizeof(double));
+    L.out = take((size_t)S * 5 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+qs_status check_circuit(const qs_gate *gates, int n_gates, int n)
+{
+    if (n_gates < 0) return fail(QS_EINVAL, "n_gates must be >= 0");
+    if (n_gates > 0 && !gates) return fail(QS_EINVAL, "gates is NULL");
+    for (int i = 0; i < n_gates; ++i) {
+        qs_status v = check_gate(gates[i], n, i);
+        if (v != QS_OK) return v;
+    }
+    return QS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t qs_traj_bytes_required(const qs_gate *gates, int n_gates, int n, qs_dtype dt, int T,
+                              const qs_plan *plan)
+{
+    if (n < 1 || n > 34 || T < 1 || (dt != QS_C64 && dt != QS_C128)) return 0;
+    if (check_circuit(gates, n_gates, n) != QS_OK) return 0;
+    Plan pl;
+    if (resolve_plan(gates, n_gates, n, dt, T, plan, pl) != QS_OK) return 0;
+    return traj_layout(n, dt, T, n_gates, pl).total;
+}
+
+qs_status qs_run_trajectories(const qs_gate *gates, int n_gates, int n, uint64_t init_index, qs_dtype dt,
+                              const qs_noise *nz, int T, int64_t marked, const qs_plan *plan,
+                              void *dev_buf, size_t buf_bytes, void *hip_stream, double *fid_out,
+                              double *p_out, double *norm_out, int32_t *layout_out)
+{
+    clear_error();
+    if (n < 1 || n > 34) return fail(QS_EINVAL, "run_trajectories: n_qubits must be in 1..34");
+    if (dt != QS_C64 && dt != QS_C128) return fail(QS_EINVAL, "run_trajectories: unknown dtype");
+    if (T < 1) return fail(QS_EINVAL, "run_trajectories: n_traj must be >= 1");
+    if (!fid_out) return fail(QS_EINVAL, "run_trajectories: fid_out is NULL");
+    if (init_index >= (1ull << n)) return fail(QS_EINVAL, "run_trajectories: init_index out of range");
+    if (marked >= (int64_t)(1ull << n)) return fail(QS_EINVAL, "run_trajectories: marked out of range");
+    if (p_out && marked < 0) return fail(QS_EINVAL, "run_trajectories: p_out needs marked >= 0");
+    if (!dev_buf || !aligned256(dev_buf))
+        return fail(QS_EINVAL, "run_trajectories: buffer must be non-NULL and 256-byte aligned");
+    qs_status v = check_circuit(gates, n_gates, n);
+    if (v != QS_OK) return v;
+    if ((v = check_noise(nz, T)) != QS_OK) return v;
+    Plan pl;
+    if ((v = resolve_plan(gates, n_gates, n, dt, T, plan, pl)) != QS_OK) return v;
+    TrajLayout L = traj_layout(n, dt, T, n_gates, pl);
+    if (buf_bytes < L.total)
+        return fail(QS_EINVAL, "run_trajectories: buffer too small (need " + std::to_string(L.total) + " bytes)");
+
+    hipStream_t st = (hipStream_t)hip_stream;
+    char *B = (char *)dev_buf;
+    const int S = T + 1;
+    void *psi = B + L.states;
+    double *tab = (double *)(B + L.tab);
+    qs_gate *gdev = (qs_gate *)(B + L.gates);
+    double *edev = (double *)(B + L.edev);
+
+    // device copy of the gates; CNOTs carry their permutation matrix for fused U2 ops
+    std::vector<qs_gate> hg(gates, gates + n_gates);
+    for (auto &g : hg)
+        if (g.kind == QS_G_CNOT) std::memcpy(g.m, kCnot4, sizeof kCnot4);
+    std::vector<double> he(S, 0.0);
+    for (int t = 0; t < T; ++t) he[t + 1] = nz ? (nz->e_per_traj ? nz->e_per_traj[t] : nz->e) : 0.0;
+    if (n_gates > 0) QS_HIP(hipMemcpyAsync(gdev, hg.data(), sizeof(qs_gate) * n_gates, hipMemcpyHostToDevice, st));
+    QS_HIP(hipMemcpyAsync(edev, he.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
+    const Program &P = pl.prog;
+    if (pl.fused) {
+        if (!P.passes.empty())
+            QS_HIP(hipMemcpyAsync(B + L.passes, P.passes.data(), sizeof(PassDesc) * P.passes.size(), hipMemcpyHostToDevice, st));
+        if (!P.rounds.empty())
+            QS_HIP(hipMemcpyAsync(B + L.rounds, P.rounds.data(), sizeof(RoundDesc) * P.rounds.size(), hipMemcpyHostToDevice, st));
+        if (!P.ops.empty())
+            QS_HIP(hipMemcpyAsync(B + L.ops, P.ops.data(), sizeof(OpDesc) * P.ops.size(), hipMemcpyHostToDevice, st));
+        if (!P.prefs.empty())
+            QS_HIP(hipMemcpyAsync(B + L.prefs, P.prefs.data(), sizeof(PhaseRef) * P.prefs.size(), hipMemcpyHostToDevice, st));
+    }
+    NoiseArgs na{};
+    na.e = 0.0;
+    na.e_dev = edev;
+    na.seed = nz ? nz->seed : 0;
+    na.request = nz ? nz->request : 0;
+    na.traj_base = nz ? nz->traj_base : 0;
+    na.first_noisy_slot = 1;
+    QS_HIP(launch_noise_table(gdev, n_gates, S, na, tab, st));
+    QS_HIP(launch_init_basis(psi, dt, n, S, init_index, st));
+
+    if (pl.fused) {
+        for (size_t p = 0; p < P.passes.size(); ++p)
+            QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (const PassDesc *)(B + L.passes) + p,
+                                     (const RoundDesc *)(B + L.rounds), (const OpDesc *)(B + L.ops),
+                                     (const PhaseRef *)(B + L.prefs), tab, gdev, st));
+    } else {
+        for (int g = 0; g < n_gates; ++g) {
+            const qs_gate &G = gates[g];
+            const double *row = tab + (size_t)g * S * 8;
+            switch (G.kind) {
+            case QS_G_U1: QS_HIP(launch_sweep_u1(psi, dt, n, S, G.q0, row, st)); break;
+            case QS_G_CP: QS_HIP(launch_sweep_cp(psi, dt, n, S, G.q0, G.q1, row, st)); break;
+            case QS_G_SWAP:
+            case QS_G_CNOT: QS_HIP(launch_sweep_perm(psi, dt, n, S, G.kind, G.q0, G.q1, st)); break;
+            case QS_G_U2: QS_HIP(launch_sweep_2q(psi, dt, n, S, G.q0, G.q1, G.m, st)); break;
+            case QS_G_FLIP: QS_HIP(launch_flip(psi, dt, n, S, G.mask, G.value, st)); break;
+            }
+        }
+    }
+    std::vector<int32_t> layout(n);
+    for (int q = 0; q < n; ++q) layout[q] = pl.fused ? P.layout[q] : q;
+    int64_t pmarked = -1;
+    if (marked >= 0) {
+        pmarked = 0;
+        for (int q = 0; q < n; ++q)
+            if ((marked >> q) & 1) pmarked |= (int64_t)1 << layout[q];
+    }
+    double *part = (double *)(B + L.partials);
+    double *out = (double *)(B + L.out);
+    QS_HIP(launch_overlaps(psi, 0, psi, dt, n, S, pmarked, part, out, st));
+    std::vector<double> h((size_t)S * 5);
+    QS_HIP(hipMemcpyAsync(h.data(), out, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+    QS_HIP(hipStreamSynchronize(st));
+    const double n0 = h[2];
+    for (int t = 0; t < T; ++t) {
+        const double *o = &h[(size_t)(t + 1) * 5];
+        fid_out[t] = (o[0] * o[0] + o[1] * o[1]) / (n0 * o[2]);
+        if (p_out) p_out[t] = o[3] * o[3] + o[4] * o[4];
+        if (norm_out) norm_out[t] = o[2];
+    }
+    if (layout_out)
+        for (int q = 0; q < n; ++q) layout_out[q] = layout[q];
+    return QS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// Fixed rank
+// ---------------------------------------------------------------------------------------
+namespace {
+
+using cd = std::complex<double>;
+
+// Cyclic Jacobi for a Hermitian m x m matrix (row-major A): on return w holds the eigenvalues
+// and the columns of Vec the eigenvectors.  Each rotation first turns A_pq real with a phase
+// on column q, then zeroes it with a real plane rotation (Golub & Van Loan, sec. 8.5).
+void jacobi_hermitian(int m, std::vector<cd> &A, std::vector<double> &w, std::vector<cd> &Vec)
+{
+    Vec.assign((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) Vec[(size_t)i * m + i] = 1.0;
+    auto at = [&](int i, int j) -> cd & { return A[(size_t)i * m + j]; };
+    double fro = 0;
+    for (auto &x : A) fro += std::norm(x);
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j)
+                if (i != j) off += std::norm(at(i, j));
+        if (off <= 1e-32 * fro || off == 0.0) break;
+        for (int p = 0; p < m - 1; ++p)
+            for (int q = p + 1; q < m; ++q) {
+                cd apq = at(p, q);
+                double r = std::abs(apq);
+                if (r == 0.0) continue;
+                cd ph = apq / r;                      // e^{i phi}
+                double app = at(p, p).real(), aqq = at(q, q).real();
+                double theta = 0.5 * std::atan2(2.0 * r, aqq - app);
+                double c = std::cos(theta), s = std::sin(theta);
+                cd em = std::conj(ph);                // e^{-i phi}
+                // J = D R: J_pp = c, J_pq = s, J_qp = -s e^{-i phi}, J_qq = c e^{-i phi}
+                for (int k = 0; k < m; ++k) {         // A <- A J
+                    cd akp = at(k, p), akq = at(k, q);
+                    at(k, p) = akp * c - akq * s * em;
+                    at(k, q) = akp * s + akq * c * em;
+                }
+                for (int k = 0; k < m; ++k) {         // A <- J^dagger A
+                    cd apk = at(p, k), aqk = at(q, k);
+                    at(p, k) = apk * c - aqk * s * ph;
+                    at(q, k) = apk * s + aqk * c * ph;
+                }
+                at(p, q) = 0.0;
+                at(q, p) = 0.0;
+                at(p, p) = at(p, p).real();
+                at(q, q) = at(q, q).real();
+                for (int k = 0; k < m; ++k) {         // Vec <- Vec J
+                    cd vkp = Vec[(size_t)k * m + p], vkq = Vec[(size_t)k * m + q];
+                    Vec[(size_t)k * m + p] = vkp * c - vkq * s * em;
+                    Vec[(size_t)k * m + q] = vkp * s + vkq * c * em;
+                }
+            }
+    }
+    w.resize(m);
+    for (int i = 0; i < m; ++i) w[i] = at(i, i).real();
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t qs_fr_bytes_required(int n, int r, qs_dtype dt)
+{
+    if (n < 1 || n > 34 || r < 1 || r > 8 || (dt != QS_C64 && dt != QS_C128)) return 0;
+    return state_bytes(n, dt, r);
+}
+
+qs_status qs_fr_create(int n, int r, qs_dtype dt, void *buf, size_t bytes, void *stream, qs_fr *out)
+{
+    clear_error();
+    if (!out) return fail(QS_EINVAL, "fr_create: out is NULL");
+    *out = nullptr;
+    if (n < 2 || n > 34) return fail(QS_EINVAL, "fr_create: n_qubits must be in 2..34");
+    if (r < 1 || r > 8) return fail(QS_EINVAL, "fr_create: rank bound r must be in 1..8");
+    if (dt != QS_C64 && dt != QS_C128) return fail(QS_EINVAL, "fr_create: unknown dtype");
+    if (!buf || !aligned256(buf)) return fail(QS_EINVAL, "fr_create: buffer must be non-NULL and 256-byte aligned");
+    if (bytes < state_bytes(n, dt, r)) return fail(QS_EINVAL, "fr_create: buffer too small");
+    auto *f = new (std::nothrow) qs_fr_s();
+    if (!f) return fail(QS_ENOMEM, "fr_create: out of host memory");
+    f->n = n;
+    f->r = r;
+    f->rank = 0;
+    f->dt = dt;
+    f->V = buf;
+    f->st = (hipStream_t)stream;
+    f->log_trace = 0.0;
+    size_t off = 0;
+    off += align256(fr_gram_partials_doubles(n, r) * 8) / 8;
+    f->off_gram = off;
+    off += 512;
+    f->off_coef = off;
+    off += 512;
+    f->off_ovp = off;
+    off += align256(reduce_partials_doubles(n, 8) * 8) / 8;
+    f->off_ovo = off;
+    off += 64;
+    f->off_tab = off;
+    off += 64 + 64;
+    hipError_t e = hipMalloc(&f->scratch, off * sizeof(double));
+    if (e != hipSuccess) {
+        delete f;
+        return hip_fail(e, "fr_create: hipMalloc scratch");
+    }
+    e = hipHostMalloc(&f->host, 1024 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipFree(f->scratch);
+        delete f;
+        return hip_fail(e, "fr_create: hipHostMalloc staging");
+    }
+    *out = f;
+    return QS_OK;
+}
+
+qs_status qs_fr_destroy(qs_fr f)
+{
+    clear_error();
+    if (!f) return QS_OK;
+    (void)hipStreamSynchronize(f->st);
+    (void)hipFree(f->scratch);
+    (void)hipHostFree(f->host);
+    delete f;
+    return QS_OK;
+}
+
+qs_status qs_fr_init_basis(qs_fr f, uint64_t index)
+{
+    clear_error();
+    if (!f) return fail(QS_EINVAL, "fr_init_basis: NULL handle");
+    if (index >= (1ull << f->n)) return fail(QS_EINVAL, "fr_init_basis: index out of range");
+    QS_HIP(launch_init_basis(f->V, f->dt, f->n, 1, index, f->st));
+    f->rank = 1;
+    f->log_trace = 0.0;
+    return QS_OK;
+}
+
+qs_status qs_fr_apply_gate(qs_fr f, const qs_gate *g)
+{
+    clear_error();
+    if (!f || !g) return fail(QS_EINVAL, "fr_apply_gate: NULL argument");
+    if (f->rank < 1) return fail(QS_EINVAL, "fr_apply_gate: call fr_init_basis first");
+    qs_status v = check_gate(*g, f->n, 0);
+    if (v != QS_OK) return v;
+    return sweep_gate(f->V, f->dt, f->n, f->rank, *g, nullptr, f->scratch + f->off_tab, f->st);
+}
+
+qs_status qs_fr_apply_kraus(qs_fr f, int q, int n_ops, const double *ops, double tau, double zero_tol,
+                            int *rank_out)
+{
+    clear_error();
+    if (!f || !ops) return fail(QS_EINVAL, "fr_apply_kraus: NULL argument");
+    if (f->rank < 1) return fail(QS_EINVAL, "fr_apply_kraus: call fr_init_basis first");
+    if (q < 0 || q >= f->n) return fail(QS_EINVAL, "fr_apply_kraus: qubit out of range");
+    if (n_ops < 1 || n_ops > 4) return fail(QS_EINVAL, "fr_apply_kraus: n_ops must be in 1..4");
+    if (!(tau >= 0) || !(zero_tol >= 0)) return fail(QS_EINVAL, "fr_apply_kraus: tau and zero_tol must be >= 0");
+    for (int i = 0; i < 8 * n_ops; ++i)
+        if (!std::isfinite(ops[i])) return fail(QS_EINVAL, "fr_apply_kraus: non-finite operator entry");
+    const int rin = f->rank;
+    double *gram_dev = f->scratch + f->off_gram;
+    QS_HIP(launch_fr_gram(f->V, f->dt, f->n, rin, q, f->scratch, gram_dev, f->st));
+    QS_HIP(hipMemcpyAsync(f->host, gram_dev, 512 * sizeof(double), hipMemcpyDeviceToHost, f->st));
+    QS_HIP(hipStreamSynchronize(f->st));
+    // Gamma[(x, c), (y, d)] at index (x * 8 + c) * 16 + (y * 8 + d)
+    auto Gam = [&](int x, int c, int y, int d) {
+        size_t i = (size_t)(x * 8 + c) * 16 + (y * 8 + d);
+        return cd(f->host[2 * i], f->host[2 * i + 1]);
+    };
+    auto E = [&](int a, int r, int c) { return cd(ops[8 * a + 2 * (2 * r + c)], ops[8 * a + 2 * (2 * r + c) + 1]); };
+    const int m = n_ops * rin;
+    std::vector<cd> GW((size_t)m * m);
+    for (int a = 0; a < n_ops; ++a)
+        for (int b = 0; b < n_ops; ++b) {
+            cd C[2][2];   // (E_a^dagger E_b)[x][y]
+            for (int x = 0; x < 2; ++x)
+                for (int y = 0; y < 2; ++y) {
+                    cd s = 0;
+                    for (int z = 0; z < 2; ++z) s += std::conj(E(a, z, x)) * E(b, z, y);
+                    C[x][y] = s;
+                }
+            for (int c = 0; c < rin; ++c)
+                for (int d = 0; d < rin; ++d) {
+                    cd s = 0;
+                    for (int x = 0; x < 2; ++x)
+                        for (int y = 0; y < 2; ++y) s += C[x][y] * Gam(x, c, y, d);
+                    GW[(size_t)(a * rin + c) * m + (b * rin + d)] = s;
+                }
+        }
+    std::vector<double> w;
+    std::vector<cd> Q;
+    jacobi_hermitian(m, GW, w, Q);
+    std::vector<int> order(m);
+    for (int i = 0; i < m; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int i, int j) { return w[i] > w[j]; });
+    const double mu_max = w[order[0]];
+    if (!(mu_max > 0)) return fail(QS_EINVAL, "fr_apply_kraus: the Kraus step annihilated the state");
+    int nz = 0;
+    for (int i = 0; i < m; ++i)
+        if (w[order[i]] > zero_tol * mu_max) ++nz;
+    int keep = std::min(nz, f->r);
+    if (nz > f->r)
+        while (keep > 0 && w[order[keep - 1]] - w[order[keep]] <= tau * mu_max) --keep;
+    if (keep < 1) return fail(QS_EINVAL, "fr_apply_kraus: tie cluster covers every kept eigenvalue");
+    double kept = 0;
+    for (int i = 0; i < keep; ++i) kept += w[order[i]];
+    const double scale = 1.0 / std::sqrt(kept);
+    // coef[(x' * 8 + k'), (y * 8 + c)] = sum_a Q[(a, c), k'] E_a[x'][y] / sqrt(kept)
+    double *coef = f->host + 512;
+    std::memset(coef, 0, 512 * sizeof(double));
+    for (int xo = 0; xo < 2; ++xo)
+        for (int ko = 0; ko < keep; ++ko)
+            for (int y = 0; y < 2; ++y)
+                for (int c = 0; c < rin; ++c) {
+                    cd s = 0;
+                    for (int a = 0; a < n_ops; ++a) s += Q[(size_t)(a * rin + c) * m + order[ko]] * E(a, xo, y);
+                    s *= scale;
+                    size_t i = (size_t)(xo * 8 + ko) * 16 + (y * 8 + c);
+                    coef[2 * i] = s.real();
+                    coef[2 * i + 1] = s.imag();
+                }
+    double *coef_dev = f->scratch + f->off_coef;
+    QS_HIP(hipMemcpyAsync(coef_dev, coef, 512 * sizeof(double), hipMemcpyHostToDevice, f->st));
+    QS_HIP(launch_fr_recombine(f->V, f->dt, f->n, rin, keep, q, coef_dev, f->st));
+    f->rank = keep;
+    f->log_trace += std::log(kept);
+    if (rank_out) *rank_out = keep;
+    return QS_OK;
+}
+
+qs_status qs_fr_apply_noisy_gate(qs_fr f, const qs_gate *g, double e, double tau, double zero_tol,
+                                 int *rank_out)
+{
+    clear_error();
+    if (!f || !g) return fail(QS_EINVAL, "fr_apply_noisy_gate: NULL argument");
+    if (!std::isfinite(e) || e < 0) return fail(QS_EINVAL, "fr_apply_noisy_gate: e must be finite and >= 0");
+    qs_status v = check_gate(*g, f->n, 0);
+    if (v != QS_OK) return v;
+    if (g->kind == QS_G_U1 && e > 0 && g->noise == QS_NOISE_ROT) {
+        double ops[16];
+        kraus_rot_ops(g->m, e, ops);
+        return qs_fr_apply_kraus(f, g->q0, 2, ops, tau, zero_tol, rank_out);
+    }
+    v = qs_fr_apply_gate(f, g);
+    if (v == QS_OK && rank_out) *rank_out = f->rank;
+    return v;
+}
+
+qs_status qs_fr_fidelity(qs_fr f, qs_state psi, int tpsi, double *f_unnorm, double *f_norm, double *log_trace)
+{
+    clear_error();
+    if (!f || !psi) return fail(QS_EINVAL, "fr_fidelity: NULL argument");
+    if (psi->n != f->n || psi->dt != f->dt) return fail(QS_EINVAL, "fr_fidelity: psi differs in n or dtype");
+    if (tpsi < 0 || tpsi >= psi->T) return fail(QS_EINVAL, "fr_fidelity: trajectory out of range");
+    if (f->rank < 1) return fail(QS_EINVAL, "fr_fidelity: call fr_init_basis first");
+    const char *pp = (const char *)psi->buf + (amp_bytes(psi->dt) << psi->n) * tpsi;
+    if (psi->st != f->st) QS_HIP(hipStreamSynchronize(psi->st));
+    double *out = f->scratch + f->off_ovo;
+    QS_HIP(launch_overlaps(pp, 0, f->V, f->dt, f->n, f->rank, -1, f->scratch + f->off_ovp, out, f->st));
+    double h[40];
+    QS_HIP(hipMemcpyAsync(h, out, sizeof(double) * 5 * f->rank, hipMemcpyDeviceToHost, f->st));
+    QS_HIP(hipStreamSynchronize(f->st));
+    double s = 0;
+    for (int c = 0; c < f->rank; ++c) s += h[5 * c] * h[5 * c] + h[5 * c + 1] * h[5 * c + 1];
+    if (f_norm) *f_norm = s;
+    if (f_unnorm) *f_unnorm = s * std::exp(f->log_trace);
+    if (log_trace) *log_trace = f->log_trace;
+    return QS_OK;
+}
+
+qs_status qs_fr_info(qs_fr f, int *rank, double *log_trace, void **columns_dev)
+{
+    clear_error();
+    if (!f) return fail(QS_EINVAL, "fr_info: NULL handle");
+    if (rank) *rank = f->rank;
+    if (log_trace) *log_trace = f->log_trace;
+    if (columns_dev) *columns_dev = f->V;
+    return QS_OK;
+}
+
+}  // extern "C"

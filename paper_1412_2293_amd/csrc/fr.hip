@@ -1,0 +1,197 @@
+// Fixed-rank density matrix kernels (Section 3.2).
+//
+// rho = sum_c |v_c><v_c| with the columns v_c stored as state vectors.  For a one-qubit Kraus
+// set {E_a} on qubit q, W = [E_a v_c] and G = W^dagger W = sum_{x,y} (E_a^dagger E_b)[x, y]
+// Gamma[(x, c), (y, d)], where Gamma is the Gram matrix of the 2r half-columns
+// h_{c,x}[k] = v_c[k with bit q = x].  The kernels compute Gamma in FP64 in one read of the
+// columns, and apply the truncated recombination v'_k[x'] = sum C[(x', k), (y, c)] h_{c,y} in
+// one read and one write.
+#include "internal.h"
+
+namespace qs {
+
+constexpr int kFrMax = 8;            // columns (rank bound r)
+constexpr int kFrG = 2 * kFrMax;     // half-columns
+constexpr int kFrChunk = 64;         // pairs staged per LDS chunk
+
+__device__ __forceinline__ uint64_t fr_ins0(uint64_t x, int q)
+{
+    uint64_t lo = x & ((1ull << q) - 1);
+    return ((x ^ lo) << 1) | lo;
+}
+
+static inline int fr_log_blocks(int n)
+{
+    // pairs per slot 2^(n-1); each block takes >= 16 chunks
+    int lb = (n - 1) - 10;
+    if (lb < 0) lb = 0;
+    if (lb > 10) lb = 10;
+    return lb;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_fr_gram(const R *V, int n, int r_in, int q, int log_blocks,
+                                                 double *partials)
+{
+    __shared__ double2 xs[kFrChunk][kFrG];
+    __shared__ double2 red[16][16][16];   // [row group][4x4 block][entry]
+    const int tid = threadIdx.x;
+    const int blk16 = tid & 15, bi = blk16 >> 2, bj = blk16 & 3, rg = tid >> 4;
+    const uint64_t N = 1ull << n;
+    const uint64_t pairs = N >> 1;
+    const uint64_t per = pairs >> log_blocks;
+    const uint64_t begin = (uint64_t)blockIdx.x * per;
+    double2 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+
+    for (uint64_t c0 = begin; c0 < begin + per; c0 += kFrChunk) {
+        const uint64_t rows = (begin + per - c0) < (uint64_t)kFrChunk ? (begin + per - c0) : kFrChunk;
+        __syncthreads();
+        for (int v = tid; v < kFrChunk * kFrG; v += 256) {
+            int a = v / kFrChunk, row = v % kFrChunk;
+            int x = a / kFrMax, c = a % kFrMax;
+            double2 val = make_double2(0.0, 0.0);
+            if (c < r_in && (uint64_t)row < rows) {
+                uint64_t i = fr_ins0(c0 + row, q) | ((uint64_t)x << q);
+                const R *p = V + ((uint64_t)c << (n + 1));
+                val = make_double2((double)p[2 * i], (double)p[2 * i + 1]);
+            }
+            xs[row][a] = val;
+        }
+        __syncthreads();
+        for (int row = rg; row < kFrChunk; row += 16) {
+            double2 xi[4], xj[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                xi[k] = xs[row][4 * bi + k];
+                xj[k] = xs[row][4 * bj + k];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    // conj(xi) * xj
+                    acc[i][j].x += xi[i].x * xj[j].x + xi[i].y * xj[j].y;
+                    acc[i][j].y += xi[i].x * xj[j].y - xi[i].y * xj[j].x;
+                }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) red[rg][blk16][4 * i + j] = acc[i][j];
+    __syncthreads();
+    {
+        // thread t owns Gram entry (I, J) = (t >> 4, t & 15)
+        const int I = tid >> 4, J = tid & 15;
+        const int b = (I >> 2) * 4 + (J >> 2), e = (I & 3) * 4 + (J & 3);
+        double sx = 0.0, sy = 0.0;
+        for (int g = 0; g < 16; ++g) {
+            sx += red[g][b][e].x;
+            sy += red[g][b][e].y;
+        }
+        double *o = partials + ((uint64_t)blockIdx.x * 256 + tid) * 2;
+        o[0] = sx;
+        o[1] = sy;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_fr_gram_final(const double *partials, int nb, double *out)
+{
+    const int t = threadIdx.x;
+    double sx = 0.0, sy = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        sx += partials[((uint64_t)b * 256 + t) * 2];
+        sy += partials[((uint64_t)b * 256 + t) * 2 + 1];
+    }
+    out[2 * t] = sx;
+    out[2 * t + 1] = sy;
+}
+
+// coef: 16 x 16 complex doubles, row (x' * 8 + k'), column (y * 8 + c).
+template <typename R>
+__global__ void __launch_bounds__(256) k_fr_recombine(R *V, int n, int r_in, int r_out, int q,
+                                                      const double *coef)
+{
+    __shared__ R cs[kFrG * kFrG][2];
+    for (int v = threadIdx.x; v < kFrG * kFrG; v += 256) {
+        cs[v][0] = (R)coef[2 * v];
+        cs[v][1] = (R)coef[2 * v + 1];
+    }
+    __syncthreads();
+    const uint64_t pairs = 1ull << (n - 1);
+    const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= pairs) return;
+    const uint64_t i0 = fr_ins0(k, q), i1 = i0 | (1ull << q);
+    R hr[kFrG], hi[kFrG];
+#pragma unroll
+    for (int a = 0; a < kFrG; ++a) {
+        int x = a / kFrMax, c = a % kFrMax;
+        hr[a] = (R)0;
+        hi[a] = (R)0;
+        if (c < r_in) {
+            const R *p = V + ((uint64_t)c << (n + 1));
+            uint64_t i = x ? i1 : i0;
+            hr[a] = p[2 * i];
+            hi[a] = p[2 * i + 1];
+        }
+    }
+    for (int o = 0; o < kFrG; ++o) {
+        int xo = o / kFrMax, ko = o % kFrMax;
+        if (ko >= r_out) continue;
+        R sr = (R)0, si = (R)0;
+#pragma unroll
+        for (int a = 0; a < kFrG; ++a) {
+            R cr = cs[o * kFrG + a][0], ci = cs[o * kFrG + a][1];
+            sr += cr * hr[a] - ci * hi[a];
+            si += cr * hi[a] + ci * hr[a];
+        }
+        R *p = V + ((uint64_t)ko << (n + 1));
+        uint64_t i = xo ? i1 : i0;
+        p[2 * i] = sr;
+        p[2 * i + 1] = si;
+    }
+}
+
+size_t fr_gram_partials_doubles(int n, int r)
+{
+    (void)r;
+    return ((size_t)1 << fr_log_blocks(n)) * 256 * 2;
+}
+
+hipError_t launch_fr_gram(const void *V, qs_dtype dt, int n, int r, int q, double *partials,
+                          double *gram_out, hipStream_t st)
+{
+    int lb = fr_log_blocks(n);
+    TimedLaunch tl("fr_gram", (double)r * (double)(1ull << n) * amp_bytes(dt), st);
+    if (dt == QS_C64)
+        hipLaunchKernelGGL(k_fr_gram<float>, dim3(1u << lb), dim3(256), 0, st, (const float *)V, n,
+                           r, q, lb, partials);
+    else
+        hipLaunchKernelGGL(k_fr_gram<double>, dim3(1u << lb), dim3(256), 0, st, (const double *)V,
+                           n, r, q, lb, partials);
+    hipLaunchKernelGGL(k_fr_gram_final, dim3(1), dim3(256), 0, st, partials, 1 << lb, gram_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fr_recombine(void *V, qs_dtype dt, int n, int r_in, int r_out, int q,
+                               const double *coef_dev, hipStream_t st)
+{
+    uint64_t pairs = 1ull << (n - 1);
+    unsigned blocks = (unsigned)((pairs + 255) / 256);
+    TimedLaunch tl("fr_recombine",
+                   ((double)r_in + (double)r_out) * (double)(1ull << n) * amp_bytes(dt), st);
+    if (dt == QS_C64)
+        hipLaunchKernelGGL(k_fr_recombine<float>, dim3(blocks), dim3(256), 0, st, (float *)V, n, r_in,
+                           r_out, q, coef_dev);
+    else
+        hipLaunchKernelGGL(k_fr_recombine<double>, dim3(blocks), dim3(256), 0, st, (double *)V, n,
+                           r_in, r_out, q, coef_dev);
+    return hipGetLastError();
+}
+
+}  // namespace qs

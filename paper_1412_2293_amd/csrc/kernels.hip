@@ -1,0 +1,803 @@
+// gfx950 kernels of libqsim: noise draws, the per-(gate, trajectory) noisy-operator table,
+// unfused per-gate sweeps over batches of state vectors, and FP64 reductions.
+//
+// Sweeps are HBM-bound: every dense gate reads and writes each amplitude once.  Threads of a
+// block take consecutive 16-byte chunks so that each wave instruction touches one contiguous
+// 1 KiB range; a chunk is two complex<float> or one complex<double>.
+#include "internal.h"
+
+#include <cmath>
+
+namespace qs {
+
+template <typename R>
+struct cx {
+    R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> cfma(cx<R> a, cx<R> b, cx<R> c)  // a * b + c
+{
+    return {a.re * b.re - a.im * b.im + c.re, a.re * b.im + a.im * b.re + c.im};
+}
+
+// Amplitudes per 16-byte vector.
+template <typename R>
+constexpr int kVec = sizeof(R) == 4 ? 2 : 1;
+
+template <typename R>
+__device__ __forceinline__ void vload(const R *psi, uint64_t i, cx<R> *a)
+{
+    if constexpr (sizeof(R) == 4) {
+        float4 v = *reinterpret_cast<const float4 *>(psi + 2 * i);
+        a[0] = {v.x, v.y};
+        a[1] = {v.z, v.w};
+    } else {
+        double2 v = *reinterpret_cast<const double2 *>(psi + 2 * i);
+        a[0] = {v.x, v.y};
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void vstore(R *psi, uint64_t i, const cx<R> *a)
+{
+    if constexpr (sizeof(R) == 4) {
+        *reinterpret_cast<float4 *>(psi + 2 * i) = make_float4(a[0].re, a[0].im, a[1].re, a[1].im);
+    } else {
+        *reinterpret_cast<double2 *>(psi + 2 * i) = make_double2(a[0].re, a[0].im);
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> sload(const R *psi, uint64_t i)
+{
+    return {psi[2 * i], psi[2 * i + 1]};
+}
+
+template <typename R>
+__device__ __forceinline__ void sstore(R *psi, uint64_t i, cx<R> a)
+{
+    psi[2 * i] = a.re;
+    psi[2 * i + 1] = a.im;
+}
+
+// Insert a 0 bit at position q of x.
+__device__ __forceinline__ uint64_t ins0(uint64_t x, int q)
+{
+    uint64_t lo = x & ((1ull << q) - 1);
+    return ((x ^ lo) << 1) | lo;
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> tab_c(const double *t, int k)
+{
+    return {(R)t[2 * k], (R)t[2 * k + 1]};
+}
+
+// ---------------------------------------------------------------------------------------
+// Noise: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and the Box-Muller cosine branch.
+// The transform uses only correctly rounded IEEE operations with contraction disabled, so a
+// deviate is a fixed function of the four counter words.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+        uint32_t hi0 = __umulhi(m0, c.x), lo0 = m0 * c.x;
+        uint32_t hi1 = __umulhi(m1, c.z), lo1 = m1 * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// ln x for positive normal x: x = m 2^k, m in [1/sqrt2, sqrt2), ln m = 2 atanh((m-1)/(m+1))
+// summed as its odd power series to s^23.
+__device__ double dev_ln(double x)
+{
+#pragma clang fp contract(off)
+    const double ln2_hi = 0x1.62e42fee00000p-1;
+    const double ln2_lo = 0x1.a39ef35793c76p-33;
+    const double sqrt2 = 0x1.6a09e667f3bcdp+0;
+    unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    int k = (int)((b >> 52) & 0x7ffull) - 1023;
+    double m = __longlong_as_double((long long)((b & 0x000fffffffffffffull) | 0x3ff0000000000000ull));
+    if (m > sqrt2) {
+        m = m * 0.5;
+        k = k + 1;
+    }
+    double s = (m - 1.0) / (m + 1.0);
+    double s2 = s * s;
+    double t = 1.0 / 23.0;
+    t = t * s2 + 1.0 / 21.0;
+    t = t * s2 + 1.0 / 19.0;
+    t = t * s2 + 1.0 / 17.0;
+    t = t * s2 + 1.0 / 15.0;
+    t = t * s2 + 1.0 / 13.0;
+    t = t * s2 + 1.0 / 11.0;
+    t = t * s2 + 1.0 / 9.0;
+    t = t * s2 + 1.0 / 7.0;
+    t = t * s2 + 1.0 / 5.0;
+    t = t * s2 + 1.0 / 3.0;
+    t = t * s2 + 1.0;
+    double kd = (double)k;
+    return kd * ln2_hi + (kd * ln2_lo + 2.0 * s * t);
+}
+
+// cos x and sin x on [0, pi/4] from their Taylor series (to x^20 and x^19).
+__device__ double dev_cos_series(double x)
+{
+#pragma clang fp contract(off)
+    double z = x * x;
+    double t = 1.0 / 2432902008176640000.0;
+    t = t * z - 1.0 / 6402373705728000.0;
+    t = t * z + 1.0 / 20922789888000.0;
+    t = t * z - 1.0 / 87178291200.0;
+    t = t * z + 1.0 / 479001600.0;
+    t = t * z - 1.0 / 3628800.0;
+    t = t * z + 1.0 / 40320.0;
+    t = t * z - 1.0 / 720.0;
+    t = t * z + 1.0 / 24.0;
+    t = t * z - 1.0 / 2.0;
+    return t * z + 1.0;
+}
+
+__device__ double dev_sin_series(double x)
+{
+#pragma clang fp contract(off)
+    double z = x * x;
+    double t = -1.0 / 121645100408832000.0;
+    t = t * z + 1.0 / 355687428096000.0;
+    t = t * z - 1.0 / 1307674368000.0;
+    t = t * z + 1.0 / 6227020800.0;
+    t = t * z - 1.0 / 39916800.0;
+    t = t * z + 1.0 / 362880.0;
+    t = t * z - 1.0 / 5040.0;
+    t = t * z + 1.0 / 120.0;
+    t = t * z - 1.0 / 6.0;
+    return x + x * (t * z);
+}
+
+// cos(2 pi u), u in [0, 1) a multiple of 2^-53: symmetric reduction to [0, pi/4].
+__device__ double dev_cos_2pi(double u)
+{
+#pragma clang fp contract(off)
+    const double two_pi = 0x1.921fb54442d18p+2;
+    double v = u >= 0.5 ? 1.0 - u : u;
+    if (v <= 0.125) return dev_cos_series(two_pi * v);
+    if (v <= 0.375) return dev_sin_series(two_pi * (0.25 - v));
+    return -dev_cos_series(two_pi * (0.5 - v));
+}
+
+__device__ double dev_normal(uint64_t seed, uint32_t site, uint32_t traj, uint32_t stream,
+                             uint32_t request)
+{
+#pragma clang fp contract(off)
+    uint4 w = philox4x32_10(make_uint4(site, traj, stream, request), (uint32_t)seed,
+                            (uint32_t)(seed >> 32));
+    unsigned long long a = ((((unsigned long long)w.x) << 32) | w.y) >> 11;
+    unsigned long long b = ((((unsigned long long)w.z) << 32) | w.w) >> 11;
+    double u1 = ((double)a + 1.0) * 0x1.0p-53;
+    double u2 = (double)b * 0x1.0p-53;
+    return __builtin_sqrt(-2.0 * dev_ln(u1)) * dev_cos_2pi(u2);
+}
+
+__global__ void k_noise_draw(uint64_t seed, uint32_t request, uint32_t stream,
+                             const uint32_t *sites, int n_sites, uint32_t traj_base, int n_traj,
+                             double *out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_sites * n_traj) return;
+    int t = (int)(i / n_sites), s = (int)(i % n_sites);
+    out[i] = dev_normal(seed, sites[s], traj_base + (uint32_t)t, stream, request);
+}
+
+// The operator gate G applies in slot s, written to o[0..7].  U1: U V(e xi) (eq. 1) as a
+// complex 2x2, products in FP64; CP: exp(-i (theta + e xi)) in the first two doubles.
+__device__ void noisy_operator(const qs_gate &G, int s, const NoiseArgs &na, double *o)
+{
+    double e = 0.0;
+    if (s >= na.first_noisy_slot) e = na.e_dev ? na.e_dev[s] : na.e;
+    uint32_t traj = na.traj_base + (uint32_t)(s - na.first_noisy_slot);
+    if (G.kind == QS_G_U1) {
+        double u[8];
+        for (int k = 0; k < 8; ++k) u[k] = G.m[k];
+        if (e != 0.0 && G.noise == QS_NOISE_ROT) {
+            double xi = dev_normal(na.seed, G.site, traj, 0u, na.request);
+            double sn, cs;
+            sincos(e * xi, &sn, &cs);
+            // V = [[cs, sn], [-sn, cs]] is real: (U V)_{r0} = U_r0 cs - U_r1 sn, (U V)_{r1} = U_r0 sn + U_r1 cs
+            for (int r = 0; r < 2; ++r) {
+                double a_re = u[4 * r], a_im = u[4 * r + 1], b_re = u[4 * r + 2], b_im = u[4 * r + 3];
+                o[4 * r + 0] = a_re * cs - b_re * sn;
+                o[4 * r + 1] = a_im * cs - b_im * sn;
+                o[4 * r + 2] = a_re * sn + b_re * cs;
+                o[4 * r + 3] = a_im * sn + b_im * cs;
+            }
+        } else {
+            for (int k = 0; k < 8; ++k) o[k] = u[k];
+        }
+    } else if (G.kind == QS_G_CP) {
+        double ang = G.theta;
+        if (e != 0.0 && G.noise == QS_NOISE_PHASE)
+            ang += e * dev_normal(na.seed, G.site, traj, 0u, na.request);
+        double sn, cs;
+        sincos(ang, &sn, &cs);
+        o[0] = cs;
+        o[1] = -sn;
+        for (int k = 2; k < 8; ++k) o[k] = 0.0;
+    } else {
+        for (int k = 0; k < 8; ++k) o[k] = 0.0;
+    }
+}
+
+// tab[(g * S + s) * 8 ..] = operator of gate g in slot s.
+__global__ void k_noise_table(const qs_gate *gates, int n_gates, int S, NoiseArgs na, double *tab)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_gates * S) return;
+    int g = (int)(i / S), s = (int)(i % S);
+    noisy_operator(gates[g], s, na, tab + i * 8);
+}
+
+__global__ void k_noise_one(qs_gate G, int S, NoiseArgs na, double *tab)
+{
+    int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (s >= S) return;
+    noisy_operator(G, s, na, tab + (int64_t)s * 8);
+}
+
+// ---------------------------------------------------------------------------------------
+// Basis initialisation: every slot <- |index>.
+// ---------------------------------------------------------------------------------------
+template <typename R>
+__global__ void k_init_basis(R *psi, int n, uint64_t total_vec, uint64_t index)
+{
+    uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= total_vec) return;
+    constexpr int VEC = kVec<R>;
+    uint64_t i = v * VEC;                        // global amplitude index (slot-major)
+    uint64_t in_slot = i & ((1ull << n) - 1);
+    cx<R> a[VEC];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) a[k] = {(R)((in_slot + k) == index ? 1 : 0), (R)0};
+    vstore(psi, i, a);
+}
+
+// ---------------------------------------------------------------------------------------
+// Dense one-qubit sweep: (psi_i0, psi_i1) <- M (psi_i0, psi_i1), i1 = i0 + 2^q (Section 2).
+// MODE 0: q >= log2(vec): a thread takes a 16-byte chunk at i0 and the matching chunk at i1.
+// MODE 1: (complex<float>, q = 0): the pair is one 16-byte chunk.
+// Items per slot are a power of two; each thread handles U items 256 apart.
+// ---------------------------------------------------------------------------------------
+template <typename R, int MODE, int U>
+__global__ void __launch_bounds__(256) k_u1(R *psi, int n, int q, const double *tab_row,
+                                            int log_items, uint64_t total)
+{
+    constexpr int VEC = kVec<R>;
+    const uint64_t base_item = (uint64_t)blockIdx.x * (256 * U) + threadIdx.x;
+    cx<R> a0[U][VEC], a1[U][VEC];
+    uint64_t i0s[U];
+    int slots[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        uint64_t it = base_item + (uint64_t)u * 256;
+        slots[u] = -1;
+        if (it >= total) continue;
+        int slot = (int)(it >> log_items);
+        uint64_t c = it & ((1ull << log_items) - 1);
+        R *p = psi + ((uint64_t)slot << (n + 1));
+        slots[u] = slot;
+        if constexpr (MODE == 0) {
+            uint64_t i0 = ins0(c * VEC, q);
+            i0s[u] = i0;
+            vload(p, i0, a0[u]);
+            vload(p, i0 | (1ull << q), a1[u]);
+        } else {
+            i0s[u] = c * 2;
+            cx<R> t[2];
+            vload(p, c * 2, t);
+            a0[u][0] = t[0];
+            a1[u][0] = t[1];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (slots[u] < 0) continue;
+        const double *t = tab_row + (uint64_t)slots[u] * 8;
+        cx<R> m00 = tab_c<R>(t, 0), m01 = tab_c<R>(t, 1), m10 = tab_c<R>(t, 2), m11 = tab_c<R>(t, 3);
+        R *p = psi + ((uint64_t)slots[u] << (n + 1));
+        constexpr int NP = MODE == 0 ? VEC : 1;
+        cx<R> b0[VEC], b1[VEC];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            b0[k] = cfma(m01, a1[u][k], cmul(m00, a0[u][k]));
+            b1[k] = cfma(m11, a1[u][k], cmul(m10, a0[u][k]));
+        }
+        if constexpr (MODE == 0) {
+            vstore(p, i0s[u], b0);
+            vstore(p, i0s[u] | (1ull << q), b1);
+        } else {
+            cx<R> t2[2] = {b0[0], b1[0]};
+            vstore(p, i0s[u], t2);
+        }
+    }
+}
+
+// Generic one-amplitude-pair-per-thread fallback for small states.
+template <typename R>
+__global__ void k_u1_small(R *psi, int n, int q, const double *tab_row, uint64_t total)
+{
+    uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= total) return;
+    int slot = (int)(it >> (n - 1));
+    uint64_t c = it & ((1ull << (n - 1)) - 1);
+    R *p = psi + ((uint64_t)slot << (n + 1));
+    const double *t = tab_row + (uint64_t)slot * 8;
+    cx<R> m00 = tab_c<R>(t, 0), m01 = tab_c<R>(t, 1), m10 = tab_c<R>(t, 2), m11 = tab_c<R>(t, 3);
+    uint64_t i0 = ins0(c, q), i1 = i0 | (1ull << q);
+    cx<R> a0 = sload(p, i0), a1 = sload(p, i1);
+    sstore(p, i0, cfma(m01, a1, cmul(m00, a0)));
+    sstore(p, i1, cfma(m11, a1, cmul(m10, a0)));
+}
+
+// ---------------------------------------------------------------------------------------
+// Two-qubit sweeps over the N/4 index groups with bits (lo, hi) fixed.
+// KIND 0: controlled phase -- the |11> amplitude times the slot's phase (eq. 2).
+// KIND 1: SWAP (01 <-> 10).  KIND 2: CNOT (control qa, target qb).  KIND 3: dense 4x4.
+// V amplitudes per chunk (V = vec when lo >= log2 vec, else 1).
+// ---------------------------------------------------------------------------------------
+struct M32 {
+    double v[32];
+};
+
+template <typename R, int KIND, int V>
+__global__ void __launch_bounds__(256) k_2q(R *psi, int n, int qa, int qb, const double *tab_row,
+                                            M32 m32, int log_items, uint64_t total)
+{
+    uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= total) return;
+    const int lo = qa < qb ? qa : qb, hi = qa < qb ? qb : qa;
+    int slot = (int)(it >> log_items);
+    uint64_t c = it & ((1ull << log_items) - 1);
+    R *p = psi + ((uint64_t)slot << (n + 1));
+    uint64_t base = ins0(ins0(c * V, lo), hi);
+    const uint64_t ba = 1ull << qa, bb = 1ull << qb;
+    auto ld = [&](uint64_t i, cx<R> *a) {
+        if constexpr (V == kVec<R> && V > 1) vload(p, i, a);
+        else if constexpr (V == 1) a[0] = sload(p, i);
+        else vload(p, i, a);
+    };
+    auto st = [&](uint64_t i, const cx<R> *a) {
+        if constexpr (V == 1) sstore(p, i, a[0]);
+        else vstore(p, i, a);
+    };
+    if constexpr (KIND == 0) {
+        const double *t = tab_row + (uint64_t)slot * 8;
+        cx<R> ph = tab_c<R>(t, 0);
+        cx<R> a[V];
+        ld(base | ba | bb, a);
+#pragma unroll
+        for (int k = 0; k < V; ++k) a[k] = cmul(ph, a[k]);
+        st(base | ba | bb, a);
+    } else if constexpr (KIND == 1 || KIND == 2) {
+        uint64_t x = KIND == 1 ? (base | ba) : (base | ba);
+        uint64_t y = KIND == 1 ? (base | bb) : (base | ba | bb);
+        cx<R> a[V], b[V];
+        ld(x, a);
+        ld(y, b);
+        st(x, b);
+        st(y, a);
+    } else {
+        cx<R> a[4][V];
+        uint64_t idx[4] = {base, base | ba, base | bb, base | ba | bb};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ld(idx[r], a[r]);
+        cx<R> m[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) m[k] = {(R)m32.v[2 * k], (R)m32.v[2 * k + 1]};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            cx<R> o[V];
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                cx<R> s = cmul(m[4 * r], a[0][k]);
+                s = cfma(m[4 * r + 1], a[1][k], s);
+                s = cfma(m[4 * r + 2], a[2][k], s);
+                s = cfma(m[4 * r + 3], a[3][k], s);
+                o[k] = s;
+            }
+            st(idx[r], o);
+        }
+    }
+}
+
+// Sign flip of every amplitude i with (i & mask) == value: the free bits of ~mask are
+// enumerated by depositing the item index into them.
+template <typename R>
+__global__ void k_flip(R *psi, int n, uint64_t mask, uint64_t value, int free_bits,
+                       uint64_t total)
+{
+    uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= total) return;
+    int slot = (int)(it >> free_bits);
+    uint64_t c = it & ((1ull << free_bits) - 1);
+    uint64_t i = value;
+    int b = 0;
+    for (int q = 0; q < n; ++q) {
+        if (mask & (1ull << q)) continue;
+        if (c & (1ull << b)) i |= 1ull << q;
+        ++b;
+    }
+    R *p = psi + ((uint64_t)slot << (n + 1));
+    p[2 * i] = -p[2 * i];
+    p[2 * i + 1] = -p[2 * i + 1];
+}
+
+// ---------------------------------------------------------------------------------------
+// FP64 reductions.  Stage 1: each block sums a fixed contiguous range in a fixed order
+// (thread-strided, then an LDS tree); stage 2: one block per slot sums the block partials in
+// a fixed order.  Results are bitwise reproducible for a given launch shape.
+// ---------------------------------------------------------------------------------------
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ void block_sum(double *sh, double (&v)[4], int nv)
+{
+    const int t = threadIdx.x;
+    for (int k = 0; k < nv; ++k) sh[k * kRedThreads + t] = v[k];
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (t < s)
+            for (int k = 0; k < nv; ++k) sh[k * kRedThreads + t] += sh[k * kRedThreads + t + s];
+        __syncthreads();
+    }
+    for (int k = 0; k < nv; ++k) v[k] = sh[k * kRedThreads];
+}
+
+static inline int red_log_blocks(int n)
+{
+    // blocks per slot: enough to fill the chip for one slot, at least 2^11 amplitudes each
+    int lb = n - 11;
+    if (lb < 0) lb = 0;
+    if (lb > 9) lb = 9;
+    return lb;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_overlap_partial(const R *ref, const R *psi, int n,
+                                                                 int log_blocks, double *partials)
+{
+    __shared__ double sh[3 * kRedThreads];
+    const int slot = blockIdx.x >> log_blocks;
+    const uint64_t blk = blockIdx.x & ((1u << log_blocks) - 1);
+    const uint64_t per = 1ull << (n - log_blocks);
+    const R *p = psi + ((uint64_t)slot << (n + 1));
+    double v[4] = {0, 0, 0, 0};
+    constexpr int VEC = kVec<R>;
+    const uint64_t begin = blk * per;
+    if (per >= (uint64_t)VEC * kRedThreads) {
+        for (uint64_t i = begin + (uint64_t)threadIdx.x * VEC; i < begin + per; i += (uint64_t)VEC * kRedThreads) {
+            cx<R> a[VEC], b[VEC];
+            vload(ref, i, a);
+            vload(p, i, b);
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) {
+                double ar = a[k].re, ai = a[k].im, br = b[k].re, bi = b[k].im;
+                v[0] += ar * br + ai * bi;
+                v[1] += ar * bi - ai * br;
+                v[2] += br * br + bi * bi;
+            }
+        }
+    } else {
+        for (uint64_t i = begin + threadIdx.x; i < begin + per; i += kRedThreads) {
+            cx<R> a = sload(ref, i), b = sload(p, i);
+            double ar = a.re, ai = a.im, br = b.re, bi = b.im;
+            v[0] += ar * br + ai * bi;
+            v[1] += ar * bi - ai * br;
+            v[2] += br * br + bi * bi;
+        }
+    }
+    block_sum(sh, v, 3);
+    if (threadIdx.x == 0) {
+        double *o = partials + (uint64_t)blockIdx.x * 3;
+        o[0] = v[0];
+        o[1] = v[1];
+        o[2] = v[2];
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_overlap_final(const R *psi, int n, int log_blocks,
+                                                               int64_t marked, const double *partials,
+                                                               double *out)
+{
+    __shared__ double sh[3 * kRedThreads];
+    const int slot = blockIdx.x;
+    const int nb = 1 << log_blocks;
+    double v[4] = {0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nb; b += kRedThreads) {
+        const double *q = partials + ((uint64_t)slot * nb + b) * 3;
+        v[0] += q[0];
+        v[1] += q[1];
+        v[2] += q[2];
+    }
+    block_sum(sh, v, 3);
+    if (threadIdx.x == 0) {
+        double *o = out + (uint64_t)slot * 5;
+        o[0] = v[0];
+        o[1] = v[1];
+        o[2] = v[2];
+        if (marked >= 0) {
+            const R *p = psi + ((uint64_t)slot << (n + 1));
+            o[3] = (double)p[2 * marked];
+            o[4] = (double)p[2 * marked + 1];
+        } else {
+            o[3] = 0.0;
+            o[4] = 0.0;
+        }
+    }
+}
+
+// <psi|rho|psi> = sum_ij conj(psi_i) rho_ij psi_j and Tr rho over vec(rho), rho_ij at i 2^n + j.
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_dm_expect_partial(const R *rho, const R *psi, int n,
+                                                                   int log_blocks, double *partials)
+{
+    __shared__ double sh[4 * kRedThreads];
+    const uint64_t per = 1ull << (2 * n - log_blocks);
+    const uint64_t begin = (uint64_t)blockIdx.x * per;
+    const uint64_t jmask = (1ull << n) - 1;
+    double v[4] = {0, 0, 0, 0};
+    for (uint64_t idx = begin + threadIdx.x; idx < begin + per; idx += kRedThreads) {
+        uint64_t i = idx >> n, j = idx & jmask;
+        cx<R> r = sload(rho, idx), pi = sload(psi, i), pj = sload(psi, j);
+        double rr = r.re, ri = r.im;
+        // conj(pi) * r * pj
+        double tr = (double)pi.re * rr + (double)pi.im * ri;
+        double ti = (double)pi.re * ri - (double)pi.im * rr;
+        v[0] += tr * (double)pj.re - ti * (double)pj.im;
+        v[1] += tr * (double)pj.im + ti * (double)pj.re;
+        if (i == j) {
+            v[2] += rr;
+            v[3] += ri;
+        }
+    }
+    block_sum(sh, v, 4);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) partials[(uint64_t)blockIdx.x * 4 + k] = v[k];
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_sum4_final(const double *partials, int nb, double *out)
+{
+    __shared__ double sh[4 * kRedThreads];
+    double v[4] = {0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nb; b += kRedThreads)
+        for (int k = 0; k < 4; ++k) v[k] += partials[(uint64_t)b * 4 + k];
+    block_sum(sh, v, 4);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) out[k] = v[k];
+}
+
+__global__ void k_copy(float4 *dst, const float4 *src, uint64_t n16)
+{
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (; i < n16; i += stride) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------------------
+static inline unsigned blocks_for(uint64_t items, unsigned per_block)
+{
+    return (unsigned)((items + per_block - 1) / per_block);
+}
+
+hipError_t launch_noise_table(const qs_gate *gates_dev, int n_gates, int S, NoiseArgs na,
+                              double *tab, hipStream_t st)
+{
+    uint64_t tot = (uint64_t)n_gates * S;
+    if (tot == 0) return hipSuccess;
+    TimedLaunch tl("noise", (double)tot * 64.0, st);
+    hipLaunchKernelGGL(k_noise_table, dim3(blocks_for(tot, 128)), dim3(128), 0, st, gates_dev,
+                       n_gates, S, na, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_noise_one(const qs_gate &g, int S, NoiseArgs na, double *tab, hipStream_t st)
+{
+    TimedLaunch tl("noise", (double)S * 64.0, st);
+    hipLaunchKernelGGL(k_noise_one, dim3((S + 127) / 128), dim3(128), 0, st, g, S, na, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_noise_draw(uint64_t seed, uint32_t request, uint32_t stream,
+                             const uint32_t *sites, int n_sites, uint32_t traj_base, int n_traj,
+                             double *out, hipStream_t st)
+{
+    uint64_t tot = (uint64_t)n_sites * n_traj;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_noise_draw, dim3(blocks_for(tot, 128)), dim3(128), 0, st, seed, request,
+                       stream, sites, n_sites, traj_base, n_traj, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_basis(void *psi, qs_dtype dt, int n, int S, uint64_t index, hipStream_t st)
+{
+    uint64_t amps = (uint64_t)S << n;
+    TimedLaunch tl("init", (double)amps * amp_bytes(dt), st);
+    if (dt == QS_C64) {
+        uint64_t tv = amps / 2;
+        if (n == 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_init_basis<float>, dim3(blocks_for(tv, 256)), dim3(256), 0, st,
+                           (float *)psi, n, tv, index);
+    } else {
+        hipLaunchKernelGGL(k_init_basis<double>, dim3(blocks_for(amps, 256)), dim3(256), 0, st,
+                           (double *)psi, n, amps, index);
+    }
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t sweep_u1_t(R *psi, int n, int S, int q, const double *tab_row, hipStream_t st)
+{
+    constexpr int VEC = kVec<R>;
+    constexpr int U = 2;
+    const uint64_t N = 1ull << n;
+    if (q >= (VEC == 2 ? 1 : 0) && (N / 2) / VEC >= 256 * U) {
+        int log_items = n - 1 - (VEC == 2 ? 1 : 0);
+        uint64_t total = (uint64_t)S << log_items;
+        hipLaunchKernelGGL((k_u1<R, 0, U>), dim3(blocks_for(total, 256 * U)), dim3(256), 0, st, psi,
+                           n, q, tab_row, log_items, total);
+    } else if (VEC == 2 && q == 0 && (N / 2) >= 256 * U) {
+        int log_items = n - 1;
+        uint64_t total = (uint64_t)S << log_items;
+        hipLaunchKernelGGL((k_u1<R, 1, U>), dim3(blocks_for(total, 256 * U)), dim3(256), 0, st, psi,
+                           n, q, tab_row, log_items, total);
+    } else {
+        uint64_t total = (uint64_t)S << (n - 1);
+        hipLaunchKernelGGL(k_u1_small<R>, dim3(blocks_for(total, 256)), dim3(256), 0, st, psi, n,
+                           q, tab_row, total);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_u1(void *psi, qs_dtype dt, int n, int S, int q, const double *tab_row,
+                           hipStream_t st)
+{
+    TimedLaunch tl("sweep_u1", 2.0 * (double)((uint64_t)S << n) * amp_bytes(dt), st);
+    if (dt == QS_C64) return sweep_u1_t((float *)psi, n, S, q, tab_row, st);
+    return sweep_u1_t((double *)psi, n, S, q, tab_row, st);
+}
+
+template <typename R, int KIND>
+static hipError_t sweep_2q_t(R *psi, int n, int S, int qa, int qb, const double *tab_row,
+                             const double *m32_host, hipStream_t st)
+{
+    M32 m32{};
+    if (m32_host)
+        for (int k = 0; k < 32; ++k) m32.v[k] = m32_host[k];
+    constexpr int VEC = kVec<R>;
+    const int lo = qa < qb ? qa : qb;
+    if (VEC == 2 && lo >= 1 && n >= 3) {
+        int log_items = n - 3;
+        uint64_t total = (uint64_t)S << log_items;
+        hipLaunchKernelGGL((k_2q<R, KIND, 2>), dim3(blocks_for(total, 256)), dim3(256), 0, st, psi,
+                           n, qa, qb, tab_row, m32, log_items, total);
+    } else {
+        int log_items = n - 2;
+        uint64_t total = (uint64_t)S << log_items;
+        hipLaunchKernelGGL((k_2q<R, KIND, 1>), dim3(blocks_for(total, 256)), dim3(256), 0, st, psi,
+                           n, qa, qb, tab_row, m32, log_items, total);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_cp(void *psi, qs_dtype dt, int n, int S, int qa, int qb,
+                           const double *tab_row, hipStream_t st)
+{
+    TimedLaunch tl("sweep_cp", 2.0 * (double)((uint64_t)S << n) / 4 * amp_bytes(dt), st);
+    if (dt == QS_C64) return sweep_2q_t<float, 0>((float *)psi, n, S, qa, qb, tab_row, nullptr, st);
+    return sweep_2q_t<double, 0>((double *)psi, n, S, qa, qb, tab_row, nullptr, st);
+}
+
+hipError_t launch_sweep_perm(void *psi, qs_dtype dt, int n, int S, int kind, int qa, int qb,
+                             hipStream_t st)
+{
+    TimedLaunch tl("sweep_swap", 2.0 * (double)((uint64_t)S << n) / 2 * amp_bytes(dt), st);
+    if (kind == QS_G_SWAP) {
+        if (dt == QS_C64) return sweep_2q_t<float, 1>((float *)psi, n, S, qa, qb, nullptr, nullptr, st);
+        return sweep_2q_t<double, 1>((double *)psi, n, S, qa, qb, nullptr, nullptr, st);
+    }
+    if (dt == QS_C64) return sweep_2q_t<float, 2>((float *)psi, n, S, qa, qb, nullptr, nullptr, st);
+    return sweep_2q_t<double, 2>((double *)psi, n, S, qa, qb, nullptr, nullptr, st);
+}
+
+hipError_t launch_sweep_2q(void *psi, qs_dtype dt, int n, int S, int qa, int qb,
+                           const double *m32, hipStream_t st)
+{
+    TimedLaunch tl("sweep_2q", 2.0 * (double)((uint64_t)S << n) * amp_bytes(dt), st);
+    if (dt == QS_C64) return sweep_2q_t<float, 3>((float *)psi, n, S, qa, qb, nullptr, m32, st);
+    return sweep_2q_t<double, 3>((double *)psi, n, S, qa, qb, nullptr, m32, st);
+}
+
+hipError_t launch_flip(void *psi, qs_dtype dt, int n, int S, uint64_t mask, uint64_t value,
+                       hipStream_t st)
+{
+    mask &= (n >= 64) ? ~0ull : ((1ull << n) - 1);
+    int free_bits = n - __builtin_popcountll(mask);
+    uint64_t total = (uint64_t)S << free_bits;
+    TimedLaunch tl("flip", 2.0 * (double)total * amp_bytes(dt), st);
+    if (dt == QS_C64)
+        hipLaunchKernelGGL(k_flip<float>, dim3(blocks_for(total, 256)), dim3(256), 0, st,
+                           (float *)psi, n, mask, value, free_bits, total);
+    else
+        hipLaunchKernelGGL(k_flip<double>, dim3(blocks_for(total, 256)), dim3(256), 0, st,
+                           (double *)psi, n, mask, value, free_bits, total);
+    return hipGetLastError();
+}
+
+size_t reduce_partials_doubles(int n, int S)
+{
+    size_t a = ((size_t)S << red_log_blocks(n)) * 3;
+    int ld = red_log_blocks(2 * n) ;
+    size_t b = ((size_t)1 << ld) * 4;
+    return a > b ? a : b;
+}
+
+hipError_t launch_overlaps(const void *ref_psi, int ref_slot, const void *psi, qs_dtype dt, int n,
+                           int S, int64_t marked, double *partials, double *out, hipStream_t st)
+{
+    int lb = red_log_blocks(n);
+    unsigned nblk = (unsigned)((uint64_t)S << lb);
+    TimedLaunch tl("reduce", 2.0 * (double)((uint64_t)S << n) * amp_bytes(dt), st);
+    if (dt == QS_C64) {
+        const float *ref = (const float *)ref_psi + ((uint64_t)ref_slot << (n + 1));
+        hipLaunchKernelGGL(k_overlap_partial<float>, dim3(nblk), dim3(kRedThreads), 0, st, ref,
+                           (const float *)psi, n, lb, partials);
+        hipLaunchKernelGGL(k_overlap_final<float>, dim3(S), dim3(kRedThreads), 0, st,
+                           (const float *)psi, n, lb, marked, partials, out);
+    } else {
+        const double *ref = (const double *)ref_psi + ((uint64_t)ref_slot << (n + 1));
+        hipLaunchKernelGGL(k_overlap_partial<double>, dim3(nblk), dim3(kRedThreads), 0, st, ref,
+                           (const double *)psi, n, lb, partials);
+        hipLaunchKernelGGL(k_overlap_final<double>, dim3(S), dim3(kRedThreads), 0, st,
+                           (const double *)psi, n, lb, marked, partials, out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dm_expect(const void *rho, const void *psi, qs_dtype dt, int n,
+                            double *partials, double *out, hipStream_t st)
+{
+    int lb = red_log_blocks(2 * n);
+    TimedLaunch tl("reduce", (double)((uint64_t)1 << (2 * n)) * amp_bytes(dt), st);
+    if (dt == QS_C64)
+        hipLaunchKernelGGL(k_dm_expect_partial<float>, dim3(1u << lb), dim3(kRedThreads), 0, st,
+                           (const float *)rho, (const float *)psi, n, lb, partials);
+    else
+        hipLaunchKernelGGL(k_dm_expect_partial<double>, dim3(1u << lb), dim3(kRedThreads), 0, st,
+                           (const double *)rho, (const double *)psi, n, lb, partials);
+    hipLaunchKernelGGL(k_sum4_final, dim3(1), dim3(kRedThreads), 0, st, partials, 1 << lb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    uint64_t n16 = bytes / 16;
+    TimedLaunch tl("copy", 2.0 * (double)bytes, st);
+    unsigned blocks = (unsigned)std::min<uint64_t>(blocks_for(n16, 256), 256u * 64u);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, st, (float4 *)dst, (const float4 *)src, n16);
+    return hipGetLastError();
+}
+
+}  // namespace qs

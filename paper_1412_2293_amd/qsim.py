@@ -1,0 +1,391 @@
+"""ctypes binding of libqsim (include/qsim.h): argument marshalling only.
+
+Every entry point has the same name as its C function without the ``qs_`` prefix.  Device
+buffers are torch tensors on a ROCm device; streams are torch streams.  A failing call raises
+QsimError with the library's message.  If libqsim.so has not been built this module raises
+on first use: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqsim.so")
+
+C64, C128 = 0, 1
+U1, CP, SWAP, CNOT, U2, FLIP = 0, 1, 2, 3, 4, 5
+NOISE_NONE, NOISE_ROT, NOISE_PHASE = 0, 1, 2
+
+__all__ = ["QsimError", "lib", "Gate", "Noise", "Plan", "C64", "C128", "gate_array",
+           "sv_bytes_required", "StateVector", "apply_gate", "apply_kraus", "fidelity",
+           "dm_fidelity", "dm_apply_gate", "noise_draw", "traj_bytes_required", "run_trajectories",
+           "timing_enable", "timing_read", "timing_reset", "copy", "FixedRank",
+           "fr_bytes_required", "LIB_PATH"]
+
+
+class QsimError(RuntimeError):
+    pass
+
+
+class Gate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("q0", ctypes.c_int32), ("q1", ctypes.c_int32),
+                ("noise", ctypes.c_int32), ("site", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("theta", ctypes.c_double), ("mask", ctypes.c_uint64), ("value", ctypes.c_uint64),
+                ("m", ctypes.c_double * 32)]
+
+
+class Noise(ctypes.Structure):
+    _fields_ = [("e", ctypes.c_double), ("seed", ctypes.c_uint64), ("request", ctypes.c_uint32),
+                ("traj_base", ctypes.c_uint32), ("e_per_traj", ctypes.POINTER(ctypes.c_double))]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("fuse", ctypes.c_int32), ("tile_bits", ctypes.c_int32),
+                ("reg_bits", ctypes.c_int32), ("run_bits", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise QsimError(f"{LIB_PATH} is missing: build it with paper_1412_2293_amd/build.py "
+                        "(or __graft_entry__.build()); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u32, u64, dbl, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                      ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double,
+                                      ctypes.c_size_t)
+    st = ctypes.c_int
+    sigs = {
+        "qs_last_error": ([], ctypes.c_char_p),
+        "qs_version": ([], ctypes.c_char_p),
+        "qs_sv_bytes_required": ([i32, i32, i32], sz),
+        "qs_sv_create": ([i32, i32, i32, P, sz, P, ctypes.POINTER(P)], st),
+        "qs_sv_destroy": ([P], st),
+        "qs_sv_init_basis": ([P, u64], st),
+        "qs_apply_gate": ([P, ctypes.POINTER(Gate), ctypes.POINTER(Noise)], st),
+        "qs_apply_kraus": ([P, i32, P, i32, P], st),
+        "qs_fidelity": ([P, i32, P, i32, P, P], st),
+        "qs_dm_apply_gate": ([P, ctypes.POINTER(Gate), dbl], st),
+        "qs_fr_apply_noisy_gate": ([P, ctypes.POINTER(Gate), dbl, dbl, dbl, P], st),
+        "qs_dm_fidelity": ([P, P, i32, P, P], st),
+        "qs_noise_draw": ([u64, u32, u32, P, i32, u32, i32, P, P], st),
+        "qs_traj_bytes_required": ([P, i32, i32, i32, i32, ctypes.POINTER(Plan)], sz),
+        "qs_run_trajectories": ([P, i32, i32, u64, i32, ctypes.POINTER(Noise), i32, i64,
+                                 ctypes.POINTER(Plan), P, sz, P, P, P, P, P], st),
+        "qs_timing_enable": ([i32], st),
+        "qs_timing_read": ([ctypes.c_char_p, P, P, P], st),
+        "qs_timing_reset": ([], st),
+        "qs_copy": ([P, P, sz, P], st),
+        "qs_fr_bytes_required": ([i32, i32, i32], sz),
+        "qs_fr_create": ([i32, i32, i32, P, sz, P, ctypes.POINTER(P)], st),
+        "qs_fr_destroy": ([P], st),
+        "qs_fr_init_basis": ([P, u64], st),
+        "qs_fr_apply_gate": ([P, ctypes.POINTER(Gate)], st),
+        "qs_fr_apply_kraus": ([P, i32, i32, P, dbl, dbl, P], st),
+        "qs_fr_fidelity": ([P, P, i32, P, P, P], st),
+        "qs_fr_info": ([P, P, P, P], st),
+    }
+    for name, (args, res) in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        msg = lib().qs_last_error().decode(errors="replace")
+        raise QsimError(f"{what} failed ({status}): {msg}")
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    if t is None:
+        return ctypes.c_void_p(0)
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data_as(ctypes.c_void_p)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------------------------------
+def make_gate(g) -> Gate:
+    """Gate struct from any object with the fields of workloads.Gate."""
+    out = Gate()
+    out.kind, out.q0, out.q1, out.noise = int(g.kind), int(g.q0), int(g.q1), int(g.noise)
+    out.site = int(g.site)
+    out.theta = float(g.theta)
+    out.mask, out.value = int(g.mask), int(g.value)
+    if g.m is not None:
+        m = np.asarray(g.m, np.complex128).reshape(-1)
+        for k, z in enumerate(m):
+            out.m[2 * k] = z.real
+            out.m[2 * k + 1] = z.imag
+    return out
+
+
+def gate_array(gates) -> ctypes.Array:
+    gs = list(gates)
+    arr = (Gate * max(len(gs), 1))()
+    for i, g in enumerate(gs):
+        arr[i] = g if isinstance(g, Gate) else make_gate(g)
+    return arr
+
+
+def _noise(e=0.0, seed=0, request=0, traj_base=0, e_per_traj=None):
+    nz = Noise()
+    nz.e, nz.seed, nz.request, nz.traj_base = float(e), int(seed), int(request), int(traj_base)
+    keep = None
+    if e_per_traj is not None:
+        keep = np.ascontiguousarray(e_per_traj, np.float64)
+        nz.e_per_traj = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return nz, keep
+
+
+# ------------------------------------------------------------------------------------------
+def sv_bytes_required(n: int, dtype: int, n_traj: int) -> int:
+    return int(lib().qs_sv_bytes_required(n, dtype, n_traj))
+
+
+class StateVector:
+    """n_traj state vectors of n qubits in a torch uint8 device buffer."""
+
+    def __init__(self, n: int, dtype: int = C128, n_traj: int = 1, buf=None, stream=None):
+        import torch
+        self.n, self.dtype, self.n_traj = n, dtype, n_traj
+        nbytes = sv_bytes_required(n, dtype, n_traj)
+        if nbytes == 0:
+            raise QsimError("sv_bytes_required rejected the arguments")
+        self.buf = buf if buf is not None else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(lib().qs_sv_create(n, dtype, n_traj, _ptr(self.buf), self.buf.numel() * self.buf.element_size(),
+                                  _stream(stream), ctypes.byref(h)), "sv_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().qs_sv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_basis(self, index: int):
+        _check(lib().qs_sv_init_basis(self.h, int(index)), "sv_init_basis")
+
+    def amplitudes(self):
+        """The states as a complex torch tensor view [n_traj, 2^n] on the device."""
+        import torch
+        ft = torch.float32 if self.dtype == C64 else torch.float64
+        N = 1 << self.n
+        v = self.buf[: sv_bytes_required(self.n, self.dtype, self.n_traj)].view(ft)
+        return torch.view_as_complex(v.view(self.n_traj, N, 2))
+
+
+def apply_gate(s: StateVector, g, e: float = 0.0, seed: int = 0, request: int = 0, traj_base: int = 0):
+    gs = g if isinstance(g, Gate) else make_gate(g)
+    nz, _ = _noise(e, seed, request, traj_base)
+    _check(lib().qs_apply_gate(s.h, ctypes.byref(gs), ctypes.byref(nz) if e else None), "apply_gate")
+
+
+def apply_kraus(rho: StateVector, qubits: Sequence[int], ops):
+    ops = np.ascontiguousarray(np.asarray(ops, np.complex128))
+    qs = np.ascontiguousarray(qubits, np.int32)
+    _check(lib().qs_apply_kraus(rho.h, qs.size, _ptr(qs), ops.shape[0], _ptr(ops.view(np.float64))),
+           "apply_kraus")
+
+
+def dm_apply_gate(rho: StateVector, g, e: float = 0.0):
+    gs = g if isinstance(g, Gate) else make_gate(g)
+    _check(lib().qs_dm_apply_gate(rho.h, ctypes.byref(gs), float(e)), "dm_apply_gate")
+
+
+def fidelity(a: StateVector, ta: int, b: StateVector, tb: int):
+    f = ctypes.c_double()
+    ov = np.zeros(2)
+    _check(lib().qs_fidelity(a.h, ta, b.h, tb, ctypes.byref(f), _ptr(ov)), "fidelity")
+    return f.value, complex(ov[0], ov[1])
+
+
+def dm_fidelity(rho: StateVector, psi: StateVector, tpsi: int = 0):
+    f, tr = ctypes.c_double(), ctypes.c_double()
+    _check(lib().qs_dm_fidelity(rho.h, psi.h, tpsi, ctypes.byref(f), ctypes.byref(tr)), "dm_fidelity")
+    return f.value, tr.value
+
+
+def noise_draw(seed: int, sites, n_traj: int, traj_base: int = 0, request: int = 0, stream_id: int = 0,
+               stream=None):
+    """xi[t, s] drawn on the device (float64 torch tensor)."""
+    import torch
+    sites_t = torch.as_tensor(np.ascontiguousarray(sites, np.uint32).view(np.int32), device="cuda")
+    out = torch.empty((n_traj, sites_t.numel()), dtype=torch.float64, device="cuda")
+    _check(lib().qs_noise_draw(int(seed), int(request), int(stream_id), _ptr(sites_t), sites_t.numel(),
+                               int(traj_base), int(n_traj), _ptr(out), _stream(stream)), "noise_draw")
+    return out
+
+
+def _plan(plan):
+    if plan is None:
+        return None
+    if isinstance(plan, Plan):
+        return plan
+    p = Plan()
+    p.fuse = int(plan.get("fuse", -1))
+    p.tile_bits = int(plan.get("tile_bits", 0))
+    p.reg_bits = int(plan.get("reg_bits", 0))
+    p.run_bits = int(plan.get("run_bits", 0))
+    return p
+
+
+def traj_bytes_required(gates, n: int, dtype: int, n_traj: int, plan=None) -> int:
+    ga = gates if isinstance(gates, ctypes.Array) else gate_array(gates)
+    p = _plan(plan)
+    return int(lib().qs_traj_bytes_required(ga, len(ga), n, dtype, n_traj,
+                                            ctypes.byref(p) if p is not None else None))
+
+
+def run_trajectories(gates, n: int, init_index: int, dtype: int, n_traj: int, e=0.0, seed: int = 0,
+                     request: int = 0, traj_base: int = 0, marked: int = -1, plan=None, buf=None,
+                     stream=None, n_gates: Optional[int] = None):
+    """Run the ideal circuit and n_traj noisy trajectories; returns a dict with numpy arrays
+    F, p (if marked >= 0), norm, layout and the device buffer holding the final states."""
+    import torch
+    ga = gates if isinstance(gates, ctypes.Array) else gate_array(gates)
+    G = len(ga) if n_gates is None else n_gates
+    p = _plan(plan)
+    e_arr = np.asarray(e, np.float64)
+    per = None if e_arr.ndim == 0 else e_arr
+    nz, keep = _noise(float(e_arr) if per is None else 0.0, seed, request, traj_base, per)
+    need = int(lib().qs_traj_bytes_required(ga, G, n, dtype, n_traj, ctypes.byref(p) if p else None))
+    if need == 0:
+        raise QsimError("traj_bytes_required rejected the arguments: " + lib().qs_last_error().decode())
+    if buf is None:
+        buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+    F = np.zeros(n_traj)
+    P = np.zeros(n_traj)
+    norms = np.zeros(n_traj)
+    layout = np.zeros(n, np.int32)
+    _check(lib().qs_run_trajectories(ga, G, n, int(init_index), dtype, ctypes.byref(nz), n_traj,
+                                     int(marked), ctypes.byref(p) if p else None, _ptr(buf),
+                                     buf.numel() * buf.element_size(), _stream(stream), _ptr(F),
+                                     _ptr(P) if marked >= 0 else None, _ptr(norms), _ptr(layout)),
+           "run_trajectories")
+    del keep
+    return {"F": F, "p": P if marked >= 0 else None, "norm": norms, "layout": layout, "buf": buf}
+
+
+def trajectory_states(res, n: int, dtype: int, n_traj: int):
+    """Final states (slot 0 = ideal) as a complex torch tensor view [n_traj + 1, 2^n] in the
+    physical qubit order res['layout']."""
+    import torch
+    ft = torch.float32 if dtype == C64 else torch.float64
+    N = 1 << n
+    nbytes = (n_traj + 1) * N * (8 if dtype == C64 else 16)
+    return torch.view_as_complex(res["buf"][:nbytes].view(ft).view(n_traj + 1, N, 2))
+
+
+def timing_enable(on: bool = True):
+    _check(lib().qs_timing_enable(1 if on else 0), "timing_enable")
+
+
+def timing_reset():
+    _check(lib().qs_timing_reset(), "timing_reset")
+
+
+def timing_read(name: str):
+    n, ms, b = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().qs_timing_read(name.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b)),
+           "timing_read")
+    return {"launches": n.value, "ms": ms.value, "alg_bytes": b.value}
+
+
+def copy(dst, src, nbytes: int, stream=None):
+    _check(lib().qs_copy(_ptr(dst), _ptr(src), int(nbytes), _stream(stream)), "copy")
+
+
+def fr_bytes_required(n: int, r: int, dtype: int) -> int:
+    return int(lib().qs_fr_bytes_required(n, r, dtype))
+
+
+class FixedRank:
+    """Fixed-rank density matrix: rho = exp(log_trace) sum_j |v_j><v_j|, at most r columns."""
+
+    def __init__(self, n: int, r: int, dtype: int = C128, buf=None, stream=None):
+        import torch
+        self.n, self.r, self.dtype = n, r, dtype
+        nbytes = fr_bytes_required(n, r, dtype)
+        if nbytes == 0:
+            raise QsimError("fr_bytes_required rejected the arguments")
+        self.buf = buf if buf is not None else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        h = ctypes.c_void_p()
+        _check(lib().qs_fr_create(n, r, dtype, _ptr(self.buf), self.buf.numel(), _stream(stream),
+                                  ctypes.byref(h)), "fr_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().qs_fr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_basis(self, index: int):
+        _check(lib().qs_fr_init_basis(self.h, int(index)), "fr_init_basis")
+
+    def apply_gate(self, g):
+        gs = g if isinstance(g, Gate) else make_gate(g)
+        _check(lib().qs_fr_apply_gate(self.h, ctypes.byref(gs)), "fr_apply_gate")
+
+    def apply_kraus(self, q: int, ops, tau: float = 1e-9, zero_tol: float = 1e-13) -> int:
+        ops = np.ascontiguousarray(np.asarray(ops, np.complex128))
+        rank = ctypes.c_int()
+        _check(lib().qs_fr_apply_kraus(self.h, int(q), ops.shape[0], _ptr(ops.view(np.float64)),
+                                       float(tau), float(zero_tol), ctypes.byref(rank)), "fr_apply_kraus")
+        return rank.value
+
+    def apply_noisy_gate(self, g, e: float, tau: float = 1e-9, zero_tol: float = 1e-13) -> int:
+        gs = g if isinstance(g, Gate) else make_gate(g)
+        rank = ctypes.c_int()
+        _check(lib().qs_fr_apply_noisy_gate(self.h, ctypes.byref(gs), float(e), float(tau), float(zero_tol),
+                                            ctypes.byref(rank)), "fr_apply_noisy_gate")
+        return rank.value
+
+    def fidelity(self, psi: StateVector, tpsi: int = 0):
+        fu, fn, lt = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().qs_fr_fidelity(self.h, psi.h, tpsi, ctypes.byref(fu), ctypes.byref(fn), ctypes.byref(lt)),
+               "fr_fidelity")
+        return fu.value, fn.value, lt.value
+
+    def info(self):
+        rank, lt, ptr = ctypes.c_int(), ctypes.c_double(), ctypes.c_void_p()
+        _check(lib().qs_fr_info(self.h, ctypes.byref(rank), ctypes.byref(lt), ctypes.byref(ptr)), "fr_info")
+        return rank.value, lt.value
+
+    def columns(self):
+        import torch
+        ft = torch.float32 if self.dtype == C64 else torch.float64
+        N = 1 << self.n
+        return torch.view_as_complex(self.buf[: fr_bytes_required(self.n, self.r, self.dtype)]
+                                     .view(ft).view(self.r, N, 2))

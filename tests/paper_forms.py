@@ -41,8 +41,8 @@ def qft_ideal(n, x):
     return np.fft.fft(ex) / math.sqrt(N)
 
 
-def qft_noisy_closed_form(circuit, xi_by_site, e):
-    """(F, psi) of one noisy QFT trajectory; xi_by_site maps gate site -> xi."""
+def qft_noisy_qubits(circuit, xi_by_site, e):
+    """(F, per-qubit final states) of one noisy QFT trajectory; xi_by_site: site -> xi."""
     n, x = circuit.n, circuit.init_index
     h_site, cp_site = {}, {}
     for g in circuit.gates:
@@ -64,13 +64,31 @@ def qft_noisy_closed_form(circuit, xi_by_site, e):
                 Phi += 2 * math.pi / (1 << (t - c + 1)) + dx
                 phi += dx
         F *= 0.5 * (1.0 + math.cos(2 * a) * math.cos(phi))
-        st = np.diag([1.0, np.exp(-1j * Phi)]) @ H @ V[:, xt]
-        qubit_states[t] = st
+        qubit_states[t] = np.diag([1.0, np.exp(-1j * Phi)]) @ H @ V[:, xt]
+    return F, qubit_states
+
+
+def qft_noisy_closed_form(circuit, xi_by_site, e):
+    """(F, psi) of one noisy QFT trajectory (full state; small n only)."""
+    n = circuit.n
+    F, qs_ = qft_noisy_qubits(circuit, xi_by_site, e)
     # the final SWAP layer puts qubit t at output bit n-1-t; kron: most significant first
     psi = np.array([1.0 + 0j])
     for b in range(n - 1, -1, -1):
-        psi = np.kron(psi, qubit_states[n - 1 - b])
+        psi = np.kron(psi, qs_[n - 1 - b])
     return F, psi
+
+
+def qft_noisy_amplitudes(circuit, xi_by_site, e, indices):
+    """(F, amplitudes at the given output indices) of one noisy QFT trajectory."""
+    n = circuit.n
+    F, qs_ = qft_noisy_qubits(circuit, xi_by_site, e)
+    idx = np.asarray(indices, np.int64)
+    amp = np.ones(idx.size, np.complex128)
+    for b in range(n):
+        st = qs_[n - 1 - b]
+        amp *= np.where((idx >> b) & 1, st[1], st[0])
+    return F, amp
 
 
 def qft_expected_fidelity(n, x, e):

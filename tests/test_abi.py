@@ -1,0 +1,107 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function include/qsim.h
+declares, and rejects invalid arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1412_2293_amd as q
+from workloads import grover, qft
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "qsim.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(qs_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 20
+    L = q.lib()
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+def test_struct_sizes_match_header_layout():
+    # qs_gate: 4 int32 + 2 uint32 + double + 2 uint64 + 32 doubles
+    assert ctypes.sizeof(q.Gate) == 16 + 8 + 8 + 16 + 256
+    assert ctypes.sizeof(q.Noise) == 8 + 8 + 4 + 4 + 8
+    assert ctypes.sizeof(q.Plan) == 16
+
+
+def test_bytes_required_rejects_bad_sizes():
+    assert q.sv_bytes_required(0, q.C128, 1) == 0
+    assert q.sv_bytes_required(35, q.C128, 1) == 0
+    assert q.sv_bytes_required(10, 7, 1) == 0
+    assert q.sv_bytes_required(10, q.C64, 0) == 0
+    assert q.sv_bytes_required(10, q.C64, 3) == 3 * 1024 * 8
+    assert q.fr_bytes_required(10, 9, q.C64) == 0
+    assert q.fr_bytes_required(10, 8, q.C128) == 8 * 1024 * 16
+
+
+def _run(gates, n, **kw):
+    L = q.lib()
+    ga = q.gate_array(gates)
+    F = np.zeros(4)
+    args = dict(init=0, dtype=q.C128, nz=None, T=4, marked=-1, plan=None, buf=None, nbytes=0)
+    args.update(kw)
+    return L.qs_run_trajectories(ga, len(gates), n, args["init"], args["dtype"], args["nz"], args["T"],
+                                 args["marked"], args["plan"], args["buf"], args["nbytes"], None,
+                                 F.ctypes.data_as(ctypes.c_void_p), None, None, None)
+
+
+def test_run_trajectories_validates_before_any_device_work():
+    c = grover(4, seed=0)
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced: validation fails first
+    assert _run(c.gates, 4, buf=None) == -1                      # NULL buffer
+    assert _run(c.gates, 4, buf=fake, nbytes=16) == -1           # too small
+    assert b"too small" in q.lib().qs_last_error()
+    assert _run(c.gates, 0, buf=fake, nbytes=1 << 30) == -1      # n out of range
+    assert _run(c.gates, 4, buf=fake, nbytes=1 << 30, init=16) == -1
+    assert _run(c.gates, 4, buf=fake, nbytes=1 << 30, T=0) == -1
+    bad = grover(4, seed=0)
+    bad.gates[3].q0 = 9
+    assert _run(bad.gates, 4, buf=fake, nbytes=1 << 30) == -1
+    assert b"gate 3" in q.lib().qs_last_error()
+    bad = qft(4, seed=0)
+    bad.gates[1].q1 = bad.gates[1].q0
+    assert _run(bad.gates, 4, buf=fake, nbytes=1 << 30) == -1
+    for bad_plan in (q.Plan(fuse=1, tile_bits=16, reg_bits=4, run_bits=0),
+                     q.Plan(fuse=1, tile_bits=12, reg_bits=5, run_bits=0),
+                     q.Plan(fuse=2, tile_bits=0, reg_bits=0, run_bits=0)):
+        assert _run(c.gates, 4, buf=fake, nbytes=1 << 30, plan=ctypes.byref(bad_plan)) == -1
+    assert _run(c.gates, 4, buf=ctypes.c_void_p((1 << 20) + 8), nbytes=1 << 30) == -1   # misaligned
+
+
+def test_traj_bytes_required_covers_states_and_program():
+    c = qft(12, seed=0)
+    for dt, s in ((q.C64, 8), (q.C128, 16)):
+        for fuse in (0, 1):
+            need = q.traj_bytes_required(c.gates, 12, dt, 5, plan={"fuse": fuse})
+            assert need >= 6 * (1 << 12) * s
+
+
+def test_handles_reject_bad_arguments():
+    L = q.lib()
+    h = ctypes.c_void_p()
+    assert L.qs_sv_create(10, q.C128, 1, None, 1 << 20, None, ctypes.byref(h)) == -1
+    assert L.qs_sv_create(10, q.C128, 1, ctypes.c_void_p(1 << 20), 16, None, ctypes.byref(h)) == -1
+    assert L.qs_fr_create(10, 0, q.C128, ctypes.c_void_p(1 << 20), 1 << 30, None, ctypes.byref(h)) == -1
+    assert L.qs_copy(None, None, 16, None) == -1
+    assert L.qs_apply_gate(None, None, None) == -1
+    assert q.lib().qs_last_error() != b""
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    import importlib
+    import paper_1412_2293_amd.qsim as qm
+    monkeypatch.setattr(qm, "_lib", None)
+    monkeypatch.setattr(qm, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(qm.QsimError):
+        qm.lib()

@@ -1,0 +1,309 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle (and, at full size, the
+closed forms the oracle is pinned to).
+
+Tolerances: complex<double> states within 1e-12 relative (2-norm of the difference over the
+norm) and fidelities within 1e-12 relative; complex<float> amplitudes (with FP64 reductions)
+within |dF| <= 1e-5 absolute, the bound stated for the single-precision path.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import fixed_rank
+from workloads import (CP, FLIP, NOISE_PHASE, NOISE_ROT, U1, Circuit, Gate, grover, qft,
+                       random_layers, random_mixed_circuit)
+
+from paper_forms import eq10, grover_p_ideal, qft_noisy_amplitudes
+
+torch = pytest.importorskip("torch")
+import paper_1412_2293_amd as q  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = {q.C128: 1e-12, q.C64: 1e-5}
+NAMES = {q.C128: "c128", q.C64: "c64"}
+
+
+def rel_err(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def unpermute(state: np.ndarray, layout, n):
+    """Logical-order amplitudes from a state stored with logical qubit q at bit layout[q]."""
+    idx = np.arange(1 << n, dtype=np.int64)
+    phys = np.zeros_like(idx)
+    for qb in range(n):
+        phys |= ((idx >> qb) & 1) << int(layout[qb])
+    return state[phys]
+
+
+def to_device_states(sv: "q.StateVector", states: np.ndarray):
+    amps = sv.amplitudes()
+    t = torch.as_tensor(states.astype(np.complex64 if sv.dtype == q.C64 else np.complex128))
+    amps.copy_(t.to(amps.device))
+    torch.cuda.synchronize()
+
+
+def from_device(sv):
+    torch.cuda.synchronize()
+    return sv.amplitudes().cpu().numpy().astype(np.complex128)
+
+
+# ----------------------------------------------------------------------------------------
+def test_noise_draws_bit_exact():
+    sites = np.arange(0, 1500, dtype=np.uint32) * 7 + 3
+    for seed, request, tb, T in [(0, 0, 0, 64), ((1 << 40) + 5, 7, 1000, 32), (0xFFFFFFFFFFFFFFFF, 3, 2**31, 8)]:
+        got = q.noise_draw(seed, sites, T, traj_base=tb, request=request).cpu().numpy()
+        ref = oracle.normals(seed, sites, np.arange(tb, tb + T, dtype=np.uint64).astype(np.uint32), request=request)
+        assert got.shape == ref.shape
+        mism = np.count_nonzero(got.view(np.uint64) != ref.view(np.uint64))
+        assert mism == 0, f"{mism} of {got.size} deviates differ (max |d| {np.max(np.abs(got - ref)):.3e})"
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 9, 13])
+def test_apply_gate_every_kind_and_position(dtype, n):
+    rng = np.random.default_rng(100 + n)
+    T = 3
+    circ = random_mixed_circuit(n, 40 if n > 1 else 10, seed=200 + n)
+    # make sure both end qubits are hit by dense one-qubit gates
+    from workloads import haar_2x2
+    circ.gates += [Gate(U1, q0=0, m=haar_2x2(rng), noise=NOISE_ROT), Gate(U1, q0=n - 1, m=haar_2x2(rng), noise=NOISE_ROT)]
+    for i, g in enumerate(circ.gates):
+        g.site = i
+    psi0 = rng.standard_normal((T, 1 << n)) + 1j * rng.standard_normal((T, 1 << n))
+    psi0 /= np.linalg.norm(psi0, axis=1, keepdims=True)
+    sv = q.StateVector(n, dtype, T)
+    to_device_states(sv, psi0)
+    e, seed, request, tb = 0.2, 77, 5, 11
+    ref = psi0.copy()
+    for g in circ.gates:
+        q.apply_gate(sv, g, e=e, seed=seed, request=request, traj_base=tb)
+        one = Circuit(n, [g])
+        for t in range(T):
+            ref[t] = oracle.sv_apply(one, ref[t], e=e, seed=seed, traj=tb + t, request=request)
+    got = from_device(sv)
+    for t in range(T):
+        err = rel_err(got[t], ref[t])
+        assert err <= (1e-12 if dtype == q.C128 else 2e-5), (NAMES[dtype], n, t, err)
+    sv.close()
+
+
+@pytest.mark.parametrize("fuse", [0, 1])
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+def test_grover_n10_200_trajectories(dtype, fuse):
+    """Plain-method workload: Grover n = 10, 200 trajectories, e = 0.01, seed 0."""
+    c = grover(10, seed=0)
+    T, e, seed = 200, 0.01, 0
+    res = q.run_trajectories(c.gates, c.n, c.init_index, dtype, T, e=e, seed=seed, marked=c.marked,
+                             plan={"fuse": fuse})
+    F_ref, p_ref = oracle.run_trajectories(c, e, seed, range(T))
+    if dtype == q.C128:
+        assert np.max(np.abs(res["F"] - F_ref) / F_ref) <= 1e-12
+        assert np.max(np.abs(res["p"] - p_ref) / p_ref) <= 1e-12
+    else:
+        assert np.max(np.abs(res["F"] - F_ref)) <= 1e-5
+        assert np.max(np.abs(res["p"] - p_ref)) <= 1e-5
+    assert np.all(np.abs(res["norm"] - 1.0) <= TOL[dtype] * 10)
+
+
+PLANS = [
+    {"fuse": 0},
+    {"fuse": 1},
+    {"fuse": 1, "tile_bits": 8, "reg_bits": 2, "run_bits": 2},
+    {"fuse": 1, "tile_bits": 9, "reg_bits": 3, "run_bits": 3},
+    {"fuse": 1, "tile_bits": 7, "reg_bits": 4, "run_bits": 1},
+    {"fuse": 1, "tile_bits": 6, "reg_bits": 2, "run_bits": 2},
+]
+
+
+@pytest.mark.parametrize("plan", PLANS, ids=lambda p: "-".join(f"{k}{v}" for k, v in p.items()))
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+@pytest.mark.parametrize("n", [11, 14])
+def test_mixed_circuits_every_plan(n, dtype, plan):
+    c = random_mixed_circuit(n, 90, seed=300 + n)
+    T, e, seed = 3, 0.15, 9
+    res = q.run_trajectories(c.gates, n, c.init_index, dtype, T, e=e, seed=seed, plan=plan, traj_base=4)
+    F_ref, _, ideal, states = oracle.run_trajectories(c, e, seed, range(4, 4 + T), keep_states=True)
+    st = q.trajectory_states(res, n, dtype, T).cpu().numpy().astype(np.complex128)
+    tol = 1e-12 if dtype == q.C128 else 3e-5
+    assert rel_err(unpermute(st[0], res["layout"], n), ideal) <= tol
+    for t in range(T):
+        assert rel_err(unpermute(st[t + 1], res["layout"], n), states[t]) <= tol
+    assert np.max(np.abs(res["F"] - F_ref)) <= (1e-12 if dtype == q.C128 else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+@pytest.mark.parametrize("n,plan", [(14, {"fuse": 1}), (15, {"fuse": 1}), (13, {"fuse": 0}),
+                                    (12, {"fuse": 1, "tile_bits": 10, "reg_bits": 4}),
+                                    (12, {"fuse": 1, "tile_bits": 6, "reg_bits": 1, "run_bits": 2})])
+def test_qft_states_and_fidelities(n, plan, dtype):
+    c = qft(n, seed=n)
+    T, e, seed = 3, 0.05, 21
+    res = q.run_trajectories(c.gates, n, c.init_index, dtype, T, e=e, seed=seed, plan=plan)
+    F_ref, _, ideal, states = oracle.run_trajectories(c, e, seed, range(T), keep_states=True)
+    st = q.trajectory_states(res, n, dtype, T).cpu().numpy().astype(np.complex128)
+    tol = 1e-12 if dtype == q.C128 else 3e-5
+    assert rel_err(unpermute(st[0], res["layout"], n), ideal) <= tol
+    for t in range(T):
+        assert rel_err(unpermute(st[t + 1], res["layout"], n), states[t]) <= tol
+    assert np.max(np.abs(res["F"] - F_ref)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+def test_random_layers_against_oracle(dtype):
+    c = random_layers(12, 6, seed=5, pairing="random")
+    T = 4
+    for plan in ({"fuse": 0}, {"fuse": 1}):
+        res = q.run_trajectories(c.gates, 12, 0, dtype, T, e=0.05, seed=3, plan=plan)
+        F_ref, _ = oracle.run_trajectories(c, 0.05, 3, range(T))
+        assert np.max(np.abs(res["F"] - F_ref)) <= TOL[dtype]
+
+
+def test_per_trajectory_noise_strength():
+    c = qft(10, seed=1)
+    es = np.array([0.0, 0.001, 0.01, 0.1, 0.3])
+    res = q.run_trajectories(c.gates, 10, c.init_index, q.C128, len(es), e=es, seed=2)
+    for t, e in enumerate(es):
+        F_ref, _ = oracle.run_trajectories(c, float(e), 2, [t])
+        assert abs(res["F"][t] - F_ref[0]) <= 1e-12
+    assert abs(res["F"][0] - 1.0) <= 1e-13
+
+
+# ----------------------------------------------------------------------------------------
+# Full-size QFT (n = 26, 64 trajectories per e in one launch): the per-trajectory product
+# closed form, evaluated with the oracle's noise draws, pins every fidelity and sampled
+# amplitudes.
+@pytest.mark.parametrize("dtype", [q.C64, q.C128])
+def test_qft26_full_size_against_closed_form(dtype):
+    n = 26
+    c = qft(n, seed=1)
+    T = 128 if dtype == q.C64 else 16
+    es = np.array([0.001] * (T // 2) + [0.01] * (T // 2))
+    seed = 1
+    print(f"qft26 {NAMES[dtype]} T={T}", flush=True)
+    res = q.run_trajectories(c.gates, n, c.init_index, dtype, T, e=es, seed=seed, plan={"fuse": 1})
+    sites = [g.site for g in c.gates]
+    xi = oracle.normals(seed, sites, np.arange(T, dtype=np.uint32))
+    st = q.trajectory_states(res, n, dtype, T)
+    rng = np.random.default_rng(0)
+    sample = rng.integers(0, 1 << n, size=64)
+    phys = np.zeros_like(sample)
+    for qb in range(n):
+        phys |= ((sample >> qb) & 1) << int(res["layout"][qb])
+    phys_t = torch.as_tensor(phys, device=st.device)
+    for t in range(T):
+        F_cf, amp_cf = qft_noisy_amplitudes(c, dict(zip(sites, xi[t])), float(es[t]), sample)
+        if dtype == q.C128:
+            assert abs(res["F"][t] - F_cf) <= 1e-12 * F_cf, (t, res["F"][t], F_cf)
+        else:
+            assert abs(res["F"][t] - F_cf) <= 1e-5, (t, res["F"][t], F_cf)
+        if t % 16 == 0:
+            amps = st[t + 1].index_select(0, phys_t).cpu().numpy().astype(np.complex128)
+            ref = amp_cf
+            assert np.max(np.abs(amps - ref)) <= (1e-14 if dtype == q.C128 else 2e-8) , t
+    assert np.all(np.abs(res["norm"] - 1.0) <= (1e-12 if dtype == q.C128 else 1e-4))
+    del res, st
+    torch.cuda.empty_cache()
+
+
+# ----------------------------------------------------------------------------------------
+# Density matrices and the fixed-rank form.
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+def test_dm_grover_against_oracle(dtype):
+    n, e = 6, 0.08
+    c = grover(n, seed=4)
+    rho = q.StateVector(2 * n, dtype, 1)
+    rho.init_basis(0)
+    for g in c.gates:
+        q.dm_apply_gate(rho, g, e)
+    ideal_sv = q.StateVector(n, dtype, 1)
+    to_device_states(ideal_sv, oracle.sv_run(c, 0.0)[None, :])
+    f, tr = q.dm_fidelity(rho, ideal_sv, 0)
+    rho_ref = oracle.dm_run(c, e)
+    f_ref, tr_ref = oracle.dm_expect(rho_ref, oracle.sv_run(c, 0.0))
+    got = from_device(rho)[0].reshape(1 << n, 1 << n)
+    tol = 1e-12 if dtype == q.C128 else 2e-5
+    assert rel_err(got, rho_ref) <= tol
+    assert abs(f - f_ref.real) <= tol * 10
+    assert abs(tr - 1.0) <= tol * 10
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+def test_apply_kraus_random_sets(dtype):
+    n = 7
+    rng = np.random.default_rng(8)
+    N = 1 << n
+    A = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    rho0 = A @ A.conj().T
+    rho0 /= np.trace(rho0)
+    sv = q.StateVector(2 * n, dtype, 1)
+    to_device_states(sv, rho0.reshape(1, -1))
+    ref = rho0
+    for qb in [0, 3, n - 1]:
+        ops = (rng.standard_normal((3, 2, 2)) + 1j * rng.standard_normal((3, 2, 2))) / 2
+        q.apply_kraus(sv, [qb], ops)
+        ref = oracle.dm_apply_kraus(ref, n, [qb], ops)
+    got = from_device(sv)[0].reshape(N, N)
+    assert rel_err(got, ref) <= (1e-12 if dtype == q.C128 else 2e-5)
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+@pytest.mark.parametrize("n", [10, 13])
+def test_fixed_rank_r1_grover_is_eq10(n, dtype):
+    e = 0.02
+    c = grover(n, seed=2)
+    fr = q.FixedRank(n, 1, dtype)
+    fr.init_basis(0)
+    for g in c.gates:
+        fr.apply_noisy_gate(g, e, tau=1e-9 if dtype == q.C128 else 1e-5,
+                            zero_tol=1e-13 if dtype == q.C128 else 1e-6)
+    w = q.StateVector(n, dtype, 1)
+    w.init_basis(c.marked)
+    pu, pn, lt = fr.fidelity(w)
+    j = c.meta["iterations"]
+    ref = eq10(n, j, e)
+    tol = 1e-12 if dtype == q.C128 else 1e-5
+    assert abs(pu - ref) <= tol * ref, (pu, ref)
+    assert abs(pn - grover_p_ideal(n, j)) <= tol
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+def test_fixed_rank_r8_against_oracle(dtype):
+    n, e, r = 8, 0.05, 8
+    c = grover(n, seed=6, iterations=4)
+    tau = 1e-9
+    zt = 1e-13 if dtype == q.C128 else 1e-6
+    fr = q.FixedRank(n, r, dtype)
+    fr.init_basis(0)
+    ranks = []
+    for g in c.gates:
+        ranks.append(fr.apply_noisy_gate(g, e, tau=tau, zero_tol=zt))
+    ref = fixed_rank.run_circuit(c, e, r, tau=tau, zero_tol=1e-13)
+    ideal = oracle.sv_run(c, 0.0)
+    psi = q.StateVector(n, dtype, 1)
+    to_device_states(psi, ideal[None, :])
+    fu, fn, lt = fr.fidelity(psi)
+    fu_ref, fn_ref, lt_ref = ref.fidelity(ideal)
+    if dtype == q.C128:
+        assert ranks[-1] == len(ref.V)
+        assert abs(fu - fu_ref) <= 1e-11 and abs(fn - fn_ref) <= 1e-11 and abs(lt - lt_ref) <= 1e-11
+        rank, _ = fr.info()
+        V = fr.columns()[:rank].cpu().numpy().T
+        np.testing.assert_allclose(np.exp(lt) * V @ V.conj().T, ref.rho(), atol=1e-12)
+    else:
+        assert abs(fu - fu_ref) <= 1e-5 and abs(fn - fn_ref) <= 1e-5
+
+
+# ----------------------------------------------------------------------------------------
+def test_timing_records_kernels():
+    c = qft(12, seed=0)
+    q.timing_reset()
+    q.timing_enable(True)
+    q.run_trajectories(c.gates, 12, c.init_index, q.C64, 4, e=0.01, seed=0, plan={"fuse": 1})
+    q.timing_enable(False)
+    t = q.timing_read("fused")
+    assert t["launches"] >= 1 and t["ms"] > 0 and t["alg_bytes"] > 0
+    q.timing_reset()
