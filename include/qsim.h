@@ -189,6 +189,21 @@ qs_status qs_run_trajectories(const qs_gate *gates, int n_gates, int n_qubits,
                               size_t buf_bytes, void *hip_stream, double *fid_out,
                               double *p_out, double *norm_out, int32_t *layout_out);
 
+/* Byte offsets, inside the qs_run_trajectories buffer, of its regions (for inspection):
+ * out[0] states, [1] noise table (per gate and slot: 8 doubles), [2] device gates, [3] per-slot
+ * noise strengths, [4] pass, [5] stage, [6] round, [7] op, [8] phase-reference, [9] outer-job,
+ * [10] outer-bit descriptors, [11] per-slot records of the last pass, [12] reduction
+ * partials, [13] results, [14] total.  No device work. */
+qs_status qs_traj_layout(const qs_gate *gates, int n_gates, int n_qubits, qs_dtype dt, int n_traj,
+                         const qs_plan *plan, size_t *out);
+
+/* The fused-pass program the library builds for this circuit and plan, as JSON text (passes,
+ * tile qubits, stages, register rounds, ops with their folded phases, final qubit layout), for
+ * inspection and host-side checks.  Writes at most cap bytes including the terminating NUL and
+ * returns the full length (excluding NUL) in *len.  No device work. */
+qs_status qs_plan_describe(const qs_gate *gates, int n_gates, int n_qubits, qs_dtype dt,
+                           const qs_plan *plan, char *buf, size_t cap, size_t *len);
+
 /* Per-kernel timing of the calling thread's launches, measured with HIP events on the stream
  * each kernel is launched on.  While enabled, every launch is bracketed by two events;
  * qs_timing_read synchronises and returns, for kernel class `name` ("sweep_u1", "sweep_cp",

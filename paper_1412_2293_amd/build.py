@@ -26,7 +26,10 @@ def common_flags():
             "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
             # packed FP32 instructions stay off: hand-written code never uses them and the
             # compiler must not form them either
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # keep the per-qubit register-update branches apart: sinking their common code
+            # merges them behind pointer phis, which forces the register tile into scratch
+            "-mllvm", "-simplifycfg-sink-common=false"]
 
 
 def build(verbose: bool = False) -> str:

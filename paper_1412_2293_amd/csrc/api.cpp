@@ -476,7 +476,7 @@ qs_status qs_timing_reset(void)
 namespace {
 
 struct TrajLayout {
-    size_t states, tab, gates, edev, passes, rounds, ops, prefs, partials, out, total;
+    size_t states, tab, gates, edev, passes, stages, rounds, ops, prefs, jobs, obits, rec, partials, out, total;
 };
 
 struct Plan {
@@ -493,9 +493,8 @@ qs_status resolve_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, in
     if (fuse == -1) fuse = 1;
     out.fused = fuse == 1;
     if (!out.fused) return QS_OK;
-    int maxK = dt == QS_C64 ? 13 : 12;
-    int K = (p && p->tile_bits > 0) ? p->tile_bits : maxK;
-    int RB = (p && p->reg_bits > 0) ? p->reg_bits : 4;
+    int K = (p && p->tile_bits > 0) ? p->tile_bits : 12;
+    int RB = (p && p->reg_bits > 0) ? p->reg_bits : 3;
     int run = (p && p->run_bits > 0) ? p->run_bits : (dt == QS_C64 ? 4 : 3);
     if (K > kMaxTileBits) return fail(QS_EINVAL, "plan: tile_bits too large");
     if ((size_t(1) << std::min(K, n)) * amp_bytes(dt) > 160 * 1024)
@@ -509,7 +508,9 @@ qs_status resolve_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, in
     out.RB = RB;
     out.run_bits = run;
     (void)T;
-    return plan_fused(gates, n_gates, n, K, RB, run, out.prog);
+    int rec_cap = stage_rec_cap(dt, K);
+    if (rec_cap < 256) return fail(QS_EINVAL, "plan: tile leaves too little LDS for the gate records");
+    return plan_fused(gates, n_gates, n, K, RB, run, rec_cap, out.prog);
 }
 
 TrajLayout traj_layout(int n, qs_dtype dt, int T, int n_gates, const Plan &pl)
@@ -527,9 +528,13 @@ TrajLayout traj_layout(int n, qs_dtype dt, int T, int n_gates, const Plan &pl)
     L.gates = take((size_t)std::max(n_gates, 1) * sizeof(qs_gate));
     L.edev = take((size_t)S * sizeof(double));
     L.passes = take(std::max<size_t>(pl.prog.passes.size(), 1) * sizeof(PassDesc));
+    L.stages = take(std::max<size_t>(pl.prog.stages.size(), 1) * sizeof(StageDesc));
     L.rounds = take(std::max<size_t>(pl.prog.rounds.size(), 1) * sizeof(RoundDesc));
     L.ops = take(std::max<size_t>(pl.prog.ops.size(), 1) * sizeof(OpDesc));
-    L.prefs = take(std::max<size_t>(pl.prog.prefs.size(), 1) * sizeof(PhaseRef));
+    L.prefs = take(std::max<size_t>(pl.prog.prefs.size(), 1) * sizeof(PrepRef));
+    L.jobs = take(std::max<size_t>(pl.prog.jobs.size(), 1) * sizeof(OuterJob));
+    L.obits = take(std::max<size_t>(pl.prog.obits.size(), 1) * sizeof(int32_t));
+    L.rec = take((size_t)std::max(pl.prog.max_rec, 1) * S * 2 * (dt == QS_C64 ? 4 : 8));
     L.partials = take(reduce_partials_doubles(n, S) * sizeof(double));
     L.out = take((size_t)S * 5 * sizeof(double));
     L.total = off;
@@ -559,6 +564,113 @@ size_t qs_traj_bytes_required(const qs_gate *gates, int n_gates, int n, qs_dtype
     Plan pl;
     if (resolve_plan(gates, n_gates, n, dt, T, plan, pl) != QS_OK) return 0;
     return traj_layout(n, dt, T, n_gates, pl).total;
+}
+
+qs_status qs_traj_layout(const qs_gate *gates, int n_gates, int n, qs_dtype dt, int T, const qs_plan *plan,
+                         size_t *out)
+{
+    clear_error();
+    if (!out) return fail(QS_EINVAL, "traj_layout: out is NULL");
+    if (n < 1 || n > 34 || T < 1 || (dt != QS_C64 && dt != QS_C128))
+        return fail(QS_EINVAL, "traj_layout: bad size or dtype");
+    qs_status v = check_circuit(gates, n_gates, n);
+    if (v != QS_OK) return v;
+    Plan pl;
+    if ((v = resolve_plan(gates, n_gates, n, dt, T, plan, pl)) != QS_OK) return v;
+    TrajLayout L = traj_layout(n, dt, T, n_gates, pl);
+    size_t vals[15] = {L.states, L.tab, L.gates, L.edev, L.passes, L.stages, L.rounds, L.ops, L.prefs,
+                       L.jobs, L.obits, L.rec, L.partials, L.out, L.total};
+    for (int i = 0; i < 15; ++i) out[i] = vals[i];
+    return QS_OK;
+}
+
+qs_status qs_plan_describe(const qs_gate *gates, int n_gates, int n, qs_dtype dt, const qs_plan *plan,
+                           char *buf, size_t cap, size_t *len)
+{
+    clear_error();
+    if (n < 1 || n > 34) return fail(QS_EINVAL, "plan_describe: n_qubits must be in 1..34");
+    if (dt != QS_C64 && dt != QS_C128) return fail(QS_EINVAL, "plan_describe: unknown dtype");
+    qs_status v = check_circuit(gates, n_gates, n);
+    if (v != QS_OK) return v;
+    Plan pl;
+    if ((v = resolve_plan(gates, n_gates, n, dt, 1, plan, pl)) != QS_OK) return v;
+    std::string o;
+    auto I = [&](const char *k, long long x) { o += "\""; o += k; o += "\":" + std::to_string(x) + ","; };
+    o += "{";
+    I("fused", pl.fused ? 1 : 0);
+    I("K", pl.prog.K);
+    I("RB", pl.prog.RB);
+    o += "\"layout\":[";
+    for (size_t q = 0; q < pl.prog.layout.size(); ++q) o += (q ? "," : "") + std::to_string(pl.prog.layout[q]);
+    o += "],\"passes\":[";
+    const Program &P = pl.prog;
+    for (size_t pi = 0; pi < P.passes.size(); ++pi) {
+        const PassDesc &pd = P.passes[pi];
+        o += pi ? ",{" : "{";
+        o += "\"q_pos\":[";
+        for (int j = 0; j < pd.K; ++j) o += (j ? "," : "") + std::to_string(pd.q_pos[j]);
+        o += "],";
+        I("outer_mask", (long long)pd.outer_mask);
+        I("rec_size", pd.rec_size);
+        I("round_begin", pd.round_begin);
+        I("round_end", pd.round_end);
+        I("op_begin", pd.op_begin);
+        I("op_end", pd.op_end);
+        I("job_begin", pd.job_begin);
+        I("job_end", pd.job_end);
+        o += "\"stages\":[";
+        for (int si = pd.stage_begin; si < pd.stage_end; ++si) {
+            const StageDesc &sd = P.stages[si];
+            o += si != pd.stage_begin ? ",{" : "{";
+            I("rec_begin", sd.rec_begin);
+            I("rec_end", sd.rec_end);
+            I("round_begin", sd.round_begin);
+            I("op_begin", sd.op_begin);
+            I("job_begin", sd.job_begin);
+            I("job_end", sd.job_end);
+            I("n_jobs", sd.job_end - sd.job_begin);
+            o += "\"rounds\":[";
+            for (int ri = sd.round_begin; ri < sd.round_end; ++ri) {
+                const RoundDesc &rd = P.rounds[ri];
+                o += ri != sd.round_begin ? ",{" : "{";
+                I("reg_mask", rd.reg_mask);
+                o += "\"ops\":[";
+                for (int oi = rd.op_begin; oi < rd.op_end; ++oi) {
+                    const OpDesc &op = P.ops[oi];
+                    o += oi != rd.op_begin ? ",{" : "{";
+                    I("type", op.type);
+                    I("p0", op.p0);
+                    I("p1", op.p1);
+                    I("gate", op.gate);
+                    I("rec", op.rec);
+                    I("diag_kind", op.diag_kind);
+                    I("lmask", op.lmask);
+                    I("lvalue", op.lvalue);
+                    I("omask", (long long)op.omask);
+                    I("ovalue", (long long)op.ovalue);
+                    o += "\"phases\":[";
+                    for (int k = op.pref_begin; k < op.pref_end; ++k) {
+                        const PrepRef &pr = P.prefs[k];
+                        o += (k != op.pref_begin ? ",[" : "[") + std::to_string(pr.kind) + "," +
+                             std::to_string(pr.post) + "," + std::to_string(pr.bit) + "," +
+                             std::to_string(pr.gate) + "]";
+                    }
+                    o += "]}";
+                }
+                o += "]}";
+            }
+            o += "]}";
+        }
+        o += "]}";
+    }
+    o += "]}";
+    if (len) *len = o.size();
+    if (buf && cap > 0) {
+        size_t k = std::min(cap - 1, o.size());
+        std::memcpy(buf, o.data(), k);
+        buf[k] = 0;
+    }
+    return QS_OK;
 }
 
 qs_status qs_run_trajectories(const qs_gate *gates, int n_gates, int n, uint64_t init_index, qs_dtype dt,
@@ -605,12 +717,18 @@ qs_status qs_run_trajectories(const qs_gate *gates, int n_gates, int n, uint64_t
     if (pl.fused) {
         if (!P.passes.empty())
             QS_HIP(hipMemcpyAsync(B + L.passes, P.passes.data(), sizeof(PassDesc) * P.passes.size(), hipMemcpyHostToDevice, st));
+        if (!P.stages.empty())
+            QS_HIP(hipMemcpyAsync(B + L.stages, P.stages.data(), sizeof(StageDesc) * P.stages.size(), hipMemcpyHostToDevice, st));
         if (!P.rounds.empty())
             QS_HIP(hipMemcpyAsync(B + L.rounds, P.rounds.data(), sizeof(RoundDesc) * P.rounds.size(), hipMemcpyHostToDevice, st));
         if (!P.ops.empty())
             QS_HIP(hipMemcpyAsync(B + L.ops, P.ops.data(), sizeof(OpDesc) * P.ops.size(), hipMemcpyHostToDevice, st));
         if (!P.prefs.empty())
-            QS_HIP(hipMemcpyAsync(B + L.prefs, P.prefs.data(), sizeof(PhaseRef) * P.prefs.size(), hipMemcpyHostToDevice, st));
+            QS_HIP(hipMemcpyAsync(B + L.prefs, P.prefs.data(), sizeof(PrepRef) * P.prefs.size(), hipMemcpyHostToDevice, st));
+        if (!P.jobs.empty())
+            QS_HIP(hipMemcpyAsync(B + L.jobs, P.jobs.data(), sizeof(OuterJob) * P.jobs.size(), hipMemcpyHostToDevice, st));
+        if (!P.obits.empty())
+            QS_HIP(hipMemcpyAsync(B + L.obits, P.obits.data(), sizeof(int32_t) * P.obits.size(), hipMemcpyHostToDevice, st));
     }
     NoiseArgs na{};
     na.e = 0.0;
@@ -623,10 +741,14 @@ qs_status qs_run_trajectories(const qs_gate *gates, int n_gates, int n, uint64_t
     QS_HIP(launch_init_basis(psi, dt, n, S, init_index, st));
 
     if (pl.fused) {
-        for (size_t p = 0; p < P.passes.size(); ++p)
-            QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (const PassDesc *)(B + L.passes) + p,
-                                     (const RoundDesc *)(B + L.rounds), (const OpDesc *)(B + L.ops),
-                                     (const PhaseRef *)(B + L.prefs), tab, gdev, st));
+        ProgramDev pdv{(const PassDesc *)(B + L.passes), (const StageDesc *)(B + L.stages),
+                       (const RoundDesc *)(B + L.rounds),
+                       (const OpDesc *)(B + L.ops), (const PrepRef *)(B + L.prefs),
+                       (const OuterJob *)(B + L.jobs), (const int32_t *)(B + L.obits)};
+        for (size_t p = 0; p < P.passes.size(); ++p) {
+            QS_HIP(launch_pass_prep(dt, S, &P.passes[p], pdv, tab, gdev, B + L.rec, st));
+            QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (int)p, pdv, B + L.rec, st));
+        }
     } else {
         for (int g = 0; g < n_gates; ++g) {
             const qs_gate &G = gates[g];

@@ -30,12 +30,6 @@ __device__ __forceinline__ cxf<R> fma_c(cxf<R> a, cxf<R> b, cxf<R> c)
     return {a.re * b.re - a.im * b.im + c.re, a.re * b.im + a.im * b.re + c.im};
 }
 
-template <typename R>
-__device__ __forceinline__ cxf<R> ld_tab(const double *t)
-{
-    return {(R)t[0], (R)t[1]};
-}
-
 // LDS slot of tile-local index l: the low five bits are xor-ed with a fold of the higher bits,
 // a bijection that spreads strided accesses over the banks.
 __device__ __forceinline__ uint32_t swz(uint32_t l)
@@ -74,53 +68,53 @@ __device__ __forceinline__ void reg_offsets(uint32_t reg_mask, int K, uint32_t (
     }
 }
 
+// Phase factors of one folded block for this thread: w (tile and thread constant) and one
+// factor per register bit, applied to a pair when that bit of the pair index is 1.
 template <typename R, int RB>
 struct PhaseSet {
-    cxf<R> w;          // tile/thread-constant factor
-    cxf<R> bit[RB];    // factor per register bit (applied when that bit of the pair index is 1)
+    cxf<R> w;
+    cxf<R> bit[RB];
     bool any;
-    bool reg;
 };
 
+// grec: the block in global memory (uniform reads, held in scalar registers); lrec: the same
+// block staged in LDS (per-thread table lookups); wout: per-tile outer products in LDS.
 template <typename R, int RB>
-__device__ __forceinline__ void gather_phases(PhaseSet<R, RB> &ps, const PhaseRef *prefs, int b,
-                                              int e, const double *tab, int S, int slot,
-                                              uint64_t outer, uint32_t lthr)
+__device__ __forceinline__ void load_phases(PhaseSet<R, RB> &ps, const cxf<R> *__restrict__ grec,
+                                            const cxf<R> *lrec, bool present, int job,
+                                            const cxf<R> *wout, uint32_t tid)
 {
-    ps.w = {(R)1, (R)0};
+    ps.any = present;
+    if (!present) return;
 #pragma unroll
-    for (int k = 0; k < RB; ++k) ps.bit[k] = {(R)1, (R)0};
-    ps.any = e > b;
-    ps.reg = false;
-    for (int k = b; k < e; ++k) {
-        const PhaseRef pr = prefs[k];
-        cxf<R> ph = ld_tab<R>(tab + ((uint64_t)pr.gate * S + slot) * 8);
-        if (pr.cls == PH_OUTER) {
-            if ((outer >> pr.bit) & 1ull) ps.w = mul(ps.w, ph);
-        } else if (pr.cls == PH_THREAD) {
-            cxf<R> t = mul(ps.w, ph);
-            bool on = (lthr >> pr.bit) & 1u;
-            ps.w.re = on ? t.re : ps.w.re;
-            ps.w.im = on ? t.im : ps.w.im;
-        } else {
-            ps.reg = true;
-#pragma unroll
-            for (int q = 0; q < RB; ++q)
-                if (pr.bit == q) ps.bit[q] = mul(ps.bit[q], ph);
-        }
-    }
+    for (int k = 0; k < RB; ++k) ps.bit[k] = lrec[k];
+    ps.w = mul(lrec[4 + (tid & 31u)], lrec[36 + ((tid >> 5) & 15u)]);
+    if (job >= 0) ps.w = mul(ps.w, wout[job]);
 }
 
 template <typename R, int RB, int P>
 __device__ __forceinline__ cxf<R> pair_phase(const PhaseSet<R, RB> &ps, int r)
 {
     cxf<R> w = ps.w;
-    if (ps.reg) {
 #pragma unroll
-        for (int q = 0; q < RB; ++q)
-            if (q != P && ((r >> q) & 1)) w = mul(w, ps.bit[q]);
-    }
+    for (int q = 0; q < RB; ++q)
+        if (q != P && ((r >> q) & 1)) w = mul(w, ps.bit[q]);
     return w;
+}
+
+// Register index of the k-th pair (bit P clear) and of the k-th quadruple (bits P0, P1 clear):
+// compile-time integer arithmetic, so that after unrolling every register access is static.
+template <int P>
+__device__ constexpr int pair_base(int k)
+{
+    return ((k >> P) << (P + 1)) | (k & ((1 << P) - 1));
+}
+
+template <int P0, int P1>
+__device__ constexpr int quad_base(int k)
+{
+    constexpr int lo = P0 < P1 ? P0 : P1, hi = P0 < P1 ? P1 : P0;
+    return pair_base<hi>(pair_base<lo>(k));
 }
 
 template <typename R, int RB, int P>
@@ -128,8 +122,8 @@ __device__ __forceinline__ void apply_u1(cxf<R> (&a)[1 << RB], const cxf<R> (&m)
                                          const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
 #pragma unroll
-    for (int r = 0; r < (1 << RB); ++r) {
-        if (r & (1 << P)) continue;
+    for (int k = 0; k < (1 << (RB - 1)); ++k) {
+        const int r = pair_base<P>(k);
         const int r1 = r | (1 << P);
         cxf<R> x0 = a[r], x1 = a[r1];
         if (pre.any) x1 = mul(pair_phase<R, RB, P>(pre, r), x1);
@@ -145,18 +139,23 @@ template <typename R, int RB, int P0, int P1>
 __device__ __forceinline__ void apply_u2(cxf<R> (&a)[1 << RB], const cxf<R> (&m)[16])
 {
 #pragma unroll
-    for (int r = 0; r < (1 << RB); ++r) {
-        if ((r & (1 << P0)) || (r & (1 << P1))) continue;
-        const int idx[4] = {r, r | (1 << P0), r | (1 << P1), r | (1 << P0) | (1 << P1)};
-        cxf<R> x[4] = {a[idx[0]], a[idx[1]], a[idx[2]], a[idx[3]]};
+    for (int k = 0; k < (1 << (RB - 2)); ++k) {
+        const int r0 = quad_base<P0, P1>(k);
+        const int r1 = r0 | (1 << P0), r2 = r0 | (1 << P1), r3 = r0 | (1 << P0) | (1 << P1);
+        const cxf<R> x0 = a[r0], x1 = a[r1], x2 = a[r2], x3 = a[r3];
+        cxf<R> y[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            cxf<R> s = mul(m[4 * i], x[0]);
-            s = fma_c(m[4 * i + 1], x[1], s);
-            s = fma_c(m[4 * i + 2], x[2], s);
-            s = fma_c(m[4 * i + 3], x[3], s);
-            a[idx[i]] = s;
+            cxf<R> s = mul(m[4 * i], x0);
+            s = fma_c(m[4 * i + 1], x1, s);
+            s = fma_c(m[4 * i + 2], x2, s);
+            s = fma_c(m[4 * i + 3], x3, s);
+            y[i] = s;
         }
+        a[r0] = y[0];
+        a[r1] = y[1];
+        a[r2] = y[2];
+        a[r3] = y[3];
     }
 }
 
@@ -177,34 +176,151 @@ template <typename R, int RB>
 __device__ __forceinline__ void dispatch_u2(int p0, int p1, cxf<R> (&a)[1 << RB], const cxf<R> (&m)[16])
 {
     if constexpr (RB >= 2) {
-#define QS_U2_CASE(A, B)                                                              \
-    if (p0 == (A) && p1 == (B)) {                                                     \
-        if constexpr ((A) < RB && (B) < RB && (A) != (B)) apply_u2<R, RB, (A) % RB, (B) % RB>(a, m); \
-        return;                                                                       \
-    }
+        switch (p0 * 4 + p1) {
+#define QS_U2_CASE(A, B) \
+    case (A) * 4 + (B): if constexpr ((A) < RB && (B) < RB) apply_u2<R, RB, (A) % RB, (B) % RB>(a, m); break;
         QS_U2_CASE(0, 1) QS_U2_CASE(1, 0) QS_U2_CASE(0, 2) QS_U2_CASE(2, 0)
         QS_U2_CASE(0, 3) QS_U2_CASE(3, 0) QS_U2_CASE(1, 2) QS_U2_CASE(2, 1)
         QS_U2_CASE(1, 3) QS_U2_CASE(3, 1) QS_U2_CASE(2, 3) QS_U2_CASE(3, 2)
 #undef QS_U2_CASE
+        default: break;
+        }
     }
 }
 
-template <typename R, int RB>
-__global__ void __launch_bounds__(512) k_fused(R *psi, int n, int S, const PassDesc *pd,
-                                               const RoundDesc *rounds, const OpDesc *ops,
-                                               const PhaseRef *prefs, const double *tab,
-                                               const qs_gate *gates)
+// ---------------------------------------------------------------------------------------
+// Per-slot records of one pass (one thread per op and slot; FP64 products rounded once).
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double2 dmul(double2 a, double2 b)
 {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+template <typename R>
+__global__ void k_pass_prep(int S, int op_begin, int n_ops, int rec_size, ProgramDev prog,
+                            const double *tab, const qs_gate *gates, cxf<R> *rec_all)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_ops * S) return;
+    const int slot = (int)(i / n_ops), ol = (int)(i % n_ops);
+    const OpDesc op = prog.ops[op_begin + ol];
+    cxf<R> *blk = rec_all + (size_t)slot * rec_size;
+    cxf<R> *rec = blk + op.rec;
+    auto tabc = [&](int g) {
+        const double *t = tab + ((uint64_t)g * S + slot) * 8;
+        return make_double2(t[0], t[1]);
+    };
+    auto put = [&](cxf<R> *dst, double2 v) { *dst = cxf<R>{(R)v.x, (R)v.y}; };
+    if (op.type == OP_U1) {
+        const double *t = tab + ((uint64_t)op.gate * S + slot) * 8;
+        for (int k = 0; k < 4; ++k) put(rec + k, make_double2(t[2 * k], t[2 * k + 1]));
+        for (int post = 0; post < 2; ++post) {
+            int block = post ? op.post_rec : op.pre_rec;
+            if (block < 0) continue;
+            double2 preg[kMaxRegBits], ptid[9];
+            for (int k = 0; k < kMaxRegBits; ++k) preg[k] = make_double2(1.0, 0.0);
+            for (int k = 0; k < 9; ++k) ptid[k] = make_double2(1.0, 0.0);
+            for (int k = op.pref_begin; k < op.pref_end; ++k) {
+                const PrepRef pr = prog.prefs[k];
+                if (pr.post != post) continue;
+                double2 ph = tabc(pr.gate);
+                if (pr.kind == PR_REG) preg[pr.bit] = dmul(preg[pr.bit], ph);
+                else if (pr.kind == PR_THREAD) ptid[pr.bit] = dmul(ptid[pr.bit], ph);
+                else put(blk + pr.slot_entry, ph);
+            }
+            cxf<R> *b = blk + block;
+            for (int k = 0; k < 4; ++k) put(b + k, k < kMaxRegBits ? preg[k] : make_double2(1.0, 0.0));
+            for (int x = 0; x < 32; ++x) {
+                double2 w = make_double2(1.0, 0.0);
+                for (int k = 0; k < 5; ++k)
+                    if ((x >> k) & 1) w = dmul(w, ptid[k]);
+                put(b + 4 + x, w);
+            }
+            for (int y = 0; y < 16; ++y) {
+                double2 w = make_double2(1.0, 0.0);
+                for (int k = 0; k < 4; ++k)
+                    if ((y >> k) & 1) w = dmul(w, ptid[5 + k]);
+                put(b + 36 + y, w);
+            }
+        }
+    } else if (op.type == OP_U2) {
+        const double *m = gates[op.gate].m;
+        for (int k = 0; k < 16; ++k) put(rec + k, make_double2(m[2 * k], m[2 * k + 1]));
+    } else {
+        put(rec, op.diag_kind == DIAG_PHASE ? tabc(op.gate) : make_double2(-1.0, 0.0));
+    }
+}
+
+// LDS of one block: the tile, then the staged op descriptors, rounds, records, per-tile outer
+// products and outer condition bits of the current stage.
+constexpr int kStageRounds = kStageOps;
+
+template <typename R>
+struct StageLds {
+    OpDesc *ops;
+    RoundDesc *rounds;
+    cxf<R> *rec;
+    cxf<R> *wout;
+    int32_t *obits;
+};
+
+template <typename R>
+__device__ __forceinline__ StageLds<R> stage_lds(unsigned char *smem, int K, int rec_cap)
+{
+    StageLds<R> L;
+    size_t off = (size_t(1) << K) * sizeof(cxf<R>);
+    L.ops = reinterpret_cast<OpDesc *>(smem + off);
+    off += sizeof(OpDesc) * kStageOps;
+    L.rounds = reinterpret_cast<RoundDesc *>(smem + off);
+    off += sizeof(RoundDesc) * kStageRounds;
+    L.rec = reinterpret_cast<cxf<R> *>(smem + off);
+    off += sizeof(cxf<R>) * rec_cap;
+    L.wout = reinterpret_cast<cxf<R> *>(smem + off);
+    off += sizeof(cxf<R>) * kStageJobs;
+    L.obits = reinterpret_cast<int32_t *>(smem + off);
+    return L;
+}
+
+__device__ __forceinline__ void copy_words(uint32_t *dst, const uint32_t *src, int words, uint32_t tid,
+                                           uint32_t nthreads)
+{
+    for (int w = (int)tid; w < words; w += (int)nthreads) dst[w] = src[w];
+}
+
+template <typename R, int RB>
+__global__ void __launch_bounds__(512, 4) k_fused(R *__restrict__ psi, int n, int S, int pass_index,
+                                                  int rec_cap,
+                                                  const PassDesc *__restrict__ g_passes,
+                                                  const StageDesc *__restrict__ g_stages,
+                                                  const RoundDesc *__restrict__ g_rounds,
+                                                  const OpDesc *__restrict__ g_ops,
+                                                  const OuterJob *__restrict__ g_jobs,
+                                                  const int32_t *__restrict__ g_obits,
+                                                  const cxf<R> *__restrict__ rec_all)
+{
+    // Descriptor arrays as separate read-only, non-aliasing arguments: their uniform reads
+    // become scalar loads that do not wait on the tile's vector memory traffic.
+    struct {
+        const PassDesc *__restrict__ passes;
+        const StageDesc *__restrict__ stages;
+        const RoundDesc *__restrict__ rounds;
+        const OpDesc *__restrict__ ops;
+        const OuterJob *__restrict__ jobs;
+        const int32_t *__restrict__ obits;
+    } prog = {g_passes, g_stages, g_rounds, g_ops, g_jobs, g_obits};
     extern __shared__ __align__(16) unsigned char smem[];
     cxf<R> *lds = reinterpret_cast<cxf<R> *>(smem);
     constexpr int NR = 1 << RB;
+    const PassDesc *pd = prog.passes + pass_index;
     const int K = pd->K;
     const int TB = K - RB;
-    const uint32_t kmask = (K >= 32) ? 0xffffffffu : ((1u << K) - 1u);
+    const uint32_t kmask = (1u << K) - 1u;
+    const StageLds<R> L = stage_lds<R>(smem, K, rec_cap);
     const int tiles_log = n - K;
     const int slot = (int)(blockIdx.x >> tiles_log);
     const uint64_t tile = (uint64_t)blockIdx.x & ((1ull << tiles_log) - 1ull);
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+    const cxf<R> *__restrict__ rec = rec_all + (size_t)slot * pd->rec_size;
 
     // Outer (tile-number) bits of the physical index.
     uint64_t outer = 0;
@@ -262,35 +378,60 @@ __global__ void __launch_bounds__(512) k_fused(R *psi, int n, int S, const PassD
         for (int r = 0; r < NR; ++r) a[r] = lds[swz(lthr | roff[r])];
     };
 
-    for (int ri = pd->round_begin; ri < pd->round_end; ++ri) {
-        const RoundDesc rd = rounds[ri];
-        if (rd.reg_mask != cur) exchange(rd.reg_mask);
-        for (int oi = rd.op_begin; oi < rd.op_end; ++oi) {
-            const OpDesc op = ops[oi];
-            if (op.type == OP_U1) {
-                const double *t = tab + ((uint64_t)op.gate * S + slot) * 8;
-                cxf<R> m[4] = {ld_tab<R>(t), ld_tab<R>(t + 2), ld_tab<R>(t + 4), ld_tab<R>(t + 6)};
-                PhaseSet<R, RB> pre, post;
-                gather_phases<R, RB>(pre, prefs, op.pre_begin, op.pre_end, tab, S, slot, outer, lthr);
-                gather_phases<R, RB>(post, prefs, op.post_begin, op.post_end, tab, S, slot, outer, lthr);
-                dispatch_u1<R, RB>(op.p0, a, m, pre, post);
-            } else if (op.type == OP_U2) {
-                const double *g = gates[op.gate].m;
-                cxf<R> m[16];
+    for (int si = pd->stage_begin; si < pd->stage_end; ++si) {
+        const StageDesc sd = prog.stages[si];
+        if (si != pd->stage_begin) __syncthreads();   // the previous stage's LDS readers are done
+        copy_words(reinterpret_cast<uint32_t *>(L.rec),
+                   reinterpret_cast<const uint32_t *>(rec + sd.rec_begin),
+                   (sd.rec_end - sd.rec_begin) * (int)(sizeof(cxf<R>) / 4), tid, nthr);
+        copy_words(reinterpret_cast<uint32_t *>(L.obits),
+                   reinterpret_cast<const uint32_t *>(prog.obits + sd.obits_begin),
+                   sd.obits_end - sd.obits_begin, tid, nthr);
+        __syncthreads();
+        // per-tile products of the phases conditioned on tile-number bits
+        const int nj = sd.job_end - sd.job_begin;
+        for (int j = (int)tid; j < nj; j += (int)nthr) {
+            const OuterJob jb = prog.jobs[sd.job_begin + j];
+            cxf<R> w = {(R)1, (R)0};
+            for (int k = 0; k < jb.n; ++k)
+                if ((outer >> L.obits[jb.bits_off - sd.obits_begin + k]) & 1ull)
+                    w = mul(w, L.rec[jb.rec_off - sd.rec_begin + k]);
+            L.wout[j] = w;
+        }
+        if (nj > 0) __syncthreads();
+        const int job_shift = sd.job_begin - pd->job_begin;
+
+        for (int ri = sd.round_begin; ri < sd.round_end; ++ri) {
+            const RoundDesc rd = prog.rounds[ri];
+            if (rd.reg_mask != cur) exchange(rd.reg_mask);
+            for (int oi = rd.op_begin; oi < rd.op_end; ++oi) {
+                const OpDesc op = prog.ops[oi];
+                const cxf<R> *orec = L.rec + (op.rec - sd.rec_begin);
+                if (op.type == OP_U1) {
+                    cxf<R> m[4] = {orec[0], orec[1], orec[2], orec[3]};
+                    PhaseSet<R, RB> pre, post;
+                    load_phases<R, RB>(pre, rec + op.pre_rec, L.rec + (op.pre_rec - sd.rec_begin),
+                                       op.pre_rec >= 0, op.pre_job < 0 ? -1 : op.pre_job - job_shift,
+                                       L.wout, tid);
+                    load_phases<R, RB>(post, rec + op.post_rec, L.rec + (op.post_rec - sd.rec_begin),
+                                       op.post_rec >= 0, op.post_job < 0 ? -1 : op.post_job - job_shift,
+                                       L.wout, tid);
+                    dispatch_u1<R, RB>(op.p0, a, m, pre, post);
+                } else if (op.type == OP_U2) {
+                    cxf<R> m[16];
 #pragma unroll
-                for (int k = 0; k < 16; ++k) m[k] = {(R)g[2 * k], (R)g[2 * k + 1]};
-                dispatch_u2<R, RB>(op.p0, op.p1, a, m);
-            } else {
-                if ((outer & op.omask) != op.ovalue) continue;
-                cxf<R> f = {(R)-1, (R)0};
-                if (op.diag_kind == DIAG_PHASE)
-                    f = ld_tab<R>(tab + ((uint64_t)op.gate * S + slot) * 8);
+                    for (int k = 0; k < 16; ++k) m[k] = orec[k];
+                    dispatch_u2<R, RB>(op.p0, op.p1, a, m);
+                } else {
+                    if ((outer & op.omask) != op.ovalue) continue;
+                    const cxf<R> f = orec[0];
 #pragma unroll
-                for (int r = 0; r < NR; ++r) {
-                    bool hit = ((lthr | roff[r]) & op.lmask) == op.lvalue;
-                    cxf<R> y = mul(f, a[r]);
-                    a[r].re = hit ? y.re : a[r].re;
-                    a[r].im = hit ? y.im : a[r].im;
+                    for (int r = 0; r < NR; ++r) {
+                        bool hit = ((lthr | roff[r]) & op.lmask) == op.lvalue;
+                        cxf<R> y = mul(f, a[r]);
+                        a[r].re = hit ? y.re : a[r].re;
+                        a[r].im = hit ? y.im : a[r].im;
+                    }
                 }
             }
         }
@@ -298,7 +439,11 @@ __global__ void __launch_bounds__(512) k_fused(R *psi, int n, int S, const PassD
     if (cur != load_mask) exchange(load_mask);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        uint64_t i = gthr | greg[r];
+        uint64_t g = 0;
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+            if (r & (1 << k)) g |= 1ull << pd->q_pos[TB + k];
+        uint64_t i = gthr | g;
         if constexpr (sizeof(R) == 4) {
             *reinterpret_cast<float2 *>(base + 2 * i) = make_float2(a[r].re, a[r].im);
         } else {
@@ -307,12 +452,49 @@ __global__ void __launch_bounds__(512) k_fused(R *psi, int n, int S, const PassD
     }
 }
 
-size_t fused_lds_bytes(qs_dtype dt, int K) { return (size_t(1) << K) * (dt == QS_C64 ? 8 : 16); }
+static size_t stage_fixed_bytes(size_t cxs)
+{
+    return sizeof(OpDesc) * kStageOps + sizeof(RoundDesc) * kStageRounds + cxs * kStageJobs +
+           sizeof(int32_t) * kStageObits;
+}
+
+int stage_rec_cap(qs_dtype dt, int K)
+{
+    const size_t cxs = dt == QS_C64 ? 8 : 16;
+    const size_t tile = (size_t(1) << K) * cxs;
+    const size_t budget = tile <= 64 * 1024 ? 80 * 1024 : 160 * 1024;
+    const size_t fixed = tile + stage_fixed_bytes(cxs);
+    if (fixed >= budget) return 0;
+    size_t cap = (budget - fixed) / cxs;
+    return (int)(cap > 4096 ? 4096 : cap);
+}
+
+size_t fused_lds_bytes(qs_dtype dt, int K)
+{
+    const size_t cxs = dt == QS_C64 ? 8 : 16;
+    return (size_t(1) << K) * cxs + stage_fixed_bytes(cxs) + (size_t)stage_rec_cap(dt, K) * cxs;
+}
+
+hipError_t launch_pass_prep(qs_dtype dt, int S, const PassDesc *h, ProgramDev prog,
+                            const double *tab, const qs_gate *gates_dev, void *rec, hipStream_t st)
+{
+    const int n_ops = h->op_end - h->op_begin;
+    const uint64_t tot = (uint64_t)n_ops * S;
+    if (tot == 0) return hipSuccess;
+    TimedLaunch tl("prep", (double)S * h->rec_size * (dt == QS_C64 ? 8 : 16), st);
+    unsigned blocks = (unsigned)((tot + 127) / 128);
+    if (dt == QS_C64)
+        hipLaunchKernelGGL(k_pass_prep<float>, dim3(blocks), dim3(128), 0, st, S, h->op_begin, n_ops,
+                           h->rec_size, prog, tab, gates_dev, (cxf<float> *)rec);
+    else
+        hipLaunchKernelGGL(k_pass_prep<double>, dim3(blocks), dim3(128), 0, st, S, h->op_begin, n_ops,
+                           h->rec_size, prog, tab, gates_dev, (cxf<double> *)rec);
+    return hipGetLastError();
+}
 
 template <typename R, int RB>
-static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, const PassDesc *pd,
-                           const RoundDesc *rounds, const OpDesc *ops, const PhaseRef *prefs,
-                           const double *tab, const qs_gate *gates, size_t lds, hipStream_t st)
+static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_index, int rec_cap,
+                           ProgramDev prog, const void *rec, size_t lds, hipStream_t st)
 {
     static bool attr_set = false;
     if (!attr_set) {
@@ -323,34 +505,35 @@ static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, const PassDe
     }
     unsigned blocks = (unsigned)((uint64_t)S << (n - h.K));
     unsigned threads = 1u << (h.K - RB);
-    hipLaunchKernelGGL((k_fused<R, RB>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pd,
-                       rounds, ops, prefs, tab, gates);
+    hipLaunchKernelGGL((k_fused<R, RB>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index,
+                       rec_cap, prog.passes, prog.stages, prog.rounds, prog.ops, prog.jobs, prog.obits,
+                       (const cxf<R> *)rec);
     return hipGetLastError();
 }
 
 hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDesc *pass_host,
-                             const PassDesc *pass_dev, const RoundDesc *rounds,
-                             const OpDesc *ops, const PhaseRef *prefs, const double *tab,
-                             const qs_gate *gates_dev, hipStream_t st)
+                             int pass_index, ProgramDev prog, const void *rec, hipStream_t st)
 {
     const PassDesc &h = *pass_host;
     size_t lds = fused_lds_bytes(dt, h.K);
+    const int rec_cap = stage_rec_cap(dt, h.K);
+    if (lds > 160 * 1024 || rec_cap <= 0) return hipErrorInvalidValue;
     TimedLaunch tl("fused", 2.0 * (double)((uint64_t)S << n) * amp_bytes(dt), st);
     if (dt == QS_C64) {
         float *p = (float *)psi;
         switch (h.RB) {
-        case 1: return launch_t<float, 1>(p, n, S, h, pass_dev, rounds, ops, prefs, tab, gates_dev, lds, st);
-        case 2: return launch_t<float, 2>(p, n, S, h, pass_dev, rounds, ops, prefs, tab, gates_dev, lds, st);
-        case 3: return launch_t<float, 3>(p, n, S, h, pass_dev, rounds, ops, prefs, tab, gates_dev, lds, st);
-        case 4: return launch_t<float, 4>(p, n, S, h, pass_dev, rounds, ops, prefs, tab, gates_dev, lds, st);
+        case 1: return launch_t<float, 1>(p, n, S, h, pass_index, rec_cap, prog, rec, lds, st);
+        case 2: return launch_t<float, 2>(p, n, S, h, pass_index, rec_cap, prog, rec, lds, st);
+        case 3: return launch_t<float, 3>(p, n, S, h, pass_index, rec_cap, prog, rec, lds, st);
+        case 4: return launch_t<float, 4>(p, n, S, h, pass_index, rec_cap, prog, rec, lds, st);
         }
     } else {
         double *p = (double *)psi;
         switch (h.RB) {
-        case 1: return launch_t<double, 1>(p, n, S, h, pass_dev, rounds, ops, prefs, tab, gates_dev, lds, st);
-        case 2: return launch_t<double, 2>(p, n, S, h, pass_dev, rounds, ops, prefs, tab, gates_dev, lds, st);
-        case 3: return launch_t<double, 3>(p, n, S, h, pass_dev, rounds, ops, prefs, tab, gates_dev, lds, st);
-        case 4: return launch_t<double, 4>(p, n, S, h, pass_dev, rounds, ops, prefs, tab, gates_dev, lds, st);
+        case 1: return launch_t<double, 1>(p, n, S, h, pass_index, rec_cap, prog, rec, lds, st);
+        case 2: return launch_t<double, 2>(p, n, S, h, pass_index, rec_cap, prog, rec, lds, st);
+        case 3: return launch_t<double, 3>(p, n, S, h, pass_index, rec_cap, prog, rec, lds, st);
+        case 4: return launch_t<double, 4>(p, n, S, h, pass_index, rec_cap, prog, rec, lds, st);
         }
     }
     return hipErrorInvalidValue;

@@ -31,9 +31,18 @@ void clear_error();
 // thread holds 2^RB amplitudes in registers; a round fixes which RB tile-local bits are the
 // register bits (reg_mask) and applies its ops in registers; rounds are linked by exchanges
 // through LDS.  Tile-local bits not in reg_mask are the thread-id bits in increasing order.
+//
+// Per slot, a prep kernel writes one record per op of the pass (complex numbers in the
+// amplitude precision): a one-qubit op's 2x2 matrix, and for its folded controlled phases
+// (conditioned on the other qubit, applied to the |1> input = "pre" or output = "post"):
+//   reg[RB]  phase factor per register bit,
+//   lo[32]   product over the thread-id bits 0..4 that are set, indexed by tid & 31,
+//   hi[16]   product over the thread-id bits 5..8 that are set, indexed by tid >> 5,
+//   outer[n] the phases conditioned on tile-number bits (multiplied per tile in the kernel).
 // ---------------------------------------------------------------------------------------
 constexpr int kMaxTileBits = 15;
 constexpr int kMaxRegBits = 4;
+constexpr int kPhaseTable = 4 + 32 + 16;   // reg + lo + hi entries of a phase block
 
 struct PassDesc {
     int32_t K;
@@ -42,7 +51,26 @@ struct PassDesc {
     int32_t round_end;
     uint64_t outer_mask;          // physical bits (< n) that are not in the tile
     int32_t q_pos[16];            // tile-local bit j -> physical bit
+    int32_t op_begin, op_end;     // the pass's ops (records)
+    int32_t rec_size;             // complex entries of the pass's records per slot
+    int32_t job_begin, job_end;   // OuterJobs of the pass (per-tile outer phase products)
+    int32_t stage_begin, stage_end;
 };
+
+// A stage: consecutive rounds whose op descriptors, records, outer jobs and outer bits are
+// copied into LDS together (record and job offsets of ops are relative to the pass; stage
+// ranges are absolute except rec_*, which are relative to the pass's record block).
+struct StageDesc {
+    int32_t round_begin, round_end;
+    int32_t op_begin, op_end;
+    int32_t rec_begin, rec_end;
+    int32_t job_begin, job_end;   // absolute OuterJob indices
+    int32_t obits_begin, obits_end;
+};
+
+constexpr int kStageOps = 48;     // op descriptors per stage
+constexpr int kStageJobs = 64;    // outer jobs per stage
+constexpr int kStageObits = 512;  // outer condition bits per stage
 
 struct RoundDesc {
     uint32_t reg_mask;            // tile-local bits held in registers during this round
@@ -53,28 +81,40 @@ struct RoundDesc {
 
 enum OpType : int32_t { OP_U1 = 0, OP_U2 = 1, OP_DIAG = 2 };
 enum DiagKind : int32_t { DIAG_NEGATE = 0, DIAG_PHASE = 1 };
-enum PhaseClass : int32_t { PH_OUTER = 0, PH_THREAD = 1, PH_REG = 2 };
+enum PrepKind : int32_t { PR_REG = 0, PR_THREAD = 1, PR_OUTER = 2 };
 
 struct OpDesc {
     int32_t type;
     int32_t p0, p1;               // register-bit positions of the target(s)
-    int32_t gate;                 // gate index: noise-table row / matrix of the gate
-    int32_t pre_begin, pre_end;   // PhaseRefs applied to the |1> input of a U1 (column phases)
-    int32_t post_begin, post_end; // PhaseRefs applied to the |1> output of a U1 (row phases)
+    int32_t gate;                 // gate index (noise-table row, matrix)
+    int32_t rec;                  // record offset (complex entries) within the slot's block
+    int32_t pre_rec, post_rec;    // phase blocks (-1: none)
+    int32_t pre_job, post_job;    // OuterJob index within the pass (-1: none)
+    int32_t pref_begin, pref_end; // PrepRefs of this op
     int32_t diag_kind;
     uint32_t lmask, lvalue;       // DIAG: tile-local condition (l & lmask) == lvalue
-    uint32_t reserved;
     uint64_t omask, ovalue;       // DIAG: tile condition (outer index & omask) == ovalue
 };
 
-// A controlled phase folded into a U1: multiply by the phase of gate `gate` when the
-// condition bit is 1.  cls PH_OUTER: physical bit `bit` of the tile's outer index;
-// PH_THREAD: tile-local bit `bit` of the thread's base index; PH_REG: register bit `bit`.
-struct PhaseRef {
-    int32_t cls;
+// A controlled phase folded into a one-qubit op: the phase of gate `gate` (noise table) when
+// the condition bit is 1.  kind PR_REG: register bit `bit`; PR_THREAD: thread-id bit `bit`;
+// PR_OUTER: stored at record entry `slot_entry`, conditioned per tile by an OuterJob.
+struct PrepRef {
+    int32_t kind;
+    int32_t post;
     int32_t bit;
     int32_t gate;
+    int32_t slot_entry;
     int32_t reserved;
+};
+
+// Per tile: w = product of the record entries rec_off .. rec_off + n - 1 whose physical bit
+// obits[bits_off + k] is set in the tile number.
+struct OuterJob {
+    int32_t op;
+    int32_t rec_off;
+    int32_t bits_off;
+    int32_t n;
 };
 
 // ---------------------------------------------------------------------------------------
@@ -119,11 +159,24 @@ hipError_t launch_dm_expect(const void *rho, const void *psi, qs_dtype dt, int n
                             double *partials, double *out, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
 
+struct ProgramDev {
+    const PassDesc *passes;
+    const StageDesc *stages;
+    const RoundDesc *rounds;
+    const OpDesc *ops;
+    const PrepRef *prefs;
+    const OuterJob *jobs;
+    const int32_t *obits;
+};
+
+// Records of pass `pass_host` for all S slots into rec (S * rec_size complex entries).
+hipError_t launch_pass_prep(qs_dtype dt, int S, const PassDesc *pass_host, ProgramDev prog,
+                            const double *tab, const qs_gate *gates_dev, void *rec, hipStream_t st);
 hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDesc *pass_host,
-                             const PassDesc *pass_dev, const RoundDesc *rounds,
-                             const OpDesc *ops, const PhaseRef *prefs, const double *tab,
-                             const qs_gate *gates_dev, hipStream_t st);
+                             int pass_index, ProgramDev prog, const void *rec, hipStream_t st);
 size_t fused_lds_bytes(qs_dtype dt, int K);
+// Record entries per stage that fit next to a tile of 2^K amplitudes (two tiles per CU).
+int stage_rec_cap(qs_dtype dt, int K);
 
 // Fixed rank: Gram of the 2r half-columns; partial blocks then a fixed-order final sum.
 size_t fr_gram_partials_doubles(int n, int r);
@@ -150,15 +203,19 @@ struct TimedLaunch {
 // ---------------------------------------------------------------------------------------
 struct Program {
     std::vector<PassDesc> passes;
+    std::vector<StageDesc> stages;
     std::vector<RoundDesc> rounds;
     std::vector<OpDesc> ops;
-    std::vector<PhaseRef> prefs;
+    std::vector<PrepRef> prefs;
+    std::vector<OuterJob> jobs;
+    std::vector<int32_t> obits;
     std::vector<int32_t> layout;  // logical qubit -> physical bit after the circuit
     int K = 0, RB = 0;
+    int max_rec = 0;              // largest per-slot record block of a pass (complex entries)
 };
 
 qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, int run_bits,
-                     Program &out);
+                     int rec_cap, Program &out);
 
 inline size_t amp_bytes(qs_dtype dt) { return dt == QS_C64 ? 8 : 16; }
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }

@@ -261,15 +261,16 @@ __global__ void k_noise_one(qs_gate G, int S, NoiseArgs na, double *tab)
 template <typename R>
 __global__ void k_init_basis(R *psi, int n, uint64_t total_vec, uint64_t index)
 {
-    uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= total_vec) return;
     constexpr int VEC = kVec<R>;
-    uint64_t i = v * VEC;                        // global amplitude index (slot-major)
-    uint64_t in_slot = i & ((1ull << n) - 1);
-    cx<R> a[VEC];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < total_vec; v += stride) {
+        uint64_t i = v * VEC;                    // global amplitude index (slot-major)
+        uint64_t in_slot = i & ((1ull << n) - 1);
+        cx<R> a[VEC];
 #pragma unroll
-    for (int k = 0; k < VEC; ++k) a[k] = {(R)((in_slot + k) == index ? 1 : 0), (R)0};
-    vstore(psi, i, a);
+        for (int k = 0; k < VEC; ++k) a[k] = {(R)((in_slot + k) == index ? 1 : 0), (R)0};
+        vstore(psi, i, a);
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -282,8 +283,9 @@ template <typename R, int MODE, int U>
 __global__ void __launch_bounds__(256) k_u1(R *psi, int n, int q, const double *tab_row,
                                             int log_items, uint64_t total)
 {
+  for (uint64_t blk = blockIdx.x; blk * (256 * U) < total; blk += gridDim.x) {
     constexpr int VEC = kVec<R>;
-    const uint64_t base_item = (uint64_t)blockIdx.x * (256 * U) + threadIdx.x;
+    const uint64_t base_item = blk * (256 * U) + threadIdx.x;
     cx<R> a0[U][VEC], a1[U][VEC];
     uint64_t i0s[U];
     int slots[U];
@@ -330,14 +332,15 @@ __global__ void __launch_bounds__(256) k_u1(R *psi, int n, int q, const double *
             vstore(p, i0s[u], t2);
         }
     }
+  }
 }
 
 // Generic one-amplitude-pair-per-thread fallback for small states.
 template <typename R>
 __global__ void k_u1_small(R *psi, int n, int q, const double *tab_row, uint64_t total)
 {
-    uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (it >= total) return;
+  for (uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+       it += (uint64_t)gridDim.x * blockDim.x) {
     int slot = (int)(it >> (n - 1));
     uint64_t c = it & ((1ull << (n - 1)) - 1);
     R *p = psi + ((uint64_t)slot << (n + 1));
@@ -347,6 +350,7 @@ __global__ void k_u1_small(R *psi, int n, int q, const double *tab_row, uint64_t
     cx<R> a0 = sload(p, i0), a1 = sload(p, i1);
     sstore(p, i0, cfma(m01, a1, cmul(m00, a0)));
     sstore(p, i1, cfma(m11, a1, cmul(m10, a0)));
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -363,8 +367,8 @@ template <typename R, int KIND, int V>
 __global__ void __launch_bounds__(256) k_2q(R *psi, int n, int qa, int qb, const double *tab_row,
                                             M32 m32, int log_items, uint64_t total)
 {
-    uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (it >= total) return;
+  for (uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+       it += (uint64_t)gridDim.x * blockDim.x) {
     const int lo = qa < qb ? qa : qb, hi = qa < qb ? qb : qa;
     int slot = (int)(it >> log_items);
     uint64_t c = it & ((1ull << log_items) - 1);
@@ -418,6 +422,7 @@ __global__ void __launch_bounds__(256) k_2q(R *psi, int n, int qa, int qb, const
             st(idx[r], o);
         }
     }
+  }
 }
 
 // Sign flip of every amplitude i with (i & mask) == value: the free bits of ~mask are
@@ -426,8 +431,8 @@ template <typename R>
 __global__ void k_flip(R *psi, int n, uint64_t mask, uint64_t value, int free_bits,
                        uint64_t total)
 {
-    uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (it >= total) return;
+  for (uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+       it += (uint64_t)gridDim.x * blockDim.x) {
     int slot = (int)(it >> free_bits);
     uint64_t c = it & ((1ull << free_bits) - 1);
     uint64_t i = value;
@@ -440,6 +445,7 @@ __global__ void k_flip(R *psi, int n, uint64_t mask, uint64_t value, int free_bi
     R *p = psi + ((uint64_t)slot << (n + 1));
     p[2 * i] = -p[2 * i];
     p[2 * i + 1] = -p[2 * i + 1];
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -596,9 +602,13 @@ __global__ void k_copy(float4 *dst, const float4 *src, uint64_t n16)
 // ---------------------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------------------
+// Grid size for `items` work items, `per_block` per block.  AMD GPUs allow fewer than 2^32
+// work items per grid dimension, so large sweeps cap the grid and loop (grid-stride).
 static inline unsigned blocks_for(uint64_t items, unsigned per_block)
 {
-    return (unsigned)((items + per_block - 1) / per_block);
+    uint64_t b = (items + per_block - 1) / per_block;
+    const uint64_t cap = (1ull << 31) / 1024;    // 2^21 blocks of <= 1024 work items
+    return (unsigned)(b < cap ? b : cap);
 }
 
 hipError_t launch_noise_table(const qs_gate *gates_dev, int n_gates, int S, NoiseArgs na,

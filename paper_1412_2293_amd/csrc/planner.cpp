@@ -47,7 +47,7 @@ int find_pos(const std::vector<int> &v, int x)
 }  // namespace
 
 qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, int run_bits,
-                     Program &P)
+                     int rec_cap, Program &P)
 {
     if (K > n) K = n;
     if (K > kMaxTileBits) K = kMaxTileBits;
@@ -128,7 +128,7 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         nd_pos[x.a].push_back((int)i);
         if (x.b >= 0) nd_pos[x.b].push_back((int)i);
     }
-    std::vector<std::vector<Attach>> pre(pg.size()), post(pg.size());
+    std::vector<std::vector<Attach>> pre_att(pg.size()), post_att(pg.size());
     std::vector<bool> standalone(pg.size(), false);
     for (size_t i = 0; i < pg.size(); ++i) {
         const PG &x = pg[i];
@@ -150,20 +150,21 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         int nx = (na < 0) ? nb : (nb < 0 ? na : std::min(na, nb));
         if (nx >= 0 && pg[nx].kind == QS_G_U1) {
             int cond = (pg[nx].a == x.a) ? x.b : x.a;
-            pre[nx].push_back({cond, x.gate});
+            pre_att[nx].push_back({cond, x.gate});
             continue;
         }
         int pa = prev_of(x.a), pb = prev_of(x.b);
         int px = std::max(pa, pb);
         if (px >= 0 && pg[px].kind == QS_G_U1) {
             int cond = (pg[px].a == x.a) ? x.b : x.a;
-            post[px].push_back({cond, x.gate});
+            post_att[px].push_back({cond, x.gate});
             continue;
         }
         standalone[i] = true;
     }
 
-    // 4. tiles and rounds
+    // 4. tiles, rounds and per-slot records
+    int max_rec = 0;
     for (size_t pi = 0; pi < passes.size(); ++pi) {
         PassBuild &pb = passes[pi];
         std::vector<int> ops_idx;
@@ -188,72 +189,175 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         }
         uint64_t nmask = (n >= 64) ? ~0ull : ((1ull << n) - 1);
         pd.outer_mask = nmask & ~qmask;
+        const uint32_t kmask = (1u << K) - 1u;
         const uint32_t load_mask = ((1u << RB) - 1u) << (K - RB);
 
-        // greedy register rounds
-        struct RB_ { uint32_t need = 0; std::vector<int> ops; };
+        // greedy register rounds, closed also when the current LDS stage is full
+        auto fill = [&](uint32_t need) {
+            uint32_t m = need;
+            for (int j = K - 1; j >= 0 && __builtin_popcount(m) < RB; --j)
+                if ((load_mask >> j) & 1u) m |= 1u << j;
+            for (int j = K - 1; j >= 0 && __builtin_popcount(m) < RB; --j) m |= 1u << j;
+            return m;
+        };
+        auto costs = [&](int i, int &rec_c, int &jobs_c, int &obits_c) {
+            const PG &x = pg[i];
+            rec_c = jobs_c = obits_c = 0;
+            if (x.kind == QS_G_U1) {
+                rec_c = 4;
+                for (int post = 0; post < 2; ++post) {
+                    const auto &att = (post ? post_att : pre_att)[i];
+                    if (att.empty()) continue;
+                    int no = 0;
+                    for (auto &at : att)
+                        if (local_of[at.cond] < 0) ++no;
+                    rec_c += kPhaseTable + no;
+                    if (no) {
+                        ++jobs_c;
+                        obits_c += no;
+                    }
+                }
+            } else if (x.kind == QS_G_U2 || x.kind == QS_G_CNOT) {
+                rec_c = 16;
+            } else {
+                rec_c = 1;
+            }
+        };
+        struct RB_ { uint32_t need = 0; uint32_t forced = 0; bool stage_start = false; std::vector<int> ops; };
         std::vector<RB_> rounds(1);
+        rounds.back().stage_start = true;
+        int st_ops = 0, st_rec = 0, st_jobs = 0, st_obits = 0;
         for (int i : ops_idx) {
             const PG &x = pg[i];
             uint32_t need = 0;
             if (x.kind == QS_G_U1) need = 1u << local_of[x.a];
             else if (x.kind == QS_G_U2 || x.kind == QS_G_CNOT) need = (1u << local_of[x.a]) | (1u << local_of[x.b]);
-            uint32_t u = rounds.back().need | need;
-            if (__builtin_popcount(u) > RB) {
-                rounds.emplace_back();
-                u = need;
+            int rc, jc, oc;
+            costs(i, rc, jc, oc);
+            RB_ &cur = rounds.back();
+            uint32_t cur_mask = cur.forced ? cur.forced : fill(cur.need);
+            bool fits_reg = cur.forced ? ((need & ~cur.forced) == 0) : (__builtin_popcount(cur.need | need) <= RB);
+            bool fits_stage = st_ops + 1 <= kStageOps && st_rec + rc <= rec_cap &&
+                              st_jobs + jc <= kStageJobs && st_obits + oc <= kStageObits;
+            if (!cur.ops.empty() && (!fits_reg || !fits_stage)) {
+                RB_ nr;
+                if (!fits_stage) {
+                    nr.stage_start = true;
+                    st_ops = st_rec = st_jobs = st_obits = 0;
+                    if (fits_reg && cur_mask != 0 && (need & ~cur_mask) == 0) {
+                        nr.forced = cur_mask;   // same register layout: no exchange
+                        nr.need = cur.need;
+                    }
+                }
+                if (!cur.forced) cur.forced = cur_mask;
+                rounds.push_back(nr);
             }
-            rounds.back().need = u;
-            rounds.back().ops.push_back(i);
+            RB_ &r2 = rounds.back();
+            if (!r2.forced) r2.need |= need;
+            r2.ops.push_back(i);
+            st_ops += 1;
+            st_rec += rc;
+            st_jobs += jc;
+            st_obits += oc;
         }
+        for (auto &rd : rounds)
+            if (!rd.forced) rd.forced = fill(rd.need);
+        pd.stage_begin = (int)P.stages.size();
         pd.round_begin = (int)P.rounds.size();
+        pd.op_begin = (int)P.ops.size();
+        pd.job_begin = (int)P.jobs.size();
+        int rec = 0;
         for (auto &rd : rounds) {
-            // fill to RB bits: prefer the load-layout register bits, then the highest others
-            uint32_t m = rd.need;
-            for (int j = K - 1; j >= 0 && __builtin_popcount(m) < RB; --j)
-                if ((load_mask >> j) & 1u) m |= 1u << j;
-            for (int j = K - 1; j >= 0 && __builtin_popcount(m) < RB; --j) m |= 1u << j;
+            uint32_t m = rd.forced;
+            if (rd.stage_start) {
+                if (P.stages.size() > (size_t)pd.stage_begin) {
+                    StageDesc &prev = P.stages.back();
+                    prev.round_end = (int)P.rounds.size();
+                    prev.op_end = (int)P.ops.size();
+                    prev.rec_end = rec;
+                    prev.job_end = (int)P.jobs.size();
+                    prev.obits_end = (int)P.obits.size();
+                }
+                StageDesc sd{};
+                sd.round_begin = (int)P.rounds.size();
+                sd.op_begin = (int)P.ops.size();
+                sd.rec_begin = rec;
+                sd.job_begin = (int)P.jobs.size();
+                sd.obits_begin = (int)P.obits.size();
+                P.stages.push_back(sd);
+            }
             RoundDesc R{};
             R.reg_mask = m;
             R.op_begin = (int)P.ops.size();
-            int reg_index[32];
+            int reg_index[32], tid_index[32];
             {
-                int k = 0;
-                for (int j = 0; j < 32; ++j) reg_index[j] = ((m >> j) & 1u) ? k++ : -1;
-            }
-            auto classify = [&](int cond, int gate_idx) {
-                PhaseRef pr{};
-                pr.gate = gate_idx;
-                int j = local_of[cond];
-                if (j < 0) {
-                    pr.cls = PH_OUTER;
-                    pr.bit = cond;
-                } else if (reg_index[j] >= 0) {
-                    pr.cls = PH_REG;
-                    pr.bit = reg_index[j];
-                } else {
-                    pr.cls = PH_THREAD;
-                    pr.bit = j;
+                int k = 0, t = 0;
+                for (int j = 0; j < 32; ++j) {
+                    bool in = j < K && ((m >> j) & 1u);
+                    reg_index[j] = in ? k++ : -1;
+                    tid_index[j] = (j < K && !in) ? t++ : -1;
                 }
-                P.prefs.push_back(pr);
-            };
+            }
+            (void)kmask;
             for (int i : rd.ops) {
                 const PG &x = pg[i];
                 OpDesc op{};
                 op.gate = x.gate;
+                op.rec = rec;
+                op.pre_rec = op.post_rec = -1;
+                op.pre_job = op.post_job = -1;
+                op.pref_begin = (int)P.prefs.size();
                 if (x.kind == QS_G_U1) {
                     op.type = OP_U1;
                     op.p0 = reg_index[local_of[x.a]];
-                    op.pre_begin = (int)P.prefs.size();
-                    for (auto &at : pre[i]) classify(at.cond, at.gate);
-                    op.pre_end = (int)P.prefs.size();
-                    op.post_begin = (int)P.prefs.size();
-                    for (auto &at : post[i]) classify(at.cond, at.gate);
-                    op.post_end = (int)P.prefs.size();
+                    rec += 4;
+                    for (int post = 0; post < 2; ++post) {
+                        const auto &lst = post ? post_att : pre_att;
+                        const auto &att = lst[i];
+                        if (att.empty()) continue;
+                        int block = rec;
+                        int n_outer = 0;
+                        for (auto &at : att)
+                            if (local_of[at.cond] < 0) ++n_outer;
+                        rec += kPhaseTable + n_outer;
+                        if (post) op.post_rec = block; else op.pre_rec = block;
+                        int outer_k = 0;
+                        int bits_off = (int)P.obits.size();
+                        for (auto &at : att) {
+                            PrepRef pr{};
+                            pr.post = post;
+                            pr.gate = at.gate;
+                            int j = local_of[at.cond];
+                            if (j < 0) {
+                                pr.kind = PR_OUTER;
+                                pr.bit = at.cond;
+                                pr.slot_entry = block + kPhaseTable + outer_k++;
+                                P.obits.push_back(at.cond);
+                            } else if (reg_index[j] >= 0) {
+                                pr.kind = PR_REG;
+                                pr.bit = reg_index[j];
+                            } else {
+                                pr.kind = PR_THREAD;
+                                pr.bit = tid_index[j];
+                            }
+                            P.prefs.push_back(pr);
+                        }
+                        if (n_outer > 0) {
+                            OuterJob jb{};
+                            jb.op = (int)P.ops.size();
+                            jb.rec_off = block + kPhaseTable;
+                            jb.bits_off = bits_off;
+                            jb.n = n_outer;
+                            if (post) op.post_job = (int)P.jobs.size() - pd.job_begin;
+                            else op.pre_job = (int)P.jobs.size() - pd.job_begin;
+                            P.jobs.push_back(jb);
+                        }
+                    }
                 } else if (x.kind == QS_G_U2 || x.kind == QS_G_CNOT) {
                     op.type = OP_U2;
                     op.p0 = reg_index[local_of[x.a]];
                     op.p1 = reg_index[local_of[x.b]];
+                    rec += 16;
                 } else {
                     op.type = OP_DIAG;
                     uint64_t mask, value;
@@ -275,15 +379,31 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                     op.lvalue = lv;
                     op.omask = mask & pd.outer_mask;
                     op.ovalue = value & pd.outer_mask;
+                    rec += 1;
                 }
+                op.pref_end = (int)P.prefs.size();
                 P.ops.push_back(op);
             }
             R.op_end = (int)P.ops.size();
             P.rounds.push_back(R);
         }
+        {
+            StageDesc &last = P.stages.back();
+            last.round_end = (int)P.rounds.size();
+            last.op_end = (int)P.ops.size();
+            last.rec_end = rec;
+            last.job_end = (int)P.jobs.size();
+            last.obits_end = (int)P.obits.size();
+        }
+        pd.stage_end = (int)P.stages.size();
         pd.round_end = (int)P.rounds.size();
+        pd.op_end = (int)P.ops.size();
+        pd.job_end = (int)P.jobs.size();
+        pd.rec_size = rec;
+        max_rec = std::max(max_rec, rec);
         P.passes.push_back(pd);
     }
+    P.max_rec = max_rec;
     return QS_OK;
 }
 

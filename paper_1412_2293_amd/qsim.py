@@ -23,7 +23,7 @@ NOISE_NONE, NOISE_ROT, NOISE_PHASE = 0, 1, 2
 __all__ = ["QsimError", "lib", "Gate", "Noise", "Plan", "C64", "C128", "gate_array",
            "sv_bytes_required", "StateVector", "apply_gate", "apply_kraus", "fidelity",
            "dm_fidelity", "dm_apply_gate", "noise_draw", "traj_bytes_required", "run_trajectories",
-           "timing_enable", "timing_read", "timing_reset", "copy", "FixedRank",
+           "timing_enable", "timing_read", "plan_describe", "traj_layout", "timing_reset", "copy", "FixedRank", "trajectory_states",
            "fr_bytes_required", "LIB_PATH"]
 
 
@@ -81,6 +81,8 @@ def lib():
         "qs_run_trajectories": ([P, i32, i32, u64, i32, ctypes.POINTER(Noise), i32, i64,
                                  ctypes.POINTER(Plan), P, sz, P, P, P, P, P], st),
         "qs_timing_enable": ([i32], st),
+        "qs_traj_layout": ([P, i32, i32, i32, i32, ctypes.POINTER(Plan), P], st),
+        "qs_plan_describe": ([P, i32, i32, i32, ctypes.POINTER(Plan), ctypes.c_char_p, sz, P], st),
         "qs_timing_read": ([ctypes.c_char_p, P, P, P], st),
         "qs_timing_reset": ([], st),
         "qs_copy": ([P, P, sz, P], st),
@@ -300,6 +302,32 @@ def trajectory_states(res, n: int, dtype: int, n_traj: int):
     N = 1 << n
     nbytes = (n_traj + 1) * N * (8 if dtype == C64 else 16)
     return torch.view_as_complex(res["buf"][:nbytes].view(ft).view(n_traj + 1, N, 2))
+
+
+def traj_layout(gates, n: int, dtype: int, n_traj: int, plan=None) -> dict:
+    """Byte offsets of the regions of the run_trajectories buffer."""
+    ga = gates if isinstance(gates, ctypes.Array) else gate_array(gates)
+    p = _plan(plan)
+    out = np.zeros(15, np.uint64)
+    _check(lib().qs_traj_layout(ga, len(ga), n, dtype, n_traj, ctypes.byref(p) if p else None, _ptr(out)),
+           "traj_layout")
+    names = ["states", "tab", "gates", "edev", "passes", "stages", "rounds", "ops", "prefs", "jobs",
+             "obits", "rec", "partials", "out", "total"]
+    return {k: int(v) for k, v in zip(names, out)}
+
+
+def plan_describe(gates, n: int, dtype: int, plan=None) -> dict:
+    """The fused-pass program the library builds for this circuit (parsed JSON)."""
+    import json
+    ga = gates if isinstance(gates, ctypes.Array) else gate_array(gates)
+    p = _plan(plan)
+    ln = ctypes.c_size_t()
+    _check(lib().qs_plan_describe(ga, len(ga), n, dtype, ctypes.byref(p) if p else None, None, 0,
+                                  ctypes.byref(ln)), "plan_describe")
+    buf = ctypes.create_string_buffer(ln.value + 1)
+    _check(lib().qs_plan_describe(ga, len(ga), n, dtype, ctypes.byref(p) if p else None, buf,
+                                  ln.value + 1, ctypes.byref(ln)), "plan_describe")
+    return json.loads(buf.value.decode())
 
 
 def timing_enable(on: bool = True):

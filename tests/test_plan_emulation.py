@@ -1,0 +1,172 @@
+"""Host-side check of the fusion planner: the fused-pass program the library builds
+(qs_plan_describe) is executed tile by tile in numpy, with the same tile-local semantics as
+the GPU kernel (register rounds, folded controlled phases conditioned on register, thread or
+tile-number bits, diagonal ops, SWAP relabelling), and compared with the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1412_2293_amd as q
+from workloads import (CNOT, CP, FLIP, NOISE_PHASE, NOISE_ROT, SWAP, U1, U2, grover, qft,
+                       random_layers, random_mixed_circuit)
+
+CNOT4 = np.array([[1, 0, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0], [0, 1, 0, 0]], np.complex128)
+
+
+def gate_operators(circuit, e, seed, traj):
+    """Per gate: the operator the method applies in this trajectory (eq. 1, eq. 2)."""
+    sites = [g.site for g in circuit.gates]
+    xi = oracle.normals(seed, sites, [traj])[0] if e else np.zeros(len(sites))
+    ops = {}
+    for gi, g in enumerate(circuit.gates):
+        if g.kind == U1:
+            M = np.asarray(g.m, np.complex128)
+            if e and g.noise == NOISE_ROT:
+                a = e * xi[gi]
+                M = M @ np.array([[math.cos(a), math.sin(a)], [-math.sin(a), math.cos(a)]])
+            ops[gi] = M
+        elif g.kind == CP:
+            th = g.theta + (e * xi[gi] if e and g.noise == NOISE_PHASE else 0.0)
+            ops[gi] = np.exp(-1j * th)
+        elif g.kind == U2:
+            ops[gi] = np.asarray(g.m, np.complex128)
+        elif g.kind == CNOT:
+            ops[gi] = CNOT4
+    return ops
+
+
+def emulate(circuit, prog, e=0.0, seed=0, traj=0):
+    n = circuit.n
+    ops = gate_operators(circuit, e, seed, traj)
+    psi = np.zeros(1 << n, np.complex128)
+    psi[circuit.init_index] = 1.0
+    for pas in prog["passes"]:
+        qpos = pas["q_pos"]
+        K = len(qpos)
+        ar = np.arange(1 << K, dtype=np.int64)
+        loc = np.zeros(1 << K, np.int64)
+        for j, qb in enumerate(qpos):
+            loc |= ((ar >> j) & 1) << qb
+        obits = [b for b in range(n) if (pas["outer_mask"] >> b) & 1]
+        for tile in range(1 << (n - K)):
+            outer = 0
+            for k, b in enumerate(obits):
+                if (tile >> k) & 1:
+                    outer |= 1 << b
+            idx = outer | loc
+            v = psi[idx].copy()
+            for stage in pas["stages"]:
+                for rnd in stage["rounds"]:
+                    m = rnd["reg_mask"]
+                    regbits = [j for j in range(K) if (m >> j) & 1]
+                    tbits = [j for j in range(K) if not (m >> j) & 1]
+                    for op in rnd["ops"]:
+                        if op["type"] == 0:
+                            j = regbits[op["p0"]]
+                            l0 = ar[((ar >> j) & 1) == 0]
+                            l1 = l0 | (1 << j)
+                            w = [np.ones(l0.size, np.complex128), np.ones(l0.size, np.complex128)]
+                            for kind, post, bit, cpg in op["phases"]:
+                                if kind == 0:
+                                    cond = (l0 >> regbits[bit]) & 1
+                                elif kind == 1:
+                                    cond = (l0 >> tbits[bit]) & 1
+                                else:
+                                    cond = np.full(l0.size, (outer >> bit) & 1)
+                                w[post] = w[post] * np.where(cond == 1, ops[cpg], 1.0)
+                            M = ops[op["gate"]]
+                            x0, x1 = v[l0], v[l1] * w[0]
+                            v[l0] = M[0, 0] * x0 + M[0, 1] * x1
+                            v[l1] = (M[1, 0] * x0 + M[1, 1] * x1) * w[1]
+                        elif op["type"] == 1:
+                            j0, j1 = regbits[op["p0"]], regbits[op["p1"]]
+                            base = ar[(((ar >> j0) & 1) == 0) & (((ar >> j1) & 1) == 0)]
+                            quad = [base, base | (1 << j0), base | (1 << j1), base | (1 << j0) | (1 << j1)]
+                            x = np.stack([v[t] for t in quad])
+                            y = ops[op["gate"]] @ x
+                            for r in range(4):
+                                v[quad[r]] = y[r]
+                        else:
+                            if (outer & op["omask"]) != op["ovalue"]:
+                                continue
+                            f = -1.0 if op["diag_kind"] == 0 else ops[op["gate"]]
+                            sel = (ar & op["lmask"]) == op["lvalue"]
+                            v[sel] *= f
+            psi[idx] = v
+    return psi, prog["layout"]
+
+
+def unpermute(state, layout, n):
+    idx = np.arange(1 << n, dtype=np.int64)
+    phys = np.zeros_like(idx)
+    for qb in range(n):
+        phys |= ((idx >> qb) & 1) << int(layout[qb])
+    return state[phys]
+
+
+PLANS = [{"fuse": 1},
+         {"fuse": 1, "tile_bits": 4, "reg_bits": 2, "run_bits": 1},
+         {"fuse": 1, "tile_bits": 5, "reg_bits": 3, "run_bits": 2},
+         {"fuse": 1, "tile_bits": 6, "reg_bits": 2, "run_bits": 2},
+         {"fuse": 1, "tile_bits": 8, "reg_bits": 2, "run_bits": 2},
+         {"fuse": 1, "tile_bits": 7, "reg_bits": 4, "run_bits": 1}]
+
+
+def circuits():
+    yield random_mixed_circuit(7, 150, seed=1)
+    yield random_mixed_circuit(9, 120, seed=2)
+    yield random_mixed_circuit(11, 90, seed=311)
+    yield qft(8, seed=3)
+    yield grover(6, seed=4, iterations=3)
+    yield random_layers(8, 5, seed=5, pairing="random")
+
+
+@pytest.mark.parametrize("plan", PLANS, ids=lambda p: "-".join(f"{k}{v}" for k, v in p.items()))
+def test_planner_program_matches_oracle(plan):
+    for c in circuits():
+        if plan.get("tile_bits", 12) > c.n and plan.get("reg_bits", 3) > c.n:
+            continue
+        prog = q.plan_describe(c.gates, c.n, q.C128, plan)
+        for e, traj in ((0.0, 0), (0.2, 3)):
+            psi, layout = emulate(c, prog, e, seed=7, traj=traj)
+            ref = oracle.sv_run(c, e, seed=7, traj=traj)
+            err = np.linalg.norm(unpermute(psi, layout, c.n) - ref)
+            assert err < 1e-12, (c.name, plan, e, err)
+
+
+def test_stages_split_long_passes():
+    c = random_mixed_circuit(7, 400, seed=9)
+    prog = q.plan_describe(c.gates, 7, q.C64, {"fuse": 1})
+    assert len(prog["passes"]) == 1 and len(prog["passes"][0]["stages"]) > 2
+    psi, layout = emulate(c, prog, 0.1, seed=1, traj=2)
+    ref = oracle.sv_run(c, 0.1, seed=1, traj=2)
+    assert np.linalg.norm(unpermute(psi, layout, 7) - ref) < 1e-12
+
+
+def test_program_ranges_are_consistent():
+    """Every pass and stage covers its own contiguous slice of rounds, ops and outer jobs."""
+    for c in circuits():
+        for plan in PLANS:
+            if plan.get("tile_bits", 12) > c.n and plan.get("reg_bits", 3) > c.n:
+                continue
+            prog = q.plan_describe(c.gates, c.n, q.C64, plan)
+            op_at = round_at = job_at = 0
+            for pas in prog["passes"]:
+                assert pas["op_begin"] == op_at and pas["round_begin"] == round_at
+                assert pas["job_begin"] == job_at
+                rec_at = 0
+                for st in pas["stages"]:
+                    assert st["op_begin"] == op_at and st["round_begin"] == round_at
+                    assert st["job_begin"] == job_at and st["rec_begin"] == rec_at
+                    for rd in st["rounds"]:
+                        for op in rd["ops"]:
+                            assert op["rec"] >= rec_at
+                        op_at += len(rd["ops"])
+                        round_at += 1
+                    job_at = st["job_end"]
+                    rec_at = st["rec_end"]
+                    assert st["rec_end"] - st["rec_begin"] <= 4096
+                assert pas["op_end"] == op_at and pas["round_end"] == round_at
+                assert pas["job_end"] == job_at and pas["rec_size"] == rec_at
