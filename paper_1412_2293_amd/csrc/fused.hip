@@ -87,7 +87,7 @@ __device__ __forceinline__ void load_phases(PhaseSet<R, RB> &ps, const cxf<R> *_
     ps.any = present;
     if (!present) return;
 #pragma unroll
-    for (int k = 0; k < RB; ++k) ps.bit[k] = lrec[k];
+    for (int k = 0; k < RB; ++k) ps.bit[k] = grec[k];
     ps.w = mul(lrec[4 + (tid & 31u)], lrec[36 + ((tid >> 5) & 15u)]);
     if (job >= 0) ps.w = mul(ps.w, wout[job]);
 }
@@ -406,7 +406,7 @@ __global__ void __launch_bounds__(512, 4) k_fused(R *__restrict__ psi, int n, in
             if (rd.reg_mask != cur) exchange(rd.reg_mask);
             for (int oi = rd.op_begin; oi < rd.op_end; ++oi) {
                 const OpDesc op = prog.ops[oi];
-                const cxf<R> *orec = L.rec + (op.rec - sd.rec_begin);
+                const cxf<R> *__restrict__ orec = rec + op.rec;
                 if (op.type == OP_U1) {
                     cxf<R> m[4] = {orec[0], orec[1], orec[2], orec[3]};
                     PhaseSet<R, RB> pre, post;
