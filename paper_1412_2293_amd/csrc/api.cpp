@@ -493,8 +493,10 @@ qs_status resolve_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, in
     if (fuse == -1) fuse = 1;
     out.fused = fuse == 1;
     if (!out.fused) return QS_OK;
-    int K = (p && p->tile_bits > 0) ? p->tile_bits : 12;
-    int RB = (p && p->reg_bits > 0) ? p->reg_bits : 3;
+    // defaults: 2^12-amplitude tiles of 8 registers per thread (complex<float>), 2^11 of 4
+    // (complex<double>): the largest register tiles that stay out of scratch memory
+    int K = (p && p->tile_bits > 0) ? p->tile_bits : (dt == QS_C64 ? 12 : 11);
+    int RB = (p && p->reg_bits > 0) ? p->reg_bits : (dt == QS_C64 ? 3 : 2);
     int run = (p && p->run_bits > 0) ? p->run_bits : (dt == QS_C64 ? 4 : 3);
     if (K > kMaxTileBits) return fail(QS_EINVAL, "plan: tile_bits too large");
     if ((size_t(1) << std::min(K, n)) * amp_bytes(dt) > 160 * 1024)

@@ -135,6 +135,26 @@ __device__ __forceinline__ void apply_u1(cxf<R> (&a)[1 << RB], const cxf<R> (&m)
     }
 }
 
+// The same update with a real matrix (m[k].im == 0): half the multiplications.
+template <typename R, int RB, int P>
+__device__ __forceinline__ void apply_u1_real(cxf<R> (&a)[1 << RB], const cxf<R> (&m)[4],
+                                              const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
+{
+    const R m0 = m[0].re, m1 = m[1].re, m2 = m[2].re, m3 = m[3].re;
+#pragma unroll
+    for (int k = 0; k < (1 << (RB - 1)); ++k) {
+        const int r = pair_base<P>(k);
+        const int r1 = r | (1 << P);
+        cxf<R> x0 = a[r], x1 = a[r1];
+        if (pre.any) x1 = mul(pair_phase<R, RB, P>(pre, r), x1);
+        cxf<R> y0 = {m0 * x0.re + m1 * x1.re, m0 * x0.im + m1 * x1.im};
+        cxf<R> y1 = {m2 * x0.re + m3 * x1.re, m2 * x0.im + m3 * x1.im};
+        if (post.any) y1 = mul(pair_phase<R, RB, P>(post, r), y1);
+        a[r] = y0;
+        a[r1] = y1;
+    }
+}
+
 template <typename R, int RB, int P0, int P1>
 __device__ __forceinline__ void apply_u2(cxf<R> (&a)[1 << RB], const cxf<R> (&m)[16])
 {
@@ -160,9 +180,19 @@ __device__ __forceinline__ void apply_u2(cxf<R> (&a)[1 << RB], const cxf<R> (&m)
 }
 
 template <typename R, int RB>
-__device__ __forceinline__ void dispatch_u1(int p, cxf<R> (&a)[1 << RB], const cxf<R> (&m)[4],
+__device__ __forceinline__ void dispatch_u1(int p, bool real, cxf<R> (&a)[1 << RB], const cxf<R> (&m)[4],
                                             const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
+    if (real) {
+        switch (p) {
+        case 0: apply_u1_real<R, RB, 0>(a, m, pre, post); break;
+        case 1: if constexpr (RB > 1) apply_u1_real<R, RB, 1 % RB>(a, m, pre, post); break;
+        case 2: if constexpr (RB > 2) apply_u1_real<R, RB, 2 % RB>(a, m, pre, post); break;
+        case 3: if constexpr (RB > 3) apply_u1_real<R, RB, 3 % RB>(a, m, pre, post); break;
+        default: break;
+        }
+        return;
+    }
     switch (p) {
     case 0: apply_u1<R, RB, 0>(a, m, pre, post); break;
     case 1: if constexpr (RB > 1) apply_u1<R, RB, 1 % RB>(a, m, pre, post); break;
@@ -251,14 +281,11 @@ __global__ void k_pass_prep(int S, int op_begin, int n_ops, int rec_size, Progra
     }
 }
 
-// LDS of one block: the tile, then the staged op descriptors, rounds, records, per-tile outer
-// products and outer condition bits of the current stage.
-constexpr int kStageRounds = kStageOps;
+// LDS of one block: the tile, then the current stage's records, per-tile outer products and
+// outer condition bits.  Op and round descriptors are read with scalar loads.
 
 template <typename R>
 struct StageLds {
-    OpDesc *ops;
-    RoundDesc *rounds;
     cxf<R> *rec;
     cxf<R> *wout;
     int32_t *obits;
@@ -269,10 +296,6 @@ __device__ __forceinline__ StageLds<R> stage_lds(unsigned char *smem, int K, int
 {
     StageLds<R> L;
     size_t off = (size_t(1) << K) * sizeof(cxf<R>);
-    L.ops = reinterpret_cast<OpDesc *>(smem + off);
-    off += sizeof(OpDesc) * kStageOps;
-    L.rounds = reinterpret_cast<RoundDesc *>(smem + off);
-    off += sizeof(RoundDesc) * kStageRounds;
     L.rec = reinterpret_cast<cxf<R> *>(smem + off);
     off += sizeof(cxf<R>) * rec_cap;
     L.wout = reinterpret_cast<cxf<R> *>(smem + off);
@@ -360,20 +383,30 @@ __global__ void __launch_bounds__(512, 4) k_fused(R *__restrict__ psi, int n, in
         }
     }
 
+    // Register layout: tile-local index of register r of this thread = lthr | roff[r].  The
+    // load layout has the thread id in the low bits; rounds bring host-built tables.
     const uint32_t load_mask = (((1u << RB) - 1u) << TB) & kmask;
     uint32_t cur = load_mask;
     uint32_t roff[NR];
-    reg_offsets<RB>(cur, K, roff);
-    uint32_t lthr = deposit32(tid, ~cur & kmask, K);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) roff[r] = (uint32_t)r << TB;
+    uint32_t lthr = tid;
 
-    auto exchange = [&](uint32_t to) {
+    auto exchange_to = [&](uint32_t to, const RoundDesc *rd) {
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < NR; ++r) lds[swz(lthr | roff[r])] = a[r];
         __syncthreads();
         cur = to;
-        reg_offsets<RB>(cur, K, roff);
-        lthr = deposit32(tid, ~cur & kmask, K);
+        if (rd) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) roff[r] = rd->roff[r];
+            lthr = (uint32_t)rd->tlo[tid & 31u] | (uint32_t)rd->thi[(tid >> 5) & 15u];
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) roff[r] = (uint32_t)r << TB;
+            lthr = tid;
+        }
 #pragma unroll
         for (int r = 0; r < NR; ++r) a[r] = lds[swz(lthr | roff[r])];
     };
@@ -402,32 +435,36 @@ __global__ void __launch_bounds__(512, 4) k_fused(R *__restrict__ psi, int n, in
         const int job_shift = sd.job_begin - pd->job_begin;
 
         for (int ri = sd.round_begin; ri < sd.round_end; ++ri) {
-            const RoundDesc rd = prog.rounds[ri];
-            if (rd.reg_mask != cur) exchange(rd.reg_mask);
-            for (int oi = rd.op_begin; oi < rd.op_end; ++oi) {
-                const OpDesc op = prog.ops[oi];
-                const cxf<R> *__restrict__ orec = rec + op.rec;
-                if (op.type == OP_U1) {
+            const RoundDesc *rd = prog.rounds + ri;
+            const uint32_t mask = rd->reg_mask;
+            if (mask != cur) exchange_to(mask, rd);
+            const int oe = rd->op_end;
+            for (int oi = rd->op_begin; oi < oe; ++oi) {
+                const OpDesc *op = prog.ops + oi;
+                const int type = op->type;
+                const cxf<R> *__restrict__ orec = rec + op->rec;
+                if (type == OP_U1) {
                     cxf<R> m[4] = {orec[0], orec[1], orec[2], orec[3]};
                     PhaseSet<R, RB> pre, post;
-                    load_phases<R, RB>(pre, rec + op.pre_rec, L.rec + (op.pre_rec - sd.rec_begin),
-                                       op.pre_rec >= 0, op.pre_job < 0 ? -1 : op.pre_job - job_shift,
-                                       L.wout, tid);
-                    load_phases<R, RB>(post, rec + op.post_rec, L.rec + (op.post_rec - sd.rec_begin),
-                                       op.post_rec >= 0, op.post_job < 0 ? -1 : op.post_job - job_shift,
-                                       L.wout, tid);
-                    dispatch_u1<R, RB>(op.p0, a, m, pre, post);
-                } else if (op.type == OP_U2) {
+                    const int prer = op->pre_rec, postr = op->post_rec;
+                    const int prej = op->pre_job, postj = op->post_job;
+                    load_phases<R, RB>(pre, rec + prer, L.rec + (prer - sd.rec_begin), prer >= 0,
+                                       prej < 0 ? -1 : prej - job_shift, L.wout, tid);
+                    load_phases<R, RB>(post, rec + postr, L.rec + (postr - sd.rec_begin), postr >= 0,
+                                       postj < 0 ? -1 : postj - job_shift, L.wout, tid);
+                    dispatch_u1<R, RB>(op->p0, (op->flags & OPF_REAL) != 0, a, m, pre, post);
+                } else if (type == OP_U2) {
                     cxf<R> m[16];
 #pragma unroll
                     for (int k = 0; k < 16; ++k) m[k] = orec[k];
-                    dispatch_u2<R, RB>(op.p0, op.p1, a, m);
+                    dispatch_u2<R, RB>(op->p0, op->p1, a, m);
                 } else {
-                    if ((outer & op.omask) != op.ovalue) continue;
+                    if ((outer & op->omask) != op->ovalue) continue;
+                    const uint32_t lmask = op->lmask, lvalue = op->lvalue;
                     const cxf<R> f = orec[0];
 #pragma unroll
                     for (int r = 0; r < NR; ++r) {
-                        bool hit = ((lthr | roff[r]) & op.lmask) == op.lvalue;
+                        bool hit = ((lthr | roff[r]) & lmask) == lvalue;
                         cxf<R> y = mul(f, a[r]);
                         a[r].re = hit ? y.re : a[r].re;
                         a[r].im = hit ? y.im : a[r].im;
@@ -436,7 +473,7 @@ __global__ void __launch_bounds__(512, 4) k_fused(R *__restrict__ psi, int n, in
             }
         }
     }
-    if (cur != load_mask) exchange(load_mask);
+    if (cur != load_mask) exchange_to(load_mask, nullptr);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         uint64_t g = 0;
@@ -454,10 +491,11 @@ __global__ void __launch_bounds__(512, 4) k_fused(R *__restrict__ psi, int n, in
 
 static size_t stage_fixed_bytes(size_t cxs)
 {
-    return sizeof(OpDesc) * kStageOps + sizeof(RoundDesc) * kStageRounds + cxs * kStageJobs +
-           sizeof(int32_t) * kStageObits;
+    return cxs * kStageJobs + sizeof(int32_t) * kStageObits;
 }
 
+// Record entries staged per stage: 8 KiB of records, or less when the tile leaves less room
+// under 80 KiB (two blocks per CU) / 160 KiB (one block per CU).
 int stage_rec_cap(qs_dtype dt, int K)
 {
     const size_t cxs = dt == QS_C64 ? 8 : 16;
@@ -466,7 +504,8 @@ int stage_rec_cap(qs_dtype dt, int K)
     const size_t fixed = tile + stage_fixed_bytes(cxs);
     if (fixed >= budget) return 0;
     size_t cap = (budget - fixed) / cxs;
-    return (int)(cap > 4096 ? 4096 : cap);
+    const size_t want = 8192 / cxs;
+    return (int)(cap > want ? want : cap);
 }
 
 size_t fused_lds_bytes(qs_dtype dt, int K)

@@ -77,22 +77,30 @@ struct RoundDesc {
     int32_t op_begin;
     int32_t op_end;
     int32_t reserved;
+    uint16_t roff[16];            // tile-local offset of register r
+    uint16_t tlo[32];             // tile-local bits of thread-id bits 0..4, indexed by tid & 31
+    uint16_t thi[16];             // tile-local bits of thread-id bits 5..8, indexed by tid >> 5
 };
 
 enum OpType : int32_t { OP_U1 = 0, OP_U2 = 1, OP_DIAG = 2 };
 enum DiagKind : int32_t { DIAG_NEGATE = 0, DIAG_PHASE = 1 };
 enum PrepKind : int32_t { PR_REG = 0, PR_THREAD = 1, PR_OUTER = 2 };
 
+enum OpFlags : int32_t { OPF_REAL = 1 };   // the one-qubit matrix is real in every slot
+
 struct OpDesc {
     int32_t type;
     int32_t p0, p1;               // register-bit positions of the target(s)
-    int32_t gate;                 // gate index (noise-table row, matrix)
+    int32_t flags;
     int32_t rec;                  // record offset (complex entries) within the slot's block
     int32_t pre_rec, post_rec;    // phase blocks (-1: none)
-    int32_t pre_job, post_job;    // OuterJob index within the pass (-1: none)
+    int32_t pre_job;              // OuterJob index within the pass (-1: none)
+    int32_t post_job;
+    int32_t gate;                 // gate index (noise-table row, matrix)
     int32_t pref_begin, pref_end; // PrepRefs of this op
     int32_t diag_kind;
     uint32_t lmask, lvalue;       // DIAG: tile-local condition (l & lmask) == lvalue
+    uint32_t reserved;
     uint64_t omask, ovalue;       // DIAG: tile condition (outer index & omask) == ovalue
 };
 

@@ -289,6 +289,28 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
             RoundDesc R{};
             R.reg_mask = m;
             R.op_begin = (int)P.ops.size();
+            {
+                std::vector<int> regpos, tpos;
+                for (int j = 0; j < K; ++j) ((m >> j) & 1u ? regpos : tpos).push_back(j);
+                for (int r = 0; r < 16; ++r) {
+                    uint32_t o = 0;
+                    for (int k = 0; k < (int)regpos.size(); ++k)
+                        if ((r >> k) & 1) o |= 1u << regpos[k];
+                    R.roff[r] = (uint16_t)o;
+                }
+                for (int x = 0; x < 32; ++x) {
+                    uint32_t o = 0;
+                    for (int b = 0; b < 5 && b < (int)tpos.size(); ++b)
+                        if ((x >> b) & 1) o |= 1u << tpos[b];
+                    R.tlo[x] = (uint16_t)o;
+                }
+                for (int y = 0; y < 16; ++y) {
+                    uint32_t o = 0;
+                    for (int b = 0; b < 4 && 5 + b < (int)tpos.size(); ++b)
+                        if ((y >> b) & 1) o |= 1u << tpos[5 + b];
+                    R.thi[y] = (uint16_t)o;
+                }
+            }
             int reg_index[32], tid_index[32];
             {
                 int k = 0, t = 0;
@@ -310,6 +332,13 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                 if (x.kind == QS_G_U1) {
                     op.type = OP_U1;
                     op.p0 = reg_index[local_of[x.a]];
+                    {
+                        // U V(e xi) is real whenever U is: V of eq. (1) is a real rotation
+                        bool real = true;
+                        for (int k = 1; k < 8; k += 2)
+                            if (gates[x.gate].m[k] != 0.0) real = false;
+                        if (real) op.flags |= OPF_REAL;
+                    }
                     rec += 4;
                     for (int post = 0; post < 2; ++post) {
                         const auto &lst = post ? post_att : pre_att;
