@@ -227,15 +227,17 @@ def sweeps(q):
     return out
 
 
-def cpu_baseline(c, prefix=40):
-    """The CPU oracle, single thread, on a bounded sample of the workload: the first `prefix`
-    gates of one noisy trajectory (e = 0.01) of the same circuit, run as one oracle call."""
+def cpu_baseline(c, prefix=None):
+    """The CPU oracle, single thread, on a bounded sample of the workload: one noisy trajectory
+    (e = 0.01) of the same circuit (all gates unless `prefix` is given), run as one oracle
+    call (about 15 s on one host core)."""
     import oracle
     from workloads import Circuit
     log("[bench] cpu baseline (oracle, 1 thread)")
     oracle.lib()
     n = c.n
     N = 1 << n
+    prefix = len(c.gates) if prefix is None else prefix
     part = Circuit(n, c.gates[:prefix], init_index=c.init_index)
     updates = sum({0: N, 1: N // 4, 2: N // 2}.get(g.kind, N) for g in part.gates)
     t0 = time.perf_counter()
