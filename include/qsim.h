@@ -249,6 +249,78 @@ qs_status qs_fr_fidelity(qs_fr fr, qs_state psi, int tpsi, double *f_unnorm, dou
 /* Current rank; columns (device pointer of column 0, columns 2^n amplitudes apart). */
 qs_status qs_fr_info(qs_fr fr, int *rank, double *log_trace, void **columns_dev);
 
+/* ------------------------------------------------------------------------------------------
+ * Request server: continuous batching of Monte Carlo trajectory requests (Section 2's method,
+ * run for many independent circuits) on one GPU.  Not described in the paper; a serving form
+ * of qs_run_trajectories.
+ *
+ * The caller hands over one device pool (never freed by the library).  A request is validated
+ * and planned in qs_srv_submit, then cut into trajectory batches of one size (at most
+ * max_chunk_traj, halved until one batch fits the pool).  A worker thread admits batches in
+ * arrival order whenever one of max_inflight streams is idle and the pool has a free range
+ * large enough for the batch (first fit, 256-byte granules); the bytes in use never exceed
+ * the pool.  Batches run on their own streams (default priority), so requests overlap on the
+ * device and a request that arrives while others run starts as soon as a stream and memory
+ * free up.  Each trajectory's result depends only on (circuit, noise, its trajectory index
+ * traj_base + t, dtype, plan): it is bit for bit the qs_run_trajectories result, alone or in
+ * any mix.  All functions are thread-safe.  Times are seconds since qs_srv_create on a
+ * monotonic clock.
+ * ---------------------------------------------------------------------------------------- */
+typedef struct qs_srv_s *qs_srv;
+
+typedef struct {
+    int32_t dtype;          /* qs_dtype of every request */
+    int32_t max_inflight;   /* batches on the device at once (one stream each), 1..16 */
+    int32_t max_chunk_traj; /* largest trajectory batch, <= 4096; <= 0 means 256 */
+    int32_t reserved;
+    qs_plan plan;           /* plan of every request, as in qs_run_trajectories */
+} qs_srv_config;
+
+typedef struct {
+    int32_t status;         /* QS_OK, or the error that ended the request */
+    int32_t n_chunks;       /* batches launched */
+    int32_t chunk_traj;     /* trajectories per batch (the last may be fewer) */
+    int32_t reserved;
+    uint64_t chunk_bytes;   /* pool bytes one batch holds */
+    double t_submit, t_admit, t_done;
+    double latency_s;       /* t_done - t_submit */
+    double queue_s;         /* t_admit - t_submit: wait for a stream and memory */
+} qs_srv_job_info;
+
+typedef struct {
+    uint64_t submitted, completed, failed;
+    uint64_t trajectories;     /* trajectories finished */
+    uint64_t chunks;           /* batches launched */
+    uint64_t admission_waits;  /* times the queue head found no free range large enough */
+    uint64_t pool_bytes, peak_bytes, in_use_bytes;
+    int32_t peak_inflight, inflight, queued, reserved;
+    double busy_s;             /* time with at least one batch on the device */
+    double elapsed_s;
+} qs_srv_stats;
+
+/* Start a server over pool[0, pool_bytes) (device memory, 256-byte aligned) on the pool's
+ * device.  Creates max_inflight streams, events and pinned result buffers. */
+qs_status qs_srv_create(const qs_srv_config *cfg, void *pool, size_t pool_bytes, qs_srv *out);
+/* Queue one request: arguments as in qs_run_trajectories (gates, noise and e_per_traj are
+ * copied).  Returns QS_ENOMEM when one trajectory does not fit the pool.  *job_out gets the
+ * request id. */
+qs_status qs_srv_submit(qs_srv srv, const qs_gate *gates, int n_gates, int n_qubits,
+                        uint64_t init_index, const qs_noise *nz, int n_traj, int64_t marked,
+                        uint64_t *job_out);
+/* *done = 1 once every batch of the request has finished (or it failed). */
+qs_status qs_srv_poll(qs_srv srv, uint64_t job, int *done);
+/* Block until the request has finished; timeout_s < 0 waits without limit, else QS_EBUSY on
+ * timeout. */
+qs_status qs_srv_wait(qs_srv srv, uint64_t job, double timeout_s);
+/* Results of a finished request (host arrays of n_traj doubles, each nullable; p_out needs
+ * marked >= 0), and its timing; releases the request id.  Returns the request's error if it
+ * failed (info is filled either way). */
+qs_status qs_srv_result(qs_srv srv, uint64_t job, double *fid_out, double *p_out, double *norm_out,
+                        qs_srv_job_info *info);
+qs_status qs_srv_stats_get(qs_srv srv, qs_srv_stats *out);
+/* Finish every queued request, then release streams, events and pinned buffers. */
+qs_status qs_srv_destroy(qs_srv srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,6 +1,7 @@
 // C ABI of libqsim: argument validation, buffer layout, launch orchestration, kernel timing,
 // and the host side of the fixed-rank step (FP64 Jacobi eigen-decomposition).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -41,7 +42,7 @@ struct TimingRecord {
 };
 
 static std::mutex g_tmu;
-static bool g_timing = false;
+static std::atomic<bool> g_timing{false};
 static std::vector<TimingRecord> g_pending;
 struct Acc {
     int64_t n = 0;
@@ -117,7 +118,6 @@ struct qs_fr_s {
 
 static size_t state_bytes(int n, qs_dtype dt, int T) { return ((size_t)T << n) * amp_bytes(dt); }
 
-static bool aligned256(const void *p) { return ((uintptr_t)p & 255u) == 0; }
 
 extern "C" {
 
@@ -556,6 +556,167 @@ qs_status check_circuit(const qs_gate *gates, int n_gates, int n)
 
 }  // namespace
 
+namespace qs {
+
+qs_status traj_prepare(const qs_gate *gates, int n_gates, int n, qs_dtype dt, const qs_plan *plan,
+                       TrajPrep &prep)
+{
+    if (n < 1 || n > 34) return fail(QS_EINVAL, "run_trajectories: n_qubits must be in 1..34");
+    if (dt != QS_C64 && dt != QS_C128) return fail(QS_EINVAL, "run_trajectories: unknown dtype");
+    qs_status v = check_circuit(gates, n_gates, n);
+    if (v != QS_OK) return v;
+    Plan pl;
+    if ((v = resolve_plan(gates, n_gates, n, dt, 1, plan, pl)) != QS_OK) return v;
+    prep.n = n;
+    prep.dt = dt;
+    prep.fused = pl.fused;
+    prep.K = pl.K;
+    prep.RB = pl.RB;
+    prep.prog = std::move(pl.prog);
+    // device copy of the gates; CNOTs carry their permutation matrix for fused U2 ops
+    prep.hg.assign(gates, gates + n_gates);
+    for (auto &g : prep.hg)
+        if (g.kind == QS_G_CNOT) std::memcpy(g.m, kCnot4, sizeof kCnot4);
+    prep.layout.resize(n);
+    for (int q = 0; q < n; ++q) prep.layout[q] = prep.fused ? prep.prog.layout[q] : q;
+    return QS_OK;
+}
+
+static TrajLayout prep_layout(const TrajPrep &prep, int T)
+{
+    Plan pl;
+    pl.fused = prep.fused;
+    // only the table sizes of the program enter the layout
+    pl.prog.passes.resize(prep.prog.passes.size());
+    pl.prog.stages.resize(prep.prog.stages.size());
+    pl.prog.rounds.resize(prep.prog.rounds.size());
+    pl.prog.ops.resize(prep.prog.ops.size());
+    pl.prog.prefs.resize(prep.prog.prefs.size());
+    pl.prog.jobs.resize(prep.prog.jobs.size());
+    pl.prog.obits.resize(prep.prog.obits.size());
+    pl.prog.max_rec = prep.prog.max_rec;
+    return traj_layout(prep.n, prep.dt, T, (int)prep.hg.size(), pl);
+}
+
+size_t traj_prep_bytes(const TrajPrep &prep, int T)
+{
+    return T < 1 ? 0 : prep_layout(prep, T).total;
+}
+
+qs_status traj_launch(const TrajPrep &prep, uint64_t init_index, const qs_noise *nz, int T, int64_t marked,
+                      void *dev_buf, size_t buf_bytes, hipStream_t st, double *host_out, TrajRun &run)
+{
+    const int n = prep.n;
+    const qs_dtype dt = prep.dt;
+    const int n_gates = (int)prep.hg.size();
+    if (T < 1) return fail(QS_EINVAL, "run_trajectories: n_traj must be >= 1");
+    if (init_index >= (1ull << n)) return fail(QS_EINVAL, "run_trajectories: init_index out of range");
+    if (marked >= (int64_t)(1ull << n)) return fail(QS_EINVAL, "run_trajectories: marked out of range");
+    if (!dev_buf || !aligned256(dev_buf))
+        return fail(QS_EINVAL, "run_trajectories: buffer must be non-NULL and 256-byte aligned");
+    qs_status v = check_noise(nz, T);
+    if (v != QS_OK) return v;
+    TrajLayout L = prep_layout(prep, T);
+    if (buf_bytes < L.total)
+        return fail(QS_EINVAL, "run_trajectories: buffer too small (need " + std::to_string(L.total) + " bytes)");
+
+    char *B = (char *)dev_buf;
+    const int S = T + 1;
+    void *psi = B + L.states;
+    double *tab = (double *)(B + L.tab);
+    qs_gate *gdev = (qs_gate *)(B + L.gates);
+    double *edev = (double *)(B + L.edev);
+    run.T = T;
+    run.he.assign(S, 0.0);
+    for (int t = 0; t < T; ++t) run.he[t + 1] = nz ? (nz->e_per_traj ? nz->e_per_traj[t] : nz->e) : 0.0;
+    if (n_gates > 0)
+        QS_HIP(hipMemcpyAsync(gdev, prep.hg.data(), sizeof(qs_gate) * n_gates, hipMemcpyHostToDevice, st));
+    QS_HIP(hipMemcpyAsync(edev, run.he.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
+    const Program &P = prep.prog;
+    if (prep.fused) {
+        if (!P.passes.empty())
+            QS_HIP(hipMemcpyAsync(B + L.passes, P.passes.data(), sizeof(PassDesc) * P.passes.size(), hipMemcpyHostToDevice, st));
+        if (!P.stages.empty())
+            QS_HIP(hipMemcpyAsync(B + L.stages, P.stages.data(), sizeof(StageDesc) * P.stages.size(), hipMemcpyHostToDevice, st));
+        if (!P.rounds.empty())
+            QS_HIP(hipMemcpyAsync(B + L.rounds, P.rounds.data(), sizeof(RoundDesc) * P.rounds.size(), hipMemcpyHostToDevice, st));
+        if (!P.ops.empty())
+            QS_HIP(hipMemcpyAsync(B + L.ops, P.ops.data(), sizeof(OpDesc) * P.ops.size(), hipMemcpyHostToDevice, st));
+        if (!P.prefs.empty())
+            QS_HIP(hipMemcpyAsync(B + L.prefs, P.prefs.data(), sizeof(PrepRef) * P.prefs.size(), hipMemcpyHostToDevice, st));
+        if (!P.jobs.empty())
+            QS_HIP(hipMemcpyAsync(B + L.jobs, P.jobs.data(), sizeof(OuterJob) * P.jobs.size(), hipMemcpyHostToDevice, st));
+        if (!P.obits.empty())
+            QS_HIP(hipMemcpyAsync(B + L.obits, P.obits.data(), sizeof(int32_t) * P.obits.size(), hipMemcpyHostToDevice, st));
+    }
+    NoiseArgs na{};
+    na.e = 0.0;
+    na.e_dev = edev;
+    na.seed = nz ? nz->seed : 0;
+    na.request = nz ? nz->request : 0;
+    na.traj_base = nz ? nz->traj_base : 0;
+    na.first_noisy_slot = 1;
+    QS_HIP(launch_noise_table(gdev, n_gates, S, na, tab, st));
+    QS_HIP(launch_init_basis(psi, dt, n, S, init_index, st));
+    if (prep.fused) {
+        ProgramDev pdv{(const PassDesc *)(B + L.passes), (const StageDesc *)(B + L.stages),
+                       (const RoundDesc *)(B + L.rounds), (const OpDesc *)(B + L.ops),
+                       (const PrepRef *)(B + L.prefs), (const OuterJob *)(B + L.jobs),
+                       (const int32_t *)(B + L.obits)};
+        for (size_t p = 0; p < P.passes.size(); ++p) {
+            QS_HIP(launch_pass_prep(dt, S, &P.passes[p], pdv, tab, gdev, B + L.rec, st));
+            QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (int)p, pdv, B + L.rec, st));
+        }
+    } else {
+        for (int g = 0; g < n_gates; ++g) {
+            const qs_gate &G = prep.hg[g];
+            const double *row = tab + (size_t)g * S * 8;
+            switch (G.kind) {
+            case QS_G_U1: QS_HIP(launch_sweep_u1(psi, dt, n, S, G.q0, row, st)); break;
+            case QS_G_CP: QS_HIP(launch_sweep_cp(psi, dt, n, S, G.q0, G.q1, row, st)); break;
+            case QS_G_SWAP:
+            case QS_G_CNOT: QS_HIP(launch_sweep_perm(psi, dt, n, S, G.kind, G.q0, G.q1, st)); break;
+            case QS_G_U2: QS_HIP(launch_sweep_2q(psi, dt, n, S, G.q0, G.q1, G.m, st)); break;
+            case QS_G_FLIP: QS_HIP(launch_flip(psi, dt, n, S, G.mask, G.value, st)); break;
+            }
+        }
+    }
+    int64_t pmarked = -1;
+    if (marked >= 0) {
+        pmarked = 0;
+        for (int q = 0; q < n; ++q)
+            if ((marked >> q) & 1) pmarked |= (int64_t)1 << prep.layout[q];
+    }
+    double *part = (double *)(B + L.partials);
+    double *out = (double *)(B + L.out);
+    QS_HIP(launch_overlaps(psi, 0, psi, dt, n, S, pmarked, part, out, st));
+    if (host_out) {
+        run.host = host_out;
+    } else {
+        run.host_own.resize((size_t)S * 5);
+        run.host = run.host_own.data();
+    }
+    QS_HIP(hipMemcpyAsync(run.host, out, sizeof(double) * S * 5, hipMemcpyDeviceToHost, st));
+    return QS_OK;
+}
+
+void traj_finalize(const TrajPrep &prep, const TrajRun &run, double *fid_out, double *p_out, double *norm_out,
+                   int32_t *layout_out)
+{
+    const double *h = run.host;
+    const double n0 = h[2];
+    for (int t = 0; t < run.T; ++t) {
+        const double *o = &h[(size_t)(t + 1) * 5];
+        if (fid_out) fid_out[t] = (o[0] * o[0] + o[1] * o[1]) / (n0 * o[2]);
+        if (p_out) p_out[t] = o[3] * o[3] + o[4] * o[4];
+        if (norm_out) norm_out[t] = o[2];
+    }
+    if (layout_out)
+        for (int q = 0; q < prep.n; ++q) layout_out[q] = prep.layout[q];
+}
+
+}  // namespace qs
+
 extern "C" {
 
 size_t qs_traj_bytes_required(const qs_gate *gates, int n_gates, int n, qs_dtype dt, int T,
@@ -681,113 +842,18 @@ qs_status qs_run_trajectories(const qs_gate *gates, int n_gates, int n, uint64_t
                               double *p_out, double *norm_out, int32_t *layout_out)
 {
     clear_error();
-    if (n < 1 || n > 34) return fail(QS_EINVAL, "run_trajectories: n_qubits must be in 1..34");
-    if (dt != QS_C64 && dt != QS_C128) return fail(QS_EINVAL, "run_trajectories: unknown dtype");
-    if (T < 1) return fail(QS_EINVAL, "run_trajectories: n_traj must be >= 1");
     if (!fid_out) return fail(QS_EINVAL, "run_trajectories: fid_out is NULL");
-    if (init_index >= (1ull << n)) return fail(QS_EINVAL, "run_trajectories: init_index out of range");
-    if (marked >= (int64_t)(1ull << n)) return fail(QS_EINVAL, "run_trajectories: marked out of range");
     if (p_out && marked < 0) return fail(QS_EINVAL, "run_trajectories: p_out needs marked >= 0");
-    if (!dev_buf || !aligned256(dev_buf))
-        return fail(QS_EINVAL, "run_trajectories: buffer must be non-NULL and 256-byte aligned");
-    qs_status v = check_circuit(gates, n_gates, n);
+    if (T < 1) return fail(QS_EINVAL, "run_trajectories: n_traj must be >= 1");
+    qs::TrajPrep prep;
+    qs_status v = qs::traj_prepare(gates, n_gates, n, dt, plan, prep);
     if (v != QS_OK) return v;
-    if ((v = check_noise(nz, T)) != QS_OK) return v;
-    Plan pl;
-    if ((v = resolve_plan(gates, n_gates, n, dt, T, plan, pl)) != QS_OK) return v;
-    TrajLayout L = traj_layout(n, dt, T, n_gates, pl);
-    if (buf_bytes < L.total)
-        return fail(QS_EINVAL, "run_trajectories: buffer too small (need " + std::to_string(L.total) + " bytes)");
-
-    hipStream_t st = (hipStream_t)hip_stream;
-    char *B = (char *)dev_buf;
-    const int S = T + 1;
-    void *psi = B + L.states;
-    double *tab = (double *)(B + L.tab);
-    qs_gate *gdev = (qs_gate *)(B + L.gates);
-    double *edev = (double *)(B + L.edev);
-
-    // device copy of the gates; CNOTs carry their permutation matrix for fused U2 ops
-    std::vector<qs_gate> hg(gates, gates + n_gates);
-    for (auto &g : hg)
-        if (g.kind == QS_G_CNOT) std::memcpy(g.m, kCnot4, sizeof kCnot4);
-    std::vector<double> he(S, 0.0);
-    for (int t = 0; t < T; ++t) he[t + 1] = nz ? (nz->e_per_traj ? nz->e_per_traj[t] : nz->e) : 0.0;
-    if (n_gates > 0) QS_HIP(hipMemcpyAsync(gdev, hg.data(), sizeof(qs_gate) * n_gates, hipMemcpyHostToDevice, st));
-    QS_HIP(hipMemcpyAsync(edev, he.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
-    const Program &P = pl.prog;
-    if (pl.fused) {
-        if (!P.passes.empty())
-            QS_HIP(hipMemcpyAsync(B + L.passes, P.passes.data(), sizeof(PassDesc) * P.passes.size(), hipMemcpyHostToDevice, st));
-        if (!P.stages.empty())
-            QS_HIP(hipMemcpyAsync(B + L.stages, P.stages.data(), sizeof(StageDesc) * P.stages.size(), hipMemcpyHostToDevice, st));
-        if (!P.rounds.empty())
-            QS_HIP(hipMemcpyAsync(B + L.rounds, P.rounds.data(), sizeof(RoundDesc) * P.rounds.size(), hipMemcpyHostToDevice, st));
-        if (!P.ops.empty())
-            QS_HIP(hipMemcpyAsync(B + L.ops, P.ops.data(), sizeof(OpDesc) * P.ops.size(), hipMemcpyHostToDevice, st));
-        if (!P.prefs.empty())
-            QS_HIP(hipMemcpyAsync(B + L.prefs, P.prefs.data(), sizeof(PrepRef) * P.prefs.size(), hipMemcpyHostToDevice, st));
-        if (!P.jobs.empty())
-            QS_HIP(hipMemcpyAsync(B + L.jobs, P.jobs.data(), sizeof(OuterJob) * P.jobs.size(), hipMemcpyHostToDevice, st));
-        if (!P.obits.empty())
-            QS_HIP(hipMemcpyAsync(B + L.obits, P.obits.data(), sizeof(int32_t) * P.obits.size(), hipMemcpyHostToDevice, st));
-    }
-    NoiseArgs na{};
-    na.e = 0.0;
-    na.e_dev = edev;
-    na.seed = nz ? nz->seed : 0;
-    na.request = nz ? nz->request : 0;
-    na.traj_base = nz ? nz->traj_base : 0;
-    na.first_noisy_slot = 1;
-    QS_HIP(launch_noise_table(gdev, n_gates, S, na, tab, st));
-    QS_HIP(launch_init_basis(psi, dt, n, S, init_index, st));
-
-    if (pl.fused) {
-        ProgramDev pdv{(const PassDesc *)(B + L.passes), (const StageDesc *)(B + L.stages),
-                       (const RoundDesc *)(B + L.rounds),
-                       (const OpDesc *)(B + L.ops), (const PrepRef *)(B + L.prefs),
-                       (const OuterJob *)(B + L.jobs), (const int32_t *)(B + L.obits)};
-        for (size_t p = 0; p < P.passes.size(); ++p) {
-            QS_HIP(launch_pass_prep(dt, S, &P.passes[p], pdv, tab, gdev, B + L.rec, st));
-            QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (int)p, pdv, B + L.rec, st));
-        }
-    } else {
-        for (int g = 0; g < n_gates; ++g) {
-            const qs_gate &G = gates[g];
-            const double *row = tab + (size_t)g * S * 8;
-            switch (G.kind) {
-            case QS_G_U1: QS_HIP(launch_sweep_u1(psi, dt, n, S, G.q0, row, st)); break;
-            case QS_G_CP: QS_HIP(launch_sweep_cp(psi, dt, n, S, G.q0, G.q1, row, st)); break;
-            case QS_G_SWAP:
-            case QS_G_CNOT: QS_HIP(launch_sweep_perm(psi, dt, n, S, G.kind, G.q0, G.q1, st)); break;
-            case QS_G_U2: QS_HIP(launch_sweep_2q(psi, dt, n, S, G.q0, G.q1, G.m, st)); break;
-            case QS_G_FLIP: QS_HIP(launch_flip(psi, dt, n, S, G.mask, G.value, st)); break;
-            }
-        }
-    }
-    std::vector<int32_t> layout(n);
-    for (int q = 0; q < n; ++q) layout[q] = pl.fused ? P.layout[q] : q;
-    int64_t pmarked = -1;
-    if (marked >= 0) {
-        pmarked = 0;
-        for (int q = 0; q < n; ++q)
-            if ((marked >> q) & 1) pmarked |= (int64_t)1 << layout[q];
-    }
-    double *part = (double *)(B + L.partials);
-    double *out = (double *)(B + L.out);
-    QS_HIP(launch_overlaps(psi, 0, psi, dt, n, S, pmarked, part, out, st));
-    std::vector<double> h((size_t)S * 5);
-    QS_HIP(hipMemcpyAsync(h.data(), out, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
-    QS_HIP(hipStreamSynchronize(st));
-    const double n0 = h[2];
-    for (int t = 0; t < T; ++t) {
-        const double *o = &h[(size_t)(t + 1) * 5];
-        fid_out[t] = (o[0] * o[0] + o[1] * o[1]) / (n0 * o[2]);
-        if (p_out) p_out[t] = o[3] * o[3] + o[4] * o[4];
-        if (norm_out) norm_out[t] = o[2];
-    }
-    if (layout_out)
-        for (int q = 0; q < n; ++q) layout_out[q] = layout[q];
+    qs::TrajRun run;
+    if ((v = qs::traj_launch(prep, init_index, nz, T, marked, dev_buf, buf_bytes, (hipStream_t)hip_stream,
+                             nullptr, run)) != QS_OK)
+        return v;
+    QS_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
+    qs::traj_finalize(prep, run, fid_out, p_out, norm_out, layout_out);
     return QS_OK;
 }
 

@@ -225,7 +225,37 @@ struct Program {
 qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, int run_bits,
                      int rec_cap, Program &out);
 
+// A circuit validated and planned once; every batch of its trajectories reuses it.  The host
+// arrays stay alive while any batch that copies from them is in flight.
+struct TrajPrep {
+    int n = 0;
+    qs_dtype dt = QS_C64;
+    bool fused = false;
+    int K = 0, RB = 0;
+    Program prog;
+    std::vector<qs_gate> hg;       // device image of the gates (CNOT carries its 4x4 matrix)
+    std::vector<int32_t> layout;   // logical qubit -> physical bit after the SWAP relabelling
+};
+
+// One enqueued batch: `host` receives S*5 doubles (per slot: Re and Im of the overlap with the
+// ideal slot, squared norm, Re and Im of the marked amplitude) when the stream reaches the copy.
+struct TrajRun {
+    int T = 0;
+    std::vector<double> he;
+    double *host = nullptr;
+    std::vector<double> host_own;
+};
+
+qs_status traj_prepare(const qs_gate *gates, int n_gates, int n, qs_dtype dt, const qs_plan *plan,
+                       TrajPrep &prep);
+size_t traj_prep_bytes(const TrajPrep &prep, int T);
+qs_status traj_launch(const TrajPrep &prep, uint64_t init_index, const qs_noise *nz, int T, int64_t marked,
+                      void *dev_buf, size_t buf_bytes, hipStream_t st, double *host_out, TrajRun &run);
+void traj_finalize(const TrajPrep &prep, const TrajRun &run, double *fid_out, double *p_out, double *norm_out,
+                   int32_t *layout_out);
+
 inline size_t amp_bytes(qs_dtype dt) { return dt == QS_C64 ? 8 : 16; }
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+inline bool aligned256(const void *p) { return ((uintptr_t)p & 255u) == 0; }
 
 }  // namespace qs

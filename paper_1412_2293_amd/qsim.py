@@ -24,7 +24,7 @@ __all__ = ["QsimError", "lib", "Gate", "Noise", "Plan", "C64", "C128", "gate_arr
            "sv_bytes_required", "StateVector", "apply_gate", "apply_kraus", "fidelity",
            "dm_fidelity", "dm_apply_gate", "noise_draw", "traj_bytes_required", "run_trajectories",
            "timing_enable", "timing_read", "plan_describe", "traj_layout", "timing_reset", "copy", "FixedRank", "trajectory_states",
-           "fr_bytes_required", "LIB_PATH"]
+           "fr_bytes_required", "Server", "SrvConfig", "SrvJobInfo", "SrvStats", "LIB_PATH"]
 
 
 class QsimError(RuntimeError):
@@ -46,6 +46,27 @@ class Noise(ctypes.Structure):
 class Plan(ctypes.Structure):
     _fields_ = [("fuse", ctypes.c_int32), ("tile_bits", ctypes.c_int32),
                 ("reg_bits", ctypes.c_int32), ("run_bits", ctypes.c_int32)]
+
+
+class SrvConfig(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("max_chunk_traj", ctypes.c_int32), ("reserved", ctypes.c_int32), ("plan", Plan)]
+
+
+class SrvJobInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_chunks", ctypes.c_int32), ("chunk_traj", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("chunk_bytes", ctypes.c_uint64), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("latency_s", ctypes.c_double),
+                ("queue_s", ctypes.c_double)]
+
+
+class SrvStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("trajectories", ctypes.c_uint64), ("chunks", ctypes.c_uint64),
+                ("admission_waits", ctypes.c_uint64), ("pool_bytes", ctypes.c_uint64),
+                ("peak_bytes", ctypes.c_uint64), ("in_use_bytes", ctypes.c_uint64),
+                ("peak_inflight", ctypes.c_int32), ("inflight", ctypes.c_int32), ("queued", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("busy_s", ctypes.c_double), ("elapsed_s", ctypes.c_double)]
 
 
 _lib = None
@@ -94,6 +115,13 @@ def lib():
         "qs_fr_apply_kraus": ([P, i32, i32, P, dbl, dbl, P], st),
         "qs_fr_fidelity": ([P, P, i32, P, P, P], st),
         "qs_fr_info": ([P, P, P, P], st),
+        "qs_srv_create": ([ctypes.POINTER(SrvConfig), P, sz, ctypes.POINTER(P)], st),
+        "qs_srv_submit": ([P, P, i32, i32, u64, ctypes.POINTER(Noise), i32, i64, ctypes.POINTER(u64)], st),
+        "qs_srv_poll": ([P, u64, ctypes.POINTER(ctypes.c_int)], st),
+        "qs_srv_wait": ([P, u64, dbl], st),
+        "qs_srv_result": ([P, u64, P, P, P, ctypes.POINTER(SrvJobInfo)], st),
+        "qs_srv_stats_get": ([P, ctypes.POINTER(SrvStats)], st),
+        "qs_srv_destroy": ([P], st),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -417,3 +445,86 @@ class FixedRank:
         N = 1 << self.n
         return torch.view_as_complex(self.buf[: fr_bytes_required(self.n, self.r, self.dtype)]
                                      .view(ft).view(self.r, N, 2))
+
+
+# ------------------------------------------------------------------------------------------
+def _struct_dict(x) -> dict:
+    return {name: getattr(x, name) for name, _ in x._fields_ if name != "reserved"}
+
+
+class Server:
+    """Continuous-batching request server over one device pool (qs_srv_*).  submit() returns a
+    request id; result() blocks until the request has finished and returns F, p, norm and its
+    timing."""
+
+    def __init__(self, pool_bytes: int, dtype: int = C64, max_inflight: int = 4,
+                 max_chunk_traj: int = 256, plan=None, pool=None):
+        import torch
+        self.dtype = dtype
+        self.pool = pool if pool is not None else torch.empty(int(pool_bytes), dtype=torch.uint8, device="cuda")
+        cfg = SrvConfig()
+        cfg.dtype = dtype
+        cfg.max_inflight = max_inflight
+        cfg.max_chunk_traj = max_chunk_traj
+        p = _plan(plan)
+        if p is not None:
+            cfg.plan = p
+        else:
+            cfg.plan.fuse = -1
+        h = ctypes.c_void_p()
+        _check(lib().qs_srv_create(ctypes.byref(cfg), _ptr(self.pool), self.pool.numel(), ctypes.byref(h)),
+               "srv_create")
+        self.h = h
+        self._meta = {}
+
+    def submit(self, gates, n: int, init_index: int, n_traj: int, e=0.0, seed: int = 0, request: int = 0,
+               traj_base: int = 0, marked: int = -1) -> int:
+        ga = gates if isinstance(gates, ctypes.Array) else gate_array(gates)
+        e_arr = np.asarray(e, np.float64)
+        per = None if e_arr.ndim == 0 else e_arr
+        nz, keep = _noise(float(e_arr) if per is None else 0.0, seed, request, traj_base, per)
+        jid = ctypes.c_uint64()
+        _check(lib().qs_srv_submit(self.h, ga, len(ga), n, int(init_index), ctypes.byref(nz), n_traj,
+                                   int(marked), ctypes.byref(jid)), "srv_submit")
+        del keep
+        self._meta[jid.value] = (n_traj, marked)
+        return jid.value
+
+    def poll(self, job: int) -> bool:
+        d = ctypes.c_int()
+        _check(lib().qs_srv_poll(self.h, job, ctypes.byref(d)), "srv_poll")
+        return bool(d.value)
+
+    def wait(self, job: int, timeout: float = -1.0):
+        _check(lib().qs_srv_wait(self.h, job, float(timeout)), "srv_wait")
+
+    def result(self, job: int, timeout: float = -1.0) -> dict:
+        self.wait(job, timeout)
+        n_traj, marked = self._meta.pop(job)
+        F, P, norms = np.zeros(n_traj), np.zeros(n_traj), np.zeros(n_traj)
+        info = SrvJobInfo()
+        _check(lib().qs_srv_result(self.h, job, _ptr(F), _ptr(P) if marked >= 0 else None, _ptr(norms),
+                                   ctypes.byref(info)), "srv_result")
+        return {"F": F, "p": P if marked >= 0 else None, "norm": norms, "info": _struct_dict(info)}
+
+    def stats(self) -> dict:
+        s = SrvStats()
+        _check(lib().qs_srv_stats_get(self.h, ctypes.byref(s)), "srv_stats")
+        return _struct_dict(s)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().qs_srv_destroy(self.h), "srv_destroy")
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

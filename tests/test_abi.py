@@ -35,6 +35,58 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(q.Plan) == 16
 
 
+def _c_layout(structs):
+    """sizeof and offsetof of each struct field as the C compiler lays them out from qsim.h."""
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "qsim.h"', "int main(void) {"]
+    for cname, py in structs:
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0; }"]
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        open(src, "w").write("\n".join(lines))
+        subprocess.check_call([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), src, "-o", exe])
+        out = subprocess.check_output([exe]).decode()
+    return dict(ln.split() for ln in out.splitlines())
+
+
+def test_every_struct_matches_the_c_layout():
+    structs = [("qs_gate", q.Gate), ("qs_noise", q.Noise), ("qs_plan", q.Plan),
+               ("qs_srv_config", q.SrvConfig), ("qs_srv_job_info", q.SrvJobInfo), ("qs_srv_stats", q.SrvStats)]
+    c = _c_layout(structs)
+    for cname, py in structs:
+        assert int(c[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(c[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_server_rejects_bad_config_before_device_work():
+    L = q.lib()
+    h = ctypes.c_void_p()
+    cfg = q.SrvConfig()
+    cfg.dtype, cfg.max_inflight = q.C64, 4
+    assert L.qs_srv_create(ctypes.byref(cfg), None, 1 << 20, ctypes.byref(h)) == -1
+    cfg.max_inflight = 0
+    assert L.qs_srv_create(ctypes.byref(cfg), ctypes.c_void_p(1 << 20), 1 << 20, ctypes.byref(h)) == -1
+    cfg.max_inflight, cfg.dtype = 4, 7
+    assert L.qs_srv_create(ctypes.byref(cfg), ctypes.c_void_p(1 << 20), 1 << 20, ctypes.byref(h)) == -1
+    cfg.dtype, cfg.max_chunk_traj = q.C64, 5000
+    assert L.qs_srv_create(ctypes.byref(cfg), ctypes.c_void_p(1 << 20), 1 << 20, ctypes.byref(h)) == -1
+    cfg.max_chunk_traj = 0
+    assert L.qs_srv_create(ctypes.byref(cfg), ctypes.c_void_p((1 << 20) + 8), 1 << 20, ctypes.byref(h)) == -1
+    assert "aligned" in L.qs_last_error().decode()
+    jid = ctypes.c_uint64()
+    assert L.qs_srv_submit(None, None, 0, 4, 0, None, 4, -1, ctypes.byref(jid)) == -1
+    assert L.qs_srv_destroy(None) == 0
+
+
 def test_bytes_required_rejects_bad_sizes():
     assert q.sv_bytes_required(0, q.C128, 1) == 0
     assert q.sv_bytes_required(35, q.C128, 1) == 0
