@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain copy of 1 GiB (for HBM counter calibration)")
     ap.add_argument("--plan", default="", help="tile_bits,reg_bits,run_bits of the fused plan")
+    ap.add_argument("--serving-requests", type=int, default=150,
+                    help="requests of the seeded serving stream to replay (0: skip)")
+    ap.add_argument("--serving-inflight", type=int, default=4)
     return ap.parse_args()
 
 
@@ -152,6 +155,9 @@ def main():
         torch.cuda.empty_cache()
         out["sweeps_n28"] = sweeps(q)
         torch.cuda.empty_cache()
+        if a.serving_requests > 0:
+            out["serving"] = serving_bench(q, torch, a.serving_requests, a.serving_inflight)
+            torch.cuda.empty_cache()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c)
     print(json.dumps(out), flush=True)
@@ -224,6 +230,42 @@ def sweeps(q):
         sv.close()
         del sv
         torch.cuda.empty_cache()
+    return out
+
+
+def serving_bench(q, torch, n_requests, inflight):
+    """Replay the first n_requests of the seeded serving stream (seed 3) with qubit counts capped
+    at 20 through the native server: once with every request at t = 0 (sustainable rate), then
+    with Poisson arrivals at 0.8x, 0.5x and 1.0x that rate."""
+    from paper_1412_2293_amd import serving
+    from workloads import serving_stream
+    reqs = serving_stream(seed=3, n_max=20)[:n_requests]
+    log(f"[bench] serving: building {len(reqs)} requests")
+    P = serving.prepare(reqs, q.C64)
+    pool_bytes = 16 << 30
+    pool = torch.empty(pool_bytes, dtype=torch.uint8, device="cuda")
+    cfg = dict(pool_bytes=pool_bytes, dtype=q.C64, max_inflight=inflight, max_chunk_traj=256, pool=pool)
+    # warm-up: the kernels' first launches load code objects
+    with q.Server(**cfg) as srv:
+        serving.replay(srv, P[:8], rate=None)
+    log("[bench] serving: calibration (all requests at t = 0)")
+    with q.Server(**cfg) as srv:
+        cal = serving.replay(srv, P, rate=None)["summary"]
+    rate = cal["requests_per_s"]
+    out = {"workload": f"first {len(reqs)} requests of the seeded serving stream (seed 3): Poisson arrivals, "
+                       "n uniform in [12, 20] (capped from [12, 28]), Grover / QFT / random layers of depth 20n, "
+                       "T uniform in [16, 256], e uniform in [0.001, 0.05], complex64, FP64 fidelities",
+           "pool_bytes": pool_bytes, "max_inflight": inflight, "calibration": cal,
+           "sustainable_requests_per_s": rate}
+    for f in (0.8, 0.5, 1.0):
+        log(f"[bench] serving: Poisson arrivals at {f} x {rate:.2f} req/s")
+        with q.Server(**cfg) as srv:
+            out[f"rate_{f}"] = serving.replay(srv, P, rate=f * rate)["summary"]
+    main = out["rate_0.8"]
+    out.update(latency_p50_s=main["latency_p50_s"], latency_p99_s=main["latency_p99_s"],
+               trajectories_per_s=main["trajectories_per_s"], hbm_frac=main["hbm_frac"],
+               arrival_rate_per_s=0.8 * rate)
+    del pool
     return out
 
 

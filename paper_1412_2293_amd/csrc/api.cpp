@@ -497,7 +497,8 @@ qs_status resolve_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, in
     // (complex<double>): the largest register tiles that stay out of scratch memory
     int K = (p && p->tile_bits > 0) ? p->tile_bits : (dt == QS_C64 ? 12 : 11);
     int RB = (p && p->reg_bits > 0) ? p->reg_bits : (dt == QS_C64 ? 3 : 2);
-    int run = (p && p->run_bits > 0) ? p->run_bits : (dt == QS_C64 ? 4 : 3);
+    // rows of 2^run_bits contiguous amplitudes: 256 bytes
+    int run = (p && p->run_bits > 0) ? p->run_bits : (dt == QS_C64 ? 5 : 4);
     if (K > kMaxTileBits) return fail(QS_EINVAL, "plan: tile_bits too large");
     if ((size_t(1) << std::min(K, n)) * amp_bytes(dt) > 160 * 1024)
         return fail(QS_EINVAL, "plan: tile does not fit the 160 KiB LDS of a gfx950 CU");
@@ -657,7 +658,8 @@ qs_status traj_launch(const TrajPrep &prep, uint64_t init_index, const qs_noise 
     na.traj_base = nz ? nz->traj_base : 0;
     na.first_noisy_slot = 1;
     QS_HIP(launch_noise_table(gdev, n_gates, S, na, tab, st));
-    QS_HIP(launch_init_basis(psi, dt, n, S, init_index, st));
+    // fused runs make the initial state inside their first pass
+    if (!prep.fused || P.passes.empty()) QS_HIP(launch_init_basis(psi, dt, n, S, init_index, st));
     if (prep.fused) {
         ProgramDev pdv{(const PassDesc *)(B + L.passes), (const StageDesc *)(B + L.stages),
                        (const RoundDesc *)(B + L.rounds), (const OpDesc *)(B + L.ops),
@@ -665,7 +667,8 @@ qs_status traj_launch(const TrajPrep &prep, uint64_t init_index, const qs_noise 
                        (const int32_t *)(B + L.obits)};
         for (size_t p = 0; p < P.passes.size(); ++p) {
             QS_HIP(launch_pass_prep(dt, S, &P.passes[p], pdv, tab, gdev, B + L.rec, st));
-            QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (int)p, pdv, B + L.rec, st));
+            QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (int)p, p == 0 ? (int64_t)init_index : -1, pdv,
+                                     B + L.rec, st));
         }
     } else {
         for (int g = 0; g < n_gates; ++g) {

@@ -312,7 +312,7 @@ __device__ __forceinline__ void copy_words(uint32_t *dst, const uint32_t *src, i
 
 template <typename R, int RB>
 __global__ void __launch_bounds__(512, 4) k_fused(R *__restrict__ psi, int n, int S, int pass_index,
-                                                  int rec_cap,
+                                                  int rec_cap, int64_t init,
                                                   const PassDesc *__restrict__ g_passes,
                                                   const StageDesc *__restrict__ g_stages,
                                                   const RoundDesc *__restrict__ g_rounds,
@@ -371,6 +371,12 @@ __global__ void __launch_bounds__(512, 4) k_fused(R *__restrict__ psi, int n, in
     }
     R *base = psi + ((uint64_t)slot << (n + 1));
     cxf<R> a[NR];
+    if (init >= 0) {
+        // first pass of a run: every slot starts in the basis state |init>, made here
+        // instead of read from memory
+#pragma unroll
+        for (int r = 0; r < NR; ++r) a[r] = {(gthr | greg[r]) == (uint64_t)init ? (R)1 : (R)0, (R)0};
+    } else {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         uint64_t i = gthr | greg[r];
@@ -381,6 +387,7 @@ __global__ void __launch_bounds__(512, 4) k_fused(R *__restrict__ psi, int n, in
             double2 v = *reinterpret_cast<const double2 *>(base + 2 * i);
             a[r] = {v.x, v.y};
         }
+    }
     }
 
     // Register layout: tile-local index of register r of this thread = lthr | roff[r].  The
@@ -533,46 +540,44 @@ hipError_t launch_pass_prep(qs_dtype dt, int S, const PassDesc *h, ProgramDev pr
 
 template <typename R, int RB>
 static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_index, int rec_cap,
-                           ProgramDev prog, const void *rec, size_t lds, hipStream_t st)
+                           int64_t init, ProgramDev prog, const void *rec, size_t lds, hipStream_t st)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_fused<R, RB>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    // thread-safe one-time opt-in to the full 160 KiB of LDS
+    static const hipError_t attr = hipFuncSetAttribute((const void *)k_fused<R, RB>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return attr;
     unsigned blocks = (unsigned)((uint64_t)S << (n - h.K));
     unsigned threads = 1u << (h.K - RB);
     hipLaunchKernelGGL((k_fused<R, RB>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index,
-                       rec_cap, prog.passes, prog.stages, prog.rounds, prog.ops, prog.jobs, prog.obits,
+                       rec_cap, init, prog.passes, prog.stages, prog.rounds, prog.ops, prog.jobs, prog.obits,
                        (const cxf<R> *)rec);
     return hipGetLastError();
 }
 
 hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDesc *pass_host,
-                             int pass_index, ProgramDev prog, const void *rec, hipStream_t st)
+                             int pass_index, int64_t init, ProgramDev prog, const void *rec, hipStream_t st)
 {
     const PassDesc &h = *pass_host;
     size_t lds = fused_lds_bytes(dt, h.K);
     const int rec_cap = stage_rec_cap(dt, h.K);
     if (lds > 160 * 1024 || rec_cap <= 0) return hipErrorInvalidValue;
-    TimedLaunch tl("fused", 2.0 * (double)((uint64_t)S << n) * amp_bytes(dt), st);
+    // a pass that makes the initial state only writes it
+    TimedLaunch tl("fused", (init >= 0 ? 1.0 : 2.0) * (double)((uint64_t)S << n) * amp_bytes(dt), st);
     if (dt == QS_C64) {
         float *p = (float *)psi;
         switch (h.RB) {
-        case 1: return launch_t<float, 1>(p, n, S, h, pass_index, rec_cap, prog, rec, lds, st);
-        case 2: return launch_t<float, 2>(p, n, S, h, pass_index, rec_cap, prog, rec, lds, st);
-        case 3: return launch_t<float, 3>(p, n, S, h, pass_index, rec_cap, prog, rec, lds, st);
-        case 4: return launch_t<float, 4>(p, n, S, h, pass_index, rec_cap, prog, rec, lds, st);
+        case 1: return launch_t<float, 1>(p, n, S, h, pass_index, rec_cap, init, prog, rec, lds, st);
+        case 2: return launch_t<float, 2>(p, n, S, h, pass_index, rec_cap, init, prog, rec, lds, st);
+        case 3: return launch_t<float, 3>(p, n, S, h, pass_index, rec_cap, init, prog, rec, lds, st);
+        case 4: return launch_t<float, 4>(p, n, S, h, pass_index, rec_cap, init, prog, rec, lds, st);
         }
     } else {
         double *p = (double *)psi;
         switch (h.RB) {
-        case 1: return launch_t<double, 1>(p, n, S, h, pass_index, rec_cap, prog, rec, lds, st);
-        case 2: return launch_t<double, 2>(p, n, S, h, pass_index, rec_cap, prog, rec, lds, st);
-        case 3: return launch_t<double, 3>(p, n, S, h, pass_index, rec_cap, prog, rec, lds, st);
-        case 4: return launch_t<double, 4>(p, n, S, h, pass_index, rec_cap, prog, rec, lds, st);
+        case 1: return launch_t<double, 1>(p, n, S, h, pass_index, rec_cap, init, prog, rec, lds, st);
+        case 2: return launch_t<double, 2>(p, n, S, h, pass_index, rec_cap, init, prog, rec, lds, st);
+        case 3: return launch_t<double, 3>(p, n, S, h, pass_index, rec_cap, init, prog, rec, lds, st);
+        case 4: return launch_t<double, 4>(p, n, S, h, pass_index, rec_cap, init, prog, rec, lds, st);
         }
     }
     return hipErrorInvalidValue;

@@ -181,7 +181,7 @@ struct ProgramDev {
 hipError_t launch_pass_prep(qs_dtype dt, int S, const PassDesc *pass_host, ProgramDev prog,
                             const double *tab, const qs_gate *gates_dev, void *rec, hipStream_t st);
 hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDesc *pass_host,
-                             int pass_index, ProgramDev prog, const void *rec, hipStream_t st);
+                             int pass_index, int64_t init, ProgramDev prog, const void *rec, hipStream_t st);
 size_t fused_lds_bytes(qs_dtype dt, int K);
 // Record entries per stage that fit next to a tile of 2^K amplitudes (two tiles per CU).
 int stage_rec_cap(qs_dtype dt, int K);

@@ -482,8 +482,11 @@ __global__ void __launch_bounds__(kRedThreads) k_overlap_partial(const R *ref, c
                                                                  int log_blocks, double *partials)
 {
     __shared__ double sh[3 * kRedThreads];
-    const int slot = blockIdx.x >> log_blocks;
-    const uint64_t blk = blockIdx.x & ((1u << log_blocks) - 1);
+    // chunk-major order: the blocks of every slot for one chunk run together, so the
+    // reference chunk is read from HBM once and from the caches by the other slots
+    const int S = (int)(gridDim.x >> log_blocks);
+    const int slot = (int)(blockIdx.x % (unsigned)S);
+    const uint64_t blk = blockIdx.x / (unsigned)S;
     const uint64_t per = 1ull << (n - log_blocks);
     const R *p = psi + ((uint64_t)slot << (n + 1));
     double v[4] = {0, 0, 0, 0};
@@ -513,7 +516,7 @@ __global__ void __launch_bounds__(kRedThreads) k_overlap_partial(const R *ref, c
     }
     block_sum(sh, v, 3);
     if (threadIdx.x == 0) {
-        double *o = partials + (uint64_t)blockIdx.x * 3;
+        double *o = partials + ((uint64_t)slot << log_blocks | blk) * 3;
         o[0] = v[0];
         o[1] = v[1];
         o[2] = v[2];
@@ -768,7 +771,8 @@ hipError_t launch_overlaps(const void *ref_psi, int ref_slot, const void *psi, q
 {
     int lb = red_log_blocks(n);
     unsigned nblk = (unsigned)((uint64_t)S << lb);
-    TimedLaunch tl("reduce", 2.0 * (double)((uint64_t)S << n) * amp_bytes(dt), st);
+    // algorithmic bytes: every state once and the reference once
+    TimedLaunch tl("reduce", (double)((uint64_t)(S + 1) << n) * amp_bytes(dt), st);
     if (dt == QS_C64) {
         const float *ref = (const float *)ref_psi + ((uint64_t)ref_slot << (n + 1));
         hipLaunchKernelGGL(k_overlap_partial<float>, dim3(nblk), dim3(kRedThreads), 0, st, ref,

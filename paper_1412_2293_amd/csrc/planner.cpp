@@ -2,7 +2,8 @@
 //
 // 1. SWAP gates become a relabelling of logical to physical qubits; no data moves.
 // 2. Gates are grouped in order into passes; a pass may target at most `max_targets`
-//    physical qubits with non-diagonal gates (one-qubit dense, two-qubit dense, CNOT).
+//    physical qubits above the low run bits with non-diagonal gates (one-qubit dense,
+//    two-qubit dense, CNOT); targets among the run bits are free, as the tile always holds them.
 //    Diagonal gates (controlled phases, sign flips) never close a pass.
 // 3. A controlled phase on (c, t) commutes with everything between the previous and the next
 //    non-diagonal gate on c or t.  It is folded into the next one-qubit gate on c or t as a
@@ -35,6 +36,7 @@ struct Attach {         // controlled phase folded into a one-qubit gate
 struct PassBuild {
     std::vector<int> items;      // indices into the PG list, in order
     std::vector<int> targets;    // physical qubits touched non-diagonally
+    int high = 0;                // targets outside the low run bits
 };
 
 int find_pos(const std::vector<int> &v, int x)
@@ -107,15 +109,19 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         if (x.kind == QS_G_U1) need = {x.a};
         else if (x.kind == QS_G_U2 || x.kind == QS_G_CNOT) need = {x.a, x.b};
         PassBuild *cur = &passes.back();
+        // the tile holds the targets and the low run bits: targets among the run bits are free
         int extra = 0;
         for (int q : need)
-            if (find_pos(cur->targets, q) < 0) ++extra;
-        if ((int)cur->targets.size() + extra > max_targets) {
+            if (find_pos(cur->targets, q) < 0 && (whole || q >= run_bits)) ++extra;
+        if (cur->high + extra > max_targets) {
             passes.emplace_back();
             cur = &passes.back();
         }
         for (int q : need)
-            if (find_pos(cur->targets, q) < 0) cur->targets.push_back(q);
+            if (find_pos(cur->targets, q) < 0) {
+                cur->targets.push_back(q);
+                if (whole || q >= run_bits) cur->high += 1;
+            }
         cur->items.push_back((int)i);
         pass_of[i] = (int)passes.size() - 1;
     }

@@ -307,6 +307,7 @@ qs_status qs_srv_create(const qs_srv_config *cfg, void *pool, size_t pool_bytes,
 qs_status qs_srv_submit(qs_srv srv, const qs_gate *gates, int n_gates, int n, uint64_t init_index,
                         const qs_noise *nz, int T, int64_t marked, uint64_t *job_out)
 {
+    const auto t_arrive = Clock::now();   // planning counts toward the request's latency
     clear_error();
     if (!srv || !job_out) return fail(QS_EINVAL, "srv_submit: NULL server or job_out");
     if (T < 1) return fail(QS_EINVAL, "srv_submit: n_traj must be >= 1");
@@ -347,7 +348,7 @@ qs_status qs_srv_submit(qs_srv srv, const qs_gate *gates, int n_gates, int n, ui
     j->F.assign(T, 0.0);
     if (marked >= 0) j->p.assign(T, 0.0);
     j->norm.assign(T, 0.0);
-    j->t_submit = Clock::now();
+    j->t_submit = t_arrive;
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stop) return fail(QS_EBUSY, "srv_submit: server is shutting down");
     j->id = srv->next_id++;

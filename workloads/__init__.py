@@ -215,3 +215,45 @@ def random_mixed_circuit(n: int, n_gates: int, seed: int) -> Circuit:
                 gates.append(Gate(k, q0=a, q1=b))
     return Circuit(n, _renumber_sites(gates), name=f"mixed{n}x{n_gates}",
                    init_index=int(rng.integers(0, N)), meta={"seed": seed})
+
+
+# ------------------------------------------------------------------------------------------
+SERVING_KINDS = ("grover", "qft", "random")
+
+
+@dataclass
+class Request:
+    """One request of a serving stream: which circuit, how many trajectories, which noise."""
+    index: int
+    arrival: float            # arrival time in units of the mean inter-arrival gap
+    kind: str
+    n: int
+    T: int
+    e: float
+    seed: int
+
+    def circuit(self) -> Circuit:
+        if self.kind == "grover":
+            # iterations capped at 10 n, the budget of the random-layer circuits (~20 n^2 gates)
+            return grover(self.n, self.seed, iterations=min(grover_iterations(self.n), 10 * self.n))
+        if self.kind == "qft":
+            return qft(self.n, self.seed)
+        return random_layers(self.n, 20 * self.n, self.seed, pairing="random")
+
+
+def serving_stream(n_requests: int = 2000, seed: int = 3, n_min: int = 12, n_max: int = 28,
+                   t_min: int = 16, t_max: int = 256, e_min: float = 0.001, e_max: float = 0.05) -> List[Request]:
+    """Seeded request stream: Poisson arrivals (exponential gaps of mean 1; the caller scales
+    them to a rate), qubit count uniform in [n_min, n_max], circuit kind uniform over Grover,
+    QFT and random layers of depth 20 n, trajectories uniform in [t_min, t_max], noise strength
+    uniform in [e_min, e_max].  Request i uses circuit seed seed * 100003 + i and Philox request
+    word i."""
+    rng = np.random.default_rng([seed, 2])
+    gaps = rng.exponential(1.0, n_requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    ns = rng.integers(n_min, n_max + 1, n_requests)
+    kinds = rng.integers(0, len(SERVING_KINDS), n_requests)
+    Ts = rng.integers(t_min, t_max + 1, n_requests)
+    es = rng.uniform(e_min, e_max, n_requests)
+    return [Request(i, float(arrivals[i]), SERVING_KINDS[int(kinds[i])], int(ns[i]), int(Ts[i]), float(es[i]),
+                    seed * 100003 + i) for i in range(n_requests)]
