@@ -30,11 +30,9 @@ __device__ __forceinline__ cxf<R> fma_c(cxf<R> a, cxf<R> b, cxf<R> c)
     return {a.re * b.re - a.im * b.im + c.re, a.re * b.im + a.im * b.re + c.im};
 }
 
-// LDS slot of tile-local index l: the low five bits are xor-ed with a fold of the higher bits,
-// a bijection that spreads strided accesses over the banks.
 __device__ __forceinline__ uint32_t swz(uint32_t l)
 {
-    return l ^ (((l >> 5) ^ (l >> 10)) & 31u);
+    return lds_swizzle(l);
 }
 
 // Deposit the low bits of x into the set bits of mask (lowest first).
@@ -117,7 +115,10 @@ __device__ constexpr int quad_base(int k)
     return pair_base<hi>(pair_base<lo>(k));
 }
 
-template <typename R, int RB, int P>
+// PRE / POST: whether the folded phase blocks are present.  They are uniform per op, so each
+// combination is its own straight-line code behind a scalar branch, with no work for an
+// absent block.
+template <typename R, int RB, int P, bool PRE, bool POST>
 __device__ __forceinline__ void apply_u1(cxf<R> (&a)[1 << RB], const cxf<R> (&m)[4],
                                          const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
@@ -126,17 +127,17 @@ __device__ __forceinline__ void apply_u1(cxf<R> (&a)[1 << RB], const cxf<R> (&m)
         const int r = pair_base<P>(k);
         const int r1 = r | (1 << P);
         cxf<R> x0 = a[r], x1 = a[r1];
-        if (pre.any) x1 = mul(pair_phase<R, RB, P>(pre, r), x1);
+        if constexpr (PRE) x1 = mul(pair_phase<R, RB, P>(pre, r), x1);
         cxf<R> y0 = fma_c(m[1], x1, mul(m[0], x0));
         cxf<R> y1 = fma_c(m[3], x1, mul(m[2], x0));
-        if (post.any) y1 = mul(pair_phase<R, RB, P>(post, r), y1);
+        if constexpr (POST) y1 = mul(pair_phase<R, RB, P>(post, r), y1);
         a[r] = y0;
         a[r1] = y1;
     }
 }
 
 // The same update with a real matrix (m[k].im == 0): half the multiplications.
-template <typename R, int RB, int P>
+template <typename R, int RB, int P, bool PRE, bool POST>
 __device__ __forceinline__ void apply_u1_real(cxf<R> (&a)[1 << RB], const cxf<R> (&m)[4],
                                               const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
@@ -146,10 +147,10 @@ __device__ __forceinline__ void apply_u1_real(cxf<R> (&a)[1 << RB], const cxf<R>
         const int r = pair_base<P>(k);
         const int r1 = r | (1 << P);
         cxf<R> x0 = a[r], x1 = a[r1];
-        if (pre.any) x1 = mul(pair_phase<R, RB, P>(pre, r), x1);
+        if constexpr (PRE) x1 = mul(pair_phase<R, RB, P>(pre, r), x1);
         cxf<R> y0 = {m0 * x0.re + m1 * x1.re, m0 * x0.im + m1 * x1.im};
         cxf<R> y1 = {m2 * x0.re + m3 * x1.re, m2 * x0.im + m3 * x1.im};
-        if (post.any) y1 = mul(pair_phase<R, RB, P>(post, r), y1);
+        if constexpr (POST) y1 = mul(pair_phase<R, RB, P>(post, r), y1);
         a[r] = y0;
         a[r1] = y1;
     }
@@ -179,26 +180,36 @@ __device__ __forceinline__ void apply_u2(cxf<R> (&a)[1 << RB], const cxf<R> (&m)
     }
 }
 
+// Dispatch on the target register bit.  There is no pass-through branch (the last position
+// is the fall-back): every path rewrites the register tile, which lets the register allocator
+// keep the tile in the same registers across ops instead of copying it at each merge.
+template <typename R, int RB, bool PRE, bool POST>
+__device__ __forceinline__ void dispatch_u1_pp(int p, bool real, cxf<R> (&a)[1 << RB], const cxf<R> (&m)[4],
+                                               const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
+{
+    if (real) {
+        if (RB > 1 && p == 0) apply_u1_real<R, RB, 0, PRE, POST>(a, m, pre, post);
+        else if (RB > 2 && p == 1) apply_u1_real<R, RB, 1 % RB, PRE, POST>(a, m, pre, post);
+        else if (RB > 3 && p == 2) apply_u1_real<R, RB, 2 % RB, PRE, POST>(a, m, pre, post);
+        else apply_u1_real<R, RB, RB - 1, PRE, POST>(a, m, pre, post);
+        return;
+    }
+    if (RB > 1 && p == 0) apply_u1<R, RB, 0, PRE, POST>(a, m, pre, post);
+    else if (RB > 2 && p == 1) apply_u1<R, RB, 1 % RB, PRE, POST>(a, m, pre, post);
+    else if (RB > 3 && p == 2) apply_u1<R, RB, 2 % RB, PRE, POST>(a, m, pre, post);
+    else apply_u1<R, RB, RB - 1, PRE, POST>(a, m, pre, post);
+}
+
 template <typename R, int RB>
 __device__ __forceinline__ void dispatch_u1(int p, bool real, cxf<R> (&a)[1 << RB], const cxf<R> (&m)[4],
                                             const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
-    if (real) {
-        switch (p) {
-        case 0: apply_u1_real<R, RB, 0>(a, m, pre, post); break;
-        case 1: if constexpr (RB > 1) apply_u1_real<R, RB, 1 % RB>(a, m, pre, post); break;
-        case 2: if constexpr (RB > 2) apply_u1_real<R, RB, 2 % RB>(a, m, pre, post); break;
-        case 3: if constexpr (RB > 3) apply_u1_real<R, RB, 3 % RB>(a, m, pre, post); break;
-        default: break;
-        }
-        return;
-    }
-    switch (p) {
-    case 0: apply_u1<R, RB, 0>(a, m, pre, post); break;
-    case 1: if constexpr (RB > 1) apply_u1<R, RB, 1 % RB>(a, m, pre, post); break;
-    case 2: if constexpr (RB > 2) apply_u1<R, RB, 2 % RB>(a, m, pre, post); break;
-    case 3: if constexpr (RB > 3) apply_u1<R, RB, 3 % RB>(a, m, pre, post); break;
-    default: break;
+    if (pre.any) {
+        if (post.any) dispatch_u1_pp<R, RB, true, true>(p, real, a, m, pre, post);
+        else dispatch_u1_pp<R, RB, true, false>(p, real, a, m, pre, post);
+    } else {
+        if (post.any) dispatch_u1_pp<R, RB, false, true>(p, real, a, m, pre, post);
+        else dispatch_u1_pp<R, RB, false, false>(p, real, a, m, pre, post);
     }
 }
 
@@ -332,7 +343,6 @@ __global__ void __launch_bounds__(512, 4) k_fused(R *__restrict__ psi, int n, in
         const int32_t *__restrict__ obits;
     } prog = {g_passes, g_stages, g_rounds, g_ops, g_jobs, g_obits};
     extern __shared__ __align__(16) unsigned char smem[];
-    cxf<R> *lds = reinterpret_cast<cxf<R> *>(smem);
     constexpr int NR = 1 << RB;
     const PassDesc *pd = prog.passes + pass_index;
     const int K = pd->K;
@@ -392,30 +402,36 @@ __global__ void __launch_bounds__(512, 4) k_fused(R *__restrict__ psi, int n, in
 
     // Register layout: tile-local index of register r of this thread = lthr | roff[r].  The
     // load layout has the thread id in the low bits; rounds bring host-built tables.
+    // LDS addresses: swz(lthr | roff[r]) = swz(lthr) ^ swz(roff[r]); the register part is a
+    // uniform byte offset soff[r] (scalar registers), so each access costs one XOR.
+    constexpr uint32_t CXS = sizeof(cxf<R>);
     const uint32_t load_mask = (((1u << RB) - 1u) << TB) & kmask;
     uint32_t cur = load_mask;
-    uint32_t roff[NR];
+    uint32_t roff[NR], soff[NR];
+    auto take_round = [&](const RoundDesc *rd) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) roff[r] = (uint32_t)r << TB;
+        for (int r = 0; r < NR; ++r) {
+            roff[r] = rd->roff[r];
+            soff[r] = rd->sroff[r] * CXS;
+        }
+    };
+    take_round(&pd->load_round);
     uint32_t lthr = tid;
 
     auto exchange_to = [&](uint32_t to, const RoundDesc *rd) {
         __syncthreads();
+        {
+            const uint32_t sw = swz(lthr) * CXS;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) lds[swz(lthr | roff[r])] = a[r];
+            for (int r = 0; r < NR; ++r) *reinterpret_cast<cxf<R> *>(smem + (sw ^ soff[r])) = a[r];
+        }
         __syncthreads();
         cur = to;
-        if (rd) {
+        take_round(rd);
+        lthr = (uint32_t)rd->tlo[tid & 31u] | (uint32_t)rd->thi[(tid >> 5) & 15u];
+        const uint32_t sw = swz(lthr) * CXS;
 #pragma unroll
-            for (int r = 0; r < NR; ++r) roff[r] = rd->roff[r];
-            lthr = (uint32_t)rd->tlo[tid & 31u] | (uint32_t)rd->thi[(tid >> 5) & 15u];
-        } else {
-#pragma unroll
-            for (int r = 0; r < NR; ++r) roff[r] = (uint32_t)r << TB;
-            lthr = tid;
-        }
-#pragma unroll
-        for (int r = 0; r < NR; ++r) a[r] = lds[swz(lthr | roff[r])];
+        for (int r = 0; r < NR; ++r) a[r] = *reinterpret_cast<const cxf<R> *>(smem + (sw ^ soff[r]));
     };
 
     for (int si = pd->stage_begin; si < pd->stage_end; ++si) {
@@ -466,12 +482,14 @@ __global__ void __launch_bounds__(512, 4) k_fused(R *__restrict__ psi, int n, in
                     for (int k = 0; k < 16; ++k) m[k] = orec[k];
                     dispatch_u2<R, RB>(op->p0, op->p1, a, m);
                 } else {
-                    if ((outer & op->omask) != op->ovalue) continue;
+                    // no early exit when the tile-number condition fails: a pass-through path
+                    // would make the register tile move between registers
+                    const bool ohit = (outer & op->omask) == op->ovalue;
                     const uint32_t lmask = op->lmask, lvalue = op->lvalue;
                     const cxf<R> f = orec[0];
 #pragma unroll
                     for (int r = 0; r < NR; ++r) {
-                        bool hit = ((lthr | roff[r]) & lmask) == lvalue;
+                        bool hit = ohit && ((lthr | roff[r]) & lmask) == lvalue;
                         cxf<R> y = mul(f, a[r]);
                         a[r].re = hit ? y.re : a[r].re;
                         a[r].im = hit ? y.im : a[r].im;
@@ -480,7 +498,7 @@ __global__ void __launch_bounds__(512, 4) k_fused(R *__restrict__ psi, int n, in
             }
         }
     }
-    if (cur != load_mask) exchange_to(load_mask, nullptr);
+    if (cur != load_mask) exchange_to(load_mask, &pd->load_round);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         uint64_t g = 0;

@@ -44,6 +44,25 @@ constexpr int kMaxTileBits = 15;
 constexpr int kMaxRegBits = 4;
 constexpr int kPhaseTable = 4 + 32 + 16;   // reg + lo + hi entries of a phase block
 
+struct RoundDesc {
+    uint32_t reg_mask;            // tile-local bits held in registers during this round
+    int32_t op_begin;
+    int32_t op_end;
+    int32_t reserved;
+    uint32_t roff[16];            // tile-local offset of register r (32-bit: scalar loads)
+    uint32_t sroff[16];           // lds_swizzle(roff[r])
+    uint16_t tlo[32];             // tile-local bits of thread-id bits 0..4, indexed by tid & 31
+    uint16_t thi[16];             // tile-local bits of thread-id bits 5..8, indexed by tid >> 5
+};
+
+// LDS slot of tile-local index l: the low five bits are xor-ed with a fold of the higher bits,
+// a bijection that spreads strided accesses over the banks.  It is linear over XOR, so for
+// disjoint thread and register bits lds_swizzle(t | r) = lds_swizzle(t) ^ lds_swizzle(r).
+__host__ __device__ inline uint32_t lds_swizzle(uint32_t l)
+{
+    return l ^ (((l >> 5) ^ (l >> 10)) & 31u);
+}
+
 struct PassDesc {
     int32_t K;
     int32_t RB;
@@ -55,6 +74,7 @@ struct PassDesc {
     int32_t rec_size;             // complex entries of the pass's records per slot
     int32_t job_begin, job_end;   // OuterJobs of the pass (per-tile outer phase products)
     int32_t stage_begin, stage_end;
+    RoundDesc load_round;         // the load layout (thread id in the low tile-local bits)
 };
 
 // A stage: consecutive rounds whose op descriptors, records, outer jobs and outer bits are
@@ -71,16 +91,6 @@ struct StageDesc {
 constexpr int kStageOps = 48;     // op descriptors per stage
 constexpr int kStageJobs = 64;    // outer jobs per stage
 constexpr int kStageObits = 512;  // outer condition bits per stage
-
-struct RoundDesc {
-    uint32_t reg_mask;            // tile-local bits held in registers during this round
-    int32_t op_begin;
-    int32_t op_end;
-    int32_t reserved;
-    uint16_t roff[16];            // tile-local offset of register r
-    uint16_t tlo[32];             // tile-local bits of thread-id bits 0..4, indexed by tid & 31
-    uint16_t thi[16];             // tile-local bits of thread-id bits 5..8, indexed by tid >> 5
-};
 
 enum OpType : int32_t { OP_U1 = 0, OP_U2 = 1, OP_DIAG = 2 };
 enum DiagKind : int32_t { DIAG_NEGATE = 0, DIAG_PHASE = 1 };

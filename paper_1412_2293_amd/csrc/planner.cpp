@@ -39,6 +39,36 @@ struct PassBuild {
     int high = 0;                // targets outside the low run bits
 };
 
+// Register offsets (plain and swizzled) and thread-id deposit tables of a round whose
+// registers hold tile-local bits m.
+RoundDesc make_round(uint32_t m, int K)
+{
+    RoundDesc R{};
+    R.reg_mask = m;
+    std::vector<int> regpos, tpos;
+    for (int j = 0; j < K; ++j) ((m >> j) & 1u ? regpos : tpos).push_back(j);
+    for (int r = 0; r < 16; ++r) {
+        uint32_t o = 0;
+        for (int k = 0; k < (int)regpos.size(); ++k)
+            if ((r >> k) & 1) o |= 1u << regpos[k];
+        R.roff[r] = o;
+        R.sroff[r] = lds_swizzle(o);
+    }
+    for (int x = 0; x < 32; ++x) {
+        uint32_t o = 0;
+        for (int b = 0; b < 5 && b < (int)tpos.size(); ++b)
+            if ((x >> b) & 1) o |= 1u << tpos[b];
+        R.tlo[x] = (uint16_t)o;
+    }
+    for (int y = 0; y < 16; ++y) {
+        uint32_t o = 0;
+        for (int b = 0; b < 4 && 5 + b < (int)tpos.size(); ++b)
+            if ((y >> b) & 1) o |= 1u << tpos[5 + b];
+        R.thi[y] = (uint16_t)o;
+    }
+    return R;
+}
+
 int find_pos(const std::vector<int> &v, int x)
 {
     for (size_t i = 0; i < v.size(); ++i)
@@ -197,6 +227,7 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         pd.outer_mask = nmask & ~qmask;
         const uint32_t kmask = (1u << K) - 1u;
         const uint32_t load_mask = ((1u << RB) - 1u) << (K - RB);
+        pd.load_round = make_round(load_mask, K);
 
         // greedy register rounds, closed also when the current LDS stage is full
         auto fill = [&](uint32_t need) {
@@ -292,31 +323,8 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                 sd.obits_begin = (int)P.obits.size();
                 P.stages.push_back(sd);
             }
-            RoundDesc R{};
-            R.reg_mask = m;
+            RoundDesc R = make_round(m, K);
             R.op_begin = (int)P.ops.size();
-            {
-                std::vector<int> regpos, tpos;
-                for (int j = 0; j < K; ++j) ((m >> j) & 1u ? regpos : tpos).push_back(j);
-                for (int r = 0; r < 16; ++r) {
-                    uint32_t o = 0;
-                    for (int k = 0; k < (int)regpos.size(); ++k)
-                        if ((r >> k) & 1) o |= 1u << regpos[k];
-                    R.roff[r] = (uint16_t)o;
-                }
-                for (int x = 0; x < 32; ++x) {
-                    uint32_t o = 0;
-                    for (int b = 0; b < 5 && b < (int)tpos.size(); ++b)
-                        if ((x >> b) & 1) o |= 1u << tpos[b];
-                    R.tlo[x] = (uint16_t)o;
-                }
-                for (int y = 0; y < 16; ++y) {
-                    uint32_t o = 0;
-                    for (int b = 0; b < 4 && 5 + b < (int)tpos.size(); ++b)
-                        if ((y >> b) & 1) o |= 1u << tpos[5 + b];
-                    R.thi[y] = (uint16_t)o;
-                }
-            }
             int reg_index[32], tid_index[32];
             {
                 int k = 0, t = 0;
