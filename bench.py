@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 METRIC = "amplitude-updates/s & %HBM peak; MC trajectories/s; p50/p99 request latency"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused_qft26.json")
 
@@ -155,6 +156,10 @@ def main():
         torch.cuda.empty_cache()
         out["sweeps_n28"] = sweeps(q)
         torch.cuda.empty_cache()
+        out["dm13"] = dm13_bench(q, torch)
+        torch.cuda.empty_cache()
+        out["fr24"] = fr24_bench(q, torch)
+        torch.cuda.empty_cache()
         if a.serving_requests > 0:
             out["serving"] = serving_bench(q, torch, a.serving_requests, a.serving_inflight)
             torch.cuda.empty_cache()
@@ -230,6 +235,102 @@ def sweeps(q):
         sv.close()
         del sv
         torch.cuda.empty_cache()
+    return out
+
+
+def dm13_bench(q, torch):
+    """Density-matrix Grover on n = 13 (vec rho: 2^26 complex<double>, 1 GiB), every Hadamard
+    as its two-operator Kraus channel (eq. 6, e = 0.02) applied as one superoperator sweep,
+    the sign flips exact; fidelity <psi_ideal|rho|psi_ideal> in FP64.  Beside it the mean
+    fidelity of 2048 Monte Carlo trajectories of the same circuit, which the channel is the
+    exact average of."""
+    import numpy as np
+    from workloads import grover
+    n, e = 13, 0.02
+    c = grover(n, seed=5)
+    ga = q.gate_array(c.gates)
+    log(f"[bench] dm13: {len(c.gates)} gates on vec(rho) of 2^{2 * n} entries")
+    rho = q.StateVector(2 * n, q.C128, 1)
+    ideal = q.StateVector(n, q.C128, 1)
+    # ideal state through the same library (noise off)
+    ideal.init_basis(0)
+    for g in ga:
+        q.apply_gate(ideal, g)
+    rho.init_basis(0)
+    q.dm_apply_gate(rho, ga[0], e)          # warm-up of the kernels
+    rho.init_basis(0)
+    torch.cuda.synchronize()
+    q.timing_reset()
+    q.timing_enable(True)
+    t0 = time.perf_counter()
+    for g in ga:
+        q.dm_apply_gate(rho, g, e)
+    f, tr = q.dm_fidelity(rho, ideal, 0)
+    t1 = time.perf_counter()
+    q.timing_enable(False)
+    k = q.timing_read("sweep_2q")
+    sweeps = k["launches"]
+    gbs = k["alg_bytes"] / (k["ms"] / 1e3) / 1e9 if k["ms"] else 0.0
+    res = q.run_trajectories(ga, n, c.init_index, q.C128, 2048, e=e, seed=11)
+    mc = float(np.mean(res["F"]))
+    mc_err = float(np.std(res["F"]) / np.sqrt(2048))
+    out = {"workload": f"grover{n} (j={c.meta['iterations']}), vec(rho) complex128, e={e}",
+           "gates": len(c.gates), "superoperator_sweeps": sweeps, "wall_s": t1 - t0,
+           "sweep_avg_ms": k["ms"] / max(sweeps, 1), "sweep_GBps": round(gbs, 1),
+           "sweep_hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "fidelity": f, "trace": tr,
+           "mc_mean_fidelity_T2048": mc, "mc_stderr": mc_err,
+           "dm_minus_mc_in_stderr": (f - mc) / mc_err if mc_err > 0 else None}
+    rho.close()
+    ideal.close()
+    return out
+
+
+def fr24_bench(q, torch, iterations=10):
+    """Fixed-rank density matrix (r = 8, complex<float> columns, FP64 Gram and eigen-solve) for
+    Grover on n = 24, e = 0.02: a bounded prefix of the circuit (the preparation layer and
+    `iterations` Grover iterations); the full circuit has 154,392 Kraus steps."""
+    from workloads import grover, grover_iterations
+    n, r, e = 24, 8, 0.02
+    c = grover(n, seed=7, iterations=iterations)
+    ga = q.gate_array(c.gates)
+    fr = q.FixedRank(n, r, q.C64)
+    fr.init_basis(0)
+    fr.apply_noisy_gate(ga[0], e, tau=1e-5, zero_tol=1e-6)
+    fr.init_basis(0)
+    torch.cuda.synchronize()
+    q.timing_reset()
+    q.timing_enable(True)
+    t0 = time.perf_counter()
+    ranks = [fr.apply_noisy_gate(g, e, tau=1e-5, zero_tol=1e-6) for g in ga]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    q.timing_enable(False)
+    w = q.StateVector(n, q.C64, 1)
+    w.init_basis(c.marked)
+    fu, fn, lt = fr.fidelity(w)
+    kr = {k: q.timing_read(k) for k in ("fr_gram", "fr_recombine")}
+    steps = sum(1 for g in c.gates if g.kind == 0)
+    full_steps = n + 2 * n * grover_iterations(n)
+    per_step = (t1 - t0) / steps
+    out = {"workload": f"grover{n} prefix: {iterations} iterations, r={r}, complex64 columns, e={e}",
+           "kraus_steps": steps, "wall_s": t1 - t0, "ms_per_kraus_step": per_step * 1e3,
+           "max_rank": max(ranks), "p_marked_unnormalised": fu, "p_marked_normalised": fn,
+           "log_trace": lt, "full_circuit_kraus_steps": full_steps,
+           "projected_full_circuit_s": per_step * full_steps}
+    for k, v in kr.items():
+        if v["launches"]:
+            gbs = v["alg_bytes"] / (v["ms"] / 1e3) / 1e9
+            out[k] = {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"], "GB/s": round(gbs, 1),
+                      "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    if kr["fr_gram"]["launches"]:
+        # Gram of the 2r half-columns: 1088 FP64 flops per amplitude index at r = 8 (the 136
+        # independent entries of a Hermitian 16 x 16, 4 real multiply-adds each), FP64 matrix peak
+        g = kr["fr_gram"]
+        tf = 1088.0 * (1 << n) / (g["ms"] / g["launches"] / 1e3) / 1e12
+        out["fr_gram"].update({"alg_TFLOPs": round(tf, 2), "fp64_peak_TFLOPs": FP64_PEAK_TFLOPS,
+                               "mfma_frac": round(tf / FP64_PEAK_TFLOPS, 4)})
+    fr.close()
+    w.close()
     return out
 
 

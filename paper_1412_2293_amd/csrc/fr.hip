@@ -100,6 +100,92 @@ __global__ void __launch_bounds__(256) k_fr_gram(const R *V, int n, int r_in, in
     }
 }
 
+// The same Gram matrix on the FP64 matrix cores.  Gamma = H^dagger H with H the
+// (pairs x 16) matrix of half-columns is a dense contraction over the pairs: with
+// H = Hr + i Hi, Re Gamma = Hr^T Hr + Hi^T Hi and Im Gamma = X - X^T with X = Hr^T Hi: three
+// real 16 x 16 x 4 products per 4 pairs.  Lane l feeds half-column m = l % 16 of pair k = l / 16 of
+// its group as both the A operand (row m, column k) and the B operand (row k, column m);
+// accumulator register i of lane l holds row 4 i + l / 16, column l % 16 of the product.  Every wave walks its
+// own range of pairs 16 at a time (4 consecutive pairs per lane and half-column), so the main
+// loop has no LDS traffic.
+typedef double fr_d4 __attribute__((ext_vector_type(4)));
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_fr_gram_mfma(const R *V, int n, int r_in, int q, int log_blocks,
+                                                      double *partials)
+{
+    __shared__ double red[4][2][256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, j = lane >> 4;
+    const int x = m / kFrMax, c = m % kFrMax;
+    const bool live = c < r_in;
+    const R *col = V + ((uint64_t)(live ? c : 0) << (n + 1));
+    const uint64_t per_block = (1ull << (n - 1)) >> log_blocks;
+    const uint64_t per_wave = per_block >> 2;
+    const uint64_t begin = (uint64_t)blockIdx.x * per_block + (uint64_t)wave * per_wave;
+    const uint64_t xbit = (uint64_t)x << q;
+    // two independent accumulator pairs alternate, so consecutive products do not wait on
+    // each other
+    fr_d4 ar0 = {0.0, 0.0, 0.0, 0.0}, ai0 = ar0, ar1 = ar0, ai1 = ar0;
+    auto prod = [&](double hr, double hi, fr_d4 &ar, fr_d4 &ai) {
+        ar = __builtin_amdgcn_mfma_f64_16x16x4f64(hr, hr, ar, 0, 0, 0);
+        ai = __builtin_amdgcn_mfma_f64_16x16x4f64(hr, hi, ai, 0, 0, 0);
+        ar = __builtin_amdgcn_mfma_f64_16x16x4f64(hi, hi, ar, 0, 0, 0);
+    };
+    if (q >= 2) {
+        // the lane's 4 consecutive pairs are 4 consecutive amplitudes: one contiguous load
+        for (uint64_t p0 = begin; p0 < begin + per_wave; p0 += 16) {
+            const uint64_t i = fr_ins0(p0 + 4 * j, q) | xbit;
+            double h[8];
+            if constexpr (sizeof(R) == 4) {
+                float4 u = {0.f, 0.f, 0.f, 0.f}, v = u;
+                if (live) {
+                    u = *reinterpret_cast<const float4 *>(col + 2 * i);
+                    v = *reinterpret_cast<const float4 *>(col + 2 * i + 4);
+                }
+                h[0] = u.x; h[1] = u.y; h[2] = u.z; h[3] = u.w;
+                h[4] = v.x; h[5] = v.y; h[6] = v.z; h[7] = v.w;
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    double2 u = live ? *reinterpret_cast<const double2 *>(col + 2 * (i + t)) : double2{0.0, 0.0};
+                    h[2 * t] = u.x;
+                    h[2 * t + 1] = u.y;
+                }
+            }
+            prod(h[0], h[1], ar0, ai0);
+            prod(h[2], h[3], ar1, ai1);
+            prod(h[4], h[5], ar0, ai0);
+            prod(h[6], h[7], ar1, ai1);
+        }
+    } else {
+        for (uint64_t p0 = begin; p0 < begin + per_wave; p0 += 16) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint64_t i = fr_ins0(p0 + 4 * j + t, q) | xbit;
+                const double hr = live ? (double)col[2 * i] : 0.0;
+                const double hi = live ? (double)col[2 * i + 1] : 0.0;
+                if (t & 1) prod(hr, hi, ar1, ai1);
+                else prod(hr, hi, ar0, ai0);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        red[wave][0][(4 * i + j) * 16 + m] = ar0[i] + ar1[i];
+        red[wave][1][(4 * i + j) * 16 + m] = ai0[i] + ai1[i];
+    }
+    __syncthreads();
+    // Im Gamma = X - X^T with X = Hr^T Hi (the imaginary accumulators hold X)
+    const int t = threadIdx.x, tt = (t & 15) * 16 + (t >> 4);
+    double sx = red[0][0][t] + red[1][0][t] + red[2][0][t] + red[3][0][t];
+    double sy = (red[0][1][t] + red[1][1][t] + red[2][1][t] + red[3][1][t]) -
+                (red[0][1][tt] + red[1][1][tt] + red[2][1][tt] + red[3][1][tt]);
+    double *o = partials + ((uint64_t)blockIdx.x * 256 + t) * 2;
+    o[0] = sx;
+    o[1] = sy;
+}
+
 __global__ void __launch_bounds__(256) k_fr_gram_final(const double *partials, int nb, double *out)
 {
     const int t = threadIdx.x;
@@ -168,7 +254,15 @@ hipError_t launch_fr_gram(const void *V, qs_dtype dt, int n, int r, int q, doubl
 {
     int lb = fr_log_blocks(n);
     TimedLaunch tl("fr_gram", (double)r * (double)(1ull << n) * amp_bytes(dt), st);
-    if (dt == QS_C64)
+    // matrix-core path: every wave needs a whole number of 16-pair groups
+    if ((n - 1) - lb - 2 >= 4) {
+        if (dt == QS_C64)
+            hipLaunchKernelGGL(k_fr_gram_mfma<float>, dim3(1u << lb), dim3(256), 0, st, (const float *)V, n,
+                               r, q, lb, partials);
+        else
+            hipLaunchKernelGGL(k_fr_gram_mfma<double>, dim3(1u << lb), dim3(256), 0, st, (const double *)V,
+                               n, r, q, lb, partials);
+    } else if (dt == QS_C64)
         hipLaunchKernelGGL(k_fr_gram<float>, dim3(1u << lb), dim3(256), 0, st, (const float *)V, n,
                            r, q, lb, partials);
     else

@@ -231,6 +231,40 @@ def test_dm_grover_against_oracle(dtype):
     assert abs(tr - 1.0) <= tol * 10
 
 
+def test_dm_grover13_full_size():
+    """vec(rho) at the full n = 13 (2^26 complex<double> entries).  A prefix of gates on the
+    lowest, middle and highest qubit plus the oracle flip is compared entry by entry with the
+    oracle; the whole circuit is checked through properties that hold at any size: the trace
+    stays 1 and <psi|rho|psi> equals the mean fidelity of Monte Carlo trajectories of the same
+    circuit (the Kraus channel of eq. 6 is the exact average over xi of eq. 1) within 5
+    standard errors."""
+    from workloads import Circuit
+    n, e = 13, 0.02
+    c = grover(n, seed=5)
+    hs = {g.q0: g for g in c.gates[:n]}
+    flip = next(g for g in c.gates if g.kind == FLIP)
+    prefix = Circuit(n, [hs[0], hs[n - 1], hs[6], flip], name="g13prefix", init_index=0, marked=c.marked)
+    rho = q.StateVector(2 * n, q.C128, 1)
+    rho.init_basis(0)
+    for g in prefix.gates:
+        q.dm_apply_gate(rho, g, e)
+    ref = oracle.dm_run(prefix, e)
+    got = from_device(rho)[0].reshape(1 << n, 1 << n)
+    assert rel_err(got, ref) <= 1e-12
+    del got, ref
+    rho.init_basis(0)
+    for g in c.gates:
+        q.dm_apply_gate(rho, g, e)
+    ideal = q.StateVector(n, q.C128, 1)
+    to_device_states(ideal, oracle.sv_run(c, 0.0)[None, :])
+    f, tr = q.dm_fidelity(rho, ideal, 0)
+    assert abs(tr - 1.0) <= 1e-11
+    T = 2048
+    res = q.run_trajectories(c.gates, n, 0, q.C128, T, e=e, seed=21)
+    mc, se = float(np.mean(res["F"])), float(np.std(res["F"]) / math.sqrt(T))
+    assert abs(f - mc) <= 5 * se, (f, mc, se)
+
+
 @pytest.mark.parametrize("dtype", [q.C128, q.C64])
 def test_apply_kraus_random_sets(dtype):
     n = 7
@@ -289,6 +323,37 @@ def test_fixed_rank_r8_against_oracle(dtype):
     fu_ref, fn_ref, lt_ref = ref.fidelity(ideal)
     if dtype == q.C128:
         assert ranks[-1] == len(ref.V)
+        assert abs(fu - fu_ref) <= 1e-11 and abs(fn - fn_ref) <= 1e-11 and abs(lt - lt_ref) <= 1e-11
+        rank, _ = fr.info()
+        V = fr.columns()[:rank].cpu().numpy().T
+        np.testing.assert_allclose(np.exp(lt) * V @ V.conj().T, ref.rho(), atol=1e-12)
+    else:
+        assert abs(fu - fu_ref) <= 1e-5 and abs(fn - fn_ref) <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+def test_fixed_rank_complex_amplitudes_against_oracle(dtype):
+    """Haar-random one-qubit gates make every amplitude complex, so the imaginary part of the
+    Gram matrix (and its orientation) matters; Grover alone stays real."""
+    from workloads import NOISE_NONE
+    n, e, r = 9, 0.05, 8
+    c = random_layers(n, 3, seed=12, pairing="random")
+    for g in c.gates:
+        if g.kind == CP:
+            g.noise = NOISE_NONE      # the fixed-rank form takes Kraus steps on one-qubit gates
+    tau = 1e-9
+    zt = 1e-13 if dtype == q.C128 else 1e-6
+    fr = q.FixedRank(n, r, dtype)
+    fr.init_basis(c.init_index)
+    ranks = [fr.apply_noisy_gate(g, e, tau=tau, zero_tol=zt) for g in c.gates]
+    ref = fixed_rank.run_circuit(c, e, r, tau=tau, zero_tol=1e-13)
+    ideal = oracle.sv_run(c, 0.0)
+    psi = q.StateVector(n, dtype, 1)
+    to_device_states(psi, ideal[None, :])
+    fu, fn, lt = fr.fidelity(psi)
+    fu_ref, fn_ref, lt_ref = ref.fidelity(ideal)
+    if dtype == q.C128:
+        assert ranks[-1] == len(ref.V) == r
         assert abs(fu - fu_ref) <= 1e-11 and abs(fn - fn_ref) <= 1e-11 and abs(lt - lt_ref) <= 1e-11
         rank, _ = fr.info()
         V = fr.columns()[:rank].cpu().numpy().T
