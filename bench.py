@@ -79,10 +79,11 @@ def main():
     seed = 1
     c = qft(n, seed=seed)
     ga = q.gate_array(c.gates)
-    plan = {"fuse": 1}
+    plan = {"fuse": -1}    # the library's automatic choice (cost model)
     if a.plan:
         kb, rb, runb = (int(x) for x in a.plan.split(","))
-        plan.update(tile_bits=kb, reg_bits=rb, run_bits=runb)
+        plan = {"fuse": 1, "tile_bits": kb, "reg_bits": rb, "run_bits": runb}
+    chosen = q.plan_choose(ga, n, q.C64)[0] if plan["fuse"] == -1 else plan
     need = q.traj_bytes_required(ga, n, q.C64, T, plan)
     buf = torch.empty(need, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
@@ -131,7 +132,7 @@ def main():
         "config": {"workload": f"qft{n}: {T} noisy trajectories (64 at e=0.001, 64 at e=0.01) + ideal, "
                                "complex64 amplitudes, FP64 fidelities, fused passes",
                    "n_qubits": n, "trajectories": T, "gates": len(c.gates), "seed": seed,
-                   "plan": plan},
+                   "plan": plan, "plan_chosen": chosen},
         "trajectories_per_s": T / (ms_step / 1e3),
         "hbm_frac_step": None,
         "roofline": roofline,

@@ -100,7 +100,8 @@ typedef struct {
 
 /* Execution plan for run_trajectories. */
 typedef struct {
-    int32_t fuse;      /* 0: one sweep kernel per gate; 1: fused passes; -1: library picks */
+    int32_t fuse;      /* 0: one sweep kernel per gate; 1: fused passes; -1: library picks
+                          (qs_plan_choose) unless a tile shape is given, then fused        */
     int32_t tile_bits; /* fused: amplitudes per tile = 2^tile_bits (0 = library picks)      */
     int32_t reg_bits;  /* fused: amplitudes per thread = 2^reg_bits (0 = library picks)     */
     int32_t run_bits;  /* fused: the 2^run_bits lowest-index amplitudes of a tile are one
@@ -196,6 +197,16 @@ qs_status qs_run_trajectories(const qs_gate *gates, int n_gates, int n_qubits,
  * partials, [13] results, [14] total.  No device work. */
 qs_status qs_traj_layout(const qs_gate *gates, int n_gates, int n_qubits, qs_dtype dt, int n_traj,
                          const qs_plan *plan, size_t *out);
+
+/* The plan chosen for fuse = -1 (with no tile shape given): unfused sweeps or a fused shape
+ * (tile_bits, reg_bits, run_bits) from a fixed set of candidates, whichever a cost model rates
+ * fastest for a batch of 64 slots.  The model prices each fused pass at the larger of its
+ * HBM time (one read and one write of the state) and its vector-ALU time (per-amplitude
+ * instruction counts of its ops), plus launches; unfused runs at each gate's sweep.  The
+ * choice depends only on the gates, n and dtype.  *model_s_per_slot (nullable) receives the
+ * modelled seconds per state slot.  No device work. */
+qs_status qs_plan_choose(const qs_gate *gates, int n_gates, int n_qubits, qs_dtype dt, qs_plan *out,
+                         double *model_s_per_slot);
 
 /* The fused-pass program the library builds for this circuit and plan, as JSON text (passes,
  * tile qubits, stages, register rounds, ops with their folded phases, final qubit layout), for

@@ -4,6 +4,7 @@
 #include <atomic>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -485,20 +486,10 @@ struct Plan {
     qs::Program prog;
 };
 
-qs_status resolve_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, int T, const qs_plan *p,
-                       Plan &out)
+qs_status fused_plan_for(const qs_gate *gates, int n_gates, int n, qs_dtype dt, int K, int RB, int run,
+                         Plan &out)
 {
-    int fuse = p ? p->fuse : -1;
-    if (fuse < -1 || fuse > 1) return fail(QS_EINVAL, "plan: fuse must be -1, 0 or 1");
-    if (fuse == -1) fuse = 1;
-    out.fused = fuse == 1;
-    if (!out.fused) return QS_OK;
-    // defaults: 2^12-amplitude tiles of 8 registers per thread (complex<float>), 2^11 of 4
-    // (complex<double>): the largest register tiles that stay out of scratch memory
-    int K = (p && p->tile_bits > 0) ? p->tile_bits : (dt == QS_C64 ? 12 : 11);
-    int RB = (p && p->reg_bits > 0) ? p->reg_bits : (dt == QS_C64 ? 3 : 2);
-    // rows of 2^run_bits contiguous amplitudes: 256 bytes
-    int run = (p && p->run_bits > 0) ? p->run_bits : (dt == QS_C64 ? 5 : 4);
+    out.fused = true;
     if (K > kMaxTileBits) return fail(QS_EINVAL, "plan: tile_bits too large");
     if ((size_t(1) << std::min(K, n)) * amp_bytes(dt) > 160 * 1024)
         return fail(QS_EINVAL, "plan: tile does not fit the 160 KiB LDS of a gfx950 CU");
@@ -510,10 +501,130 @@ qs_status resolve_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, in
     out.K = K;
     out.RB = RB;
     out.run_bits = run;
-    (void)T;
     int rec_cap = stage_rec_cap(dt, K);
     if (rec_cap < 256) return fail(QS_EINVAL, "plan: tile leaves too little LDS for the gate records");
     return plan_fused(gates, n_gates, n, K, RB, run, rec_cap, out.prog);
+}
+
+// ---------------------------------------------------------------------------------------
+// Plan cost model: seconds per state slot.  Each fused pass costs the larger of its HBM time
+// (one read and one write of the state, the first pass only a write) and its vector-ALU time
+// (per-amplitude instruction counts of each op kind, measured from the kernel's code), plus
+// the launch of its prep and pass kernels; an unfused run costs each gate's sweep.  The
+// constants are properties of the kernels on gfx950, so the choice is a pure function of the
+// circuit, n and the dtype.
+// ---------------------------------------------------------------------------------------
+constexpr double kModelHbm = 5.5e12;          // sustained bytes/s of a streaming kernel
+constexpr double kModelValu = 39.3e12 * 0.9;  // lane-instructions/s: 1024 SIMDs x 64 lanes / 4 cycles
+                                              // x 2.4 GHz, at the utilisation the pass reaches
+constexpr double kModelLaunch = 8e-6;         // s per pass (two launches, amortised over slots below)
+constexpr int kModelSlots = 64;
+
+// Fraction of the streaming bandwidth reached with rows of 2^run_bits contiguous amplitudes.
+static double row_efficiency(int run_bits, qs_dtype dt)
+{
+    const double bytes = std::ldexp((double)amp_bytes(dt), run_bits);
+    return bytes >= 256 ? 1.0 : bytes >= 128 ? 0.85 : bytes >= 64 ? 0.7 : 0.5;
+}
+
+double model_cost_fused(const Program &P, int n, qs_dtype dt, int S, int run_bits)
+{
+    const double N = std::ldexp(1.0, n), amp = (double)amp_bytes(dt);
+    const double wide = dt == QS_C128 ? 2.0 : 1.0;   // FP64 arithmetic: twice the instructions
+    const double eff = P.passes.size() && P.passes[0].outer_mask ? row_efficiency(run_bits, dt) : 1.0;
+    double total = 0.0;
+    for (size_t pi = 0; pi < P.passes.size(); ++pi) {
+        const PassDesc &pd = P.passes[pi];
+        double per_amp = 20.0;                                  // load/store, tile set-up
+        per_amp += 6.0 * (pd.round_end - pd.round_begin + 1);   // LDS exchanges
+        for (int oi = pd.op_begin; oi < pd.op_end; ++oi) {
+            const OpDesc &op = P.ops[oi];
+            if (op.type == OP_U1) {
+                per_amp += (op.flags & OPF_REAL) ? 7.0 : 10.0;
+                per_amp += 5.0 * ((op.pre_rec >= 0) + (op.post_rec >= 0));
+            } else if (op.type == OP_U2) {
+                per_amp += 27.0;
+            } else {
+                per_amp += 5.0;
+            }
+        }
+        const double mem = (pi == 0 ? 1.0 : 2.0) * N * amp / (kModelHbm * eff);
+        const double alu = N * per_amp * wide / kModelValu;
+        // the two overlap only in part: a pass waits on both its loads and its arithmetic
+        total += std::max(mem, alu) + 0.5 * std::min(mem, alu);
+    }
+    return total + kModelLaunch * (double)P.passes.size() / std::max(S, 1);
+}
+
+double model_cost_unfused(const qs_gate *gates, int n_gates, int n, qs_dtype dt, int S)
+{
+    const double N = std::ldexp(1.0, n), amp = (double)amp_bytes(dt);
+    double t = N * amp / kModelHbm;   // initial state
+    for (int g = 0; g < n_gates; ++g) {
+        double frac = 1.0;
+        switch (gates[g].kind) {
+        case QS_G_CP: frac = 0.5; break;   // touches N/4 amplitudes in lines of half the state
+        case QS_G_SWAP: frac = 1.0; break;
+        case QS_G_FLIP: frac = 0.0; break;
+        default: frac = 1.0;
+        }
+        t += 2.0 * frac * N * amp / kModelHbm + 4e-6 / std::max(S, 1);
+    }
+    return t;
+}
+
+// Candidate shapes per dtype: (tile bits, register bits, run bits).
+static const int kCandC64[][3] = {{12, 3, 5}, {12, 3, 4}, {12, 3, 3}, {11, 3, 4}, {11, 2, 3}, {10, 2, 3}};
+static const int kCandC128[][3] = {{11, 2, 4}, {11, 2, 3}, {10, 2, 3}, {10, 1, 3}};
+
+qs_status autotune_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, int S, Plan &out,
+                        double *cost_out)
+{
+    bool two_qubit_dense = false;
+    for (int g = 0; g < n_gates; ++g)
+        if (gates[g].kind == QS_G_U2 || gates[g].kind == QS_G_CNOT) two_qubit_dense = true;
+    double best = model_cost_unfused(gates, n_gates, n, dt, S);
+    out = Plan();
+    out.fused = false;
+    const int ncand = dt == QS_C64 ? 6 : 4;
+    for (int c = 0; c < ncand; ++c) {
+        const int *k = dt == QS_C64 ? kCandC64[c] : kCandC128[c];
+        if (two_qubit_dense && k[1] < 2) continue;
+        Plan cand;
+        if (fused_plan_for(gates, n_gates, n, dt, k[0], k[1], k[2], cand) != QS_OK) {
+            clear_error();
+            continue;
+        }
+        const double cost = model_cost_fused(cand.prog, n, dt, S, cand.run_bits);
+        if (cost < best * 0.999) {
+            best = cost;
+            out = std::move(cand);
+        }
+    }
+    if (cost_out) *cost_out = best;
+    return QS_OK;
+}
+
+qs_status resolve_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, int T, const qs_plan *p,
+                       Plan &out)
+{
+    int fuse = p ? p->fuse : -1;
+    if (fuse < -1 || fuse > 1) return fail(QS_EINVAL, "plan: fuse must be -1, 0 or 1");
+    const bool shape_given = p && (p->tile_bits > 0 || p->reg_bits > 0 || p->run_bits > 0);
+    // the automatic choice is priced for a batch of 64 slots whatever T is, so that every batch
+    // of a request (and the request alone) gets the same plan
+    (void)T;
+    if (fuse == -1 && !shape_given) return autotune_plan(gates, n_gates, n, dt, kModelSlots, out, nullptr);
+    if (fuse == -1) fuse = 1;
+    out.fused = fuse == 1;
+    if (!out.fused) return QS_OK;
+    // defaults: 2^12-amplitude tiles of 8 registers per thread (complex<float>), 2^11 of 4
+    // (complex<double>): the largest register tiles that stay out of scratch memory
+    int K = (p && p->tile_bits > 0) ? p->tile_bits : (dt == QS_C64 ? 12 : 11);
+    int RB = (p && p->reg_bits > 0) ? p->reg_bits : (dt == QS_C64 ? 3 : 2);
+    // rows of 2^run_bits contiguous amplitudes: 256 bytes
+    int run = (p && p->run_bits > 0) ? p->run_bits : (dt == QS_C64 ? 5 : 4);
+    return fused_plan_for(gates, n_gates, n, dt, K, RB, run, out);
 }
 
 TrajLayout traj_layout(int n, qs_dtype dt, int T, int n_gates, const Plan &pl)
@@ -750,6 +861,26 @@ qs_status qs_traj_layout(const qs_gate *gates, int n_gates, int n, qs_dtype dt, 
     return QS_OK;
 }
 
+qs_status qs_plan_choose(const qs_gate *gates, int n_gates, int n, qs_dtype dt, qs_plan *out,
+                         double *model_s_per_slot)
+{
+    clear_error();
+    if (!out) return fail(QS_EINVAL, "plan_choose: out is NULL");
+    if (n < 1 || n > 34) return fail(QS_EINVAL, "plan_choose: n_qubits must be in 1..34");
+    if (dt != QS_C64 && dt != QS_C128) return fail(QS_EINVAL, "plan_choose: unknown dtype");
+    qs_status v = check_circuit(gates, n_gates, n);
+    if (v != QS_OK) return v;
+    Plan pl;
+    double cost = 0.0;
+    if ((v = autotune_plan(gates, n_gates, n, dt, kModelSlots, pl, &cost)) != QS_OK) return v;
+    out->fuse = pl.fused ? 1 : 0;
+    out->tile_bits = pl.fused ? pl.K : 0;
+    out->reg_bits = pl.fused ? pl.RB : 0;
+    out->run_bits = pl.fused ? pl.run_bits : 0;
+    if (model_s_per_slot) *model_s_per_slot = cost;
+    return QS_OK;
+}
+
 qs_status qs_plan_describe(const qs_gate *gates, int n_gates, int n, qs_dtype dt, const qs_plan *plan,
                            char *buf, size_t cap, size_t *len)
 {
@@ -766,6 +897,14 @@ qs_status qs_plan_describe(const qs_gate *gates, int n_gates, int n, qs_dtype dt
     I("fused", pl.fused ? 1 : 0);
     I("K", pl.prog.K);
     I("RB", pl.prog.RB);
+    I("run_bits", pl.run_bits);
+    {
+        const double cost = pl.fused ? model_cost_fused(pl.prog, n, dt, kModelSlots, pl.run_bits)
+                                     : model_cost_unfused(gates, n_gates, n, dt, kModelSlots);
+        char b[64];
+        std::snprintf(b, sizeof b, "\"model_s_per_slot\":%.6e,", cost);
+        o += b;
+    }
     o += "\"layout\":[";
     for (size_t q = 0; q < pl.prog.layout.size(); ++q) o += (q ? "," : "") + std::to_string(pl.prog.layout[q]);
     o += "],\"passes\":[";

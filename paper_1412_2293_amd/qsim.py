@@ -23,7 +23,7 @@ NOISE_NONE, NOISE_ROT, NOISE_PHASE = 0, 1, 2
 __all__ = ["QsimError", "lib", "Gate", "Noise", "Plan", "C64", "C128", "gate_array",
            "sv_bytes_required", "StateVector", "apply_gate", "apply_kraus", "fidelity",
            "dm_fidelity", "dm_apply_gate", "noise_draw", "traj_bytes_required", "run_trajectories",
-           "timing_enable", "timing_read", "plan_describe", "traj_layout", "timing_reset", "copy", "FixedRank", "trajectory_states",
+           "timing_enable", "timing_read", "plan_describe", "plan_choose", "traj_layout", "timing_reset", "copy", "FixedRank", "trajectory_states",
            "fr_bytes_required", "Server", "SrvConfig", "SrvJobInfo", "SrvStats", "LIB_PATH"]
 
 
@@ -104,6 +104,7 @@ def lib():
         "qs_timing_enable": ([i32], st),
         "qs_traj_layout": ([P, i32, i32, i32, i32, ctypes.POINTER(Plan), P], st),
         "qs_plan_describe": ([P, i32, i32, i32, ctypes.POINTER(Plan), ctypes.c_char_p, sz, P], st),
+        "qs_plan_choose": ([P, i32, i32, i32, ctypes.POINTER(Plan), ctypes.POINTER(dbl)], st),
         "qs_timing_read": ([ctypes.c_char_p, P, P, P], st),
         "qs_timing_reset": ([], st),
         "qs_copy": ([P, P, sz, P], st),
@@ -342,6 +343,15 @@ def traj_layout(gates, n: int, dtype: int, n_traj: int, plan=None) -> dict:
     names = ["states", "tab", "gates", "edev", "passes", "stages", "rounds", "ops", "prefs", "jobs",
              "obits", "rec", "partials", "out", "total"]
     return {k: int(v) for k, v in zip(names, out)}
+
+
+def plan_choose(gates, n: int, dtype: int):
+    """The plan the library picks for fuse = -1 and its modelled seconds per state slot."""
+    ga = gates if isinstance(gates, ctypes.Array) else gate_array(gates)
+    p = Plan()
+    cost = ctypes.c_double()
+    _check(lib().qs_plan_choose(ga, len(ga), n, dtype, ctypes.byref(p), ctypes.byref(cost)), "plan_choose")
+    return {"fuse": p.fuse, "tile_bits": p.tile_bits, "reg_bits": p.reg_bits, "run_bits": p.run_bits}, cost.value
 
 
 def plan_describe(gates, n: int, dtype: int, plan=None) -> dict:

@@ -1,0 +1,64 @@
+"""Plan choice without a GPU: the library's cost-model choice (qs_plan_choose) and the
+measured-autotuner cache lookups."""
+import json
+
+import pytest
+
+import paper_1412_2293_amd as q
+from paper_1412_2293_amd import autotune
+from workloads import grover, qft, random_layers, random_mixed_circuit
+
+
+CIRCUITS = [qft(26, 1), qft(14, 2), grover(22, 1, iterations=5), random_layers(20, 10, 3, pairing="random"),
+            random_mixed_circuit(16, 80, 4), grover(9, 2)]
+
+
+@pytest.mark.parametrize("dtype", [q.C64, q.C128])
+def test_choice_is_valid_and_deterministic(dtype):
+    for c in CIRCUITS:
+        p1, c1 = q.plan_choose(c.gates, c.n, dtype)
+        p2, c2 = q.plan_choose(q.gate_array(c.gates), c.n, dtype)
+        assert p1 == p2 and c1 == c2 and c1 > 0
+        assert p1["fuse"] in (0, 1)
+        # the chosen plan is accepted as an explicit plan and builds the same program
+        d = q.plan_describe(c.gates, c.n, dtype, p1)
+        auto = q.plan_describe(c.gates, c.n, dtype, {"fuse": -1})
+        assert d == auto
+        assert q.traj_bytes_required(c.gates, c.n, dtype, 4, {"fuse": -1}) > 0
+
+
+def test_model_prefers_long_rows_on_qft26():
+    p, _ = q.plan_choose(qft(26, 1).gates, 26, q.C64)
+    assert p == {"fuse": 1, "tile_bits": 12, "reg_bits": 3, "run_bits": 5}
+
+
+def test_model_cost_matches_describe():
+    c = qft(24, 5)
+    p, cost = q.plan_choose(c.gates, c.n, q.C64)
+    d = q.plan_describe(c.gates, c.n, q.C64, p)
+    assert d["model_s_per_slot"] == pytest.approx(cost, rel=1e-6)
+    # fused beats per-gate sweeps by a wide margin on a QFT
+    unf = q.plan_describe(c.gates, c.n, q.C64, {"fuse": 0})
+    assert unf["fused"] == 0 and unf["model_s_per_slot"] > 5 * cost
+
+
+def test_circuit_class_is_the_same_for_both_gate_forms():
+    for c in CIRCUITS:
+        assert autotune.circuit_class(c.gates) == autotune.circuit_class(q.gate_array(c.gates))
+    assert autotune.circuit_class(qft(12, 0).gates) != autotune.circuit_class(grover(12, 0).gates)
+
+
+def test_cache_lookup_and_fallback(tmp_path):
+    c = qft(18, 3)
+    path = str(tmp_path / "plans.json")
+    assert autotune.plan_for(c.gates, c.n, q.C64, path, arch="gfx950") == {"fuse": -1}
+    key = autotune.cache_key(c.n, q.C64, c.gates, "gfx950")
+    plan = {"fuse": 1, "tile_bits": 11, "reg_bits": 3, "run_bits": 4}
+    with open(path, "w") as fh:
+        json.dump({key: {"plan": plan, "seconds": 1.0}}, fh)
+    assert autotune.lookup(c.gates, c.n, q.C64, path, arch="gfx950") == plan
+    assert autotune.plan_for(c.gates, c.n, q.C64, path, arch="gfx950") == plan
+    # another dtype, size or architecture misses
+    assert autotune.lookup(c.gates, c.n, q.C128, path, arch="gfx950") is None
+    assert autotune.lookup(c.gates, 17, q.C64, path, arch="gfx950") is None
+    assert autotune.lookup(c.gates, c.n, q.C64, path, arch="gfx942") is None
