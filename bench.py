@@ -157,6 +157,7 @@ def main():
         torch.cuda.empty_cache()
         out["sweeps_n28"] = sweeps(q)
         torch.cuda.empty_cache()
+        out["graph_replay"] = graph_bench(q, torch)
         out["dm13"] = dm13_bench(q, torch)
         torch.cuda.empty_cache()
         out["fr24"] = fr24_bench(q, torch)
@@ -237,6 +238,36 @@ def sweeps(q):
         del sv
         torch.cuda.empty_cache()
     return out
+
+
+def graph_bench(q, torch, reps=20):
+    """A launch-bound run: random layers on n = 14 (depth 60, random pairs), 16 trajectories,
+    complex64, hundreds of short fused passes.  Eager launches vs one captured-graph replay per
+    run; the results are identical."""
+    import numpy as np
+    from workloads import random_layers
+    c = random_layers(14, 60, 8, pairing="random")
+    ga = q.gate_array(c.gates)
+    T = 16
+    need = q.traj_bytes_required(ga, c.n, q.C64, T)
+    buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+    eager = q.run_trajectories(ga, c.n, 0, q.C64, T, e=0.01, seed=1, buf=buf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(reps):
+        q.run_trajectories(ga, c.n, 0, q.C64, T, e=0.01, seed=1 + k, buf=buf)
+    t_eager = (time.perf_counter() - t0) / reps
+    with q.TrajGraph(ga, c.n, q.C64, T) as g:
+        got = g.launch(0, e=0.01, seed=1)
+        same = bool(np.array_equal(got["F"], eager["F"]))
+        t0 = time.perf_counter()
+        for k in range(reps):
+            g.launch(0, e=0.01, seed=1 + k)
+        t_graph = (time.perf_counter() - t0) / reps
+    passes = len(q.plan_describe(ga, c.n, q.C64)["passes"])
+    return {"workload": f"random14x60 (random pairs), T={T}, complex64", "fused_passes": passes,
+            "kernel_launches": 2 * passes + 3, "eager_ms": t_eager * 1e3, "graph_ms": t_graph * 1e3,
+            "speedup": t_eager / t_graph, "results_identical": same}
 
 
 def dm13_bench(q, torch):

@@ -190,6 +190,24 @@ qs_status qs_run_trajectories(const qs_gate *gates, int n_gates, int n_qubits,
                               size_t buf_bytes, void *hip_stream, double *fid_out,
                               double *p_out, double *norm_out, int32_t *layout_out);
 
+/* Captured trajectory runs: the whole launch sequence of qs_run_trajectories for one circuit,
+ * n_traj and buffer, recorded once as a HIP graph and replayed per run.  The per-run values
+ * (noise seed, request, trajectory base, per-trajectory strengths, initial and marked index)
+ * travel through pinned host memory and device memory read by the kernels, so one graph
+ * serves every run; results equal qs_run_trajectories with the same plan bit for bit.  For
+ * circuits whose passes are short (small n, many gates) replay removes the per-launch host
+ * cost.  The graph owns a stream, pinned buffers and the instantiated graph; the caller owns
+ * dev_buf, which must stay allocated and unused by other work until qs_traj_graph_destroy. */
+typedef struct qs_traj_graph_s *qs_traj_graph;
+qs_status qs_traj_graph_bytes_required(const qs_gate *gates, int n_gates, int n_qubits, qs_dtype dt,
+                                       int n_traj, const qs_plan *plan, size_t *bytes);
+qs_status qs_traj_graph_create(const qs_gate *gates, int n_gates, int n_qubits, qs_dtype dt, int n_traj,
+                               const qs_plan *plan, void *dev_buf, size_t buf_bytes, qs_traj_graph *out);
+/* One replay; blocks until the results (as in qs_run_trajectories) are on the host. */
+qs_status qs_traj_graph_launch(qs_traj_graph g, uint64_t init_index, const qs_noise *nz, int64_t marked,
+                               double *fid_out, double *p_out, double *norm_out, int32_t *layout_out);
+qs_status qs_traj_graph_destroy(qs_traj_graph g);
+
 /* Byte offsets, inside the qs_run_trajectories buffer, of its regions (for inspection):
  * out[0] states, [1] noise table (per gate and slot: 8 doubles), [2] device gates, [3] per-slot
  * noise strengths, [4] pass, [5] stage, [6] round, [7] op, [8] phase-reference, [9] outer-job,

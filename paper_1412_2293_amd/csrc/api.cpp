@@ -54,6 +54,8 @@ static std::vector<std::pair<std::string, Acc>> g_acc;
 TimedLaunch::TimedLaunch(const char *nm, double bytes, hipStream_t s) : name(nm), alg_bytes(bytes), st(s)
 {
     if (!g_timing) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;   // graphs: untimed
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
     if (hipEventRecord(a, st) != hipSuccess) return;
     on = true;
@@ -477,7 +479,7 @@ qs_status qs_timing_reset(void)
 namespace {
 
 struct TrajLayout {
-    size_t states, tab, gates, edev, passes, stages, rounds, ops, prefs, jobs, obits, rec, partials, out, total;
+    size_t states, tab, gates, edev, passes, stages, rounds, ops, prefs, jobs, obits, rec, partials, out, dyn, total;
 };
 
 struct Plan {
@@ -651,6 +653,7 @@ TrajLayout traj_layout(int n, qs_dtype dt, int T, int n_gates, const Plan &pl)
     L.rec = take((size_t)std::max(pl.prog.max_rec, 1) * S * 2 * (dt == QS_C64 ? 4 : 8));
     L.partials = take(reduce_partials_doubles(n, S) * sizeof(double));
     L.out = take((size_t)S * 5 * sizeof(double));
+    L.dyn = take(sizeof(RunParams));
     L.total = off;
     return L;
 }
@@ -715,62 +718,55 @@ size_t traj_prep_bytes(const TrajPrep &prep, int T)
     return T < 1 ? 0 : prep_layout(prep, T).total;
 }
 
-qs_status traj_launch(const TrajPrep &prep, uint64_t init_index, const qs_noise *nz, int T, int64_t marked,
-                      void *dev_buf, size_t buf_bytes, hipStream_t st, double *host_out, TrajRun &run)
+// Host-to-device copies of the gates and the fused program (the host arrays stay in prep).
+static qs_status upload_program(const TrajPrep &prep, const TrajLayout &L, char *B, hipStream_t st)
+{
+    const int n_gates = (int)prep.hg.size();
+    if (n_gates > 0)
+        QS_HIP(hipMemcpyAsync(B + L.gates, prep.hg.data(), sizeof(qs_gate) * n_gates, hipMemcpyHostToDevice, st));
+    const Program &P = prep.prog;
+    if (!prep.fused) return QS_OK;
+    if (!P.passes.empty())
+        QS_HIP(hipMemcpyAsync(B + L.passes, P.passes.data(), sizeof(PassDesc) * P.passes.size(), hipMemcpyHostToDevice, st));
+    if (!P.stages.empty())
+        QS_HIP(hipMemcpyAsync(B + L.stages, P.stages.data(), sizeof(StageDesc) * P.stages.size(), hipMemcpyHostToDevice, st));
+    if (!P.rounds.empty())
+        QS_HIP(hipMemcpyAsync(B + L.rounds, P.rounds.data(), sizeof(RoundDesc) * P.rounds.size(), hipMemcpyHostToDevice, st));
+    if (!P.ops.empty())
+        QS_HIP(hipMemcpyAsync(B + L.ops, P.ops.data(), sizeof(OpDesc) * P.ops.size(), hipMemcpyHostToDevice, st));
+    if (!P.prefs.empty())
+        QS_HIP(hipMemcpyAsync(B + L.prefs, P.prefs.data(), sizeof(PrepRef) * P.prefs.size(), hipMemcpyHostToDevice, st));
+    if (!P.jobs.empty())
+        QS_HIP(hipMemcpyAsync(B + L.jobs, P.jobs.data(), sizeof(OuterJob) * P.jobs.size(), hipMemcpyHostToDevice, st));
+    if (!P.obits.empty())
+        QS_HIP(hipMemcpyAsync(B + L.obits, P.obits.data(), sizeof(int32_t) * P.obits.size(), hipMemcpyHostToDevice, st));
+    return QS_OK;
+}
+
+// Noise table, initial state, the circuit (fused passes or per-gate sweeps) and the FP64
+// reductions into L.out.  With dyn non-null the seed, request, trajectory base, initial index
+// and marked index come from device memory (captured graphs).
+static qs_status enqueue_compute(const TrajPrep &prep, const TrajLayout &L, char *B, int S, uint64_t init_index,
+                                 int64_t pmarked, const qs_noise *nz, const RunParams *dyn, hipStream_t st)
 {
     const int n = prep.n;
     const qs_dtype dt = prep.dt;
     const int n_gates = (int)prep.hg.size();
-    if (T < 1) return fail(QS_EINVAL, "run_trajectories: n_traj must be >= 1");
-    if (init_index >= (1ull << n)) return fail(QS_EINVAL, "run_trajectories: init_index out of range");
-    if (marked >= (int64_t)(1ull << n)) return fail(QS_EINVAL, "run_trajectories: marked out of range");
-    if (!dev_buf || !aligned256(dev_buf))
-        return fail(QS_EINVAL, "run_trajectories: buffer must be non-NULL and 256-byte aligned");
-    qs_status v = check_noise(nz, T);
-    if (v != QS_OK) return v;
-    TrajLayout L = prep_layout(prep, T);
-    if (buf_bytes < L.total)
-        return fail(QS_EINVAL, "run_trajectories: buffer too small (need " + std::to_string(L.total) + " bytes)");
-
-    char *B = (char *)dev_buf;
-    const int S = T + 1;
     void *psi = B + L.states;
     double *tab = (double *)(B + L.tab);
     qs_gate *gdev = (qs_gate *)(B + L.gates);
-    double *edev = (double *)(B + L.edev);
-    run.T = T;
-    run.he.assign(S, 0.0);
-    for (int t = 0; t < T; ++t) run.he[t + 1] = nz ? (nz->e_per_traj ? nz->e_per_traj[t] : nz->e) : 0.0;
-    if (n_gates > 0)
-        QS_HIP(hipMemcpyAsync(gdev, prep.hg.data(), sizeof(qs_gate) * n_gates, hipMemcpyHostToDevice, st));
-    QS_HIP(hipMemcpyAsync(edev, run.he.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
     const Program &P = prep.prog;
-    if (prep.fused) {
-        if (!P.passes.empty())
-            QS_HIP(hipMemcpyAsync(B + L.passes, P.passes.data(), sizeof(PassDesc) * P.passes.size(), hipMemcpyHostToDevice, st));
-        if (!P.stages.empty())
-            QS_HIP(hipMemcpyAsync(B + L.stages, P.stages.data(), sizeof(StageDesc) * P.stages.size(), hipMemcpyHostToDevice, st));
-        if (!P.rounds.empty())
-            QS_HIP(hipMemcpyAsync(B + L.rounds, P.rounds.data(), sizeof(RoundDesc) * P.rounds.size(), hipMemcpyHostToDevice, st));
-        if (!P.ops.empty())
-            QS_HIP(hipMemcpyAsync(B + L.ops, P.ops.data(), sizeof(OpDesc) * P.ops.size(), hipMemcpyHostToDevice, st));
-        if (!P.prefs.empty())
-            QS_HIP(hipMemcpyAsync(B + L.prefs, P.prefs.data(), sizeof(PrepRef) * P.prefs.size(), hipMemcpyHostToDevice, st));
-        if (!P.jobs.empty())
-            QS_HIP(hipMemcpyAsync(B + L.jobs, P.jobs.data(), sizeof(OuterJob) * P.jobs.size(), hipMemcpyHostToDevice, st));
-        if (!P.obits.empty())
-            QS_HIP(hipMemcpyAsync(B + L.obits, P.obits.data(), sizeof(int32_t) * P.obits.size(), hipMemcpyHostToDevice, st));
-    }
     NoiseArgs na{};
+    na.dyn = dyn;
     na.e = 0.0;
-    na.e_dev = edev;
+    na.e_dev = (double *)(B + L.edev);
     na.seed = nz ? nz->seed : 0;
     na.request = nz ? nz->request : 0;
     na.traj_base = nz ? nz->traj_base : 0;
     na.first_noisy_slot = 1;
     QS_HIP(launch_noise_table(gdev, n_gates, S, na, tab, st));
     // fused runs make the initial state inside their first pass
-    if (!prep.fused || P.passes.empty()) QS_HIP(launch_init_basis(psi, dt, n, S, init_index, st));
+    if (!prep.fused || P.passes.empty()) QS_HIP(launch_init_basis(psi, dt, n, S, init_index, st, dyn));
     if (prep.fused) {
         ProgramDev pdv{(const PassDesc *)(B + L.passes), (const StageDesc *)(B + L.stages),
                        (const RoundDesc *)(B + L.rounds), (const OpDesc *)(B + L.ops),
@@ -779,7 +775,7 @@ qs_status traj_launch(const TrajPrep &prep, uint64_t init_index, const qs_noise 
         for (size_t p = 0; p < P.passes.size(); ++p) {
             QS_HIP(launch_pass_prep(dt, S, &P.passes[p], pdv, tab, gdev, B + L.rec, st));
             QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (int)p, p == 0 ? (int64_t)init_index : -1, pdv,
-                                     B + L.rec, st));
+                                     B + L.rec, st, dyn));
         }
     } else {
         for (int g = 0; g < n_gates; ++g) {
@@ -795,22 +791,51 @@ qs_status traj_launch(const TrajPrep &prep, uint64_t init_index, const qs_noise 
             }
         }
     }
-    int64_t pmarked = -1;
-    if (marked >= 0) {
-        pmarked = 0;
-        for (int q = 0; q < n; ++q)
-            if ((marked >> q) & 1) pmarked |= (int64_t)1 << prep.layout[q];
-    }
-    double *part = (double *)(B + L.partials);
-    double *out = (double *)(B + L.out);
-    QS_HIP(launch_overlaps(psi, 0, psi, dt, n, S, pmarked, part, out, st));
+    QS_HIP(launch_overlaps(psi, 0, psi, dt, n, S, pmarked, (double *)(B + L.partials), (double *)(B + L.out), st,
+                           dyn));
+    return QS_OK;
+}
+
+static int64_t physical_marked(const TrajPrep &prep, int64_t marked)
+{
+    if (marked < 0) return -1;
+    int64_t pm = 0;
+    for (int q = 0; q < prep.n; ++q)
+        if ((marked >> q) & 1) pm |= (int64_t)1 << prep.layout[q];
+    return pm;
+}
+
+qs_status traj_launch(const TrajPrep &prep, uint64_t init_index, const qs_noise *nz, int T, int64_t marked,
+                      void *dev_buf, size_t buf_bytes, hipStream_t st, double *host_out, TrajRun &run)
+{
+    const int n = prep.n;
+    if (T < 1) return fail(QS_EINVAL, "run_trajectories: n_traj must be >= 1");
+    if (init_index >= (1ull << n)) return fail(QS_EINVAL, "run_trajectories: init_index out of range");
+    if (marked >= (int64_t)(1ull << n)) return fail(QS_EINVAL, "run_trajectories: marked out of range");
+    if (!dev_buf || !aligned256(dev_buf))
+        return fail(QS_EINVAL, "run_trajectories: buffer must be non-NULL and 256-byte aligned");
+    qs_status v = check_noise(nz, T);
+    if (v != QS_OK) return v;
+    TrajLayout L = prep_layout(prep, T);
+    if (buf_bytes < L.total)
+        return fail(QS_EINVAL, "run_trajectories: buffer too small (need " + std::to_string(L.total) + " bytes)");
+
+    char *B = (char *)dev_buf;
+    const int S = T + 1;
+    run.T = T;
+    run.he.assign(S, 0.0);
+    for (int t = 0; t < T; ++t) run.he[t + 1] = nz ? (nz->e_per_traj ? nz->e_per_traj[t] : nz->e) : 0.0;
+    if ((v = upload_program(prep, L, B, st)) != QS_OK) return v;
+    QS_HIP(hipMemcpyAsync(B + L.edev, run.he.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
+    if ((v = enqueue_compute(prep, L, B, S, init_index, physical_marked(prep, marked), nz, nullptr, st)) != QS_OK)
+        return v;
     if (host_out) {
         run.host = host_out;
     } else {
         run.host_own.resize((size_t)S * 5);
         run.host = run.host_own.data();
     }
-    QS_HIP(hipMemcpyAsync(run.host, out, sizeof(double) * S * 5, hipMemcpyDeviceToHost, st));
+    QS_HIP(hipMemcpyAsync(run.host, B + L.out, sizeof(double) * S * 5, hipMemcpyDeviceToHost, st));
     return QS_OK;
 }
 
@@ -996,6 +1021,160 @@ qs_status qs_run_trajectories(const qs_gate *gates, int n_gates, int n, uint64_t
         return v;
     QS_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
     qs::traj_finalize(prep, run, fid_out, p_out, norm_out, layout_out);
+    return QS_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Captured trajectory runs
+// ---------------------------------------------------------------------------------------
+struct qs_traj_graph_s {
+    qs::TrajPrep prep;
+    int T = 0;
+    char *buf = nullptr;
+    TrajLayout L{};
+    int device = 0;
+    hipStream_t st = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double *h_out = nullptr;          // pinned: S * 5 result doubles
+    double *h_e = nullptr;            // pinned: S per-slot noise strengths
+    RunParams *h_params = nullptr;    // pinned: per-run values
+};
+
+static void graph_free(qs_traj_graph_s *g)
+{
+    if (!g) return;
+    if (g->st) (void)hipStreamSynchronize(g->st);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->h_out) (void)hipHostFree(g->h_out);
+    if (g->h_e) (void)hipHostFree(g->h_e);
+    if (g->h_params) (void)hipHostFree(g->h_params);
+    if (g->st) (void)hipStreamDestroy(g->st);
+    delete g;
+}
+
+qs_status qs_traj_graph_bytes_required(const qs_gate *gates, int n_gates, int n, qs_dtype dt, int T,
+                                       const qs_plan *plan, size_t *bytes)
+{
+    clear_error();
+    if (!bytes) return fail(QS_EINVAL, "traj_graph_bytes_required: bytes is NULL");
+    if (T < 1) return fail(QS_EINVAL, "traj_graph_bytes_required: n_traj must be >= 1");
+    qs::TrajPrep prep;
+    qs_status v = qs::traj_prepare(gates, n_gates, n, dt, plan, prep);
+    if (v != QS_OK) return v;
+    *bytes = qs::traj_prep_bytes(prep, T);
+    return QS_OK;
+}
+
+qs_status qs_traj_graph_create(const qs_gate *gates, int n_gates, int n, qs_dtype dt, int T, const qs_plan *plan,
+                               void *dev_buf, size_t buf_bytes, qs_traj_graph *out)
+{
+    clear_error();
+    if (!out) return fail(QS_EINVAL, "traj_graph_create: out is NULL");
+    *out = nullptr;
+    if (T < 1) return fail(QS_EINVAL, "traj_graph_create: n_traj must be >= 1");
+    if (!dev_buf || !aligned256(dev_buf))
+        return fail(QS_EINVAL, "traj_graph_create: buffer must be non-NULL and 256-byte aligned");
+    auto *g = new qs_traj_graph_s();
+    qs_status v = qs::traj_prepare(gates, n_gates, n, dt, plan, g->prep);
+    if (v != QS_OK) {
+        delete g;
+        return v;
+    }
+    g->T = T;
+    g->L = qs::prep_layout(g->prep, T);
+    if (buf_bytes < g->L.total) {
+        delete g;
+        return fail(QS_EINVAL, "traj_graph_create: buffer too small (need " + std::to_string(g->L.total) + " bytes)");
+    }
+    g->buf = (char *)dev_buf;
+    const int S = T + 1;
+    auto bail = [&](hipError_t e, const char *what) {
+        (void)hipGetLastError();
+        if (g->st) {
+            hipGraph_t partial = nullptr;
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(g->st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+                (void)hipStreamEndCapture(g->st, &partial);
+                if (partial) (void)hipGraphDestroy(partial);
+            }
+        }
+        graph_free(g);
+        return hip_fail(e, what);
+    };
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&g->st, hipStreamNonBlocking)) != hipSuccess) return bail(e, "stream");
+    if ((e = hipHostMalloc((void **)&g->h_out, sizeof(double) * 5 * S, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&g->h_e, sizeof(double) * S, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&g->h_params, sizeof(RunParams), hipHostMallocDefault)) != hipSuccess)
+        return bail(e, "hipHostMalloc");
+    std::memset(g->h_e, 0, sizeof(double) * S);
+    std::memset(g->h_params, 0, sizeof(RunParams));
+    if ((v = qs::upload_program(g->prep, g->L, g->buf, g->st)) != QS_OK) {
+        graph_free(g);
+        return v;
+    }
+    if ((e = hipStreamSynchronize(g->st)) != hipSuccess) return bail(e, "upload");
+    if ((e = fused_prepare_attributes()) != hipSuccess) return bail(e, "fused kernel attributes");
+    const RunParams *dyn = (const RunParams *)(g->buf + g->L.dyn);
+    if ((e = hipStreamBeginCapture(g->st, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return bail(e, "hipStreamBeginCapture");
+    if ((e = hipMemcpyAsync(g->buf + g->L.dyn, g->h_params, sizeof(RunParams), hipMemcpyHostToDevice, g->st)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(g->buf + g->L.edev, g->h_e, sizeof(double) * S, hipMemcpyHostToDevice, g->st)) !=
+            hipSuccess)
+        return bail(e, "capture copies");
+    // kernel arguments that dyn overrides carry placeholders: the first pass is always a
+    // making pass (init 0) and the marked amplitude is read when dyn->marked >= 0
+    if ((v = qs::enqueue_compute(g->prep, g->L, g->buf, S, 0, 0, nullptr, dyn, g->st)) != QS_OK) {
+        std::string msg = qs_last_error();
+        (void)bail(hipSuccess, "capture");
+        return fail(v, msg);
+    }
+    if ((e = hipMemcpyAsync(g->h_out, g->buf + g->L.out, sizeof(double) * 5 * S, hipMemcpyDeviceToHost, g->st)) !=
+        hipSuccess)
+        return bail(e, "capture copies");
+    if ((e = hipStreamEndCapture(g->st, &g->graph)) != hipSuccess) return bail(e, "hipStreamEndCapture");
+    if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess)
+        return bail(e, "hipGraphInstantiate");
+    *out = g;
+    return QS_OK;
+}
+
+qs_status qs_traj_graph_launch(qs_traj_graph g, uint64_t init_index, const qs_noise *nz, int64_t marked,
+                               double *fid_out, double *p_out, double *norm_out, int32_t *layout_out)
+{
+    clear_error();
+    if (!g || !fid_out) return fail(QS_EINVAL, "traj_graph_launch: NULL graph or fid_out");
+    const int n = g->prep.n, T = g->T, S = T + 1;
+    if (init_index >= (1ull << n)) return fail(QS_EINVAL, "traj_graph_launch: init_index out of range");
+    if (marked >= (int64_t)(1ull << n)) return fail(QS_EINVAL, "traj_graph_launch: marked out of range");
+    if (p_out && marked < 0) return fail(QS_EINVAL, "traj_graph_launch: p_out needs marked >= 0");
+    qs_status v = check_noise(nz, T);
+    if (v != QS_OK) return v;
+    // the previous replay has finished (launch blocks), so the pinned inputs are free
+    g->h_params->seed = nz ? nz->seed : 0;
+    g->h_params->request = nz ? nz->request : 0;
+    g->h_params->traj_base = nz ? nz->traj_base : 0;
+    g->h_params->init = (int64_t)init_index;
+    g->h_params->marked = qs::physical_marked(g->prep, marked);
+    g->h_e[0] = 0.0;
+    for (int t = 0; t < T; ++t) g->h_e[t + 1] = nz ? (nz->e_per_traj ? nz->e_per_traj[t] : nz->e) : 0.0;
+    QS_HIP(hipGraphLaunch(g->exec, g->st));
+    QS_HIP(hipStreamSynchronize(g->st));
+    qs::TrajRun run;
+    run.T = T;
+    run.host = g->h_out;
+    qs::traj_finalize(g->prep, run, fid_out, p_out, norm_out, layout_out);
+    (void)S;
+    return QS_OK;
+}
+
+qs_status qs_traj_graph_destroy(qs_traj_graph g)
+{
+    clear_error();
+    graph_free(g);
     return QS_OK;
 }
 

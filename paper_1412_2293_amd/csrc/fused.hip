@@ -324,6 +324,7 @@ __device__ __forceinline__ void copy_words(uint32_t *dst, const uint32_t *src, i
 template <typename R, int RB>
 __global__ void __launch_bounds__(512, 4) k_fused(R *__restrict__ psi, int n, int S, int pass_index,
                                                   int rec_cap, int64_t init,
+                                                  const RunParams *__restrict__ dyn,
                                                   const PassDesc *__restrict__ g_passes,
                                                   const StageDesc *__restrict__ g_stages,
                                                   const RoundDesc *__restrict__ g_rounds,
@@ -381,6 +382,7 @@ __global__ void __launch_bounds__(512, 4) k_fused(R *__restrict__ psi, int n, in
     }
     R *base = psi + ((uint64_t)slot << (n + 1));
     cxf<R> a[NR];
+    if (init >= 0 && dyn) init = dyn->init;
     if (init >= 0) {
         // first pass of a run: every slot starts in the basis state |init>, made here
         // instead of read from memory
@@ -556,24 +558,44 @@ hipError_t launch_pass_prep(qs_dtype dt, int S, const PassDesc *h, ProgramDev pr
     return hipGetLastError();
 }
 
+// thread-safe one-time opt-in to the full 160 KiB of LDS
 template <typename R, int RB>
-static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_index, int rec_cap,
-                           int64_t init, ProgramDev prog, const void *rec, size_t lds, hipStream_t st)
+static hipError_t fused_attr()
 {
-    // thread-safe one-time opt-in to the full 160 KiB of LDS
     static const hipError_t attr = hipFuncSetAttribute((const void *)k_fused<R, RB>,
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    return attr;
+}
+
+hipError_t fused_prepare_attributes()
+{
+    hipError_t e;
+    if ((e = fused_attr<float, 1>()) != hipSuccess || (e = fused_attr<float, 2>()) != hipSuccess ||
+        (e = fused_attr<float, 3>()) != hipSuccess || (e = fused_attr<float, 4>()) != hipSuccess ||
+        (e = fused_attr<double, 1>()) != hipSuccess || (e = fused_attr<double, 2>()) != hipSuccess ||
+        (e = fused_attr<double, 3>()) != hipSuccess || (e = fused_attr<double, 4>()) != hipSuccess)
+        return e;
+    return hipSuccess;
+}
+
+template <typename R, int RB>
+static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_index, int rec_cap,
+                           int64_t init, const RunParams *dyn, ProgramDev prog, const void *rec, size_t lds,
+                           hipStream_t st)
+{
+    const hipError_t attr = fused_attr<R, RB>();
     if (attr != hipSuccess) return attr;
     unsigned blocks = (unsigned)((uint64_t)S << (n - h.K));
     unsigned threads = 1u << (h.K - RB);
     hipLaunchKernelGGL((k_fused<R, RB>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index,
-                       rec_cap, init, prog.passes, prog.stages, prog.rounds, prog.ops, prog.jobs, prog.obits,
+                       rec_cap, init, dyn, prog.passes, prog.stages, prog.rounds, prog.ops, prog.jobs, prog.obits,
                        (const cxf<R> *)rec);
     return hipGetLastError();
 }
 
 hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDesc *pass_host,
-                             int pass_index, int64_t init, ProgramDev prog, const void *rec, hipStream_t st)
+                             int pass_index, int64_t init, ProgramDev prog, const void *rec, hipStream_t st,
+                             const RunParams *dyn)
 {
     const PassDesc &h = *pass_host;
     size_t lds = fused_lds_bytes(dt, h.K);
@@ -584,18 +606,18 @@ hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDes
     if (dt == QS_C64) {
         float *p = (float *)psi;
         switch (h.RB) {
-        case 1: return launch_t<float, 1>(p, n, S, h, pass_index, rec_cap, init, prog, rec, lds, st);
-        case 2: return launch_t<float, 2>(p, n, S, h, pass_index, rec_cap, init, prog, rec, lds, st);
-        case 3: return launch_t<float, 3>(p, n, S, h, pass_index, rec_cap, init, prog, rec, lds, st);
-        case 4: return launch_t<float, 4>(p, n, S, h, pass_index, rec_cap, init, prog, rec, lds, st);
+        case 1: return launch_t<float, 1>(p, n, S, h, pass_index, rec_cap, init, dyn, prog, rec, lds, st);
+        case 2: return launch_t<float, 2>(p, n, S, h, pass_index, rec_cap, init, dyn, prog, rec, lds, st);
+        case 3: return launch_t<float, 3>(p, n, S, h, pass_index, rec_cap, init, dyn, prog, rec, lds, st);
+        case 4: return launch_t<float, 4>(p, n, S, h, pass_index, rec_cap, init, dyn, prog, rec, lds, st);
         }
     } else {
         double *p = (double *)psi;
         switch (h.RB) {
-        case 1: return launch_t<double, 1>(p, n, S, h, pass_index, rec_cap, init, prog, rec, lds, st);
-        case 2: return launch_t<double, 2>(p, n, S, h, pass_index, rec_cap, init, prog, rec, lds, st);
-        case 3: return launch_t<double, 3>(p, n, S, h, pass_index, rec_cap, init, prog, rec, lds, st);
-        case 4: return launch_t<double, 4>(p, n, S, h, pass_index, rec_cap, init, prog, rec, lds, st);
+        case 1: return launch_t<double, 1>(p, n, S, h, pass_index, rec_cap, init, dyn, prog, rec, lds, st);
+        case 2: return launch_t<double, 2>(p, n, S, h, pass_index, rec_cap, init, dyn, prog, rec, lds, st);
+        case 3: return launch_t<double, 3>(p, n, S, h, pass_index, rec_cap, init, dyn, prog, rec, lds, st);
+        case 4: return launch_t<double, 4>(p, n, S, h, pass_index, rec_cap, init, dyn, prog, rec, lds, st);
         }
     }
     return hipErrorInvalidValue;

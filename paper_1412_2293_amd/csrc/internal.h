@@ -139,7 +139,19 @@ struct OuterJob {
 // Launchers (kernels.hip / fused.hip / fr.hip).  All asynchronous on `st`.
 // Noise table: tab[(g * S + s) * 8 + 0..7] = complex 2x2 (U1) or phase in [0..1] (CP), FP64.
 // ---------------------------------------------------------------------------------------
+// Per-run values read from device memory by a replayed launch sequence (a captured graph
+// keeps kernel arguments fixed): when a kernel gets a non-null RunParams pointer, these
+// replace the seed, request, trajectory base, initial basis index and marked index.
+struct RunParams {
+    uint64_t seed;
+    uint32_t request;
+    uint32_t traj_base;
+    int64_t init;                 // initial basis index (physical)
+    int64_t marked;               // physical marked index, -1: none
+};
+
 struct NoiseArgs {
+    const RunParams *dyn;         // nullptr: the fields below
     double e;                     // used when e_dev == nullptr
     const double *e_dev;          // per-slot strength (device, S entries) or nullptr
     uint64_t seed;
@@ -153,7 +165,8 @@ hipError_t launch_noise_table(const qs_gate *gates_dev, int n_gates, int S, Nois
 hipError_t launch_noise_draw(uint64_t seed, uint32_t request, uint32_t stream,
                              const uint32_t *sites, int n_sites, uint32_t traj_base, int n_traj,
                              double *out, hipStream_t st);
-hipError_t launch_init_basis(void *psi, qs_dtype dt, int n, int S, uint64_t index, hipStream_t st);
+hipError_t launch_init_basis(void *psi, qs_dtype dt, int n, int S, uint64_t index, hipStream_t st,
+                             const RunParams *dyn = nullptr);
 hipError_t launch_sweep_u1(void *psi, qs_dtype dt, int n, int S, int q, const double *tab_row,
                            hipStream_t st);
 hipError_t launch_sweep_cp(void *psi, qs_dtype dt, int n, int S, int qa, int qb,
@@ -171,7 +184,8 @@ hipError_t launch_flip(void *psi, qs_dtype dt, int n, int S, uint64_t mask, uint
 // with ref = slot ref_slot of ref_psi; out has S * 5 doubles.  partials: reduce_partials_size.
 size_t reduce_partials_doubles(int n, int S);
 hipError_t launch_overlaps(const void *ref_psi, int ref_slot, const void *psi, qs_dtype dt, int n,
-                           int S, int64_t marked, double *partials, double *out, hipStream_t st);
+                           int S, int64_t marked, double *partials, double *out, hipStream_t st,
+                           const RunParams *dyn = nullptr);
 // <psi|rho|psi> and Tr rho over vec(rho) of n qubits: out = (Re f, Im f, Re tr, Im tr).
 hipError_t launch_dm_expect(const void *rho, const void *psi, qs_dtype dt, int n,
                             double *partials, double *out, hipStream_t st);
@@ -190,8 +204,12 @@ struct ProgramDev {
 // Records of pass `pass_host` for all S slots into rec (S * rec_size complex entries).
 hipError_t launch_pass_prep(qs_dtype dt, int S, const PassDesc *pass_host, ProgramDev prog,
                             const double *tab, const qs_gate *gates_dev, void *rec, hipStream_t st);
+// Sets the fused kernels' LDS limit (done by the first launch otherwise); call before capturing
+// a graph.
+hipError_t fused_prepare_attributes();
 hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDesc *pass_host,
-                             int pass_index, int64_t init, ProgramDev prog, const void *rec, hipStream_t st);
+                             int pass_index, int64_t init, ProgramDev prog, const void *rec, hipStream_t st,
+                             const RunParams *dyn = nullptr);
 size_t fused_lds_bytes(qs_dtype dt, int K);
 // Record entries per stage that fit next to a tile of 2^K amplitudes (two tiles per CU).
 int stage_rec_cap(qs_dtype dt, int K);

@@ -244,6 +244,11 @@ __global__ void k_noise_table(const qs_gate *gates, int n_gates, int S, NoiseArg
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)n_gates * S) return;
+    if (na.dyn) {
+        na.seed = na.dyn->seed;
+        na.request = na.dyn->request;
+        na.traj_base = na.dyn->traj_base;
+    }
     int g = (int)(i / S), s = (int)(i % S);
     noisy_operator(gates[g], s, na, tab + i * 8);
 }
@@ -259,8 +264,9 @@ __global__ void k_noise_one(qs_gate G, int S, NoiseArgs na, double *tab)
 // Basis initialisation: every slot <- |index>.
 // ---------------------------------------------------------------------------------------
 template <typename R>
-__global__ void k_init_basis(R *psi, int n, uint64_t total_vec, uint64_t index)
+__global__ void k_init_basis(R *psi, int n, uint64_t total_vec, uint64_t index, const RunParams *dyn)
 {
+    if (dyn) index = (uint64_t)dyn->init;
     constexpr int VEC = kVec<R>;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < total_vec; v += stride) {
@@ -526,9 +532,10 @@ __global__ void __launch_bounds__(kRedThreads) k_overlap_partial(const R *ref, c
 template <typename R>
 __global__ void __launch_bounds__(kRedThreads) k_overlap_final(const R *psi, int n, int log_blocks,
                                                                int64_t marked, const double *partials,
-                                                               double *out)
+                                                               double *out, const RunParams *dyn)
 {
     __shared__ double sh[3 * kRedThreads];
+    if (dyn) marked = dyn->marked;
     const int slot = blockIdx.x;
     const int nb = 1 << log_blocks;
     double v[4] = {0, 0, 0, 0};
@@ -643,7 +650,8 @@ hipError_t launch_noise_draw(uint64_t seed, uint32_t request, uint32_t stream,
     return hipGetLastError();
 }
 
-hipError_t launch_init_basis(void *psi, qs_dtype dt, int n, int S, uint64_t index, hipStream_t st)
+hipError_t launch_init_basis(void *psi, qs_dtype dt, int n, int S, uint64_t index, hipStream_t st,
+                             const RunParams *dyn)
 {
     uint64_t amps = (uint64_t)S << n;
     TimedLaunch tl("init", (double)amps * amp_bytes(dt), st);
@@ -651,10 +659,10 @@ hipError_t launch_init_basis(void *psi, qs_dtype dt, int n, int S, uint64_t inde
         uint64_t tv = amps / 2;
         if (n == 0) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_init_basis<float>, dim3(blocks_for(tv, 256)), dim3(256), 0, st,
-                           (float *)psi, n, tv, index);
+                           (float *)psi, n, tv, index, dyn);
     } else {
         hipLaunchKernelGGL(k_init_basis<double>, dim3(blocks_for(amps, 256)), dim3(256), 0, st,
-                           (double *)psi, n, amps, index);
+                           (double *)psi, n, amps, index, dyn);
     }
     return hipGetLastError();
 }
@@ -767,7 +775,8 @@ size_t reduce_partials_doubles(int n, int S)
 }
 
 hipError_t launch_overlaps(const void *ref_psi, int ref_slot, const void *psi, qs_dtype dt, int n,
-                           int S, int64_t marked, double *partials, double *out, hipStream_t st)
+                           int S, int64_t marked, double *partials, double *out, hipStream_t st,
+                           const RunParams *dyn)
 {
     int lb = red_log_blocks(n);
     unsigned nblk = (unsigned)((uint64_t)S << lb);
@@ -778,13 +787,13 @@ hipError_t launch_overlaps(const void *ref_psi, int ref_slot, const void *psi, q
         hipLaunchKernelGGL(k_overlap_partial<float>, dim3(nblk), dim3(kRedThreads), 0, st, ref,
                            (const float *)psi, n, lb, partials);
         hipLaunchKernelGGL(k_overlap_final<float>, dim3(S), dim3(kRedThreads), 0, st,
-                           (const float *)psi, n, lb, marked, partials, out);
+                           (const float *)psi, n, lb, marked, partials, out, dyn);
     } else {
         const double *ref = (const double *)ref_psi + ((uint64_t)ref_slot << (n + 1));
         hipLaunchKernelGGL(k_overlap_partial<double>, dim3(nblk), dim3(kRedThreads), 0, st, ref,
                            (const double *)psi, n, lb, partials);
         hipLaunchKernelGGL(k_overlap_final<double>, dim3(S), dim3(kRedThreads), 0, st,
-                           (const double *)psi, n, lb, marked, partials, out);
+                           (const double *)psi, n, lb, marked, partials, out, dyn);
     }
     return hipGetLastError();
 }

@@ -24,7 +24,7 @@ __all__ = ["QsimError", "lib", "Gate", "Noise", "Plan", "C64", "C128", "gate_arr
            "sv_bytes_required", "StateVector", "apply_gate", "apply_kraus", "fidelity",
            "dm_fidelity", "dm_apply_gate", "noise_draw", "traj_bytes_required", "run_trajectories",
            "timing_enable", "timing_read", "plan_describe", "plan_choose", "traj_layout", "timing_reset", "copy", "FixedRank", "trajectory_states",
-           "fr_bytes_required", "Server", "SrvConfig", "SrvJobInfo", "SrvStats", "LIB_PATH"]
+           "fr_bytes_required", "TrajGraph", "Server", "SrvConfig", "SrvJobInfo", "SrvStats", "LIB_PATH"]
 
 
 class QsimError(RuntimeError):
@@ -116,6 +116,10 @@ def lib():
         "qs_fr_apply_kraus": ([P, i32, i32, P, dbl, dbl, P], st),
         "qs_fr_fidelity": ([P, P, i32, P, P, P], st),
         "qs_fr_info": ([P, P, P, P], st),
+        "qs_traj_graph_bytes_required": ([P, i32, i32, i32, i32, ctypes.POINTER(Plan), ctypes.POINTER(sz)], st),
+        "qs_traj_graph_create": ([P, i32, i32, i32, i32, ctypes.POINTER(Plan), P, sz, ctypes.POINTER(P)], st),
+        "qs_traj_graph_launch": ([P, u64, ctypes.POINTER(Noise), i64, P, P, P, P], st),
+        "qs_traj_graph_destroy": ([P], st),
         "qs_srv_create": ([ctypes.POINTER(SrvConfig), P, sz, ctypes.POINTER(P)], st),
         "qs_srv_submit": ([P, P, i32, i32, u64, ctypes.POINTER(Noise), i32, i64, ctypes.POINTER(u64)], st),
         "qs_srv_poll": ([P, u64, ctypes.POINTER(ctypes.c_int)], st),
@@ -455,6 +459,57 @@ class FixedRank:
         N = 1 << self.n
         return torch.view_as_complex(self.buf[: fr_bytes_required(self.n, self.r, self.dtype)]
                                      .view(ft).view(self.r, N, 2))
+
+
+# ------------------------------------------------------------------------------------------
+class TrajGraph:
+    """A captured run_trajectories launch sequence for one circuit, n_traj and buffer; launch()
+    replays it with new noise parameters, initial index and marked index."""
+
+    def __init__(self, gates, n: int, dtype: int, n_traj: int, plan=None, buf=None):
+        import torch
+        self.ga = gates if isinstance(gates, ctypes.Array) else gate_array(gates)
+        self.n, self.dtype, self.n_traj = n, dtype, n_traj
+        p = _plan(plan)
+        need = ctypes.c_size_t()
+        _check(lib().qs_traj_graph_bytes_required(self.ga, len(self.ga), n, dtype, n_traj,
+                                                  ctypes.byref(p) if p else None, ctypes.byref(need)),
+               "traj_graph_bytes_required")
+        self.buf = buf if buf is not None else torch.empty(need.value, dtype=torch.uint8, device="cuda")
+        h = ctypes.c_void_p()
+        _check(lib().qs_traj_graph_create(self.ga, len(self.ga), n, dtype, n_traj, ctypes.byref(p) if p else None,
+                                          _ptr(self.buf), self.buf.numel(), ctypes.byref(h)), "traj_graph_create")
+        self.h = h
+
+    def launch(self, init_index: int, e=0.0, seed: int = 0, request: int = 0, traj_base: int = 0,
+               marked: int = -1) -> dict:
+        e_arr = np.asarray(e, np.float64)
+        per = None if e_arr.ndim == 0 else e_arr
+        nz, keep = _noise(float(e_arr) if per is None else 0.0, seed, request, traj_base, per)
+        T = self.n_traj
+        F, P, norms, layout = np.zeros(T), np.zeros(T), np.zeros(T), np.zeros(self.n, np.int32)
+        _check(lib().qs_traj_graph_launch(self.h, int(init_index), ctypes.byref(nz), int(marked), _ptr(F),
+                                          _ptr(P) if marked >= 0 else None, _ptr(norms), _ptr(layout)),
+               "traj_graph_launch")
+        del keep
+        return {"F": F, "p": P if marked >= 0 else None, "norm": norms, "layout": layout, "buf": self.buf}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().qs_traj_graph_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------------------------------
