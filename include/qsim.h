@@ -150,7 +150,9 @@ qs_status qs_apply_kraus(qs_state rho, int k, const int32_t *qubits, int n_ops, 
  * its Kraus channel {U E1, U E2} with E1, E2 of eq. (6) (lambda_1,2 = (1 +- exp(-2 e^2)) / 2),
  * applied as one superoperator sweep; other one-qubit gates as U (x) U*; SWAP, CNOT, U2 and
  * noiseless CP as U on the ket bits then U* on the bra bits; FLIP as the sign flip of the
- * selected rows and columns.  A PHASE-tagged CP with e > 0 returns QS_EUNSUPPORTED.
+ * selected rows and columns.  A PHASE-tagged CP with e > 0 becomes its averaged channel
+ * (eq. 9): entry rho_ij is multiplied by exp(-i theta (b_i - b_j)) exp(-e^2 (b_i - b_j)^2 / 2)
+ * where b = 1 when both qubits of the row (column) index are 1.
  * Asynchronous. */
 qs_status qs_dm_apply_gate(qs_state rho, const qs_gate *g, double e);
 

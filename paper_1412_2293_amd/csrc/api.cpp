@@ -353,8 +353,20 @@ qs_status qs_dm_apply_gate(qs_state rho, const qs_gate *g, double e)
         QS_HIP(launch_flip(rho->buf, rho->dt, rho->n, 1, g->mask, g->value, rho->st));
         return QS_OK;
     }
-    if (g->kind == QS_G_CP && e > 0 && g->noise == QS_NOISE_PHASE)
-        return fail(QS_EUNSUPPORTED, "dm_apply_gate: the noisy controlled phase (eq. 9) is not implemented on vec(rho)");
+    if (g->kind == QS_G_CP && e > 0 && g->noise == QS_NOISE_PHASE) {
+        // The average over xi of U(theta + e xi) rho U(theta + e xi)^dagger (the channel of
+        // eq. 9): rho_ij gets exp(-i theta (b_i - b_j)) exp(-e^2 (b_i - b_j)^2 / 2), b = 1 when
+        // both qubits are 1.  Three pattern sweeps: rows with b_i = 1 by f = exp(-i theta) sqrt(P),
+        // columns with b_j = 1 by conj(f), and entries with both by 1 / P (P = exp(-e^2)).
+        const uint64_t cm = (1ull << g->q0) | (1ull << g->q1);
+        const double P = std::exp(-e * e), sp = std::exp(-0.5 * e * e);
+        const double fre = std::cos(g->theta) * sp, fim = -std::sin(g->theta) * sp;
+        QS_HIP(launch_scale_pattern(rho->buf, rho->dt, rho->n, 1, cm << n, cm << n, fre, fim, rho->st));
+        QS_HIP(launch_scale_pattern(rho->buf, rho->dt, rho->n, 1, cm, cm, fre, -fim, rho->st));
+        QS_HIP(launch_scale_pattern(rho->buf, rho->dt, rho->n, 1, cm | (cm << n), cm | (cm << n), 1.0 / P, 0.0,
+                                    rho->st));
+        return QS_OK;
+    }
     // two-qubit unitary: U on the ket bits, conj(U) on the bra bits
     qs_gate ket = *g, bra = *g;
     ket.q0 += n;

@@ -180,6 +180,9 @@ hipError_t launch_sweep_2q(void *psi, qs_dtype dt, int n, int S, int qa, int qb,
 hipError_t launch_noise_one(const qs_gate &g, int S, NoiseArgs na, double *tab, hipStream_t st);
 hipError_t launch_flip(void *psi, qs_dtype dt, int n, int S, uint64_t mask, uint64_t value,
                        hipStream_t st);
+// Multiply the amplitudes with (index & mask) == value by fre + i fim.
+hipError_t launch_scale_pattern(void *psi, qs_dtype dt, int n, int S, uint64_t mask, uint64_t value,
+                                double fre, double fim, hipStream_t st);
 // Per-slot (Re <ref|psi_s>, Im <ref|psi_s>, <psi_s|psi_s>, Re psi_s[marked], Im psi_s[marked])
 // with ref = slot ref_slot of ref_psi; out has S * 5 doubles.  partials: reduce_partials_size.
 size_t reduce_partials_doubles(int n, int S);

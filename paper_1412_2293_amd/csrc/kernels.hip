@@ -454,6 +454,31 @@ __global__ void k_flip(R *psi, int n, uint64_t mask, uint64_t value, int free_bi
   }
 }
 
+// The same enumeration, multiplying every selected amplitude by one complex factor (the
+// averaged controlled phase on vec(rho)).
+template <typename R>
+__global__ void k_scale_pattern(R *psi, int n, uint64_t mask, uint64_t value, int free_bits,
+                                uint64_t total, double fre, double fim)
+{
+  const R cr = (R)fre, ci = (R)fim;
+  for (uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+       it += (uint64_t)gridDim.x * blockDim.x) {
+    int slot = (int)(it >> free_bits);
+    uint64_t c = it & ((1ull << free_bits) - 1);
+    uint64_t i = value;
+    int b = 0;
+    for (int q = 0; q < n; ++q) {
+        if (mask & (1ull << q)) continue;
+        if (c & (1ull << b)) i |= 1ull << q;
+        ++b;
+    }
+    R *p = psi + ((uint64_t)slot << (n + 1));
+    const R ar = p[2 * i], ai = p[2 * i + 1];
+    p[2 * i] = cr * ar - ci * ai;
+    p[2 * i + 1] = cr * ai + ci * ar;
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // FP64 reductions.  Stage 1: each block sums a fixed contiguous range in a fixed order
 // (thread-strided, then an LDS tree); stage 2: one block per slot sums the block partials in
@@ -763,6 +788,21 @@ hipError_t launch_flip(void *psi, qs_dtype dt, int n, int S, uint64_t mask, uint
     else
         hipLaunchKernelGGL(k_flip<double>, dim3(blocks_for(total, 256)), dim3(256), 0, st,
                            (double *)psi, n, mask, value, free_bits, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_pattern(void *psi, qs_dtype dt, int n, int S, uint64_t mask, uint64_t value,
+                                double fre, double fim, hipStream_t st)
+{
+    const int free_bits = n - __builtin_popcountll(mask);
+    const uint64_t total = (uint64_t)S << free_bits;
+    TimedLaunch tl("flip", 2.0 * (double)total * amp_bytes(dt), st);
+    if (dt == QS_C64)
+        hipLaunchKernelGGL(k_scale_pattern<float>, dim3(blocks_for(total, 256)), dim3(256), 0, st,
+                           (float *)psi, n, mask, value, free_bits, total, fre, fim);
+    else
+        hipLaunchKernelGGL(k_scale_pattern<double>, dim3(blocks_for(total, 256)), dim3(256), 0, st,
+                           (double *)psi, n, mask, value, free_bits, total, fre, fim);
     return hipGetLastError();
 }
 

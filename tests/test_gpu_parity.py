@@ -231,6 +231,27 @@ def test_dm_grover_against_oracle(dtype):
     assert abs(tr - 1.0) <= tol * 10
 
 
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+def test_dm_qft_with_noisy_controlled_phases(dtype):
+    """Noisy Hadamards (eq. 6) and noisy controlled phases (eq. 9) on vec(rho) against the
+    oracle's Kraus channels, entry by entry."""
+    n, e = 6, 0.15
+    c = qft(n, seed=3)
+    rho = q.StateVector(2 * n, dtype, 1)
+    rho.init_basis(c.init_index * ((1 << n) + 1))     # |x><x|: index x * 2^n + x
+    for g in c.gates:
+        q.dm_apply_gate(rho, g, e)
+    ref = oracle.dm_run(c, e)
+    got = from_device(rho)[0].reshape(1 << n, 1 << n)
+    tol = 1e-12 if dtype == q.C128 else 2e-5
+    assert rel_err(got, ref) <= tol
+    ideal_sv = q.StateVector(n, dtype, 1)
+    to_device_states(ideal_sv, oracle.sv_run(c, 0.0)[None, :])
+    f, tr = q.dm_fidelity(rho, ideal_sv, 0)
+    f_ref, _ = oracle.dm_expect(ref, oracle.sv_run(c, 0.0))
+    assert abs(f - f_ref.real) <= 10 * tol and abs(tr - 1.0) <= 10 * tol
+
+
 def test_dm_grover13_full_size():
     """vec(rho) at the full n = 13 (2^26 complex<double> entries).  A prefix of gates on the
     lowest, middle and highest qubit plus the oracle flip is compared entry by entry with the
