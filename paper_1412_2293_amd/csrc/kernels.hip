@@ -54,6 +54,36 @@ __device__ __forceinline__ void vstore(R *psi, uint64_t i, const cx<R> *a)
     }
 }
 
+// Streaming (non-temporal) forms: the sweep reads and writes every line once, so it keeps
+// them out of the caches.
+typedef float qs_f4 __attribute__((ext_vector_type(4)));
+typedef double qs_d2 __attribute__((ext_vector_type(2)));
+
+template <typename R>
+__device__ __forceinline__ void vload_nt(const R *psi, uint64_t i, cx<R> *a)
+{
+    if constexpr (sizeof(R) == 4) {
+        qs_f4 v = __builtin_nontemporal_load(reinterpret_cast<const qs_f4 *>(psi + 2 * i));
+        a[0] = {v.x, v.y};
+        a[1] = {v.z, v.w};
+    } else {
+        qs_d2 v = __builtin_nontemporal_load(reinterpret_cast<const qs_d2 *>(psi + 2 * i));
+        a[0] = {v.x, v.y};
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void vstore_nt(R *psi, uint64_t i, const cx<R> *a)
+{
+    if constexpr (sizeof(R) == 4) {
+        qs_f4 v = {a[0].re, a[0].im, a[1].re, a[1].im};
+        __builtin_nontemporal_store(v, reinterpret_cast<qs_f4 *>(psi + 2 * i));
+    } else {
+        qs_d2 v = {a[0].re, a[0].im};
+        __builtin_nontemporal_store(v, reinterpret_cast<qs_d2 *>(psi + 2 * i));
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ cx<R> sload(const R *psi, uint64_t i)
 {
@@ -307,12 +337,18 @@ __global__ void __launch_bounds__(256) k_u1(R *psi, int n, int q, const double *
         if constexpr (MODE == 0) {
             uint64_t i0 = ins0(c * VEC, q);
             i0s[u] = i0;
-            vload(p, i0, a0[u]);
-            vload(p, i0 | (1ull << q), a1[u]);
+            // streaming accesses pay off when the two streams are at least 4 amplitudes apart
+            if (q >= 2) {
+                vload_nt(p, i0, a0[u]);
+                vload_nt(p, i0 | (1ull << q), a1[u]);
+            } else {
+                vload(p, i0, a0[u]);
+                vload(p, i0 | (1ull << q), a1[u]);
+            }
         } else {
             i0s[u] = c * 2;
             cx<R> t[2];
-            vload(p, c * 2, t);
+            vload_nt(p, c * 2, t);
             a0[u][0] = t[0];
             a1[u][0] = t[1];
         }
@@ -331,11 +367,16 @@ __global__ void __launch_bounds__(256) k_u1(R *psi, int n, int q, const double *
             b1[k] = cfma(m11, a1[u][k], cmul(m10, a0[u][k]));
         }
         if constexpr (MODE == 0) {
-            vstore(p, i0s[u], b0);
-            vstore(p, i0s[u] | (1ull << q), b1);
+            if (q >= 2) {
+                vstore_nt(p, i0s[u], b0);
+                vstore_nt(p, i0s[u] | (1ull << q), b1);
+            } else {
+                vstore(p, i0s[u], b0);
+                vstore(p, i0s[u] | (1ull << q), b1);
+            }
         } else {
             cx<R> t2[2] = {b0[0], b1[0]};
-            vstore(p, i0s[u], t2);
+            vstore_nt(p, i0s[u], t2);
         }
     }
   }
