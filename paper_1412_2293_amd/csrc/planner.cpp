@@ -87,6 +87,8 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
     if (RB > kMaxRegBits) RB = kMaxRegBits;
     if (K < 1 || RB < 1) return fail(QS_EINVAL, "fused plan: tile and register bits must be >= 1");
     if (K - RB > 9) return fail(QS_EINVAL, "fused plan: at most 512 threads per tile (tile_bits - reg_bits <= 9)");
+    if (RB == 4 && K - RB > 8)
+        return fail(QS_EINVAL, "fused plan: reg_bits 4 allows at most 256 threads per tile (tile_bits <= 12)");
     const bool whole = (n == K);
     int max_targets = whole ? K : K - run_bits;
     if (max_targets < 2) return fail(QS_EINVAL, "fused plan: tile too small for the run length");

@@ -29,7 +29,7 @@ def test_choice_is_valid_and_deterministic(dtype):
 
 def test_model_prefers_long_rows_on_qft26():
     p, _ = q.plan_choose(qft(26, 1).gates, 26, q.C64)
-    assert p == {"fuse": 1, "tile_bits": 12, "reg_bits": 3, "run_bits": 5}
+    assert p == {"fuse": 1, "tile_bits": 12, "reg_bits": 4, "run_bits": 5}
 
 
 def test_model_cost_matches_describe():
