@@ -404,22 +404,25 @@ __global__ void __launch_bounds__(RB == 4 ? 256 : 512, RB == 4 ? 1 : 4) k_fused(
     }
     }
 
-    // Register layout: tile-local index of register r of this thread = lthr | roff[r].  The
-    // load layout has the thread id in the low bits; rounds bring host-built tables.
-    // LDS addresses: swz(lthr | roff[r]) = swz(lthr) ^ swz(roff[r]); the register part is a
-    // uniform byte offset soff[r] (scalar registers), so each access costs one XOR.
+    // Register layout: tile-local index of register r of this thread = lthr | roff[r], with
+    // roff from the current round's descriptor (cur_rd; the load layout has the thread id in the
+    // low bits).  LDS addresses: swz(lthr | roff[r]) = swz(lthr) ^ swz(roff[r]); the register
+    // part is the descriptor's sroff (one scalar load of 16 words), so each access costs one
+    // XOR.  The tile sits at the start of the dynamic LDS, addressed directly.
     constexpr uint32_t CXS = sizeof(cxf<R>);
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) v2 lds_v2;
+    // dynamic LDS begins after the kernel's static LDS (none: the offset folds to nothing)
+    auto lds_put = [](uint32_t byte, cxf<R> x) {
+        *reinterpret_cast<lds_v2 *>((size_t)(__builtin_amdgcn_groupstaticsize() + byte)) = v2{x.re, x.im};
+    };
+    auto lds_get = [](uint32_t byte) {
+        const v2 v = *reinterpret_cast<const lds_v2 *>((size_t)(__builtin_amdgcn_groupstaticsize() + byte));
+        return cxf<R>{v.x, v.y};
+    };
     const uint32_t load_mask = (((1u << RB) - 1u) << TB) & kmask;
     uint32_t cur = load_mask;
-    uint32_t roff[NR], soff[NR];
-    auto take_round = [&](const RoundDesc *rd) {
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            roff[r] = rd->roff[r];
-            soff[r] = rd->sroff[r] * CXS;
-        }
-    };
-    take_round(&pd->load_round);
+    const RoundDesc *cur_rd = &pd->load_round;
     uint32_t lthr = tid;
 
     auto exchange_to = [&](uint32_t to, const RoundDesc *rd) {
@@ -427,15 +430,15 @@ __global__ void __launch_bounds__(RB == 4 ? 256 : 512, RB == 4 ? 1 : 4) k_fused(
         {
             const uint32_t sw = swz(lthr) * CXS;
 #pragma unroll
-            for (int r = 0; r < NR; ++r) *reinterpret_cast<cxf<R> *>(smem + (sw ^ soff[r])) = a[r];
+            for (int r = 0; r < NR; ++r) lds_put(sw ^ (cur_rd->sroff[r] * CXS), a[r]);
         }
         __syncthreads();
         cur = to;
-        take_round(rd);
+        cur_rd = rd;
         lthr = (uint32_t)rd->tlo[tid & 31u] | (uint32_t)rd->thi[(tid >> 5) & 15u];
         const uint32_t sw = swz(lthr) * CXS;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) a[r] = *reinterpret_cast<const cxf<R> *>(smem + (sw ^ soff[r]));
+        for (int r = 0; r < NR; ++r) a[r] = lds_get(sw ^ (rd->sroff[r] * CXS));
     };
 
     for (int si = pd->stage_begin; si < pd->stage_end; ++si) {
@@ -493,7 +496,7 @@ __global__ void __launch_bounds__(RB == 4 ? 256 : 512, RB == 4 ? 1 : 4) k_fused(
                     const cxf<R> f = orec[0];
 #pragma unroll
                     for (int r = 0; r < NR; ++r) {
-                        bool hit = ohit && ((lthr | roff[r]) & lmask) == lvalue;
+                        bool hit = ohit && ((lthr | cur_rd->roff[r]) & lmask) == lvalue;
                         cxf<R> y = mul(f, a[r]);
                         a[r].re = hit ? y.re : a[r].re;
                         a[r].im = hit ? y.im : a[r].im;
