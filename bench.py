@@ -157,6 +157,8 @@ def main():
         torch.cuda.empty_cache()
         out["sweeps_n28"] = sweeps(q)
         torch.cuda.empty_cache()
+        out["large_state_n32"] = large_state_bench(q, torch)
+        torch.cuda.empty_cache()
         out["graph_replay"] = graph_bench(q, torch)
         out["dm13"] = dm13_bench(q, torch)
         torch.cuda.empty_cache()
@@ -238,6 +240,60 @@ def sweeps(q):
         del sv
         torch.cuda.empty_cache()
     return out
+
+
+def large_state_bench(q, torch, prefix_layers=2):
+    """One large state: n = 32 complex64 (32 GiB per slot), 40 layers of Haar one-qubit gates
+    and brickwork CZ, e = 0.005, 4 trajectories + ideal (160 GiB), automatic plan, run in full.
+    Beside it the first `prefix_layers` layers as per-gate sweeps and as fused passes, which
+    gives the per-layer speed-up without a 100-second unfused run."""
+    import numpy as np
+    from workloads import Circuit, random_layers
+    n, depth, T, e, seed = 32, 40, 4, 0.005, 4
+    c = random_layers(n, depth, seed, pairing="brickwork")
+    ga = q.gate_array(c.gates)
+    plan = q.plan_choose(ga, n, q.C64)[0]
+    need = q.traj_bytes_required(ga, n, q.C64, T)
+    log(f"[bench] large state n={n}: {len(c.gates)} gates, {need / 2**30:.1f} GiB")
+    buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+    q.timing_reset()
+    q.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = q.run_trajectories(ga, n, 0, q.C64, T, e=e, seed=seed, buf=buf)
+    t1 = time.perf_counter()
+    q.timing_enable(False)
+    fz = q.timing_read("fused")
+    F = res["F"].tolist()
+    norms = res["norm"].tolist()
+    per_layer = len(c.gates) // depth
+    pre = Circuit(n, c.gates[:prefix_layers * per_layer], name="prefix")
+    pga = q.gate_array(pre.gates)
+    times = {}
+    for name, pl in (("fused", {"fuse": -1}), ("unfused", {"fuse": 0})):
+        q.timing_reset()
+        q.timing_enable(True)
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        r = q.run_trajectories(pga, n, 0, q.C64, T, e=e, seed=seed, plan=pl, buf=buf)
+        times[name] = time.perf_counter() - a0
+        q.timing_enable(False)
+        if name == "fused":
+            Fp = r["F"].copy()
+        else:
+            sw = q.timing_read("sweep_u1")
+            Fu = r["F"].copy()
+    del buf
+    u1_gbs = sw["alg_bytes"] / (sw["ms"] / 1e3) / 1e9 if sw["ms"] else 0.0
+    return {"workload": f"random{n}x{depth} brickwork, complex64, {T} trajectories + ideal, e={e}",
+            "bytes": need, "plan": plan, "passes": fz["launches"], "wall_s": t1 - t0,
+            "fused_avg_ms": fz["ms"] / max(fz["launches"], 1),
+            "fused_GBps": round(fz["alg_bytes"] / (fz["ms"] / 1e3) / 1e9, 1),
+            "F": F, "norm": norms,
+            "prefix_layers": prefix_layers, "prefix_fused_s": times["fused"], "prefix_unfused_s": times["unfused"],
+            "prefix_speedup": times["unfused"] / times["fused"],
+            "prefix_max_abs_dF_fused_vs_unfused": float(np.max(np.abs(Fp - Fu))),
+            "unfused_u1_GBps": round(u1_gbs, 1), "unfused_u1_hbm_frac": round(u1_gbs / HBM_PEAK_GBS, 4)}
 
 
 def graph_bench(q, torch, reps=20):

@@ -150,3 +150,39 @@ def full_gate_matrix(n, g):
         elif g.kind == 5:
             M[col, col] = -1.0 if (col & g.mask) == g.value else 1.0
     return M
+
+
+def first_layer_pairs(circuit, xi_by_site, e):
+    """Per-pair two-qubit states of one trajectory of a circuit made of one dense one-qubit
+    gate per qubit (rotation noise, eq. 1: U V(e xi) with V = [[c, s], [-s, c]]) followed by
+    controlled phases on disjoint pairs covering every qubit (phase noise: theta + e xi), from
+    |0...0>.  Returns {(a, b): 4-vector over (bit a) + 2 (bit b)}."""
+    col = {}
+    for g in circuit.gates:
+        if g.kind == 0:
+            a = e * xi_by_site.get(g.site, 0.0) if g.noise == 1 else 0.0
+            V = np.array([[math.cos(a), math.sin(a)], [-math.sin(a), math.cos(a)]])
+            col[g.q0] = (np.asarray(g.m) @ V)[:, 0]
+    pairs = {}
+    for g in circuit.gates:
+        if g.kind == 1:
+            th = g.theta + (e * xi_by_site.get(g.site, 0.0) if g.noise == 2 else 0.0)
+            v = np.kron(col[g.q1], col[g.q0]).astype(np.complex128)   # index bit(q0) + 2 bit(q1)
+            v[3] *= np.exp(-1j * th)
+            pairs[(g.q0, g.q1)] = v
+    return pairs
+
+
+def pair_product_amplitudes(pairs, indices):
+    idx = np.asarray(indices, np.int64)
+    amp = np.ones(idx.size, np.complex128)
+    for (a, b), v in pairs.items():
+        amp *= v[((idx >> a) & 1) + 2 * ((idx >> b) & 1)]
+    return amp
+
+
+def pair_product_fidelity(pairs_ideal, pairs):
+    F = 1.0
+    for k, v in pairs.items():
+        F *= abs(np.vdot(pairs_ideal[k], v)) ** 2 / (np.vdot(v, v).real * np.vdot(pairs_ideal[k], pairs_ideal[k]).real)
+    return F

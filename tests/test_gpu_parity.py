@@ -15,7 +15,8 @@ from oracle import fixed_rank
 from workloads import (CP, FLIP, NOISE_PHASE, NOISE_ROT, U1, Circuit, Gate, grover, qft,
                        random_layers, random_mixed_circuit)
 
-from paper_forms import eq10, grover_p_ideal, qft_noisy_amplitudes
+from paper_forms import (eq10, first_layer_pairs, grover_p_ideal, pair_product_amplitudes,
+                         pair_product_fidelity, qft_noisy_amplitudes)
 
 torch = pytest.importorskip("torch")
 import paper_1412_2293_amd as q  # noqa: E402
@@ -250,6 +251,34 @@ def test_dm_qft_with_noisy_controlled_phases(dtype):
     f, tr = q.dm_fidelity(rho, ideal_sv, 0)
     f_ref, _ = oracle.dm_expect(ref, oracle.sv_run(c, 0.0))
     assert abs(f - f_ref.real) <= 10 * tol and abs(tr - 1.0) <= 10 * tol
+
+
+def test_random_layer_n32_full_size_against_closed_form():
+    """n = 32 complex<float> (two 32 GiB slots, the shape of the 40-layer large-state run): the
+    first layer of the random circuit (Haar gates with rotation noise, then noisy CZ on the
+    brickwork pairs) leaves a product of two-qubit states, so sampled amplitudes and the
+    fidelity have closed forms given the oracle's noise draws."""
+    n, e, seed = 32, 0.05, 4
+    c = random_layers(n, 1, seed, pairing="brickwork")
+    T = 1
+    res = q.run_trajectories(c.gates, n, 0, q.C64, T, e=e, seed=seed)
+    assert list(res["layout"]) == list(range(n))
+    xi = oracle.normals(seed, [g.site for g in c.gates], [0])[0]
+    xi_by_site = {g.site: float(x) for g, x in zip(c.gates, xi)}
+    pairs = first_layer_pairs(c, xi_by_site, e)
+    ideal = first_layer_pairs(c, {}, 0.0)
+    assert abs(res["F"][0] - pair_product_fidelity(ideal, pairs)) <= 1e-5
+    assert abs(res["norm"][0] - 1.0) <= 1e-5
+    rng = np.random.default_rng(5)
+    idx = np.concatenate([[0, (1 << n) - 1, 0x55555555, 0xAAAAAAAA], rng.integers(0, 1 << n, 4092)])
+    states = q.trajectory_states(res, n, q.C64, T)
+    got = states[1][torch.as_tensor(idx, device=states.device)].cpu().numpy().astype(np.complex128)
+    ref = pair_product_amplitudes(pairs, idx)
+    got0 = states[0][torch.as_tensor(idx, device=states.device)].cpu().numpy().astype(np.complex128)
+    ref0 = pair_product_amplitudes(ideal, idx)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(got - ref)) <= 1e-5 * scale
+    assert np.max(np.abs(got0 - ref0)) <= 1e-5 * np.max(np.abs(ref0))
 
 
 def test_dm_grover13_full_size():

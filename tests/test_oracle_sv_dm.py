@@ -9,7 +9,7 @@ from oracle import fixed_rank
 from workloads import (CP, FLIP, NOISE_NONE, NOISE_PHASE, NOISE_ROT, U1, Circuit, Gate,
                        grover, qft, random_layers, random_mixed_circuit)
 
-from paper_forms import (eq10, eq11, eq15, full_gate_matrix, grover_ideal, grover_p_ideal,
+from paper_forms import (first_layer_pairs, pair_product_amplitudes, pair_product_fidelity, eq10, eq11, eq15, full_gate_matrix, grover_ideal, grover_p_ideal,
                          lambdas, qft_expected_fidelity, qft_ideal, qft_noisy_closed_form)
 
 
@@ -77,6 +77,22 @@ def test_noisy_qft_matches_product_closed_form(n, e):
         F_cf, psi_cf = qft_noisy_closed_form(c, dict(zip(sites, xi[k])), e)
         np.testing.assert_allclose(psi, psi_cf, atol=1e-13)
         assert abs(oracle.fidelity(ideal, psi) - F_cf) < 1e-13
+
+
+@pytest.mark.parametrize("n", [6, 10])
+def test_first_random_layer_is_a_product_of_pair_states(n):
+    """One layer of Haar gates (rotation noise) and brickwork CZ (phase noise) from |0>: every
+    amplitude and F factor over the CZ pairs (the closed form the n = 32 GPU test uses)."""
+    from workloads import random_layers
+    e, seed = 0.07, 4
+    c = random_layers(n, 1, seed, pairing="brickwork")
+    for t in range(3):
+        xi = oracle.normals(seed, [g.site for g in c.gates], [t])[0]
+        pairs = first_layer_pairs(c, {g.site: float(x) for g, x in zip(c.gates, xi)}, e)
+        psi = oracle.sv_run(c, e, seed=seed, traj=t)
+        np.testing.assert_allclose(pair_product_amplitudes(pairs, np.arange(1 << n)), psi, atol=1e-14)
+        F, _ = oracle.run_trajectories(c, e, seed, [t])
+        assert abs(F[0] - pair_product_fidelity(first_layer_pairs(c, {}, 0.0), pairs)) <= 1e-13
 
 
 def test_norm_preserved_by_noisy_trajectories():
