@@ -91,7 +91,10 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         return fail(QS_EINVAL, "fused plan: reg_bits 4 allows at most 256 threads per tile (tile_bits <= 12)");
     const bool whole = (n == K);
     int max_targets = whole ? K : K - run_bits;
-    if (max_targets < 2) return fail(QS_EINVAL, "fused plan: tile too small for the run length");
+    bool two_qubit = false;
+    for (int g = 0; g < n_gates; ++g)
+        if (gates[g].kind == QS_G_U2 || gates[g].kind == QS_G_CNOT) two_qubit = true;
+    if (max_targets < (two_qubit ? 2 : 1)) return fail(QS_EINVAL, "fused plan: tile too small for the run length");
 
     if (RB < 2)
         for (int g = 0; g < n_gates; ++g)

@@ -175,7 +175,7 @@ def make_gate(g) -> Gate:
 
 def gate_array(gates) -> ctypes.Array:
     gs = list(gates)
-    arr = (Gate * max(len(gs), 1))()
+    arr = (Gate * len(gs))()    # may be empty: the library accepts n_gates = 0
     for i, g in enumerate(gs):
         arr[i] = g if isinstance(g, Gate) else make_gate(g)
     return arr
