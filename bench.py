@@ -173,7 +173,8 @@ def main():
 
 
 def fp64_unfused(q, c, ga, n, T, es, seed, F_c64, fused_value):
-    """The same step as plain per-gate sweeps in complex<double> (one timed run)."""
+    """The same step as plain per-gate sweeps in complex<double> (one timed run), and fused in
+    complex<double> (one timed run after a warm-up)."""
     import numpy as np
     import torch
     log("[bench] fp64 unfused per-gate comparison (1 run)")
@@ -192,7 +193,32 @@ def fp64_unfused(q, c, ga, n, T, es, seed, F_c64, fused_value):
     per = {k: q.timing_read(k) for k in ("sweep_u1", "sweep_cp", "sweep_swap")}
     v = c.amplitude_updates() * T / (ms / 1e3)
     dF = float(np.max(np.abs(res["F"] - F_c64)))
-    del res, buf
+    F64 = res["F"].copy()
+    del res
+    # the same step fused in complex<double> (automatic plan), on the same buffer size class
+    fplan = {"fuse": -1}
+    need_f = q.traj_bytes_required(ga, n, q.C128, T, fplan)
+    if need_f > buf.numel():
+        del buf
+        torch.cuda.empty_cache()
+        buf = torch.empty(need_f, dtype=torch.uint8, device="cuda")
+    q.run_trajectories(ga, n, c.init_index, q.C128, T, e=es, seed=seed, plan=fplan, buf=buf)   # warm-up
+    torch.cuda.synchronize()
+    q.timing_reset()
+    q.timing_enable(True)
+    f0 = time.perf_counter()
+    resf = q.run_trajectories(ga, n, c.init_index, q.C128, T, e=es, seed=seed, plan=fplan, buf=buf)
+    torch.cuda.synchronize()
+    f1 = time.perf_counter()
+    q.timing_enable(False)
+    fz = q.timing_read("fused")
+    fused64 = {"ms_per_step": (f1 - f0) * 1e3, "value": c.amplitude_updates() * T / (f1 - f0),
+               "plan": q.plan_choose(ga, n, q.C128)[0], "passes": fz["launches"],
+               "fused_avg_ms": fz["ms"] / max(fz["launches"], 1),
+               "fused_GBps": round(fz["alg_bytes"] / (fz["ms"] / 1e3) / 1e9, 1) if fz["ms"] else None,
+               "max_abs_dF_vs_unfused_f64": float(np.max(np.abs(resf["F"] - F64))),
+               "max_abs_dF_vs_fused_f32": float(np.max(np.abs(resf["F"] - F_c64)))}
+    del resf, buf
     sweeps_ = {}
     for k, d in per.items():
         if d["launches"]:
@@ -201,7 +227,7 @@ def fp64_unfused(q, c, ga, n, T, es, seed, F_c64, fused_value):
                           "frac": d["alg_bytes"] / (d["ms"] / 1e3) / 1e9 / HBM_PEAK_GBS}
     return {"dtype": "f64", "ms_per_step": ms, "value": v, "unit": "amplitude-updates/s",
             "speedup_fused_f32_over_unfused_f64": fused_value / v,
-            "max_abs_dF_f32_fused_vs_f64_unfused": dF, "kernels": sweeps_}
+            "max_abs_dF_f32_fused_vs_f64_unfused": dF, "kernels": sweeps_, "fused_f64": fused64}
 
 
 def sweeps(q):

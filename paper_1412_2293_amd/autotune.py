@@ -19,7 +19,7 @@ from . import qsim as q
 
 CANDIDATES = {
     q.C64: [(12, 4, 5), (12, 4, 4), (12, 3, 5), (12, 3, 4), (12, 3, 3), (11, 3, 4), (11, 2, 3), (10, 2, 3)],
-    q.C128: [(11, 2, 4), (11, 2, 3), (10, 2, 3), (10, 1, 3)],
+    q.C128: [(11, 3, 4), (11, 3, 3), (11, 2, 4), (11, 2, 3), (10, 2, 3), (10, 1, 3)],
 }
 DTYPE_NAMES = {q.C64: "c64", q.C128: "c128"}
 

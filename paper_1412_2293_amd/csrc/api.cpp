@@ -512,6 +512,9 @@ qs_status fused_plan_for(const qs_gate *gates, int n_gates, int n, qs_dtype dt, 
         K = n;   // the whole state is one tile: the circuit runs as one launch
         if (RB > K) RB = K;
     }
+    // wide register tiles (16 complex<float>, 8 or 16 complex<double>) run 256-thread blocks
+    if ((RB == 4 || (dt == QS_C128 && RB == 3)) && K - RB > 8)
+        return fail(QS_EINVAL, "plan: this register tile allows at most 256 threads (tile_bits - reg_bits <= 8)");
     out.K = K;
     out.RB = RB;
     out.run_bits = run;
@@ -590,7 +593,7 @@ double model_cost_unfused(const qs_gate *gates, int n_gates, int n, qs_dtype dt,
 // Candidate shapes per dtype: (tile bits, register bits, run bits).
 static const int kCandC64[][3] = {{12, 4, 5}, {12, 4, 4}, {12, 3, 5}, {12, 3, 4}, {12, 3, 3}, {11, 3, 4},
                                   {11, 2, 3}, {10, 2, 3}};
-static const int kCandC128[][3] = {{11, 2, 4}, {11, 2, 3}, {10, 2, 3}, {10, 1, 3}};
+static const int kCandC128[][3] = {{11, 3, 4}, {11, 3, 3}, {11, 2, 4}, {11, 2, 3}, {10, 2, 3}, {10, 1, 3}};
 
 qs_status autotune_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, int S, Plan &out,
                         double *cost_out)
@@ -601,7 +604,7 @@ qs_status autotune_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, i
     double best = model_cost_unfused(gates, n_gates, n, dt, S);
     out = Plan();
     out.fused = false;
-    const int ncand = dt == QS_C64 ? 8 : 4;
+    const int ncand = dt == QS_C64 ? 8 : 6;
     for (int c = 0; c < ncand; ++c) {
         const int *k = dt == QS_C64 ? kCandC64[c] : kCandC128[c];
         if (two_qubit_dense && k[1] < 2) continue;
@@ -633,12 +636,12 @@ qs_status resolve_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, in
     if (fuse == -1) fuse = 1;
     out.fused = fuse == 1;
     if (!out.fused) return QS_OK;
-    // defaults: 2^12-amplitude tiles of 16 registers per thread (complex<float>, 256 threads),
-    // 2^11 of 4 (complex<double>): the largest register tiles that stay out of scratch memory
+    // defaults: 2^12-amplitude tiles of 16 registers per thread (complex<float>), 2^11 of 8
+    // (complex<double>), both 256 threads: the largest register tiles that stay out of scratch
+    // memory; rows of 256 B (complex<float>) and 128 B (complex<double>), the fastest measured
     int K = (p && p->tile_bits > 0) ? p->tile_bits : (dt == QS_C64 ? 12 : 11);
-    int RB = (p && p->reg_bits > 0) ? p->reg_bits : (dt == QS_C64 ? 4 : 2);
-    // rows of 2^run_bits contiguous amplitudes: 256 bytes
-    int run = (p && p->run_bits > 0) ? p->run_bits : (dt == QS_C64 ? 5 : 4);
+    int RB = (p && p->reg_bits > 0) ? p->reg_bits : (dt == QS_C64 ? 4 : 3);
+    int run = (p && p->run_bits > 0) ? p->run_bits : (dt == QS_C64 ? 5 : 3);
     return fused_plan_for(gates, n_gates, n, dt, K, RB, run, out);
 }
 

@@ -321,10 +321,13 @@ __device__ __forceinline__ void copy_words(uint32_t *dst, const uint32_t *src, i
     for (int w = (int)tid; w < words; w += (int)nthreads) dst[w] = src[w];
 }
 
-// 16 registers per thread (RB = 4) need more than 128 VGPRs: those tiles have at most 256
-// threads and may use the whole register file.
+// Register tiles of 16 complex<float> or 8 complex<double> (and more) need more than 128
+// VGPRs: those tiles have at most 256 threads and may use the whole register file.
 template <typename R, int RB>
-__global__ void __launch_bounds__(RB == 4 ? 256 : 512, RB == 4 ? 1 : 4) k_fused(R *__restrict__ psi, int n, int S, int pass_index,
+constexpr bool kWideTile = RB == 4 || (sizeof(R) == 8 && RB == 3);
+
+template <typename R, int RB>
+__global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512, (kWideTile<R, RB>) ? 1 : 4) k_fused(R *__restrict__ psi, int n, int S, int pass_index,
                                                   int rec_cap, int64_t init,
                                                   const RunParams *__restrict__ dyn,
                                                   const PassDesc *__restrict__ g_passes,
