@@ -422,14 +422,25 @@ __global__ void __launch_bounds__(256) k_2q(R *psi, int n, int qa, int qb, const
     R *p = psi + ((uint64_t)slot << (n + 1));
     uint64_t base = ins0(ins0(c * V, lo), hi);
     const uint64_t ba = 1ull << qa, bb = 1ull << qb;
+    // 16-byte vectors (two complex<float> or one complex<double>); streaming accesses for the
+    // phase and dense kinds when the runs of contiguous amplitudes are at least 4 long (the
+    // permutations measured slower with them)
+    const bool nt = (KIND == 0 || KIND == 3) && lo >= 2;
     auto ld = [&](uint64_t i, cx<R> *a) {
-        if constexpr (V == kVec<R> && V > 1) vload(p, i, a);
-        else if constexpr (V == 1) a[0] = sload(p, i);
-        else vload(p, i, a);
+        if constexpr (V == kVec<R>) {
+            if (nt) vload_nt(p, i, a);
+            else vload(p, i, a);
+        } else {
+            a[0] = sload(p, i);
+        }
     };
     auto st = [&](uint64_t i, const cx<R> *a) {
-        if constexpr (V == 1) sstore(p, i, a[0]);
-        else vstore(p, i, a);
+        if constexpr (V == kVec<R>) {
+            if (nt) vstore_nt(p, i, a);
+            else vstore(p, i, a);
+        } else {
+            sstore(p, i, a[0]);
+        }
     };
     if constexpr (KIND == 0) {
         const double *t = tab_row + (uint64_t)slot * 8;
