@@ -398,10 +398,12 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512, (kWideTile<R, 
     for (int r = 0; r < NR; ++r) {
         uint64_t i = gthr | greg[r];
         if constexpr (sizeof(R) == 4) {
-            float2 v = *reinterpret_cast<const float2 *>(base + 2 * i);
+            typedef float f2 __attribute__((ext_vector_type(2)));
+            f2 v = __builtin_nontemporal_load(reinterpret_cast<const f2 *>(base + 2 * i));
             a[r] = {v.x, v.y};
         } else {
-            double2 v = *reinterpret_cast<const double2 *>(base + 2 * i);
+            typedef double d2 __attribute__((ext_vector_type(2)));
+            d2 v = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(base + 2 * i));
             a[r] = {v.x, v.y};
         }
     }
@@ -517,9 +519,11 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512, (kWideTile<R, 
             if (r & (1 << k)) g |= 1ull << pd->q_pos[TB + k];
         uint64_t i = gthr | g;
         if constexpr (sizeof(R) == 4) {
-            *reinterpret_cast<float2 *>(base + 2 * i) = make_float2(a[r].re, a[r].im);
+            typedef float f2 __attribute__((ext_vector_type(2)));
+            __builtin_nontemporal_store(f2{a[r].re, a[r].im}, reinterpret_cast<f2 *>(base + 2 * i));
         } else {
-            *reinterpret_cast<double2 *>(base + 2 * i) = make_double2(a[r].re, a[r].im);
+            typedef double d2 __attribute__((ext_vector_type(2)));
+            __builtin_nontemporal_store(d2{a[r].re, a[r].im}, reinterpret_cast<d2 *>(base + 2 * i));
         }
     }
 }

@@ -579,7 +579,7 @@ __global__ void __launch_bounds__(kRedThreads) k_overlap_partial(const R *ref, c
         for (uint64_t i = begin + (uint64_t)threadIdx.x * VEC; i < begin + per; i += (uint64_t)VEC * kRedThreads) {
             cx<R> a[VEC], b[VEC];
             vload(ref, i, a);
-            vload(p, i, b);
+            vload_nt(p, i, b);
 #pragma unroll
             for (int k = 0; k < VEC; ++k) {
                 double ar = a[k].re, ai = a[k].im, br = b[k].re, bi = b[k].im;
