@@ -355,6 +355,43 @@ def test_fixed_rank_r1_grover_is_eq10(n, dtype):
 
 
 @pytest.mark.parametrize("dtype", [q.C128, q.C64])
+def test_fixed_rank_full_size_n24(dtype):
+    """The fixed-rank configuration's size, n = 24.  Rank 1: every Kraus step keeps the
+    dominant branch, so p(marked) after j Grover iterations is eq. (10) for any j (here 3).
+    Rank 8: invariants of the truncated form — rank <= 8, trace <= 1, orthogonal stored
+    columns of total weight 1, F_unnorm = exp(log_trace) F_norm."""
+    n, e = 24, 0.02
+    c = grover(n, seed=7, iterations=3)
+    tau = 1e-9 if dtype == q.C128 else 1e-5
+    zt = 1e-13 if dtype == q.C128 else 1e-6
+    tol = 1e-12 if dtype == q.C128 else 1e-5
+    w = q.StateVector(n, dtype, 1)
+    w.init_basis(c.marked)
+    fr = q.FixedRank(n, 1, dtype)
+    fr.init_basis(0)
+    for g in c.gates:
+        fr.apply_noisy_gate(g, e, tau=tau, zero_tol=zt)
+    pu, pn, lt = fr.fidelity(w)
+    assert abs(pu - eq10(n, 3, e)) <= tol * eq10(n, 3, e)
+    assert abs(pn - grover_p_ideal(n, 3)) <= tol
+    fr.close()
+    g1 = grover(n, seed=7, iterations=1)
+    fr = q.FixedRank(n, 8, dtype)
+    fr.init_basis(0)
+    ranks = [fr.apply_noisy_gate(g, e, tau=tau, zero_tol=zt) for g in g1.gates]
+    rank, lt = fr.info()
+    assert max(ranks) <= 8 and rank == ranks[-1] and lt <= 1e-12
+    V = fr.columns()[:rank]
+    G = (V.conj() @ V.T).cpu().numpy().astype(np.complex128) if dtype == q.C128 else \
+        (V.to(torch.complex128).conj() @ V.to(torch.complex128).T).cpu().numpy()
+    gtol = 1e-12 if dtype == q.C128 else 1e-5
+    assert abs(np.trace(G).real - 1.0) <= gtol
+    assert np.max(np.abs(G - np.diag(np.diag(G)))) <= gtol
+    pu, pn, lt2 = fr.fidelity(w)
+    assert lt2 == lt and abs(pu - math.exp(lt) * pn) <= 1e-12 and 0.0 <= pn <= 1.0 + gtol
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
 def test_fixed_rank_r8_against_oracle(dtype):
     n, e, r = 8, 0.05, 8
     c = grover(n, seed=6, iterations=4)
