@@ -157,3 +157,59 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(qm, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(qm.QsimError):
         qm.lib()
+
+
+def test_graph_and_plan_entry_points_validate_before_device_work():
+    L = q.lib()
+    c = qft(10, 1)
+    ga = q.gate_array(c.gates)
+    h = ctypes.c_void_p()
+    sz = ctypes.c_size_t()
+    # bytes_required
+    assert L.qs_traj_graph_bytes_required(ga, len(ga), 10, q.C64, 4, None, ctypes.byref(sz)) == 0 and sz.value > 0
+    assert L.qs_traj_graph_bytes_required(ga, len(ga), 10, q.C64, 0, None, ctypes.byref(sz)) == -1
+    assert L.qs_traj_graph_bytes_required(ga, len(ga), 10, q.C64, 4, None, None) == -1
+    # create: NULL out, T < 1, NULL / misaligned buffer, bad circuit, too small a buffer
+    fake = ctypes.c_void_p(1 << 30)
+    assert L.qs_traj_graph_create(ga, len(ga), 10, q.C64, 4, None, fake, 1 << 30, None) == -1
+    assert L.qs_traj_graph_create(ga, len(ga), 10, q.C64, 0, None, fake, 1 << 30, ctypes.byref(h)) == -1
+    assert L.qs_traj_graph_create(ga, len(ga), 10, q.C64, 4, None, None, 1 << 30, ctypes.byref(h)) == -1
+    assert L.qs_traj_graph_create(ga, len(ga), 10, q.C64, 4, None, ctypes.c_void_p((1 << 30) + 64), 1 << 30,
+                                  ctypes.byref(h)) == -1
+    assert L.qs_traj_graph_create(ga, len(ga), 9, q.C64, 4, None, fake, 1 << 30, ctypes.byref(h)) == -1   # qubit 9 out of range
+    assert L.qs_traj_graph_create(ga, len(ga), 10, q.C64, 4, None, fake, 1024, ctypes.byref(h)) == -1
+    assert "too small" in L.qs_last_error().decode()
+    F = np.zeros(4)
+    assert L.qs_traj_graph_launch(None, 0, None, -1, F.ctypes.data_as(ctypes.c_void_p), None, None, None) == -1
+    assert L.qs_traj_graph_destroy(None) == 0
+    # plan choice
+    assert L.qs_plan_choose(ga, len(ga), 10, q.C64, None, None) == -1
+    p = q.Plan()
+    assert L.qs_plan_choose(ga, len(ga), 35, q.C64, ctypes.byref(p), None) == -1
+    assert L.qs_plan_choose(ga, len(ga), 10, 5, ctypes.byref(p), None) == -1
+    assert L.qs_plan_choose(ga, len(ga), 10, q.C64, ctypes.byref(p), None) == 0 and p.fuse in (0, 1)
+
+
+def test_server_calls_reject_null_handles():
+    L = q.lib()
+    d = ctypes.c_int()
+    info = q.SrvJobInfo()
+    st = q.SrvStats()
+    assert L.qs_srv_poll(None, 1, ctypes.byref(d)) == -1
+    assert L.qs_srv_wait(None, 1, 0.0) == -1
+    assert L.qs_srv_result(None, 1, None, None, None, ctypes.byref(info)) == -1
+    assert L.qs_srv_stats_get(None, ctypes.byref(st)) == -1
+
+
+def test_fused_plan_limits():
+    c = qft(14, 2)
+    ok = {"fuse": 1, "tile_bits": 12, "reg_bits": 4, "run_bits": 5}
+    assert q.traj_bytes_required(c.gates, 14, q.C64, 2, ok) > 0
+    # 16-register complex<float> tiles allow at most 256 threads; complex<double> 8-register too
+    assert q.traj_bytes_required(c.gates, 14, q.C64, 2, {"fuse": 1, "tile_bits": 13, "reg_bits": 4}) == 0
+    assert q.traj_bytes_required(c.gates, 14, q.C128, 2, {"fuse": 1, "tile_bits": 12, "reg_bits": 3}) == 0
+    assert q.traj_bytes_required(c.gates, 14, q.C128, 2, {"fuse": 1, "tile_bits": 11, "reg_bits": 3}) > 0
+    # one-qubit circuits fuse into one whole-state tile
+    from workloads import U1, Gate, haar_2x2
+    g = [Gate(U1, q0=0, m=haar_2x2(np.random.default_rng(0)))]
+    assert q.traj_bytes_required(g, 1, q.C64, 2, {"fuse": 1}) > 0
