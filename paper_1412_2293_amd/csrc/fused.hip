@@ -410,38 +410,47 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512, (kWideTile<R, 
     }
 
     // Register layout: tile-local index of register r of this thread = lthr | roff[r], with
-    // roff from the current round's descriptor (cur_rd; the load layout has the thread id in the
+    // roff from the current round's descriptor (cur_ri; the load layout has the thread id in the
     // low bits).  LDS addresses: swz(lthr | roff[r]) = swz(lthr) ^ swz(roff[r]); the register
     // part is the descriptor's sroff (one scalar load of 16 words), so each access costs one
     // XOR.  The tile sits at the start of the dynamic LDS, addressed directly.
     constexpr uint32_t CXS = sizeof(cxf<R>);
     typedef R v2 __attribute__((ext_vector_type(2)));
     typedef __attribute__((address_space(3))) v2 lds_v2;
-    // dynamic LDS begins after the kernel's static LDS (none: the offset folds to nothing)
+    // the kernel declares no static LDS (checked on the host before its first launch), so the
+    // dynamic LDS, and the tile at its start, begins at LDS address 0
     auto lds_put = [](uint32_t byte, cxf<R> x) {
-        *reinterpret_cast<lds_v2 *>((size_t)(__builtin_amdgcn_groupstaticsize() + byte)) = v2{x.re, x.im};
+        *reinterpret_cast<lds_v2 *>((size_t)byte) = v2{x.re, x.im};
     };
     auto lds_get = [](uint32_t byte) {
-        const v2 v = *reinterpret_cast<const lds_v2 *>((size_t)(__builtin_amdgcn_groupstaticsize() + byte));
+        const v2 v = *reinterpret_cast<const lds_v2 *>((size_t)byte);
         return cxf<R>{v.x, v.y};
     };
     const uint32_t load_mask = (((1u << RB) - 1u) << TB) & kmask;
     uint32_t cur = load_mask;
-    const RoundDesc *cur_rd = &pd->load_round;
+    // current register layout as an index into the rounds array: loads through the kernel
+    // argument with a uniform index stay scalar
+    int cur_ri = pd->load_round;
     uint32_t lthr = tid;
 
-    auto exchange_to = [&](uint32_t to, const RoundDesc *rd) {
+    auto exchange_to = [&](uint32_t to, int ri) {
         __syncthreads();
         {
-            const uint32_t sw = swz(lthr) * CXS;
+            // opaque to the optimiser, which would otherwise distribute the swizzle and the
+            // scaling over every access (three VALU ops per access instead of one XOR)
+            uint32_t sw = swz(lthr) * CXS;
+            asm volatile("" : "+v"(sw));
+            const RoundDesc *from = prog.rounds + cur_ri;
 #pragma unroll
-            for (int r = 0; r < NR; ++r) lds_put(sw ^ (cur_rd->sroff[r] * CXS), a[r]);
+            for (int r = 0; r < NR; ++r) lds_put(sw ^ (from->sroff[r] * CXS), a[r]);
         }
         __syncthreads();
+        const RoundDesc *rd = prog.rounds + ri;
         cur = to;
-        cur_rd = rd;
+        cur_ri = ri;
         lthr = (uint32_t)rd->tlo[tid & 31u] | (uint32_t)rd->thi[(tid >> 5) & 15u];
-        const uint32_t sw = swz(lthr) * CXS;
+        uint32_t sw = swz(lthr) * CXS;
+        asm volatile("" : "+v"(sw));
 #pragma unroll
         for (int r = 0; r < NR; ++r) a[r] = lds_get(sw ^ (rd->sroff[r] * CXS));
     };
@@ -472,7 +481,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512, (kWideTile<R, 
         for (int ri = sd.round_begin; ri < sd.round_end; ++ri) {
             const RoundDesc *rd = prog.rounds + ri;
             const uint32_t mask = rd->reg_mask;
-            if (mask != cur) exchange_to(mask, rd);
+            if (mask != cur) exchange_to(mask, ri);
             const int oe = rd->op_end;
             for (int oi = rd->op_begin; oi < oe; ++oi) {
                 const OpDesc *op = prog.ops + oi;
@@ -501,7 +510,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512, (kWideTile<R, 
                     const cxf<R> f = orec[0];
 #pragma unroll
                     for (int r = 0; r < NR; ++r) {
-                        bool hit = ohit && ((lthr | cur_rd->roff[r]) & lmask) == lvalue;
+                        bool hit = ohit && ((lthr | prog.rounds[cur_ri].roff[r]) & lmask) == lvalue;
                         cxf<R> y = mul(f, a[r]);
                         a[r].re = hit ? y.re : a[r].re;
                         a[r].im = hit ? y.im : a[r].im;
@@ -510,7 +519,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512, (kWideTile<R, 
             }
         }
     }
-    if (cur != load_mask) exchange_to(load_mask, &pd->load_round);
+    if (cur != load_mask) exchange_to(load_mask, pd->load_round);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         uint64_t g = 0;
@@ -574,8 +583,15 @@ hipError_t launch_pass_prep(qs_dtype dt, int S, const PassDesc *h, ProgramDev pr
 template <typename R, int RB>
 static hipError_t fused_attr()
 {
-    static const hipError_t attr = hipFuncSetAttribute((const void *)k_fused<R, RB>,
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    static const hipError_t attr = [] {
+        // the kernel addresses its tile at LDS address 0: it must have no static LDS
+        hipFuncAttributes fa;
+        hipError_t e = hipFuncGetAttributes(&fa, (const void *)k_fused<R, RB>);
+        if (e != hipSuccess) return e;
+        if (fa.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
+        return hipFuncSetAttribute((const void *)k_fused<R, RB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024);
+    }();
     return attr;
 }
 

@@ -74,7 +74,9 @@ struct PassDesc {
     int32_t rec_size;             // complex entries of the pass's records per slot
     int32_t job_begin, job_end;   // OuterJobs of the pass (per-tile outer phase products)
     int32_t stage_begin, stage_end;
-    RoundDesc load_round;         // the load layout (thread id in the low tile-local bits)
+    int32_t load_round;           // index in the rounds array of the load layout (thread id in
+                                  // the low tile-local bits), stored just before round_begin
+    int32_t reserved;
 };
 
 // A stage: consecutive rounds whose op descriptors, records, outer jobs and outer bits are

@@ -232,7 +232,7 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         pd.outer_mask = nmask & ~qmask;
         const uint32_t kmask = (1u << K) - 1u;
         const uint32_t load_mask = ((1u << RB) - 1u) << (K - RB);
-        pd.load_round = make_round(load_mask, K);
+        const RoundDesc load_rd = make_round(load_mask, K);
 
         // greedy register rounds, closed also when the current LDS stage is full
         auto fill = [&](uint32_t need) {
@@ -305,6 +305,8 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         for (auto &rd : rounds)
             if (!rd.forced) rd.forced = fill(rd.need);
         pd.stage_begin = (int)P.stages.size();
+        pd.load_round = (int)P.rounds.size();
+        P.rounds.push_back(load_rd);
         pd.round_begin = (int)P.rounds.size();
         pd.op_begin = (int)P.ops.size();
         pd.job_begin = (int)P.jobs.size();

@@ -154,6 +154,12 @@ def test_program_ranges_are_consistent():
             prog = q.plan_describe(c.gates, c.n, q.C64, plan)
             op_at = round_at = job_at = 0
             for pas in prog["passes"]:
+                # the pass's load layout is the rounds-array entry just before its rounds
+                assert pas["load_round"] == round_at
+                K = len(pas["q_pos"])
+                rb = bin(pas["load_reg_mask"]).count("1")
+                assert rb >= 1 and pas["load_reg_mask"] == ((1 << rb) - 1) << (K - rb)
+                round_at += 1
                 assert pas["op_begin"] == op_at and pas["round_begin"] == round_at
                 assert pas["job_begin"] == job_at
                 rec_at = 0
