@@ -30,6 +30,15 @@ __device__ __forceinline__ cxf<R> fma_c(cxf<R> a, cxf<R> b, cxf<R> c)
     return {a.re * b.re - a.im * b.im + c.re, a.re * b.im + a.im * b.re + c.im};
 }
 
+// Register-tile element: one complex amplitude as a two-lane vector, so that the compiler keeps
+// it in an aligned register pair and moves it with one 64-bit move.
+template <typename R>
+using tv = R __attribute__((ext_vector_type(2)));
+template <typename R>
+__device__ __forceinline__ cxf<R> cx(tv<R> v) { return {v.x, v.y}; }
+template <typename R>
+__device__ __forceinline__ tv<R> tvec(cxf<R> c) { return tv<R>{c.re, c.im}; }
+
 __device__ __forceinline__ uint32_t swz(uint32_t l)
 {
     return lds_swizzle(l);
@@ -119,26 +128,26 @@ __device__ constexpr int quad_base(int k)
 // combination is its own straight-line code behind a scalar branch, with no work for an
 // absent block.
 template <typename R, int RB, int P, bool PRE, bool POST>
-__device__ __forceinline__ void apply_u1(cxf<R> (&a)[1 << RB], const cxf<R> (&m)[4],
+__device__ __forceinline__ void apply_u1(tv<R> (&a)[1 << RB], const cxf<R> (&m)[4],
                                          const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
 #pragma unroll
     for (int k = 0; k < (1 << (RB - 1)); ++k) {
         const int r = pair_base<P>(k);
         const int r1 = r | (1 << P);
-        cxf<R> x0 = a[r], x1 = a[r1];
+        cxf<R> x0 = cx<R>(a[r]), x1 = cx<R>(a[r1]);
         if constexpr (PRE) x1 = mul(pair_phase<R, RB, P>(pre, r), x1);
         cxf<R> y0 = fma_c(m[1], x1, mul(m[0], x0));
         cxf<R> y1 = fma_c(m[3], x1, mul(m[2], x0));
         if constexpr (POST) y1 = mul(pair_phase<R, RB, P>(post, r), y1);
-        a[r] = y0;
-        a[r1] = y1;
+        a[r] = tvec(y0);
+        a[r1] = tvec(y1);
     }
 }
 
 // The same update with a real matrix (m[k].im == 0): half the multiplications.
 template <typename R, int RB, int P, bool PRE, bool POST>
-__device__ __forceinline__ void apply_u1_real(cxf<R> (&a)[1 << RB], const cxf<R> (&m)[4],
+__device__ __forceinline__ void apply_u1_real(tv<R> (&a)[1 << RB], const cxf<R> (&m)[4],
                                               const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
     const R m0 = m[0].re, m1 = m[1].re, m2 = m[2].re, m3 = m[3].re;
@@ -146,24 +155,24 @@ __device__ __forceinline__ void apply_u1_real(cxf<R> (&a)[1 << RB], const cxf<R>
     for (int k = 0; k < (1 << (RB - 1)); ++k) {
         const int r = pair_base<P>(k);
         const int r1 = r | (1 << P);
-        cxf<R> x0 = a[r], x1 = a[r1];
+        cxf<R> x0 = cx<R>(a[r]), x1 = cx<R>(a[r1]);
         if constexpr (PRE) x1 = mul(pair_phase<R, RB, P>(pre, r), x1);
         cxf<R> y0 = {m0 * x0.re + m1 * x1.re, m0 * x0.im + m1 * x1.im};
         cxf<R> y1 = {m2 * x0.re + m3 * x1.re, m2 * x0.im + m3 * x1.im};
         if constexpr (POST) y1 = mul(pair_phase<R, RB, P>(post, r), y1);
-        a[r] = y0;
-        a[r1] = y1;
+        a[r] = tvec(y0);
+        a[r1] = tvec(y1);
     }
 }
 
 template <typename R, int RB, int P0, int P1>
-__device__ __forceinline__ void apply_u2(cxf<R> (&a)[1 << RB], const cxf<R> (&m)[16])
+__device__ __forceinline__ void apply_u2(tv<R> (&a)[1 << RB], const cxf<R> (&m)[16])
 {
 #pragma unroll
     for (int k = 0; k < (1 << (RB - 2)); ++k) {
         const int r0 = quad_base<P0, P1>(k);
         const int r1 = r0 | (1 << P0), r2 = r0 | (1 << P1), r3 = r0 | (1 << P0) | (1 << P1);
-        const cxf<R> x0 = a[r0], x1 = a[r1], x2 = a[r2], x3 = a[r3];
+        const cxf<R> x0 = cx<R>(a[r0]), x1 = cx<R>(a[r1]), x2 = cx<R>(a[r2]), x3 = cx<R>(a[r3]);
         cxf<R> y[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -173,10 +182,10 @@ __device__ __forceinline__ void apply_u2(cxf<R> (&a)[1 << RB], const cxf<R> (&m)
             s = fma_c(m[4 * i + 3], x3, s);
             y[i] = s;
         }
-        a[r0] = y[0];
-        a[r1] = y[1];
-        a[r2] = y[2];
-        a[r3] = y[3];
+        a[r0] = tvec(y[0]);
+        a[r1] = tvec(y[1]);
+        a[r2] = tvec(y[2]);
+        a[r3] = tvec(y[3]);
     }
 }
 
@@ -184,7 +193,7 @@ __device__ __forceinline__ void apply_u2(cxf<R> (&a)[1 << RB], const cxf<R> (&m)
 // is the fall-back): every path rewrites the register tile, which lets the register allocator
 // keep the tile in the same registers across ops instead of copying it at each merge.
 template <typename R, int RB, bool PRE, bool POST>
-__device__ __forceinline__ void dispatch_u1_pp(int p, bool real, cxf<R> (&a)[1 << RB], const cxf<R> (&m)[4],
+__device__ __forceinline__ void dispatch_u1_pp(int p, bool real, tv<R> (&a)[1 << RB], const cxf<R> (&m)[4],
                                                const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
     if (real) {
@@ -201,7 +210,7 @@ __device__ __forceinline__ void dispatch_u1_pp(int p, bool real, cxf<R> (&a)[1 <
 }
 
 template <typename R, int RB>
-__device__ __forceinline__ void dispatch_u1(int p, bool real, cxf<R> (&a)[1 << RB], const cxf<R> (&m)[4],
+__device__ __forceinline__ void dispatch_u1(int p, bool real, tv<R> (&a)[1 << RB], const cxf<R> (&m)[4],
                                             const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
     if (pre.any) {
@@ -214,7 +223,7 @@ __device__ __forceinline__ void dispatch_u1(int p, bool real, cxf<R> (&a)[1 << R
 }
 
 template <typename R, int RB>
-__device__ __forceinline__ void dispatch_u2(int p0, int p1, cxf<R> (&a)[1 << RB], const cxf<R> (&m)[16])
+__device__ __forceinline__ void dispatch_u2(int p0, int p1, tv<R> (&a)[1 << RB], const cxf<R> (&m)[16])
 {
     if constexpr (RB >= 2) {
         switch (p0 * 4 + p1) {
@@ -326,8 +335,16 @@ __device__ __forceinline__ void copy_words(uint32_t *dst, const uint32_t *src, i
 template <typename R, int RB>
 constexpr bool kWideTile = RB == 4 || (sizeof(R) == 8 && RB == 3);
 
+// Waves per SIMD the register allocation must allow.  complex<float> with 16-register tiles is
+// held to 128 VGPRs, so that four 256-thread blocks share a CU (their 32 KiB tiles plus records
+// fit the 160 KiB of LDS, see stage_rec_cap): more waves hide the tile loads and the LDS
+// exchanges better than the registers the compiler would otherwise keep for scheduling.
 template <typename R, int RB>
-__global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512, (kWideTile<R, RB>) ? 1 : 4) k_fused(R *__restrict__ psi, int n, int S, int pass_index,
+constexpr int kMinWaves = (sizeof(R) == 4 && RB == 4) ? 4 : 1;
+
+template <typename R, int RB>
+__global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
+    __attribute__((amdgpu_waves_per_eu(kMinWaves<R, RB>, 8))) k_fused(R *__restrict__ psi, int n, int S, int pass_index,
                                                   int rec_cap, int64_t init,
                                                   const RunParams *__restrict__ dyn,
                                                   const PassDesc *__restrict__ g_passes,
@@ -386,13 +403,13 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512, (kWideTile<R, 
         greg[r] = g;
     }
     R *base = psi + ((uint64_t)slot << (n + 1));
-    cxf<R> a[NR];
+    tv<R> a[NR];
     if (init >= 0 && dyn) init = dyn->init;
     if (init >= 0) {
         // first pass of a run: every slot starts in the basis state |init>, made here
         // instead of read from memory
 #pragma unroll
-        for (int r = 0; r < NR; ++r) a[r] = {(gthr | greg[r]) == (uint64_t)init ? (R)1 : (R)0, (R)0};
+        for (int r = 0; r < NR; ++r) a[r] = tv<R>{(gthr | greg[r]) == (uint64_t)init ? (R)1 : (R)0, (R)0};
     } else {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -400,11 +417,11 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512, (kWideTile<R, 
         if constexpr (sizeof(R) == 4) {
             typedef float f2 __attribute__((ext_vector_type(2)));
             f2 v = __builtin_nontemporal_load(reinterpret_cast<const f2 *>(base + 2 * i));
-            a[r] = {v.x, v.y};
+            a[r] = tv<R>{v.x, v.y};
         } else {
             typedef double d2 __attribute__((ext_vector_type(2)));
             d2 v = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(base + 2 * i));
-            a[r] = {v.x, v.y};
+            a[r] = tv<R>{v.x, v.y};
         }
     }
     }
@@ -442,7 +459,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512, (kWideTile<R, 
             asm volatile("" : "+v"(sw));
             const RoundDesc *from = prog.rounds + cur_ri;
 #pragma unroll
-            for (int r = 0; r < NR; ++r) lds_put(sw ^ (from->sroff[r] * CXS), a[r]);
+            for (int r = 0; r < NR; ++r) lds_put(sw ^ (from->sroff[r] * CXS), cx<R>(a[r]));
         }
         __syncthreads();
         const RoundDesc *rd = prog.rounds + ri;
@@ -452,7 +469,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512, (kWideTile<R, 
         uint32_t sw = swz(lthr) * CXS;
         asm volatile("" : "+v"(sw));
 #pragma unroll
-        for (int r = 0; r < NR; ++r) a[r] = lds_get(sw ^ (rd->sroff[r] * CXS));
+        for (int r = 0; r < NR; ++r) a[r] = tvec(lds_get(sw ^ (rd->sroff[r] * CXS)));
     };
 
     for (int si = pd->stage_begin; si < pd->stage_end; ++si) {
@@ -511,9 +528,8 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512, (kWideTile<R, 
 #pragma unroll
                     for (int r = 0; r < NR; ++r) {
                         bool hit = ohit && ((lthr | prog.rounds[cur_ri].roff[r]) & lmask) == lvalue;
-                        cxf<R> y = mul(f, a[r]);
-                        a[r].re = hit ? y.re : a[r].re;
-                        a[r].im = hit ? y.im : a[r].im;
+                        const tv<R> y = tvec(mul(f, cx<R>(a[r])));
+                        a[r] = hit ? y : a[r];
                     }
                 }
             }
@@ -529,10 +545,10 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512, (kWideTile<R, 
         uint64_t i = gthr | g;
         if constexpr (sizeof(R) == 4) {
             typedef float f2 __attribute__((ext_vector_type(2)));
-            __builtin_nontemporal_store(f2{a[r].re, a[r].im}, reinterpret_cast<f2 *>(base + 2 * i));
+            __builtin_nontemporal_store(a[r], reinterpret_cast<f2 *>(base + 2 * i));
         } else {
             typedef double d2 __attribute__((ext_vector_type(2)));
-            __builtin_nontemporal_store(d2{a[r].re, a[r].im}, reinterpret_cast<d2 *>(base + 2 * i));
+            __builtin_nontemporal_store(a[r], reinterpret_cast<d2 *>(base + 2 * i));
         }
     }
 }
@@ -543,12 +559,15 @@ static size_t stage_fixed_bytes(size_t cxs)
 }
 
 // Record entries staged per stage: 8 KiB of records, or less when the tile leaves less room
-// under 80 KiB (two blocks per CU) / 160 KiB (one block per CU).
+// under 40 KiB (complex<float> tiles of 32 KiB: four blocks per CU), 80 KiB (two blocks per CU)
+// or 160 KiB (one block per CU).
 int stage_rec_cap(qs_dtype dt, int K)
 {
     const size_t cxs = dt == QS_C64 ? 8 : 16;
     const size_t tile = (size_t(1) << K) * cxs;
-    const size_t budget = tile <= 64 * 1024 ? 80 * 1024 : 160 * 1024;
+    const size_t budget = (dt == QS_C64 && tile <= 32 * 1024) ? 40 * 1024
+                          : tile <= 64 * 1024                 ? 80 * 1024
+                                                              : 160 * 1024;
     const size_t fixed = tile + stage_fixed_bytes(cxs);
     if (fixed >= budget) return 0;
     size_t cap = (budget - fixed) / cxs;
