@@ -537,11 +537,12 @@ constexpr double kModelValu = 39.3e12 * 0.9;  // lane-instructions/s: 1024 SIMDs
 constexpr double kModelLaunch = 8e-6;         // s per pass (two launches, amortised over slots below)
 constexpr int kModelSlots = 64;
 
-// Fraction of the streaming bandwidth reached with rows of 2^run_bits contiguous amplitudes.
+// Fraction of the streaming bandwidth reached with rows of 2^run_bits contiguous amplitudes
+// (measured with the fused pass: rows of 128 bytes stream as well as longer ones).
 static double row_efficiency(int run_bits, qs_dtype dt)
 {
     const double bytes = std::ldexp((double)amp_bytes(dt), run_bits);
-    return bytes >= 256 ? 1.0 : bytes >= 128 ? 0.85 : bytes >= 64 ? 0.7 : 0.5;
+    return bytes >= 128 ? 1.0 : bytes >= 64 ? 0.8 : bytes >= 32 ? 0.45 : 0.3;
 }
 
 double model_cost_fused(const Program &P, int n, qs_dtype dt, int S, int run_bits)
@@ -638,10 +639,11 @@ qs_status resolve_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, in
     if (!out.fused) return QS_OK;
     // defaults: 2^12-amplitude tiles of 16 registers per thread (complex<float>), 2^11 of 8
     // (complex<double>), both 256 threads: the largest register tiles that stay out of scratch
-    // memory; rows of 256 B (complex<float>) and 128 B (complex<double>), the fastest measured
+    // memory; rows of 128 B, the shortest that still stream at full rate (fewer register rounds
+    // than longer rows), the fastest measured
     int K = (p && p->tile_bits > 0) ? p->tile_bits : (dt == QS_C64 ? 12 : 11);
     int RB = (p && p->reg_bits > 0) ? p->reg_bits : (dt == QS_C64 ? 4 : 3);
-    int run = (p && p->run_bits > 0) ? p->run_bits : (dt == QS_C64 ? 5 : 3);
+    int run = (p && p->run_bits > 0) ? p->run_bits : (dt == QS_C64 ? 4 : 3);
     return fused_plan_for(gates, n_gates, n, dt, K, RB, run, out);
 }
 
