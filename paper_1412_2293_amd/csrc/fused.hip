@@ -405,6 +405,15 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     R *base = psi + ((uint64_t)slot << (n + 1));
     tv<R> a[NR];
     if (init >= 0 && dyn) init = dyn->init;
+    if (init >= 0 && (outer ^ ((uint64_t)init & pd->outer_mask)) != 0) {
+        // First pass from the basis state |init>: its gates act on tile qubits only (controlled
+        // phases just rescale), so a tile whose tile-number bits differ from init's stays zero.
+        // Uniform per block: the whole block stores zeros and leaves.
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            __builtin_nontemporal_store(tv<R>{(R)0, (R)0}, reinterpret_cast<tv<R> *>(base + 2 * (gthr | greg[r])));
+        return;
+    }
     if (init >= 0) {
         // first pass of a run: every slot starts in the basis state |init>, made here
         // instead of read from memory
