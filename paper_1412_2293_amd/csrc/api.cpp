@@ -792,8 +792,8 @@ static qs_status enqueue_compute(const TrajPrep &prep, const TrajLayout &L, char
                        (const int32_t *)(B + L.obits)};
         for (size_t p = 0; p < P.passes.size(); ++p) {
             QS_HIP(launch_pass_prep(dt, S, &P.passes[p], pdv, tab, gdev, B + L.rec, st));
-            QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (int)p, p == 0 ? (int64_t)init_index : -1, pdv,
-                                     B + L.rec, st, dyn));
+            QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (int)p, p == 0 ? (int64_t)init_index : -1,
+                                     (int64_t)init_index, pdv, B + L.rec, st, dyn));
         }
     } else {
         for (int g = 0; g < n_gates; ++g) {
@@ -959,6 +959,7 @@ qs_status qs_plan_describe(const qs_gate *gates, int n_gates, int n, qs_dtype dt
         for (int j = 0; j < pd.K; ++j) o += (j ? "," : "") + std::to_string(pd.q_pos[j]);
         o += "],";
         I("outer_mask", (long long)pd.outer_mask);
+        I("classical", (long long)pd.classical);
         I("rec_size", pd.rec_size);
         I("load_round", pd.load_round);
         I("load_reg_mask", P.rounds[pd.load_round].reg_mask);

@@ -345,7 +345,7 @@ constexpr int kMinWaves = (sizeof(R) == 4 && RB == 4) ? 4 : 1;
 template <typename R, int RB>
 __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     __attribute__((amdgpu_waves_per_eu(kMinWaves<R, RB>, 8))) k_fused(R *__restrict__ psi, int n, int S, int pass_index,
-                                                  int rec_cap, int64_t init,
+                                                  int rec_cap, int64_t init, int64_t basis,
                                                   const RunParams *__restrict__ dyn,
                                                   const PassDesc *__restrict__ g_passes,
                                                   const StageDesc *__restrict__ g_stages,
@@ -404,14 +404,21 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     }
     R *base = psi + ((uint64_t)slot << (n + 1));
     tv<R> a[NR];
-    if (init >= 0 && dyn) init = dyn->init;
-    if (init >= 0 && (outer ^ ((uint64_t)init & pd->outer_mask)) != 0) {
-        // First pass from the basis state |init>: its gates act on tile qubits only (controlled
-        // phases just rescale), so a tile whose tile-number bits differ from init's stays zero.
-        // Uniform per block: the whole block stores zeros and leaves.
+    if (dyn) {
+        basis = dyn->init;
+        if (init >= 0) init = basis;
+    }
+    if (((outer ^ (uint64_t)basis) & pd->classical) != 0) {
+        // A run starts in the basis state |basis>, and a physical qubit no non-diagonal gate has
+        // touched still holds its basis value (controlled phases only rescale): a tile whose
+        // tile-number bits differ from it there holds zeros before and after this pass.  The
+        // first pass stores them; later passes leave the tile as it is.  Uniform per block.
+        if (init >= 0) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r)
-            __builtin_nontemporal_store(tv<R>{(R)0, (R)0}, reinterpret_cast<tv<R> *>(base + 2 * (gthr | greg[r])));
+            for (int r = 0; r < NR; ++r)
+                __builtin_nontemporal_store(tv<R>{(R)0, (R)0},
+                                            reinterpret_cast<tv<R> *>(base + 2 * (gthr | greg[r])));
+        }
         return;
     }
     if (init >= 0) {
@@ -636,44 +643,47 @@ hipError_t fused_prepare_attributes()
 
 template <typename R, int RB>
 static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_index, int rec_cap,
-                           int64_t init, const RunParams *dyn, ProgramDev prog, const void *rec, size_t lds,
-                           hipStream_t st)
+                           int64_t init, int64_t basis, const RunParams *dyn, ProgramDev prog, const void *rec,
+                           size_t lds, hipStream_t st)
 {
     const hipError_t attr = fused_attr<R, RB>();
     if (attr != hipSuccess) return attr;
     unsigned blocks = (unsigned)((uint64_t)S << (n - h.K));
     unsigned threads = 1u << (h.K - RB);
     hipLaunchKernelGGL((k_fused<R, RB>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index,
-                       rec_cap, init, dyn, prog.passes, prog.stages, prog.rounds, prog.ops, prog.jobs, prog.obits,
+                       rec_cap, init, basis, dyn, prog.passes, prog.stages, prog.rounds, prog.ops, prog.jobs, prog.obits,
                        (const cxf<R> *)rec);
     return hipGetLastError();
 }
 
 hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDesc *pass_host,
-                             int pass_index, int64_t init, ProgramDev prog, const void *rec, hipStream_t st,
-                             const RunParams *dyn)
+                             int pass_index, int64_t init, int64_t basis, ProgramDev prog, const void *rec,
+                             hipStream_t st, const RunParams *dyn)
 {
     const PassDesc &h = *pass_host;
     size_t lds = fused_lds_bytes(dt, h.K);
     const int rec_cap = stage_rec_cap(dt, h.K);
-    if (lds > 160 * 1024 || rec_cap <= 0) return hipErrorInvalidValue;
-    // a pass that makes the initial state only writes it
-    TimedLaunch tl("fused", (init >= 0 ? 1.0 : 2.0) * (double)((uint64_t)S << n) * amp_bytes(dt), st);
+    if (lds > 160 * 1024 || rec_cap <= 0 || basis < 0) return hipErrorInvalidValue;
+    // Algorithmic bytes: a pass that makes the initial state writes every tile once; a later
+    // pass reads and writes the tiles that can hold amplitude, a 2^-popcount(classical) share
+    // of them (the others hold zeros and are left alone).
+    const double share = init >= 0 ? 1.0 : std::ldexp(1.0, -__builtin_popcountll(h.classical));
+    TimedLaunch tl("fused", (init >= 0 ? 1.0 : 2.0) * share * (double)((uint64_t)S << n) * amp_bytes(dt), st);
     if (dt == QS_C64) {
         float *p = (float *)psi;
         switch (h.RB) {
-        case 1: return launch_t<float, 1>(p, n, S, h, pass_index, rec_cap, init, dyn, prog, rec, lds, st);
-        case 2: return launch_t<float, 2>(p, n, S, h, pass_index, rec_cap, init, dyn, prog, rec, lds, st);
-        case 3: return launch_t<float, 3>(p, n, S, h, pass_index, rec_cap, init, dyn, prog, rec, lds, st);
-        case 4: return launch_t<float, 4>(p, n, S, h, pass_index, rec_cap, init, dyn, prog, rec, lds, st);
+        case 1: return launch_t<float, 1>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, lds, st);
+        case 2: return launch_t<float, 2>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, lds, st);
+        case 3: return launch_t<float, 3>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, lds, st);
+        case 4: return launch_t<float, 4>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, lds, st);
         }
     } else {
         double *p = (double *)psi;
         switch (h.RB) {
-        case 1: return launch_t<double, 1>(p, n, S, h, pass_index, rec_cap, init, dyn, prog, rec, lds, st);
-        case 2: return launch_t<double, 2>(p, n, S, h, pass_index, rec_cap, init, dyn, prog, rec, lds, st);
-        case 3: return launch_t<double, 3>(p, n, S, h, pass_index, rec_cap, init, dyn, prog, rec, lds, st);
-        case 4: return launch_t<double, 4>(p, n, S, h, pass_index, rec_cap, init, dyn, prog, rec, lds, st);
+        case 1: return launch_t<double, 1>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, lds, st);
+        case 2: return launch_t<double, 2>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, lds, st);
+        case 3: return launch_t<double, 3>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, lds, st);
+        case 4: return launch_t<double, 4>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, lds, st);
         }
     }
     return hipErrorInvalidValue;

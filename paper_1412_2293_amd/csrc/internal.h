@@ -69,6 +69,9 @@ struct PassDesc {
     int32_t round_begin;
     int32_t round_end;
     uint64_t outer_mask;          // physical bits (< n) that are not in the tile
+    uint64_t classical;           // outer bits that no non-diagonal gate has touched before this
+                                  // pass: they still hold the initial basis index's values, so a
+                                  // tile whose bits there differ from it holds only zeros
     int32_t q_pos[16];            // tile-local bit j -> physical bit
     int32_t op_begin, op_end;     // the pass's ops (records)
     int32_t rec_size;             // complex entries of the pass's records per slot
@@ -212,9 +215,11 @@ hipError_t launch_pass_prep(qs_dtype dt, int S, const PassDesc *pass_host, Progr
 // Sets the fused kernels' LDS limit (done by the first launch otherwise); call before capturing
 // a graph.
 hipError_t fused_prepare_attributes();
+// init >= 0: the first pass of a run, which makes |init> instead of reading the state; basis:
+// the run's initial basis index (every pass, for the zero tiles of untouched qubits).
 hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDesc *pass_host,
-                             int pass_index, int64_t init, ProgramDev prog, const void *rec, hipStream_t st,
-                             const RunParams *dyn = nullptr);
+                             int pass_index, int64_t init, int64_t basis, ProgramDev prog, const void *rec,
+                             hipStream_t st, const RunParams *dyn = nullptr);
 size_t fused_lds_bytes(qs_dtype dt, int K);
 // Record entries per stage that fit next to a tile of 2^K amplitudes (two tiles per CU).
 int stage_rec_cap(qs_dtype dt, int K);

@@ -206,6 +206,7 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
 
     // 4. tiles, rounds and per-slot records
     int max_rec = 0;
+    uint64_t touched = 0;   // physical qubits targeted by non-diagonal gates of earlier passes
     for (size_t pi = 0; pi < passes.size(); ++pi) {
         PassBuild &pb = passes[pi];
         std::vector<int> ops_idx;
@@ -230,6 +231,8 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         }
         uint64_t nmask = (n >= 64) ? ~0ull : ((1ull << n) - 1);
         pd.outer_mask = nmask & ~qmask;
+        pd.classical = pd.outer_mask & ~touched;
+        for (int q : pb.targets) touched |= 1ull << q;
         const uint32_t kmask = (1u << K) - 1u;
         const uint32_t load_mask = ((1u << RB) - 1u) << (K - RB);
         const RoundDesc load_rd = make_round(load_mask, K);

@@ -42,7 +42,14 @@ def emulate(circuit, prog, e=0.0, seed=0, traj=0):
     ops = gate_operators(circuit, e, seed, traj)
     psi = np.zeros(1 << n, np.complex128)
     psi[circuit.init_index] = 1.0
+    all_idx = np.arange(1 << n, dtype=np.int64)
     for pas in prog["passes"]:
+        # Amplitudes outside the support the planner claims (qubits no non-diagonal gate has
+        # touched still hold the initial index's values) must be exactly zero before the pass;
+        # the kernel leaves those tiles alone, and so does the emulation.
+        cl = pas["classical"]
+        assert (cl & ~pas["outer_mask"]) == 0
+        assert not np.any(psi[((all_idx ^ circuit.init_index) & cl) != 0])
         qpos = pas["q_pos"]
         K = len(qpos)
         ar = np.arange(1 << K, dtype=np.int64)
@@ -55,6 +62,8 @@ def emulate(circuit, prog, e=0.0, seed=0, traj=0):
             for k, b in enumerate(obits):
                 if (tile >> k) & 1:
                     outer |= 1 << b
+            if (outer ^ circuit.init_index) & cl:
+                continue
             idx = outer | loc
             v = psi[idx].copy()
             for stage in pas["stages"]:
@@ -176,3 +185,46 @@ def test_program_ranges_are_consistent():
                     assert st["rec_end"] - st["rec_begin"] <= 4096
                 assert pas["op_end"] == op_at and pas["round_end"] == round_at
                 assert pas["job_end"] == job_at and pas["rec_size"] == rec_at
+
+
+def pass_targets(pas):
+    """Physical qubits targeted by the non-diagonal ops of a pass (register bit -> tile-local
+    bit -> physical bit)."""
+    out = 0
+    K = len(pas["q_pos"])
+    for st in pas["stages"]:
+        for rd in st["rounds"]:
+            regbits = [j for j in range(K) if (rd["reg_mask"] >> j) & 1]
+            for op in rd["ops"]:
+                if op["type"] == 0:
+                    out |= 1 << pas["q_pos"][regbits[op["p0"]]]
+                elif op["type"] == 1:
+                    out |= 1 << pas["q_pos"][regbits[op["p0"]]]
+                    out |= 1 << pas["q_pos"][regbits[op["p1"]]]
+    return out
+
+
+@pytest.mark.parametrize("plan", PLANS, ids=lambda p: "-".join(f"{k}{v}" for k, v in p.items()))
+def test_classical_bits_are_the_untouched_tile_number_bits(plan):
+    for c in circuits():
+        if plan.get("tile_bits", 12) > c.n and plan.get("reg_bits", 3) > c.n:
+            continue
+        prog = q.plan_describe(c.gates, c.n, q.C64, plan)
+        touched = 0
+        for pas in prog["passes"]:
+            assert pas["classical"] == pas["outer_mask"] & ~touched, (c.name, plan)
+            touched |= pass_targets(pas)
+
+
+def test_qft_second_pass_has_a_support_bound():
+    """On a QFT from a basis state the low qubits are transformed last, so the second pass still
+    has classical tile-number bits: most of its tiles hold zeros and are left alone."""
+    c = qft(14, seed=6)
+    plan = {"fuse": 1, "tile_bits": 6, "reg_bits": 2, "run_bits": 2}
+    prog = q.plan_describe(c.gates, c.n, q.C64, plan)
+    assert len(prog["passes"]) >= 3
+    assert prog["passes"][0]["classical"] == prog["passes"][0]["outer_mask"]
+    assert prog["passes"][1]["classical"] != 0
+    psi, layout = emulate(c, prog, 0.1, seed=2, traj=1)
+    ref = oracle.sv_run(c, 0.1, seed=2, traj=1)
+    assert np.linalg.norm(unpermute(psi, layout, c.n) - ref) < 1e-12
