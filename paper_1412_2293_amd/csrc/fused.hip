@@ -372,16 +372,27 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     const int TB = K - RB;
     const uint32_t kmask = (1u << K) - 1u;
     const StageLds<R> L = stage_lds<R>(smem, K, rec_cap);
-    const int tiles_log = n - K;
+    // A run starts in the basis state |basis>, and a physical qubit no non-diagonal gate has
+    // touched still holds its basis value (controlled phases only rescale), so only the tiles
+    // that agree with it on the pass's classical bits hold amplitude.  The first pass makes the
+    // state and stores every tile (the others as zeros); a later pass is launched over the
+    // tiles that hold amplitude only: its blocks walk the other tile-number bits.
+    const bool first = init >= 0;
+    if (dyn) {
+        basis = dyn->init;
+        if (first) init = basis;
+    }
+    const uint64_t walk = first ? pd->outer_mask : (pd->outer_mask & ~pd->classical);
+    const int tiles_log = __builtin_popcountll(walk);
     const int slot = (int)(blockIdx.x >> tiles_log);
     const uint64_t tile = (uint64_t)blockIdx.x & ((1ull << tiles_log) - 1ull);
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
     const cxf<R> *__restrict__ rec = rec_all + (size_t)slot * pd->rec_size;
 
     // Outer (tile-number) bits of the physical index.
-    uint64_t outer = 0;
+    uint64_t outer = first ? 0 : ((uint64_t)basis & pd->classical);
     {
-        uint64_t m = pd->outer_mask, t = tile;
+        uint64_t m = walk, t = tile;
         while (m) {
             uint64_t low = m & (~m + 1ull);
             if (t & 1ull) outer |= low;
@@ -404,21 +415,11 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     }
     R *base = psi + ((uint64_t)slot << (n + 1));
     tv<R> a[NR];
-    if (dyn) {
-        basis = dyn->init;
-        if (init >= 0) init = basis;
-    }
-    if (((outer ^ (uint64_t)basis) & pd->classical) != 0) {
-        // A run starts in the basis state |basis>, and a physical qubit no non-diagonal gate has
-        // touched still holds its basis value (controlled phases only rescale): a tile whose
-        // tile-number bits differ from it there holds zeros before and after this pass.  The
-        // first pass stores them; later passes leave the tile as it is.  Uniform per block.
-        if (init >= 0) {
+    if (first && ((outer ^ (uint64_t)basis) & pd->classical) != 0) {
+        // a tile of the first pass outside the support: zeros (uniform per block)
 #pragma unroll
-            for (int r = 0; r < NR; ++r)
-                __builtin_nontemporal_store(tv<R>{(R)0, (R)0},
-                                            reinterpret_cast<tv<R> *>(base + 2 * (gthr | greg[r])));
-        }
+        for (int r = 0; r < NR; ++r)
+            __builtin_nontemporal_store(tv<R>{(R)0, (R)0}, reinterpret_cast<tv<R> *>(base + 2 * (gthr | greg[r])));
         return;
     }
     if (init >= 0) {
@@ -648,7 +649,9 @@ static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_ind
 {
     const hipError_t attr = fused_attr<R, RB>();
     if (attr != hipSuccess) return attr;
-    unsigned blocks = (unsigned)((uint64_t)S << (n - h.K));
+    // the first pass stores every tile; a later one runs over the tiles that hold amplitude
+    const int free_bits = n - h.K - (init >= 0 ? 0 : __builtin_popcountll(h.classical));
+    unsigned blocks = (unsigned)((uint64_t)S << free_bits);
     unsigned threads = 1u << (h.K - RB);
     hipLaunchKernelGGL((k_fused<R, RB>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index,
                        rec_cap, init, basis, dyn, prog.passes, prog.stages, prog.rounds, prog.ops, prog.jobs, prog.obits,
