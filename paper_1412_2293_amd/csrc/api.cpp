@@ -960,6 +960,8 @@ qs_status qs_plan_describe(const qs_gate *gates, int n_gates, int n, qs_dtype dt
         o += "],";
         I("outer_mask", (long long)pd.outer_mask);
         I("classical", (long long)pd.classical);
+        I("lclassical", (long long)pd.lclassical);
+        I("zero_fill", pd.zero_fill);
         I("rec_size", pd.rec_size);
         I("load_round", pd.load_round);
         I("load_reg_mask", P.rounds[pd.load_round].reg_mask);

@@ -374,15 +374,18 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     const StageLds<R> L = stage_lds<R>(smem, K, rec_cap);
     // A run starts in the basis state |basis>, and a physical qubit no non-diagonal gate has
     // touched still holds its basis value (controlled phases only rescale), so only the tiles
-    // that agree with it on the pass's classical bits hold amplitude.  The first pass makes the
-    // state and stores every tile (the others as zeros); a later pass is launched over the
-    // tiles that hold amplitude only: its blocks walk the other tile-number bits.
+    // that agree with it on the pass's classical bits hold amplitude, and inside a tile only the
+    // amplitudes that agree with it on the tile-local classical bits.  A pass is launched over
+    // the tiles that hold amplitude (its blocks walk the other tile-number bits) and reads only
+    // those amplitudes; the first pass also stores the other tiles as zeros when no later pass
+    // rewrites them.
     const bool first = init >= 0;
     if (dyn) {
         basis = dyn->init;
         if (first) init = basis;
     }
-    const uint64_t walk = first ? pd->outer_mask : (pd->outer_mask & ~pd->classical);
+    const bool fill = first && pd->zero_fill;
+    const uint64_t walk = fill ? pd->outer_mask : (pd->outer_mask & ~pd->classical);
     const int tiles_log = __builtin_popcountll(walk);
     const int slot = (int)(blockIdx.x >> tiles_log);
     const uint64_t tile = (uint64_t)blockIdx.x & ((1ull << tiles_log) - 1ull);
@@ -390,7 +393,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     const cxf<R> *__restrict__ rec = rec_all + (size_t)slot * pd->rec_size;
 
     // Outer (tile-number) bits of the physical index.
-    uint64_t outer = first ? 0 : ((uint64_t)basis & pd->classical);
+    uint64_t outer = fill ? 0 : ((uint64_t)basis & pd->classical);
     {
         uint64_t m = walk, t = tile;
         while (m) {
@@ -415,7 +418,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     }
     R *base = psi + ((uint64_t)slot << (n + 1));
     tv<R> a[NR];
-    if (first && ((outer ^ (uint64_t)basis) & pd->classical) != 0) {
+    if (fill && ((outer ^ (uint64_t)basis) & pd->classical) != 0) {
         // a tile of the first pass outside the support: zeros (uniform per block)
 #pragma unroll
         for (int r = 0; r < NR; ++r)
@@ -428,19 +431,24 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
 #pragma unroll
         for (int r = 0; r < NR; ++r) a[r] = tv<R>{(gthr | greg[r]) == (uint64_t)init ? (R)1 : (R)0, (R)0};
     } else {
+        // read only the amplitudes that can be nonzero: tile-local index tid | r << TB agrees
+        // with the basis index on the tile-local classical bits (thread part per lane, register
+        // part uniform)
+        const uint32_t lc = pd->lclassical;
+        uint32_t blocal = 0;
+        for (int j = 0; j < K; ++j)
+            if (((uint64_t)basis >> pd->q_pos[j]) & 1ull) blocal |= 1u << j;
+        const uint32_t tmask = (1u << TB) - 1u;
+        const bool tok = ((tid ^ blocal) & lc & tmask) == 0;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        uint64_t i = gthr | greg[r];
-        if constexpr (sizeof(R) == 4) {
-            typedef float f2 __attribute__((ext_vector_type(2)));
-            f2 v = __builtin_nontemporal_load(reinterpret_cast<const f2 *>(base + 2 * i));
-            a[r] = tv<R>{v.x, v.y};
-        } else {
-            typedef double d2 __attribute__((ext_vector_type(2)));
-            d2 v = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(base + 2 * i));
-            a[r] = tv<R>{v.x, v.y};
+        for (int r = 0; r < NR; ++r) {
+            const bool rok = ((((uint32_t)r << TB) ^ blocal) & lc & ~tmask) == 0;
+            a[r] = tv<R>{(R)0, (R)0};
+            if (rok && tok) {
+                const uint64_t i = gthr | greg[r];
+                a[r] = __builtin_nontemporal_load(reinterpret_cast<const tv<R> *>(base + 2 * i));
+            }
         }
-    }
     }
 
     // Register layout: tile-local index of register r of this thread = lthr | roff[r], with
@@ -649,8 +657,9 @@ static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_ind
 {
     const hipError_t attr = fused_attr<R, RB>();
     if (attr != hipSuccess) return attr;
-    // the first pass stores every tile; a later one runs over the tiles that hold amplitude
-    const int free_bits = n - h.K - (init >= 0 ? 0 : __builtin_popcountll(h.classical));
+    // the first pass may store every tile; otherwise a pass runs over the tiles that hold amplitude
+    const bool fill = init >= 0 && h.zero_fill;
+    const int free_bits = n - h.K - (fill ? 0 : __builtin_popcountll(h.classical));
     unsigned blocks = (unsigned)((uint64_t)S << free_bits);
     unsigned threads = 1u << (h.K - RB);
     hipLaunchKernelGGL((k_fused<R, RB>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index,
@@ -667,11 +676,13 @@ hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDes
     size_t lds = fused_lds_bytes(dt, h.K);
     const int rec_cap = stage_rec_cap(dt, h.K);
     if (lds > 160 * 1024 || rec_cap <= 0 || basis < 0) return hipErrorInvalidValue;
-    // Algorithmic bytes: a pass that makes the initial state writes every tile once; a later
-    // pass reads and writes the tiles that can hold amplitude, a 2^-popcount(classical) share
-    // of them (the others hold zeros and are left alone).
-    const double share = init >= 0 ? 1.0 : std::ldexp(1.0, -__builtin_popcountll(h.classical));
-    TimedLaunch tl("fused", (init >= 0 ? 1.0 : 2.0) * share * (double)((uint64_t)S << n) * amp_bytes(dt), st);
+    // Algorithmic bytes: a pass writes the tiles that can hold amplitude (a 2^-popcount(classical)
+    // share; every tile when the first pass stores the zeros) and reads, except the first pass,
+    // the amplitudes of the support inside them (a further 2^-popcount(lclassical) share).
+    const bool fill_all = init >= 0 && h.zero_fill;
+    const double tiles_share = fill_all ? 1.0 : std::ldexp(1.0, -__builtin_popcountll(h.classical));
+    const double read_share = init >= 0 ? 0.0 : std::ldexp(1.0, -__builtin_popcount(h.lclassical));
+    TimedLaunch tl("fused", (1.0 + read_share) * tiles_share * (double)((uint64_t)S << n) * amp_bytes(dt), st);
     if (dt == QS_C64) {
         float *p = (float *)psi;
         switch (h.RB) {

@@ -79,6 +79,11 @@ struct PassDesc {
     int32_t stage_begin, stage_end;
     int32_t load_round;           // index in the rounds array of the load layout (thread id in
                                   // the low tile-local bits), stored just before round_begin
+    uint32_t lclassical;          // tile-local bits whose qubits no non-diagonal gate has touched
+                                  // before this pass: only the amplitudes that agree with the
+                                  // basis index there can be nonzero, and only those are read
+    int32_t zero_fill;            // first pass: store the tiles outside the support as zeros
+                                  // (needed unless the last pass rewrites every amplitude)
     int32_t reserved;
 };
 

@@ -232,6 +232,9 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         uint64_t nmask = (n >= 64) ? ~0ull : ((1ull << n) - 1);
         pd.outer_mask = nmask & ~qmask;
         pd.classical = pd.outer_mask & ~touched;
+        pd.lclassical = 0;
+        for (int j = 0; j < K; ++j)
+            if (!((touched >> Q[j]) & 1ull)) pd.lclassical |= 1u << j;
         for (int q : pb.targets) touched |= 1ull << q;
         const uint32_t kmask = (1u << K) - 1u;
         const uint32_t load_mask = ((1u << RB) - 1u) << (K - RB);
@@ -456,6 +459,10 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         max_rec = std::max(max_rec, rec);
         P.passes.push_back(pd);
     }
+    // The first pass stores the zero tiles unless the last pass rewrites every amplitude (no
+    // tile-number bit of it is still classical); every other pass reads only amplitudes of the
+    // support, which the pass before it wrote.
+    if (!P.passes.empty()) P.passes.front().zero_fill = P.passes.back().classical != 0;
     P.max_rec = max_rec;
     return QS_OK;
 }

@@ -38,34 +38,53 @@ def gate_operators(circuit, e, seed, traj):
 
 
 def emulate(circuit, prog, e=0.0, seed=0, traj=0):
+    """Run the program the way the kernel does, on memory that starts as garbage (NaN): the
+    first pass makes the basis state in its tile, a pass works only on the tiles that can hold
+    amplitude and reads only the amplitudes of the support (every one of them must have been
+    written by an earlier pass), and the first pass stores the other tiles as zeros only when
+    the program asks for it.  At the end every amplitude must have been written."""
     n = circuit.n
     ops = gate_operators(circuit, e, seed, traj)
-    psi = np.zeros(1 << n, np.complex128)
-    psi[circuit.init_index] = 1.0
+    b = circuit.init_index
+    psi = np.full(1 << n, np.nan, np.complex128)
     all_idx = np.arange(1 << n, dtype=np.int64)
-    for pas in prog["passes"]:
-        # Amplitudes outside the support the planner claims (qubits no non-diagonal gate has
-        # touched still hold the initial index's values) must be exactly zero before the pass;
-        # the kernel leaves those tiles alone, and so does the emulation.
-        cl = pas["classical"]
-        assert (cl & ~pas["outer_mask"]) == 0
-        assert not np.any(psi[((all_idx ^ circuit.init_index) & cl) != 0])
+    for pi, pas in enumerate(prog["passes"]):
+        first = pi == 0
+        cl, lc = pas["classical"], pas["lclassical"]
         qpos = pas["q_pos"]
         K = len(qpos)
+        assert (cl & ~pas["outer_mask"]) == 0 and lc < (1 << K)
+        # Before the pass, amplitudes outside the support (untouched qubits hold b's values:
+        # the classical tile-number bits and the tile-local classical bits) are zero wherever
+        # they have been written.
+        untouched = cl | sum(1 << qpos[j] for j in range(K) if (lc >> j) & 1)
+        outside = psi[((all_idx ^ b) & untouched) != 0]
+        assert np.all(np.isnan(outside) | (outside == 0)), (pi, "support")
         ar = np.arange(1 << K, dtype=np.int64)
         loc = np.zeros(1 << K, np.int64)
+        blocal = 0
         for j, qb in enumerate(qpos):
             loc |= ((ar >> j) & 1) << qb
-        obits = [b for b in range(n) if (pas["outer_mask"] >> b) & 1]
+            blocal |= ((b >> qb) & 1) << j
+        readable = ((ar ^ blocal) & lc) == 0
+        obits = [bb for bb in range(n) if (pas["outer_mask"] >> bb) & 1]
         for tile in range(1 << (n - K)):
             outer = 0
-            for k, b in enumerate(obits):
+            for k, bb in enumerate(obits):
                 if (tile >> k) & 1:
-                    outer |= 1 << b
-            if (outer ^ circuit.init_index) & cl:
-                continue
+                    outer |= 1 << bb
             idx = outer | loc
-            v = psi[idx].copy()
+            if (outer ^ b) & cl:
+                if first and pas["zero_fill"]:
+                    psi[idx] = 0.0
+                continue
+            if first:
+                v = (idx == b).astype(np.complex128)
+            else:
+                v = np.zeros(1 << K, np.complex128)
+                vals = psi[idx[readable]]
+                assert np.all(np.isfinite(vals)), (pi, "read of an amplitude no pass wrote")
+                v[readable] = vals
             for stage in pas["stages"]:
                 for rnd in stage["rounds"]:
                     m = rnd["reg_mask"]
@@ -104,6 +123,7 @@ def emulate(circuit, prog, e=0.0, seed=0, traj=0):
                             sel = (ar & op["lmask"]) == op["lvalue"]
                             v[sel] *= f
             psi[idx] = v
+    assert np.all(np.isfinite(psi)), "amplitudes no pass wrote"
     return psi, prog["layout"]
 
 
