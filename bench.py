@@ -116,15 +116,22 @@ def main():
     launch_bytes = fused["alg_bytes"] / max(fused["launches"], 1)
     achieved = launch_bytes / (launch_ms / 1e3) / 1e9
     traffic = None
+    valu_busy = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
         if tr.get("source_hash") == source_hash() and tr.get("n") == n and tr.get("T") == T:
             traffic = tr.get("hbm_bytes_per_launch")
+            valu_busy = tr.get("valu_busy_by_pass")
+    # Algorithmic bytes of a pass count the tiles that can hold amplitude and the support
+    # amplitudes read inside them (a run starts from a basis state); the pass that dominates
+    # the step is bound by vector-instruction issue, whose profiled busy fraction is given
+    # beside the HBM figures.
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_fused<float,RB>", "launches_per_step": fused["launches"] / a.steps,
-                "avg_launch_ms": round(launch_ms, 4), "alg_bytes_per_launch": launch_bytes}
+                "avg_launch_ms": round(launch_ms, 4), "alg_bytes_per_launch": launch_bytes,
+                "valu_busy_by_pass_profiled": valu_busy}
     out = {
         "metric": METRIC, "value": value, "unit": "amplitude-updates/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",

@@ -15,9 +15,23 @@ import numpy as np
 from . import qsim as q
 
 
+def state_bytes_per_slot(desc: dict, n: int, amp: int) -> float:
+    """Algorithmic HBM bytes of one slot's state traffic under a plan, as the library counts
+    them for a fused plan: a pass writes the tiles that can hold amplitude (all of them when the
+    first pass stores the zeros) and, after the first, reads the support amplitudes inside them."""
+    N = float(1 << n)
+    total = 0.0
+    for i, p in enumerate(desc["passes"]):
+        first = i == 0
+        tiles = 1.0 if (first and p["zero_fill"]) else 2.0 ** -bin(p["classical"]).count("1")
+        reads = 0.0 if first else 2.0 ** -bin(p["lclassical"]).count("1")
+        total += (1.0 + reads) * tiles * N * amp
+    return total
+
+
 def prepare(requests, dtype: int = q.C64, plan=None) -> List[dict]:
     """Build every request's circuit and gate array up front (outside any timed region) and its
-    algorithmic HBM bytes: fused passes x (T + 1) states x read + write of 2^n amplitudes."""
+    algorithmic HBM bytes: (T + 1) states x the state traffic of its plan."""
     amp = 8 if dtype == q.C64 else 16
     out = []
     for r in requests:
@@ -25,8 +39,9 @@ def prepare(requests, dtype: int = q.C64, plan=None) -> List[dict]:
         ga = q.gate_array(c.gates)
         desc = q.plan_describe(ga, c.n, dtype, plan)
         passes = len(desc["passes"]) if desc["fused"] else len(c.gates)
+        per_slot = state_bytes_per_slot(desc, c.n, amp) if desc["fused"] else 2.0 * (1 << c.n) * amp * len(c.gates)
         out.append({"req": r, "circ": c, "ga": ga, "passes": passes,
-                    "alg_bytes": passes * 2.0 * (1 << c.n) * amp * (r.T + 1),
+                    "alg_bytes": per_slot * (r.T + 1),
                     "marked": c.marked if c.marked is not None else -1})
     return out
 
