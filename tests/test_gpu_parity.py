@@ -459,3 +459,61 @@ def test_timing_records_kernels():
     t = q.timing_read("fused")
     assert t["launches"] >= 1 and t["ms"] > 0 and t["alg_bytes"] > 0
     q.timing_reset()
+
+
+def partially_touched_circuit(n: int, n_gates: int, active, seed: int):
+    """Random gates whose non-diagonal targets all lie in `active`; controlled phases, sign flips
+    and SWAPs may involve every qubit.  The other qubits keep the initial index's values (up to
+    relabelling), so fused passes leave tiles and amplitudes outside that support alone and the
+    first pass stores the zero tiles."""
+    from workloads import CNOT, NOISE_NONE, SWAP, U2, _renumber_sites, haar_2x2, random_unitary
+    rng = np.random.default_rng(seed)
+    N = 1 << n
+    act = list(active)
+    gates = []
+    for _ in range(n_gates):
+        k = int(rng.integers(0, 7))
+        if k <= 2:
+            gates.append(Gate(U1, q0=int(rng.choice(act)), m=haar_2x2(rng), noise=NOISE_ROT))
+        elif k == 3:
+            a, b = (int(v) for v in rng.choice(n, size=2, replace=False))
+            gates.append(Gate(CP, q0=a, q1=b, theta=float(rng.uniform(0, 2 * math.pi)), noise=NOISE_PHASE))
+        elif k == 4:
+            a, b = (int(v) for v in rng.choice(act, size=2, replace=False))
+            gates.append(Gate(U2, q0=a, q1=b, m=random_unitary(4, rng)) if rng.random() < 0.5
+                         else Gate(CNOT, q0=a, q1=b))
+        elif k == 5:
+            mask = int(rng.integers(0, N)) | (1 << int(rng.integers(0, n)))
+            gates.append(Gate(FLIP, mask=mask, value=int(rng.integers(0, N)) & mask))
+        else:
+            # a SWAP moves the roles of qubits: keep the active set closed under it
+            a, b = (int(v) for v in rng.choice(act, size=2, replace=False))
+            gates.append(Gate(SWAP, q0=a, q1=b))
+    return Circuit(n, _renumber_sites(gates), name=f"partial{n}", init_index=int(rng.integers(0, N)))
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+@pytest.mark.parametrize("plan", [{"fuse": 1}, {"fuse": 1, "tile_bits": 6, "reg_bits": 2, "run_bits": 2},
+                                  {"fuse": 1, "tile_bits": 8, "reg_bits": 3, "run_bits": 3}],
+                         ids=["default", "t6r2", "t8r3"])
+def test_untouched_qubits_full_states(dtype, plan):
+    """Circuits that leave qubits untouched by non-diagonal gates: every amplitude of every
+    trajectory (including those the passes never compute, stored as zeros by the first pass)
+    against the oracle, for several initial indices."""
+    engaged = False
+    for n, active, seed in ((12, [0, 3, 4, 9, 10], 1), (13, [1, 2, 5, 6, 7, 11, 12], 2), (14, [13, 12, 8], 3)):
+        c = partially_touched_circuit(n, 60, active, seed)
+        desc = q.plan_describe(c.gates, n, dtype, plan)
+        engaged |= any(p["classical"] for p in desc["passes"][1:]) or desc["passes"][0]["zero_fill"] == 1
+        T, e, s = 3, 0.1, 5
+        for init in (c.init_index, (1 << n) - 1, 0):
+            res = q.run_trajectories(c.gates, n, init, dtype, T, e=e, seed=s, plan=plan)
+            ci = Circuit(n, c.gates, name=c.name, init_index=init)
+            F_ref, _, ideal, states = oracle.run_trajectories(ci, e, s, range(T), keep_states=True)
+            st = q.trajectory_states(res, n, dtype, T).cpu().numpy().astype(np.complex128)
+            tol = 1e-12 if dtype == q.C128 else 3e-5
+            assert rel_err(unpermute(st[0], res["layout"], n), ideal) <= tol, (n, init)
+            for t in range(T):
+                assert rel_err(unpermute(st[t + 1], res["layout"], n), states[t]) <= tol, (n, init, t)
+            assert np.max(np.abs(res["F"] - F_ref)) <= TOL[dtype]
+    assert engaged
