@@ -186,16 +186,31 @@ __global__ void __launch_bounds__(256) k_fr_gram_mfma(const R *V, int n, int r_i
     o[1] = sy;
 }
 
+// One block per Gram entry: its threads take the blocks' partials in a fixed stride, then a
+// fixed-order tree over the threads.
 __global__ void __launch_bounds__(256) k_fr_gram_final(const double *partials, int nb, double *out)
 {
-    const int t = threadIdx.x;
+    __shared__ double sh[2][256];
+    const int e = blockIdx.x, t = threadIdx.x;
     double sx = 0.0, sy = 0.0;
-    for (int b = 0; b < nb; ++b) {
-        sx += partials[((uint64_t)b * 256 + t) * 2];
-        sy += partials[((uint64_t)b * 256 + t) * 2 + 1];
+    for (int b = t; b < nb; b += 256) {
+        sx += partials[((uint64_t)b * 256 + e) * 2];
+        sy += partials[((uint64_t)b * 256 + e) * 2 + 1];
     }
-    out[2 * t] = sx;
-    out[2 * t + 1] = sy;
+    sh[0][t] = sx;
+    sh[1][t] = sy;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) {
+            sh[0][t] += sh[0][t + s];
+            sh[1][t] += sh[1][t + s];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[2 * e] = sh[0][0];
+        out[2 * e + 1] = sh[1][0];
+    }
 }
 
 // coef: 16 x 16 complex doubles, row (x' * 8 + k'), column (y * 8 + c).
@@ -268,7 +283,7 @@ hipError_t launch_fr_gram(const void *V, qs_dtype dt, int n, int r, int q, doubl
     else
         hipLaunchKernelGGL(k_fr_gram<double>, dim3(1u << lb), dim3(256), 0, st, (const double *)V,
                            n, r, q, lb, partials);
-    hipLaunchKernelGGL(k_fr_gram_final, dim3(1), dim3(256), 0, st, partials, 1 << lb, gram_out);
+    hipLaunchKernelGGL(k_fr_gram_final, dim3(256), dim3(256), 0, st, partials, 1 << lb, gram_out);
     return hipGetLastError();
 }
 
