@@ -169,6 +169,8 @@ def main():
         out["graph_replay"] = graph_bench(q, torch)
         out["dm13"] = dm13_bench(q, torch)
         torch.cuda.empty_cache()
+        out["dm_qft13"] = dm_qft13_bench(q, torch)
+        torch.cuda.empty_cache()
         out["fr24"] = fr24_bench(q, torch)
         torch.cuda.empty_cache()
         if a.serving_requests > 0:
@@ -404,6 +406,65 @@ def dm13_bench(q, torch):
     rho.close()
     ideal.close()
     return out
+
+
+def dm_qft13_bench(q, torch, es=(0.005, 0.01, 0.02, 0.05), n_inputs=4):
+    """Density-matrix QFT on n = 13 (vec rho: 2^26 complex<double>), noisy Hadamards as their
+    eq. (6) channel and noisy controlled phases as their eq. (9) channel, for a seeded sample of
+    basis inputs and several noise strengths: the exact fidelity <psi_ideal|rho|psi_ideal> of
+    each, their mean, and beside it the Section 3.3 lower estimates eq. (11) and eq. (15) (a
+    synthetic counterpart of the paper's QFT fidelity figure)."""
+    import math
+
+    import numpy as np
+    from workloads import qft
+    n = 13
+    rng = np.random.default_rng(13)
+    inputs = [int(x) for x in rng.integers(0, 1 << n, size=n_inputs)]
+    log(f"[bench] dm_qft13: {len(es)} noise strengths x {n_inputs} inputs on vec(rho) of 2^{2 * n} entries")
+
+    def eq11(e):
+        PH = 0.5 * (1 + math.exp(-2 * e * e))
+        PR = math.exp(-e * e)
+        return PH ** n * PR ** (n * (n - 1) / 8)
+
+    def eq15(e):
+        PH = 0.5 * (1 + math.exp(-2 * e * e))
+        P = math.exp(-e * e)
+        f = (math.sqrt(1 + 3 * P) - P - 1) / math.sqrt(P * (1 - P))
+        PRt = (math.sqrt(P) + f * math.sqrt(1 - P)) ** 2 / (1 + f * f) ** 4
+        return PH ** n * PRt ** (n * (n - 1) / 8)
+
+    rho = q.StateVector(2 * n, q.C128, 1)
+    ideal = q.StateVector(n, q.C128, 1)
+    rows = []
+    q.timing_reset()
+    q.timing_enable(True)
+    t0 = time.perf_counter()
+    for e in es:
+        fs = []
+        for x in inputs:
+            ga = q.gate_array(qft(n, seed=1).gates)
+            ideal.init_basis(x)
+            for g in ga:
+                q.apply_gate(ideal, g)
+            rho.init_basis(x * ((1 << n) + 1))
+            for g in ga:
+                q.dm_apply_gate(rho, g, e)
+            f, tr = q.dm_fidelity(rho, ideal, 0)
+            fs.append(f)
+        rows.append({"e": e, "fidelity_by_input": fs, "fidelity_mean": float(np.mean(fs)),
+                     "eq11": eq11(e), "eq15": eq15(e)})
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    q.timing_enable(False)
+    k = q.timing_read("sweep_2q")
+    gbs = k["alg_bytes"] / (k["ms"] / 1e3) / 1e9 if k["ms"] else 0.0
+    rho.close()
+    ideal.close()
+    return {"workload": f"qft{n} on vec(rho) complex128, noisy H (eq. 6) and controlled phases (eq. 9)",
+            "inputs": inputs, "by_e": rows, "wall_s": t1 - t0, "runs": len(es) * len(inputs),
+            "sweep_GBps": round(gbs, 1), "sweep_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def fr24_bench(q, torch, iterations=10):

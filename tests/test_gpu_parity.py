@@ -517,3 +517,37 @@ def test_untouched_qubits_full_states(dtype, plan):
                 assert rel_err(unpermute(st[t + 1], res["layout"], n), states[t]) <= tol, (n, init, t)
             assert np.max(np.abs(res["F"] - F_ref)) <= TOL[dtype]
     assert engaged
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+def test_dm_qft13_full_size_against_closed_form(dtype):
+    """Density-matrix QFT at n = 13 (vec(rho) of 2^26 entries), noisy Hadamards (eq. 6) and noisy
+    controlled phases (eq. 9): the fidelity to the ideal output equals the noise average of the
+    trajectory fidelity, prod_t (1 + exp(-2e^2) exp(-e^2 m_t / 2)) / 2 (m_t = ones of x below
+    t), for inputs with few and many ones; Tr rho = 1."""
+    from paper_forms import qft_expected_fidelity
+    n, e = 13, 0.05
+    for x in (1, (1 << n) - 2, 0x0A5B):
+        c = qft(n, seed=1)
+        c = Circuit(n, c.gates, name=c.name, init_index=x)
+        rho = q.StateVector(2 * n, dtype, 1)
+        rho.init_basis(x * ((1 << n) + 1))
+        for g in c.gates:
+            q.dm_apply_gate(rho, g, e)
+        ideal = q.StateVector(n, dtype, 1)
+        to_device_states(ideal, qft_ideal_state(n, x)[None, :])
+        f, tr = q.dm_fidelity(rho, ideal, 0)
+        F = qft_expected_fidelity(n, x, e)
+        tol = 1e-12 if dtype == q.C128 else 2e-5
+        assert abs(f - F) <= tol * F if dtype == q.C128 else abs(f - F) <= tol, (x, f, F)
+        assert abs(tr - 1.0) <= tol, (x, tr)
+        rho.close()
+        ideal.close()
+
+
+def qft_ideal_state(n, x):
+    """QFT|x> = N^-1/2 sum_y exp(-2 pi i x y / N)|y>, the transform's ideal output (numpy FFT)."""
+    N = 1 << n
+    ex = np.zeros(N, np.complex128)
+    ex[x] = 1.0
+    return np.fft.fft(ex) / math.sqrt(N)
