@@ -173,6 +173,8 @@ def main():
         torch.cuda.empty_cache()
         out["fr24"] = fr24_bench(q, torch)
         torch.cuda.empty_cache()
+        out["fr_vs_dm12"] = fr_vs_dm12_bench(q, torch)
+        torch.cuda.empty_cache()
         if a.serving_requests > 0:
             out["serving"] = serving_bench(q, torch, a.serving_requests, a.serving_inflight)
             torch.cuda.empty_cache()
@@ -465,6 +467,42 @@ def dm_qft13_bench(q, torch, es=(0.005, 0.01, 0.02, 0.05), n_inputs=4):
     return {"workload": f"qft{n} on vec(rho) complex128, noisy H (eq. 6) and controlled phases (eq. 9)",
             "inputs": inputs, "by_e": rows, "wall_s": t1 - t0, "runs": len(es) * len(inputs),
             "sweep_GBps": round(gbs, 1), "sweep_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def fr_vs_dm12_bench(q, torch, ranks=(1, 2, 4, 8)):
+    """Fixed rank against the exact density matrix on the paper's small case (Grover n = 12,
+    e = 0.01, the whole circuit): the marked probability, unnormalised (can only fall short of
+    the exact value) and normalised, for several ranks, and the exact value from vec(rho)."""
+    from workloads import grover
+    n, e = 12, 0.01
+    c = grover(n, seed=12)
+    ga = q.gate_array(c.gates)
+    log(f"[bench] fr_vs_dm12: ranks {ranks}, {len(c.gates)} gates")
+    w = q.StateVector(n, q.C128, 1)
+    w.init_basis(c.marked)
+    rho = q.StateVector(2 * n, q.C128, 1)
+    rho.init_basis(0)
+    t0 = time.perf_counter()
+    for g in ga:
+        q.dm_apply_gate(rho, g, e)
+    p_dm, tr = q.dm_fidelity(rho, w, 0)
+    t_dm = time.perf_counter() - t0
+    rows = []
+    for r in ranks:
+        fr = q.FixedRank(n, r, q.C128)
+        fr.init_basis(0)
+        t0 = time.perf_counter()
+        for g in ga:
+            fr.apply_noisy_gate(g, e)
+        fu, fn, lt = fr.fidelity(w)
+        rows.append({"r": r, "p_unnormalised": fu, "p_normalised": fn, "log_trace": lt,
+                     "abs_err_unnormalised": abs(fu - p_dm), "abs_err_normalised": abs(fn - p_dm),
+                     "wall_s": time.perf_counter() - t0})
+        fr.close()
+    rho.close()
+    w.close()
+    return {"workload": f"grover{n} (j={c.meta['iterations']}), e={e}, complex128", "p_exact_dm": p_dm,
+            "trace_dm": tr, "dm_wall_s": t_dm, "by_rank": rows}
 
 
 def fr24_bench(q, torch, iterations=10):

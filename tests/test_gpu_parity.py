@@ -551,3 +551,35 @@ def qft_ideal_state(n, x):
     ex = np.zeros(N, np.complex128)
     ex[x] = 1.0
     return np.fft.fft(ex) / math.sqrt(N)
+
+
+def test_fixed_rank_unnormalised_never_exceeds_the_density_matrix():
+    """Truncation removes a positive semidefinite part at every Kraus step and the later channels
+    are positive maps, so the unnormalised fixed-rank <w|rho_r|w> can only fall short of the
+    exact density-matrix value, for every r; rank 1 is eq. (10) exactly."""
+    n, e = 10, 0.05
+    c = grover(n, seed=8, iterations=6)
+    w = q.StateVector(n, q.C128, 1)
+    w.init_basis(c.marked)
+    rho = q.StateVector(2 * n, q.C128, 1)
+    rho.init_basis(0)
+    for g in c.gates:
+        q.dm_apply_gate(rho, g, e)
+    p_dm, tr = q.dm_fidelity(rho, w, 0)
+    assert abs(tr - 1.0) <= 1e-12
+    prev = None
+    for r in (1, 2, 4, 8):
+        fr = q.FixedRank(n, r, q.C128)
+        fr.init_basis(0)
+        for g in c.gates:
+            fr.apply_noisy_gate(g, e)
+        fu, fn, lt = fr.fidelity(w)
+        assert fu <= p_dm * (1 + 1e-12), (r, fu, p_dm)
+        assert lt <= 1e-12
+        if r == 1:
+            assert abs(fu - eq10(n, c.meta["iterations"], e)) <= 1e-12 * eq10(n, c.meta["iterations"], e)
+        prev = fu
+        fr.close()
+    assert prev > 0.5 * p_dm   # r = 8 keeps most of it
+    rho.close()
+    w.close()
