@@ -175,6 +175,8 @@ def main():
         torch.cuda.empty_cache()
         out["fr_vs_dm12"] = fr_vs_dm12_bench(q, torch)
         torch.cuda.empty_cache()
+        out["choi"] = choi_bench(q, torch)
+        torch.cuda.empty_cache()
         if a.serving_requests > 0:
             out["serving"] = serving_bench(q, torch, a.serving_requests, a.serving_inflight)
             torch.cuda.empty_cache()
@@ -503,6 +505,32 @@ def fr_vs_dm12_bench(q, torch, ranks=(1, 2, 4, 8)):
     w.close()
     return {"workload": f"grover{n} (j={c.meta['iterations']}), e={e}, complex128", "p_exact_dm": p_dm,
             "trace_dm": tr, "dm_wall_s": t_dm, "by_rank": rows}
+
+
+def choi_bench(q, torch):
+    """Choi-Jamiolkowski relative states (Section 4) on the density-matrix path: the three-qubit
+    phase-error code against the phase-error probability p, with eq. (18) beside it (the paper
+    states its fidelity as the square root of the overlap), and the five-qubit QFT under
+    amplitude and phase relaxation (T1, T2 in units of one gate time)."""
+    import math
+
+    import workloads as w
+    from paper_1412_2293_amd import choi
+    log("[bench] choi: phase code and QFT5 relative states")
+    t0 = time.perf_counter()
+    code = []
+    for p in (0.01, 0.05, 0.1, 0.2, 0.3):
+        F, tr = choi.relative_state_fidelity(w.phase_code(p), q.C128)
+        code.append({"p": p, "overlap": F, "sqrt_overlap": math.sqrt(max(F, 0.0)),
+                     "eq18_F_min": math.sqrt(1 - 3 * p * p + 2 * p ** 3), "trace": tr})
+    qft = []
+    for T1, T2 in ((10.0, 5.0), (30.0, 20.0), (100.0, 70.0), (300.0, 200.0), (1000.0, 700.0)):
+        t1 = time.perf_counter()
+        F, tr = choi.relative_state_fidelity(w.qft_relaxation(5, T1, T2), q.C128)
+        qft.append({"T1": T1, "T2": T2, "overlap": F, "trace": tr, "wall_s": time.perf_counter() - t1})
+    return {"workload": "relative states on vec(rho) complex128: phase code (3 + 1 reference qubits), "
+                        "qft5 with relaxation after every gate (5 + 5 reference qubits, 2^20 entries)",
+            "phase_code": code, "qft5": qft, "wall_s": time.perf_counter() - t0}
 
 
 def fr24_bench(q, torch, iterations=10):

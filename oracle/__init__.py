@@ -262,3 +262,58 @@ def kraus_phase(theta: float, e: float) -> np.ndarray:
     E1 = np.diag([1.0, 1.0, 1.0, ph * np.sqrt(P)])
     E2 = np.diag([0.0, 0.0, 0.0, ph * np.sqrt(1.0 - P)])
     return np.stack([E1, E2]).astype(np.complex128)
+
+
+# ------------------------------------------------------------------------------------------
+# Choi-Jamiolkowski relative states (Section 4, eq. 16-17)
+# ------------------------------------------------------------------------------------------
+def _gate_unitary(g):
+    """(qubits, unitary) of a gate of the circuit description, for a one-operator Kraus step."""
+    from workloads import CNOT, CP, SWAP, U1, U2
+    if g.kind == U1:
+        return [g.q0], np.asarray(g.m, np.complex128)
+    if g.kind == U2:
+        return [g.q0, g.q1], np.asarray(g.m, np.complex128)
+    if g.kind == CNOT:   # control q0, target q1; local index bit(q0) + 2 bit(q1)
+        return [g.q0, g.q1], np.array([[1, 0, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0], [0, 1, 0, 0]], np.complex128)
+    if g.kind == CP:
+        return [g.q0, g.q1], np.diag([1, 1, 1, np.exp(-1j * g.theta)]).astype(np.complex128)
+    if g.kind == SWAP:
+        return [g.q0, g.q1], np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]], np.complex128)
+    raise ValueError("gate kind not supported in relative-state programs")
+
+
+def choi_state(prog) -> np.ndarray:
+    """rho_E of eq. (17) for the register and its references: |0><0|, the entangling gates of
+    eq. (16), then the program's gates (U rho U^dagger) and channels (sum_k E_k rho E_k^dagger)."""
+    from workloads import Channel, choi_preparation
+    N = prog.total_qubits()
+    rho = np.zeros((1 << N, 1 << N), np.complex128)
+    rho[0, 0] = 1.0
+    for st in choi_preparation(prog) + list(prog.steps):
+        if isinstance(st, Channel):
+            rho = dm_apply_kraus(rho, N, list(st.qubits), st.ops)
+        else:
+            qs, U = _gate_unitary(st)
+            rho = dm_apply_kraus(rho, N, qs, U[None])
+    return rho
+
+
+def choi_target(prog, index: int) -> np.ndarray:
+    """The ideal relative state with the ancillas in the basis values of `index`."""
+    from workloads import Circuit, choi_preparation
+    N = prog.total_qubits()
+    c = Circuit(N, choi_preparation(prog) + list(prog.ideal), init_index=index)
+    return sv_run(c, 0.0)
+
+
+def choi_fidelity(prog):
+    """Relative-state fidelity sum_a <target_a|rho_E|target_a> over the ancilla assignments a
+    (the ancillas traced out), and Tr rho_E."""
+    from workloads import ancilla_indices
+    rho = choi_state(prog)
+    F = 0.0
+    for idx in ancilla_indices(prog):
+        f, tr = dm_expect(rho, choi_target(prog, idx))
+        F += f.real
+    return F, dm_expect(rho, choi_target(prog, 0))[1].real

@@ -257,3 +257,112 @@ def serving_stream(n_requests: int = 2000, seed: int = 3, n_min: int = 12, n_max
     es = rng.uniform(e_min, e_max, n_requests)
     return [Request(i, float(arrivals[i]), SERVING_KINDS[int(kinds[i])], int(ns[i]), int(Ts[i]), float(es[i]),
                     seed * 100003 + i) for i in range(n_requests)]
+
+
+# ------------------------------------------------------------------------------------------
+# Choi-Jamiolkowski relative states (Section 4): a register of qubits, the qubits whose input is
+# entangled with a reference (eq. 16), the noisy steps (gates and Kraus channels), the ideal
+# gates that define the target, and the ancillas that are traced out at the end.
+# ------------------------------------------------------------------------------------------
+@dataclass
+class Channel:
+    """A Kraus channel {E_k} on one or two qubits (sum_k E_k^dagger E_k = I); 4x4 operators use
+    the local index bit(qubits[0]) + 2 * bit(qubits[1])."""
+    qubits: tuple
+    ops: np.ndarray
+
+
+@dataclass
+class ChoiProgram:
+    n: int                      # register qubits (references are added after them)
+    logical: List[int]          # register qubits entangled with reference n + k (eq. 16)
+    steps: list                 # Gate or Channel, applied to the register (eq. 17)
+    ideal: List[Gate]           # gates that map the entangled input to the target
+    ancillas: List[int] = field(default_factory=list)   # traced out in the fidelity
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    def total_qubits(self) -> int:
+        return self.n + len(self.logical)
+
+
+def amplitude_damping(t: float, T1: float) -> np.ndarray:
+    """Amplitude relaxation over time t (textbook channel): gamma = 1 - exp(-t / T1)."""
+    g = 1.0 - math.exp(-t / T1)
+    return np.array([[[1, 0], [0, math.sqrt(1 - g)]], [[0, math.sqrt(g)], [0, 0]]], np.complex128)
+
+
+def dephasing(p: float) -> np.ndarray:
+    """Phase error with probability p: {sqrt(1 - p) I, sqrt(p) Z}."""
+    return np.array([[[math.sqrt(1 - p), 0], [0, math.sqrt(1 - p)]],
+                     [[math.sqrt(p), 0], [0, -math.sqrt(p)]]], np.complex128)
+
+
+def dephasing_from_T2(t: float, T2: float) -> np.ndarray:
+    """Phase relaxation over time t with the probability of eq. (19): T2 = -t / ln(1 - 2p)."""
+    return dephasing(0.5 * (1.0 - math.exp(-t / T2)))
+
+
+def _u1(q: int, m) -> Gate:
+    return Gate(U1, q0=q, m=np.asarray(m, np.complex128))
+
+
+_T = np.diag([1.0, np.exp(1j * math.pi / 4)])
+_TDG = np.diag([1.0, np.exp(-1j * math.pi / 4)])
+
+
+def toffoli_gates(c1: int, c2: int, t: int) -> List[Gate]:
+    """Toffoli (controls c1, c2, target t) as Hadamards, T / T^dagger and six CNOTs (the standard
+    exact decomposition)."""
+    return [_u1(t, H_MATRIX), Gate(CNOT, q0=c2, q1=t), _u1(t, _TDG), Gate(CNOT, q0=c1, q1=t), _u1(t, _T),
+            Gate(CNOT, q0=c2, q1=t), _u1(t, _TDG), Gate(CNOT, q0=c1, q1=t), _u1(c2, _T), _u1(t, _T),
+            _u1(t, H_MATRIX), Gate(CNOT, q0=c1, q1=c2), _u1(c1, _T), _u1(c2, _TDG), Gate(CNOT, q0=c1, q1=c2)]
+
+
+def phase_code(p: float) -> ChoiProgram:
+    """Three-qubit phase-error code (Section 4.1) on the logical qubit 0: encode (CNOTs then
+    Hadamards), a phase error with probability p on each code qubit, decode (Hadamards, CNOTs,
+    and the majority correction as a Toffoli controlled by the syndrome qubits 1 and 2).  The
+    target is the identity on the logical qubit; the syndrome qubits are traced out."""
+    enc = [Gate(CNOT, q0=0, q1=1), Gate(CNOT, q0=0, q1=2)] + [_u1(q, H_MATRIX) for q in range(3)]
+    noise = [Channel((q,), dephasing(p)) for q in range(3)]
+    dec = [_u1(q, H_MATRIX) for q in range(3)] + [Gate(CNOT, q0=0, q1=1), Gate(CNOT, q0=0, q1=2)]
+    dec += toffoli_gates(1, 2, 0)
+    return ChoiProgram(3, [0], enc + noise + dec, [], ancillas=[1, 2], name=f"phase_code p={p}",
+                       meta={"p": p})
+
+
+def qft_relaxation(n: int, T1: float, T2: float, t: float = 1.0) -> ChoiProgram:
+    """QFT on n qubits (Section 4.3; the noiseless gates of ``qft``) with amplitude and phase
+    relaxation on every qubit after every gate, each gate lasting t."""
+    gates = [Gate(g.kind, q0=g.q0, q1=g.q1, m=g.m, theta=g.theta) for g in qft(n, 0, noisy_h=False).gates]
+    steps = []
+    for g in gates:
+        steps.append(g)
+        for q in range(n):
+            steps.append(Channel((q,), amplitude_damping(t, T1)))
+            steps.append(Channel((q,), dephasing_from_T2(t, T2)))
+    return ChoiProgram(n, list(range(n)), steps, gates, name=f"qft{n} T1={T1} T2={T2}",
+                       meta={"T1": T1, "T2": T2, "t": t})
+
+
+def choi_preparation(prog: ChoiProgram) -> List[Gate]:
+    """Gates that make the maximally entangled input of eq. (16) from |0...0>: a Hadamard on
+    each logical qubit and a CNOT onto its reference qubit n + k."""
+    out: List[Gate] = []
+    for k, l in enumerate(prog.logical):
+        out.append(_u1(l, H_MATRIX))
+        out.append(Gate(CNOT, q0=l, q1=prog.n + k))
+    return out
+
+
+def ancilla_indices(prog: ChoiProgram) -> List[int]:
+    """Basis indices of every assignment of the traced-out ancillas (all other qubits 0)."""
+    out = []
+    for a in range(1 << len(prog.ancillas)):
+        idx = 0
+        for b, q in enumerate(prog.ancillas):
+            if (a >> b) & 1:
+                idx |= 1 << q
+        out.append(idx)
+    return out
