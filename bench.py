@@ -510,8 +510,9 @@ def fr_vs_dm12_bench(q, torch, ranks=(1, 2, 4, 8)):
 def choi_bench(q, torch):
     """Choi-Jamiolkowski relative states (Section 4) on the density-matrix path: the three-qubit
     phase-error code against the phase-error probability p, with eq. (18) beside it (the paper
-    states its fidelity as the square root of the overlap), and the five-qubit QFT under
-    amplitude and phase relaxation (T1, T2 in units of one gate time)."""
+    states its fidelity as the square root of the overlap), Shor's nine-qubit code under the same
+    errors (with the three-qubit code and an unprotected qubit beside it), and the five-qubit QFT
+    under amplitude and phase relaxation (T1, T2 in units of one gate time)."""
     import math
 
     import workloads as w
@@ -523,6 +524,11 @@ def choi_bench(q, torch):
         F, tr = choi.relative_state_fidelity(w.phase_code(p), q.C128)
         code.append({"p": p, "overlap": F, "sqrt_overlap": math.sqrt(max(F, 0.0)),
                      "eq18_F_min": math.sqrt(1 - 3 * p * p + 2 * p ** 3), "trace": tr})
+    shor = []
+    for p in (0.001, 0.01, 0.05, 0.1):
+        F, tr = choi.relative_state_fidelity(w.shor_code(p), q.C128)
+        shor.append({"p": p, "overlap": F, "sqrt_overlap": math.sqrt(max(F, 0.0)), "trace": tr,
+                     "phase_code_overlap": 1 - 3 * p * p + 2 * p ** 3, "unprotected_overlap": 1 - p})
     qft = []
     for T1, T2 in ((10.0, 5.0), (30.0, 20.0), (100.0, 70.0), (300.0, 200.0), (1000.0, 700.0)):
         t1 = time.perf_counter()
@@ -530,7 +536,7 @@ def choi_bench(q, torch):
         qft.append({"T1": T1, "T2": T2, "overlap": F, "trace": tr, "wall_s": time.perf_counter() - t1})
     return {"workload": "relative states on vec(rho) complex128: phase code (3 + 1 reference qubits), "
                         "qft5 with relaxation after every gate (5 + 5 reference qubits, 2^20 entries)",
-            "phase_code": code, "qft5": qft, "wall_s": time.perf_counter() - t0}
+            "phase_code": code, "shor_code": shor, "qft5": qft, "wall_s": time.perf_counter() - t0}
 
 
 def fr24_bench(q, torch, iterations=10):

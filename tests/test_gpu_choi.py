@@ -46,3 +46,15 @@ def test_one_qubit_channel_closed_form():
     F, tr = choi.relative_state_fidelity(w.ChoiProgram(1, [0], steps, []), q.C128)
     s = math.sqrt(1.0 - g)
     assert abs(F - ((1 - p) * ((1 + s) / 2) ** 2 + p * ((1 - s) / 2) ** 2)) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+def test_shor_code_against_closed_form(dtype):
+    """Shor's code under phase errors: F = 1 - 3q^2 + 2q^3, q = 3p(1-p)^2 + p^3 (eight traced-out
+    qubits, 2^20-entry vec(rho))."""
+    for p in (0.0, 0.02, 0.1):
+        F, tr = choi.relative_state_fidelity(w.shor_code(p), dtype)
+        qb = 3 * p * (1 - p) ** 2 + p ** 3
+        tol = 1e-12 if dtype == q.C128 else 5e-6
+        assert abs(F - (1 - 3 * qb * qb + 2 * qb ** 3)) <= tol, (p, F)
+        assert abs(tr - 1.0) <= tol

@@ -57,3 +57,13 @@ def test_noiseless_program_has_unit_fidelity():
 def test_relaxation_lowers_qft_fidelity_monotonically():
     Fs = [oracle.choi_fidelity(w.qft_relaxation(3, T, T))[0] for T in (5.0, 20.0, 100.0, 1e6)]
     assert Fs[0] < Fs[1] < Fs[2] < Fs[3] and abs(Fs[3] - 1.0) < 1e-4
+
+
+def test_shor_code_phase_errors():
+    """Under phase errors alone each block of Shor's code carries a phase flip when an odd number
+    of its qubits is hit, q = 3p(1-p)^2 + p^3, and the outer code corrects one flipped block:
+    F = 1 - 3q^2 + 2q^3."""
+    p = 0.07
+    F, tr = oracle.choi_fidelity(w.shor_code(p))
+    qb = 3 * p * (1 - p) ** 2 + p ** 3
+    assert abs(F - (1 - 3 * qb * qb + 2 * qb ** 3)) < 1e-12 and abs(tr - 1.0) < 1e-12

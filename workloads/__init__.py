@@ -366,3 +366,23 @@ def ancilla_indices(prog: ChoiProgram) -> List[int]:
                 idx |= 1 << q
         out.append(idx)
     return out
+
+
+def shor_code(p: float) -> ChoiProgram:
+    """Shor's nine-qubit code (Section 4.2) on the logical qubit 0 with a phase error of
+    probability p on every code qubit.  Encode: CNOTs 0 -> 3, 6, Hadamards on 0, 3, 6, then
+    CNOTs b -> b+1, b+2 in each block b = 0, 3, 6.  Decode: in each block the CNOTs again and a
+    Toffoli controlled by b+1, b+2 onto b (bit correction), then Hadamards on 0, 3, 6, CNOTs
+    0 -> 3, 6 and a Toffoli controlled by 3, 6 onto 0 (phase correction).  The target is the
+    identity on the logical qubit; the other eight qubits are traced out."""
+    enc = [Gate(CNOT, q0=0, q1=3), Gate(CNOT, q0=0, q1=6)] + [_u1(b, H_MATRIX) for b in (0, 3, 6)]
+    for b in (0, 3, 6):
+        enc += [Gate(CNOT, q0=b, q1=b + 1), Gate(CNOT, q0=b, q1=b + 2)]
+    noise = [Channel((q,), dephasing(p)) for q in range(9)]
+    dec = []
+    for b in (0, 3, 6):
+        dec += [Gate(CNOT, q0=b, q1=b + 1), Gate(CNOT, q0=b, q1=b + 2)] + toffoli_gates(b + 1, b + 2, b)
+    dec += [_u1(b, H_MATRIX) for b in (0, 3, 6)] + [Gate(CNOT, q0=0, q1=3), Gate(CNOT, q0=0, q1=6)]
+    dec += toffoli_gates(3, 6, 0)
+    return ChoiProgram(9, [0], enc + noise + dec, [], ancillas=list(range(1, 9)), name=f"shor_code p={p}",
+                       meta={"p": p})
