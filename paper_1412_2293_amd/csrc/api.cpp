@@ -491,7 +491,8 @@ qs_status qs_timing_reset(void)
 namespace {
 
 struct TrajLayout {
-    size_t states, tab, gates, edev, passes, stages, rounds, ops, prefs, jobs, obits, rec, partials, out, dyn, total;
+    size_t states, tab, gates, edev, passes, stages, rounds, ops, prefs, jobs, obits, chains, rec, partials, out, dyn,
+        total;
 };
 
 struct Plan {
@@ -668,6 +669,7 @@ TrajLayout traj_layout(int n, qs_dtype dt, int T, int n_gates, const Plan &pl)
     L.prefs = take(std::max<size_t>(pl.prog.prefs.size(), 1) * sizeof(PrepRef));
     L.jobs = take(std::max<size_t>(pl.prog.jobs.size(), 1) * sizeof(OuterJob));
     L.obits = take(std::max<size_t>(pl.prog.obits.size(), 1) * sizeof(int32_t));
+    L.chains = take(std::max<size_t>(pl.prog.chain_gates.size() + pl.prog.chain_off.size(), 1) * sizeof(int32_t));
     L.rec = take((size_t)std::max(pl.prog.max_rec, 1) * S * 2 * (dt == QS_C64 ? 4 : 8));
     L.partials = take(reduce_partials_doubles(n, S) * sizeof(double));
     L.out = take((size_t)S * 5 * sizeof(double));
@@ -727,6 +729,8 @@ static TrajLayout prep_layout(const TrajPrep &prep, int T)
     pl.prog.prefs.resize(prep.prog.prefs.size());
     pl.prog.jobs.resize(prep.prog.jobs.size());
     pl.prog.obits.resize(prep.prog.obits.size());
+    pl.prog.chain_gates.resize(prep.prog.chain_gates.size());
+    pl.prog.chain_off.resize(prep.prog.chain_off.size());
     pl.prog.max_rec = prep.prog.max_rec;
     return traj_layout(prep.n, prep.dt, T, (int)prep.hg.size(), pl);
 }
@@ -758,6 +762,12 @@ static qs_status upload_program(const TrajPrep &prep, const TrajLayout &L, char 
         QS_HIP(hipMemcpyAsync(B + L.jobs, P.jobs.data(), sizeof(OuterJob) * P.jobs.size(), hipMemcpyHostToDevice, st));
     if (!P.obits.empty())
         QS_HIP(hipMemcpyAsync(B + L.obits, P.obits.data(), sizeof(int32_t) * P.obits.size(), hipMemcpyHostToDevice, st));
+    if (!P.chain_off.empty()) {
+        QS_HIP(hipMemcpyAsync(B + L.chains, P.chain_off.data(), sizeof(int32_t) * P.chain_off.size(),
+                              hipMemcpyHostToDevice, st));
+        QS_HIP(hipMemcpyAsync(B + L.chains + sizeof(int32_t) * P.chain_off.size(), P.chain_gates.data(),
+                              sizeof(int32_t) * P.chain_gates.size(), hipMemcpyHostToDevice, st));
+    }
     return QS_OK;
 }
 
@@ -783,6 +793,10 @@ static qs_status enqueue_compute(const TrajPrep &prep, const TrajLayout &L, char
     na.traj_base = nz ? nz->traj_base : 0;
     na.first_noisy_slot = 1;
     QS_HIP(launch_noise_table(gdev, n_gates, S, na, tab, st));
+    if (prep.fused && !P.chain_off.empty()) {
+        const int32_t *off = (const int32_t *)(B + L.chains);
+        QS_HIP(launch_phase_chains(tab, S, off + P.chain_off.size(), off, (int)P.chain_off.size() - 1, st));
+    }
     // fused runs make the initial state inside their first pass
     if (!prep.fused || P.passes.empty()) QS_HIP(launch_init_basis(psi, dt, n, S, init_index, st, dyn));
     if (prep.fused) {
@@ -898,9 +912,9 @@ qs_status qs_traj_layout(const qs_gate *gates, int n_gates, int n, qs_dtype dt, 
     Plan pl;
     if ((v = resolve_plan(gates, n_gates, n, dt, T, plan, pl)) != QS_OK) return v;
     TrajLayout L = traj_layout(n, dt, T, n_gates, pl);
-    size_t vals[15] = {L.states, L.tab, L.gates, L.edev, L.passes, L.stages, L.rounds, L.ops, L.prefs,
-                       L.jobs, L.obits, L.rec, L.partials, L.out, L.total};
-    for (int i = 0; i < 15; ++i) out[i] = vals[i];
+    size_t vals[16] = {L.states, L.tab, L.gates, L.edev, L.passes, L.stages, L.rounds, L.ops, L.prefs,
+                       L.jobs, L.obits, L.chains, L.rec, L.partials, L.out, L.total};
+    for (int i = 0; i < 16; ++i) out[i] = vals[i];
     return QS_OK;
 }
 
@@ -950,6 +964,13 @@ qs_status qs_plan_describe(const qs_gate *gates, int n_gates, int n, qs_dtype dt
     }
     o += "\"layout\":[";
     for (size_t q = 0; q < pl.prog.layout.size(); ++q) o += (q ? "," : "") + std::to_string(pl.prog.layout[q]);
+    o += "],\"chains\":[";
+    for (size_t c = 0; c + 1 < pl.prog.chain_off.size(); ++c) {
+        o += c ? ",[" : "[";
+        for (int k = pl.prog.chain_off[c]; k < pl.prog.chain_off[c + 1]; ++k)
+            o += (k != pl.prog.chain_off[c] ? "," : "") + std::to_string(pl.prog.chain_gates[k]);
+        o += "]";
+    }
     o += "],\"passes\":[";
     const Program &P = pl.prog;
     for (size_t pi = 0; pi < P.passes.size(); ++pi) {
@@ -992,6 +1013,7 @@ qs_status qs_plan_describe(const qs_gate *gates, int n_gates, int n, qs_dtype dt
                     const OpDesc &op = P.ops[oi];
                     o += oi != rd.op_begin ? ",{" : "{";
                     I("type", op.type);
+                    I("flags", op.flags);
                     I("p0", op.p0);
                     I("p1", op.p1);
                     I("gate", op.gate);

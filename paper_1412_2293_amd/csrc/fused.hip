@@ -86,26 +86,32 @@ struct PhaseSet {
 
 // grec: the block in global memory (uniform reads, held in scalar registers); lrec: the same
 // block staged in LDS (per-thread table lookups); wout: per-tile outer products in LDS.
+// bits: whether the block has phases conditioned on register bits (else only w is used).
 template <typename R, int RB>
 __device__ __forceinline__ void load_phases(PhaseSet<R, RB> &ps, const cxf<R> *__restrict__ grec,
-                                            const cxf<R> *lrec, bool present, int job,
+                                            const cxf<R> *lrec, bool present, bool bits, int job,
                                             const cxf<R> *wout, uint32_t tid)
 {
     ps.any = present;
     if (!present) return;
+    if (bits) {
 #pragma unroll
-    for (int k = 0; k < RB; ++k) ps.bit[k] = grec[k];
+        for (int k = 0; k < RB; ++k) ps.bit[k] = grec[k];
+    }
     ps.w = mul(lrec[4 + (tid & 31u)], lrec[36 + ((tid >> 5) & 15u)]);
     if (job >= 0) ps.w = mul(ps.w, wout[job]);
 }
 
-template <typename R, int RB, int P>
+// Phase of the pair at register index r: w, times the register-bit factors when BITS.
+template <typename R, int RB, int P, bool BITS>
 __device__ __forceinline__ cxf<R> pair_phase(const PhaseSet<R, RB> &ps, int r)
 {
     cxf<R> w = ps.w;
+    if constexpr (BITS) {
 #pragma unroll
-    for (int q = 0; q < RB; ++q)
-        if (q != P && ((r >> q) & 1)) w = mul(w, ps.bit[q]);
+        for (int q = 0; q < RB; ++q)
+            if (q != P && ((r >> q) & 1)) w = mul(w, ps.bit[q]);
+    }
     return w;
 }
 
@@ -124,10 +130,10 @@ __device__ constexpr int quad_base(int k)
     return pair_base<hi>(pair_base<lo>(k));
 }
 
-// PRE / POST: whether the folded phase blocks are present.  They are uniform per op, so each
-// combination is its own straight-line code behind a scalar branch, with no work for an
-// absent block.
-template <typename R, int RB, int P, bool PRE, bool POST>
+// PRE: input phase kind (0 none, 1 one factor per thread, 2 with register-bit factors); POST:
+// whether the folded output block is present.  They are uniform per op, so each combination
+// is its own straight-line code behind a scalar branch, with no work for an absent block.
+template <typename R, int RB, int P, int PRE, bool POST>
 __device__ __forceinline__ void apply_u1(tv<R> (&a)[1 << RB], const cxf<R> (&m)[4],
                                          const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
@@ -136,17 +142,17 @@ __device__ __forceinline__ void apply_u1(tv<R> (&a)[1 << RB], const cxf<R> (&m)[
         const int r = pair_base<P>(k);
         const int r1 = r | (1 << P);
         cxf<R> x0 = cx<R>(a[r]), x1 = cx<R>(a[r1]);
-        if constexpr (PRE) x1 = mul(pair_phase<R, RB, P>(pre, r), x1);
+        if constexpr (PRE > 0) x1 = mul(pair_phase<R, RB, P, PRE == 2>(pre, r), x1);
         cxf<R> y0 = fma_c(m[1], x1, mul(m[0], x0));
         cxf<R> y1 = fma_c(m[3], x1, mul(m[2], x0));
-        if constexpr (POST) y1 = mul(pair_phase<R, RB, P>(post, r), y1);
+        if constexpr (POST) y1 = mul(pair_phase<R, RB, P, true>(post, r), y1);
         a[r] = tvec(y0);
         a[r1] = tvec(y1);
     }
 }
 
 // The same update with a real matrix (m[k].im == 0): half the multiplications.
-template <typename R, int RB, int P, bool PRE, bool POST>
+template <typename R, int RB, int P, int PRE, bool POST>
 __device__ __forceinline__ void apply_u1_real(tv<R> (&a)[1 << RB], const cxf<R> (&m)[4],
                                               const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
@@ -156,10 +162,10 @@ __device__ __forceinline__ void apply_u1_real(tv<R> (&a)[1 << RB], const cxf<R> 
         const int r = pair_base<P>(k);
         const int r1 = r | (1 << P);
         cxf<R> x0 = cx<R>(a[r]), x1 = cx<R>(a[r1]);
-        if constexpr (PRE) x1 = mul(pair_phase<R, RB, P>(pre, r), x1);
+        if constexpr (PRE > 0) x1 = mul(pair_phase<R, RB, P, PRE == 2>(pre, r), x1);
         cxf<R> y0 = {m0 * x0.re + m1 * x1.re, m0 * x0.im + m1 * x1.im};
         cxf<R> y1 = {m2 * x0.re + m3 * x1.re, m2 * x0.im + m3 * x1.im};
-        if constexpr (POST) y1 = mul(pair_phase<R, RB, P>(post, r), y1);
+        if constexpr (POST) y1 = mul(pair_phase<R, RB, P, true>(post, r), y1);
         a[r] = tvec(y0);
         a[r1] = tvec(y1);
     }
@@ -192,7 +198,7 @@ __device__ __forceinline__ void apply_u2(tv<R> (&a)[1 << RB], const cxf<R> (&m)[
 // Dispatch on the target register bit.  There is no pass-through branch (the last position
 // is the fall-back): every path rewrites the register tile, which lets the register allocator
 // keep the tile in the same registers across ops instead of copying it at each merge.
-template <typename R, int RB, bool PRE, bool POST>
+template <typename R, int RB, int PRE, bool POST>
 __device__ __forceinline__ void dispatch_u1_pp(int p, bool real, tv<R> (&a)[1 << RB], const cxf<R> (&m)[4],
                                                const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
@@ -210,15 +216,19 @@ __device__ __forceinline__ void dispatch_u1_pp(int p, bool real, tv<R> (&a)[1 <<
 }
 
 template <typename R, int RB>
-__device__ __forceinline__ void dispatch_u1(int p, bool real, tv<R> (&a)[1 << RB], const cxf<R> (&m)[4],
-                                            const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
+__device__ __forceinline__ void dispatch_u1(int p, bool real, int prekind, tv<R> (&a)[1 << RB],
+                                            const cxf<R> (&m)[4], const PhaseSet<R, RB> &pre,
+                                            const PhaseSet<R, RB> &post)
 {
-    if (pre.any) {
-        if (post.any) dispatch_u1_pp<R, RB, true, true>(p, real, a, m, pre, post);
-        else dispatch_u1_pp<R, RB, true, false>(p, real, a, m, pre, post);
+    if (prekind == 2) {
+        if (post.any) dispatch_u1_pp<R, RB, 2, true>(p, real, a, m, pre, post);
+        else dispatch_u1_pp<R, RB, 2, false>(p, real, a, m, pre, post);
+    } else if (prekind == 1) {
+        if (post.any) dispatch_u1_pp<R, RB, 1, true>(p, real, a, m, pre, post);
+        else dispatch_u1_pp<R, RB, 1, false>(p, real, a, m, pre, post);
     } else {
-        if (post.any) dispatch_u1_pp<R, RB, false, true>(p, real, a, m, pre, post);
-        else dispatch_u1_pp<R, RB, false, false>(p, real, a, m, pre, post);
+        if (post.any) dispatch_u1_pp<R, RB, 0, true>(p, real, a, m, pre, post);
+        else dispatch_u1_pp<R, RB, 0, false>(p, real, a, m, pre, post);
     }
 }
 
@@ -246,6 +256,79 @@ __device__ __forceinline__ double2 dmul(double2 a, double2 b)
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+__device__ __forceinline__ double2 dconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// a / |a| (1 for a == 0)
+__device__ __forceinline__ double2 dunit(double2 a)
+{
+    const double h = hypot(a.x, a.y);
+    return h > 0.0 ? make_double2(a.x / h, a.y / h) : make_double2(1.0, 0.0);
+}
+
+// ---------------------------------------------------------------------------------------
+// Phase chains (one thread per chain and slot, FP64).  Along a chain of one-qubit gates on
+// one wire, each inner gate's matrix M (with the phase carried from the gate before it
+// multiplied into its |1> column) is factored as M = p * diag(1, b) * Rm * diag(1, d) with
+// unit p, b, d and Rm real.  Its row is rewritten as Rm in words 0, 2, 4, 6 and the input
+// phase d in words 1, 3; b is carried to the next gate, p into the global phase, which the
+// last gate of the chain takes along with the carried b (its row stays a complex matrix).
+// The factors: p = phase(M00), d = phase(M01) / p, and b from the larger of the second row's
+// entries, phase(M11) / (p d) or -phase(M10) / p; Rm is the real part of M with those phases
+// divided out.  For a unitary M (M10 = -e^{it} conj(M01), M11 = e^{it} conj(M00)) the
+// divided-out entries are real, so the factors reproduce M; a phase taken from a zero or
+// rounding-sized entry only affects entries of that size.  (phase(0) = 1.)
+// ---------------------------------------------------------------------------------------
+__global__ void k_phase_chains(double *tab, int S, const int32_t *chain_gates, const int32_t *chain_off,
+                               int n_chains)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_chains * S) return;
+    const int c = (int)(i / S), s = (int)(i % S);
+    const int kb = chain_off[c], ke = chain_off[c + 1];
+    double2 carry = make_double2(1.0, 0.0), glob = make_double2(1.0, 0.0);
+    for (int k = kb; k < ke; ++k) {
+        double *t = tab + ((int64_t)chain_gates[k] * S + s) * 8;
+        const double2 m00 = make_double2(t[0], t[1]), m10 = make_double2(t[4], t[5]);
+        const double2 m01 = dmul(make_double2(t[2], t[3]), carry);
+        const double2 m11 = dmul(make_double2(t[6], t[7]), carry);
+        if (k == ke - 1) {
+            const double2 o[4] = {dmul(glob, m00), dmul(glob, m01), dmul(glob, m10), dmul(glob, m11)};
+            for (int j = 0; j < 4; ++j) {
+                t[2 * j] = o[j].x;
+                t[2 * j + 1] = o[j].y;
+            }
+            break;
+        }
+        const double2 p = dunit(m00);
+        const double2 d = dmul(dunit(m01), dconj(p));
+        const double2 b = hypot(m11.x, m11.y) >= hypot(m10.x, m10.y)
+                              ? dmul(dunit(m11), dconj(dmul(p, d)))
+                              : dmul(make_double2(-1.0, 0.0), dmul(dunit(m10), dconj(p)));
+        const double2 pb = dmul(p, b), pd = dmul(p, d);
+        t[0] = dmul(m00, dconj(p)).x;
+        t[2] = dmul(m01, dconj(pd)).x;
+        t[4] = dmul(m10, dconj(pb)).x;
+        t[6] = dmul(m11, dconj(dmul(pb, d))).x;
+        t[1] = d.x;
+        t[3] = d.y;
+        t[5] = 0.0;
+        t[7] = 0.0;
+        carry = b;
+        glob = dmul(glob, p);
+    }
+}
+
+hipError_t launch_phase_chains(double *tab, int S, const int32_t *chain_gates, const int32_t *chain_off,
+                               int n_chains, hipStream_t st)
+{
+    const int64_t tot = (int64_t)n_chains * S;
+    if (tot <= 0) return hipSuccess;
+    TimedLaunch tl("chains", (double)tot * 64.0, st);
+    hipLaunchKernelGGL(k_phase_chains, dim3((unsigned)((tot + 127) / 128)), dim3(128), 0, st, tab, S,
+                       chain_gates, chain_off, n_chains);
+    return hipGetLastError();
+}
+
 template <typename R>
 __global__ void k_pass_prep(int S, int op_begin, int n_ops, int rec_size, ProgramDev prog,
                             const double *tab, const qs_gate *gates, cxf<R> *rec_all)
@@ -263,7 +346,17 @@ __global__ void k_pass_prep(int S, int op_begin, int n_ops, int rec_size, Progra
     auto put = [&](cxf<R> *dst, double2 v) { *dst = cxf<R>{(R)v.x, (R)v.y}; };
     if (op.type == OP_U1) {
         const double *t = tab + ((uint64_t)op.gate * S + slot) * 8;
-        for (int k = 0; k < 4; ++k) put(rec + k, make_double2(t[2 * k], t[2 * k + 1]));
+        const bool chain = (op.flags & OPF_CHAIN) != 0;
+        double2 uni = make_double2(1.0, 0.0);
+        if (chain) {
+            // phase-chain layout: the real matrix in the even words, the input phase in words
+            // 1 and 3; the phase joins the folded input block, else record entry 4
+            for (int k = 0; k < 4; ++k) put(rec + k, make_double2(t[2 * k], 0.0));
+            uni = make_double2(t[1], t[3]);
+            if (op.flags & OPF_UPHASE) put(rec + 4, uni);
+        } else {
+            for (int k = 0; k < 4; ++k) put(rec + k, make_double2(t[2 * k], t[2 * k + 1]));
+        }
         for (int post = 0; post < 2; ++post) {
             int block = post ? op.post_rec : op.pre_rec;
             if (block < 0) continue;
@@ -281,7 +374,7 @@ __global__ void k_pass_prep(int S, int op_begin, int n_ops, int rec_size, Progra
             cxf<R> *b = blk + block;
             for (int k = 0; k < 4; ++k) put(b + k, k < kMaxRegBits ? preg[k] : make_double2(1.0, 0.0));
             for (int x = 0; x < 32; ++x) {
-                double2 w = make_double2(1.0, 0.0);
+                double2 w = post ? make_double2(1.0, 0.0) : uni;
                 for (int k = 0; k < 5; ++k)
                     if ((x >> k) & 1) w = dmul(w, ptid[k]);
                 put(b + 4 + x, w);
@@ -532,13 +625,24 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                 if (type == OP_U1) {
                     cxf<R> m[4] = {orec[0], orec[1], orec[2], orec[3]};
                     PhaseSet<R, RB> pre, post;
+                    const int flags = op->flags;
                     const int prer = op->pre_rec, postr = op->post_rec;
                     const int prej = op->pre_job, postj = op->post_job;
-                    load_phases<R, RB>(pre, rec + prer, L.rec + (prer - sd.rec_begin), prer >= 0,
-                                       prej < 0 ? -1 : prej - job_shift, L.wout, tid);
-                    load_phases<R, RB>(post, rec + postr, L.rec + (postr - sd.rec_begin), postr >= 0,
+                    int prekind;
+                    if (flags & OPF_UPHASE) {
+                        // uniform input phase (an inner phase-chain member with no folded block)
+                        pre.any = true;
+                        pre.w = orec[4];
+                        prekind = 1;
+                    } else {
+                        const bool bits = !(flags & OPF_PREW);
+                        load_phases<R, RB>(pre, rec + prer, L.rec + (prer - sd.rec_begin), prer >= 0, bits,
+                                           prej < 0 ? -1 : prej - job_shift, L.wout, tid);
+                        prekind = prer < 0 ? 0 : bits ? 2 : 1;
+                    }
+                    load_phases<R, RB>(post, rec + postr, L.rec + (postr - sd.rec_begin), postr >= 0, true,
                                        postj < 0 ? -1 : postj - job_shift, L.wout, tid);
-                    dispatch_u1<R, RB>(op->p0, (op->flags & OPF_REAL) != 0, a, m, pre, post);
+                    dispatch_u1<R, RB>(op->p0, (flags & OPF_REAL) != 0, prekind, a, m, pre, post);
                 } else if (type == OP_U2) {
                     cxf<R> m[16];
 #pragma unroll

@@ -106,7 +106,12 @@ enum OpType : int32_t { OP_U1 = 0, OP_U2 = 1, OP_DIAG = 2 };
 enum DiagKind : int32_t { DIAG_NEGATE = 0, DIAG_PHASE = 1 };
 enum PrepKind : int32_t { PR_REG = 0, PR_THREAD = 1, PR_OUTER = 2 };
 
-enum OpFlags : int32_t { OPF_REAL = 1 };   // the one-qubit matrix is real in every slot
+// OPF_REAL: the one-qubit matrix the kernel applies is real in every slot.  OPF_CHAIN: the gate
+// is an inner member of a phase chain (its table rows hold a real matrix and an input phase,
+// written by the chain kernel).  OPF_UPHASE: the op has no folded input block, and its input
+// phase is the uniform record entry rec + 4.  OPF_PREW: the op's input phase does not depend
+// on register bits (a per-thread or uniform factor only).
+enum OpFlags : int32_t { OPF_REAL = 1, OPF_CHAIN = 2, OPF_UPHASE = 4, OPF_PREW = 8 };
 
 struct OpDesc {
     int32_t type;
@@ -172,6 +177,10 @@ struct NoiseArgs {
 
 hipError_t launch_noise_table(const qs_gate *gates_dev, int n_gates, int S, NoiseArgs na,
                               double *tab, hipStream_t st);
+// Rewrites the noise-table rows of the phase chains (chain layout in the fused path's
+// documentation); chain_gates / chain_off in device memory, n_chains >= 1.
+hipError_t launch_phase_chains(double *tab, int S, const int32_t *chain_gates, const int32_t *chain_off,
+                               int n_chains, hipStream_t st);
 hipError_t launch_noise_draw(uint64_t seed, uint32_t request, uint32_t stream,
                              const uint32_t *sites, int n_sites, uint32_t traj_base, int n_traj,
                              double *out, hipStream_t st);
@@ -261,6 +270,9 @@ struct Program {
     std::vector<OuterJob> jobs;
     std::vector<int32_t> obits;
     std::vector<int32_t> layout;  // logical qubit -> physical bit after the circuit
+    // Phase chains: chain c is gates chain_gates[chain_off[c] .. chain_off[c + 1]), in circuit
+    // order (empty: no chains; otherwise chain_off has one entry per chain plus one).
+    std::vector<int32_t> chain_gates, chain_off;
     int K = 0, RB = 0;
     int max_rec = 0;              // largest per-slot record block of a pass (complex entries)
 };

@@ -12,6 +12,7 @@
 // 4. Each pass's tile is its targets plus the lowest remaining physical bits (for coalesced
 //    rows of 2^run_bits amplitudes); its ops are grouped into register rounds of RB bits.
 #include <algorithm>
+#include <cmath>
 #include <map>
 
 #include "internal.h"
@@ -134,6 +135,63 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         pg.push_back(x);
     }
     P.layout = perm;
+
+    // 1b. phase chains.  A unitary 2x2 matrix factors as M = e^{i phi} diag(1, e^{i beta}) R
+    // diag(1, e^{i delta}) with R real.  The output factor diag(1, e^{i beta}) commutes with
+    // every diagonal gate (controlled phases, sign flips) and with a CNOT on whose control it
+    // sits, and a SWAP only relabels the wire (the physical bit stays), so it can be carried to
+    // the next one-qubit gate on the same physical bit and multiplied into its matrix.  Along a
+    // run of complex one-qubit gates on one wire every gate but the last then applies a real
+    // matrix after a uniform input phase (half the multiplications of a complex one), and the
+    // last absorbs the carried phase and the accumulated global phase.  A real gate, a CNOT
+    // target or a dense two-qubit gate ends the run on its wire.
+    std::vector<int8_t> chain_role(n_gates, 0);   // 1: inner member, 2: last member
+    {
+        auto chainable = [&](const qs_gate &G) {
+            const double *m = G.m;
+            bool real = true;
+            for (int k = 1; k < 8; k += 2)
+                if (m[k] != 0.0) real = false;
+            if (real) return false;
+            // unitary to within a few roundings: the factors reproduce M only then
+            const double a[4][2] = {{m[0], m[1]}, {m[2], m[3]}, {m[4], m[5]}, {m[6], m[7]}};
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) {
+                    // (M^dagger M)_{ij} = sum_k conj(M_ki) M_kj
+                    double re = 0, im = 0;
+                    for (int k = 0; k < 2; ++k) {
+                        const double *x = a[2 * k + i], *y = a[2 * k + j];
+                        re += x[0] * y[0] + x[1] * y[1];
+                        im += x[0] * y[1] - x[1] * y[0];
+                    }
+                    if (std::fabs(re - (i == j ? 1.0 : 0.0)) > 1e-14 || std::fabs(im) > 1e-14) return false;
+                }
+            return true;
+        };
+        std::vector<std::vector<int32_t>> open(n);
+        auto close = [&](int bit) {
+            auto &c = open[bit];
+            if (c.size() >= 2) {
+                if (P.chain_off.empty()) P.chain_off.push_back(0);
+                for (size_t k = 0; k < c.size(); ++k) chain_role[c[k]] = k + 1 < c.size() ? 1 : 2;
+                P.chain_gates.insert(P.chain_gates.end(), c.begin(), c.end());
+                P.chain_off.push_back((int32_t)P.chain_gates.size());
+            }
+            c.clear();
+        };
+        for (const PG &x : pg) {
+            if (x.kind == QS_G_U1) {
+                if (chainable(gates[x.gate])) open[x.a].push_back(x.gate);
+                else close(x.a);
+            } else if (x.kind == QS_G_CNOT) {
+                close(x.b);
+            } else if (x.kind == QS_G_U2) {
+                close(x.a);
+                close(x.b);
+            }
+        }
+        for (int b = 0; b < n; ++b) close(b);
+    }
 
     // 2. passes
     std::vector<PassBuild> passes(1);
@@ -367,6 +425,15 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                         if (real) op.flags |= OPF_REAL;
                     }
                     rec += 4;
+                    if (chain_role[x.gate] == 1) {
+                        // inner chain member: real matrix; its input phase joins the folded
+                        // input block, or takes record entry rec + 4 when there is none
+                        op.flags |= OPF_REAL | OPF_CHAIN;
+                        if (pre_att[i].empty()) {
+                            op.flags |= OPF_UPHASE | OPF_PREW;
+                            rec += 1;
+                        }
+                    }
                     for (int post = 0; post < 2; ++post) {
                         const auto &lst = post ? post_att : pre_att;
                         const auto &att = lst[i];
@@ -397,6 +464,12 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                                 pr.bit = tid_index[j];
                             }
                             P.prefs.push_back(pr);
+                        }
+                        if (!post) {
+                            bool reg = false;
+                            for (auto &at : att)
+                                if (local_of[at.cond] >= 0 && reg_index[local_of[at.cond]] >= 0) reg = true;
+                            if (!reg) op.flags |= OPF_PREW;
                         }
                         if (n_outer > 0) {
                             OuterJob jb{};

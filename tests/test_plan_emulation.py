@@ -37,6 +37,35 @@ def gate_operators(circuit, e, seed, traj):
     return ops
 
 
+def _unit(z):
+    return z / abs(z) if z != 0 else 1.0 + 0j
+
+
+def chain_operators(ops, chains):
+    """The phase-chain rewrite of the operators: along each chain every inner gate becomes a
+    real matrix after an input phase d (M = p diag(1, b) Rm diag(1, d), with b carried into
+    the next gate's |1> column and p into the global phase), and the last gate takes the carried
+    phase and the global phase.  Inner entries become ("chain", Rm, d)."""
+    out = dict(ops)
+    for ch in chains:
+        carry, glob = 1.0 + 0j, 1.0 + 0j
+        for k, g in enumerate(ch):
+            M = np.array(ops[g], np.complex128)
+            M[:, 1] *= carry
+            if k == len(ch) - 1:
+                out[g] = glob * M
+                break
+            p = _unit(M[0, 0])
+            d = _unit(M[0, 1]) / p
+            b = (_unit(M[1, 1]) / (p * d) if abs(M[1, 1]) >= abs(M[1, 0]) else -_unit(M[1, 0]) / p)
+            ph = np.array([[p, p * d], [p * b, p * b * d]])
+            Rm = (M / ph).real
+            assert np.abs((M / ph).imag).max() < 1e-14
+            out[g] = ("chain", Rm, d)
+            carry, glob = b, glob * p
+    return out
+
+
 def emulate(circuit, prog, e=0.0, seed=0, traj=0):
     """Run the program the way the kernel does, on memory that starts as garbage (NaN): the
     first pass makes the basis state in its tile, a pass works only on the tiles that can hold
@@ -44,7 +73,7 @@ def emulate(circuit, prog, e=0.0, seed=0, traj=0):
     written by an earlier pass), and the first pass stores the other tiles as zeros only when
     the program asks for it.  At the end every amplitude must have been written."""
     n = circuit.n
-    ops = gate_operators(circuit, e, seed, traj)
+    ops = chain_operators(gate_operators(circuit, e, seed, traj), prog["chains"])
     b = circuit.init_index
     psi = np.full(1 << n, np.nan, np.complex128)
     all_idx = np.arange(1 << n, dtype=np.int64)
@@ -105,6 +134,13 @@ def emulate(circuit, prog, e=0.0, seed=0, traj=0):
                                     cond = np.full(l0.size, (outer >> bit) & 1)
                                 w[post] = w[post] * np.where(cond == 1, ops[cpg], 1.0)
                             M = ops[op["gate"]]
+                            assert bool(op["flags"] & 2) == isinstance(M, tuple)
+                            if op["flags"] & 2:
+                                # inner chain member: a real matrix after a uniform input phase
+                                if op["flags"] & 4:
+                                    assert not any(ph[1] == 0 for ph in op["phases"])
+                                _, M, d = M
+                                w[0] = w[0] * d
                             x0, x1 = v[l0], v[l1] * w[0]
                             v[l0] = M[0, 0] * x0 + M[0, 1] * x1
                             v[l1] = (M[1, 0] * x0 + M[1, 1] * x1) * w[1]
@@ -248,3 +284,38 @@ def test_qft_second_pass_has_a_support_bound():
     psi, layout = emulate(c, prog, 0.1, seed=2, traj=1)
     ref = oracle.sv_run(c, 0.1, seed=2, traj=1)
     assert np.linalg.norm(unpermute(psi, layout, c.n) - ref) < 1e-12
+
+
+def test_phase_chains_follow_the_wire():
+    """Runs of complex one-qubit gates on one physical bit form a chain across diagonal gates, a
+    CNOT control and a SWAP (which keeps the physical bit); a real gate, a CNOT target or a
+    dense two-qubit gate ends it, and a lone complex gate is no chain."""
+    from workloads import Circuit, Gate, haar_2x2
+    rng = np.random.default_rng(12)
+    Hm = np.array([[1, 1], [1, -1]], np.complex128) / math.sqrt(2.0)
+
+    def u(qb):
+        return Gate(U1, q0=qb, m=haar_2x2(rng), noise=NOISE_ROT)
+
+    g = [u(0),                                # 0
+         Gate(CP, q0=0, q1=1, theta=0.3),     # 1  diagonal
+         Gate(CNOT, q0=0, q1=2),              # 2  q0 is the control
+         u(0),                                # 3  continues 0
+         Gate(SWAP, q0=0, q1=3),              # 4  logical 3 now sits on the physical bit of 0
+         u(3),                                # 5  continues 0, 3
+         u(1),                                # 6
+         Gate(CNOT, q0=0, q1=1),              # 7  q1 is the target: ends the run of 6 alone
+         u(1),                                # 8
+         Gate(U1, q0=1, m=Hm),                # 9  real: ends 8 alone
+         u(2), u(2),                          # 10, 11
+         Gate(U2, q0=2, q1=1, m=np.eye(4, dtype=np.complex128)),   # 12 ends 10, 11
+         u(2)]                                # 13 alone
+    for i, gg in enumerate(g):
+        gg.site = i
+    c = Circuit(4, g, name="chains4")
+    prog = q.plan_describe(c.gates, c.n, q.C128, {"fuse": 1, "tile_bits": 4, "reg_bits": 2, "run_bits": 1})
+    assert sorted(prog["chains"]) == [[0, 3, 5], [10, 11]]
+    for e, traj in ((0.0, 0), (0.3, 2)):
+        psi, layout = emulate(c, prog, e, seed=5, traj=traj)
+        ref = oracle.sv_run(c, e, seed=5, traj=traj)
+        assert np.linalg.norm(unpermute(psi, layout, c.n) - ref) < 1e-12
