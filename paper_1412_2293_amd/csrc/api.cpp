@@ -1014,6 +1014,7 @@ qs_status qs_plan_describe(const qs_gate *gates, int n_gates, int n, qs_dtype dt
                     o += oi != rd.op_begin ? ",{" : "{";
                     I("type", op.type);
                     I("flags", op.flags);
+                    I("creg", op.creg);
                     I("p0", op.p0);
                     I("p1", op.p1);
                     I("gate", op.gate);

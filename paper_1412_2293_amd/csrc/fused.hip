@@ -510,6 +510,10 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
         greg[r] = g;
     }
     R *base = psi + ((uint64_t)slot << (n + 1));
+    // the basis index's bits at the tile-local positions
+    uint32_t blocal = 0;
+    for (int j = 0; j < K; ++j)
+        if (((uint64_t)basis >> pd->q_pos[j]) & 1ull) blocal |= 1u << j;
     tv<R> a[NR];
     if (fill && ((outer ^ (uint64_t)basis) & pd->classical) != 0) {
         // a tile of the first pass outside the support: zeros (uniform per block)
@@ -528,9 +532,6 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
         // with the basis index on the tile-local classical bits (thread part per lane, register
         // part uniform)
         const uint32_t lc = pd->lclassical;
-        uint32_t blocal = 0;
-        for (int j = 0; j < K; ++j)
-            if (((uint64_t)basis >> pd->q_pos[j]) & 1ull) blocal |= 1u << j;
         const uint32_t tmask = (1u << TB) - 1u;
         const bool tok = ((tid ^ blocal) & lc & tmask) == 0;
 #pragma unroll
@@ -628,8 +629,15 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                     const int flags = op->flags;
                     const int prer = op->pre_rec, postr = op->post_rec;
                     const int prej = op->pre_job, postj = op->post_job;
+                    // a target qubit no earlier gate has touched holds the basis bit: when that
+                    // bit is 0 every |1> input is zero, and its input phase has nothing to do
+                    const bool zero_in = ((op->creg >> op->p0) & 1u) &&
+                                         !(blocal & prog.rounds[cur_ri].roff[1 << op->p0]);
                     int prekind;
-                    if (flags & OPF_UPHASE) {
+                    if (zero_in) {
+                        pre.any = false;
+                        prekind = 0;
+                    } else if (flags & OPF_UPHASE) {
                         // uniform input phase (an inner phase-chain member with no folded block)
                         pre.any = true;
                         pre.w = orec[4];

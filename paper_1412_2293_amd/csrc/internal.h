@@ -125,7 +125,9 @@ struct OpDesc {
     int32_t pref_begin, pref_end; // PrepRefs of this op
     int32_t diag_kind;
     uint32_t lmask, lvalue;       // DIAG: tile-local condition (l & lmask) == lvalue
-    uint32_t reserved;
+    // U1: register-index bits whose tile-local qubits no non-diagonal gate has touched before
+    // this op (they still hold the run's basis bits, so registers that disagree there are zero)
+    uint32_t creg;
     uint64_t omask, ovalue;       // DIAG: tile condition (outer index & omask) == ovalue
 };
 

@@ -294,6 +294,7 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         for (int j = 0; j < K; ++j)
             if (!((touched >> Q[j]) & 1ull)) pd.lclassical |= 1u << j;
         for (int q : pb.targets) touched |= 1ull << q;
+        uint32_t lcls = pd.lclassical;   // tile-local bits untouched so far in this pass
         const uint32_t kmask = (1u << K) - 1u;
         const uint32_t load_mask = ((1u << RB) - 1u) << (K - RB);
         const RoundDesc load_rd = make_round(load_mask, K);
@@ -417,6 +418,9 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                 if (x.kind == QS_G_U1) {
                     op.type = OP_U1;
                     op.p0 = reg_index[local_of[x.a]];
+                    for (int j = 0; j < K; ++j)
+                        if (((lcls >> j) & 1u) && reg_index[j] >= 0) op.creg |= 1u << reg_index[j];
+                    lcls &= ~(1u << local_of[x.a]);
                     {
                         // U V(e xi) is real whenever U is: V of eq. (1) is a real rotation
                         bool real = true;
@@ -486,6 +490,7 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                     op.type = OP_U2;
                     op.p0 = reg_index[local_of[x.a]];
                     op.p1 = reg_index[local_of[x.b]];
+                    lcls &= ~((1u << local_of[x.a]) | (1u << local_of[x.b]));
                     rec += 16;
                 } else {
                     op.type = OP_DIAG;

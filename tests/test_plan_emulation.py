@@ -121,6 +121,12 @@ def emulate(circuit, prog, e=0.0, seed=0, traj=0):
                     tbits = [j for j in range(K) if not (m >> j) & 1]
                     for op in rnd["ops"]:
                         if op["type"] == 0:
+                            # creg: register bits no earlier gate touched; amplitudes that
+                            # disagree with the basis index there must be zero
+                            for k, jj in enumerate(regbits):
+                                if (op["creg"] >> k) & 1:
+                                    off = ((ar ^ blocal) >> jj) & 1 == 1
+                                    assert np.all(v[off] == 0), (pi, "creg")
                             j = regbits[op["p0"]]
                             l0 = ar[((ar >> j) & 1) == 0]
                             l1 = l0 | (1 << j)
