@@ -583,3 +583,64 @@ def test_fixed_rank_unnormalised_never_exceeds_the_density_matrix():
     assert prev > 0.5 * p_dm   # r = 8 keeps most of it
     rho.close()
     w.close()
+
+
+def chain_heavy_circuit(n: int, n_gates: int, seed: int):
+    """Mostly complex one-qubit gates, so that long phase chains form, with every gate that a
+    chain crosses (controlled phases, sign flips, SWAPs, CNOT controls) or that ends one (real
+    gates, CNOT targets, dense two-qubit gates) in between, some of the one-qubit gates
+    noiseless and diagonal (T-like)."""
+    from workloads import CNOT, NOISE_NONE, SWAP, U2, _renumber_sites, haar_2x2, random_unitary
+    rng = np.random.default_rng(seed)
+    N = 1 << n
+    hm = np.array([[1, 1], [1, -1]], np.complex128) / math.sqrt(2.0)
+    gates = []
+    for _ in range(n_gates):
+        k = int(rng.integers(0, 20))
+        qa = int(rng.integers(0, n))
+        if k < 11:
+            gates.append(Gate(U1, q0=qa, m=haar_2x2(rng), noise=NOISE_ROT))
+        elif k == 11:
+            ph = np.exp(1j * rng.uniform(0, 2 * math.pi))
+            gates.append(Gate(U1, q0=qa, m=np.diag([1.0, ph]).astype(np.complex128), noise=NOISE_NONE))
+        elif k == 12:
+            gates.append(Gate(U1, q0=qa, m=hm, noise=NOISE_ROT))
+        elif k in (13, 14):
+            a, b = (int(v) for v in rng.choice(n, size=2, replace=False))
+            gates.append(Gate(CP, q0=a, q1=b, theta=float(rng.uniform(0, 2 * math.pi)), noise=NOISE_PHASE))
+        elif k == 15:
+            a, b = (int(v) for v in rng.choice(n, size=2, replace=False))
+            gates.append(Gate(SWAP, q0=a, q1=b))
+        elif k == 16:
+            a, b = (int(v) for v in rng.choice(n, size=2, replace=False))
+            gates.append(Gate(CNOT, q0=a, q1=b))
+        elif k == 17:
+            a, b = (int(v) for v in rng.choice(n, size=2, replace=False))
+            gates.append(Gate(U2, q0=a, q1=b, m=random_unitary(4, rng)))
+        else:
+            mask = int(rng.integers(0, N)) | (1 << qa)
+            gates.append(Gate(FLIP, mask=mask, value=int(rng.integers(0, N)) & mask))
+    return Circuit(n, _renumber_sites(gates), name=f"chains{n}", init_index=int(rng.integers(0, N)))
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+@pytest.mark.parametrize("plan", [{"fuse": 1}, {"fuse": 1, "tile_bits": 6, "reg_bits": 2, "run_bits": 2},
+                                  {"fuse": 1, "tile_bits": 9, "reg_bits": 3, "run_bits": 2}],
+                         ids=["default", "t6r2", "t9r3"])
+def test_phase_chains_full_states(dtype, plan):
+    """Complex one-qubit gates applied as real rotations after an input phase, the leftover
+    phases carried along each wire (across diagonal gates, CNOT controls and SWAPs) into the
+    chain's last gate: every amplitude of every trajectory against the oracle."""
+    for n, seed in ((11, 1), (13, 2)):
+        c = chain_heavy_circuit(n, 160, seed)
+        desc = q.plan_describe(c.gates, n, dtype, plan)
+        assert max(len(ch) for ch in desc["chains"]) >= 5
+        T, e, s = 3, 0.2, 8
+        res = q.run_trajectories(c.gates, n, c.init_index, dtype, T, e=e, seed=s, plan=plan)
+        F_ref, _, ideal, states = oracle.run_trajectories(c, e, s, range(T), keep_states=True)
+        st = q.trajectory_states(res, n, dtype, T).cpu().numpy().astype(np.complex128)
+        tol = 1e-12 if dtype == q.C128 else 3e-5
+        assert rel_err(unpermute(st[0], res["layout"], n), ideal) <= tol, n
+        for t in range(T):
+            assert rel_err(unpermute(st[t + 1], res["layout"], n), states[t]) <= tol, (n, t)
+        assert np.max(np.abs(res["F"] - F_ref)) <= TOL[dtype]
