@@ -109,7 +109,7 @@ def main():
     q.timing_enable(False)
     ms_step = (t1 - t0) * 1e3 / a.steps
     fused = q.timing_read("fused")
-    kernels = {k: q.timing_read(k) for k in ("fused", "noise", "init", "reduce")}
+    kernels = {k: q.timing_read(k) for k in ("fused", "noise", "chains", "prep", "jobs", "init", "reduce")}
     value = updates_per_traj * T / (ms_step / 1e3)
     F_c64 = res["F"].copy()
     launch_ms = fused["ms"] / max(fused["launches"], 1)

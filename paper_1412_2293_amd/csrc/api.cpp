@@ -491,8 +491,8 @@ qs_status qs_timing_reset(void)
 namespace {
 
 struct TrajLayout {
-    size_t states, tab, gates, edev, passes, stages, rounds, ops, prefs, jobs, obits, chains, rec, partials, out, dyn,
-        total;
+    size_t states, tab, gates, edev, passes, stages, rounds, ops, prefs, jobs, obits, chains, wtab, rec, partials, out,
+        dyn, total;
 };
 
 struct Plan {
@@ -593,7 +593,7 @@ double model_cost_unfused(const qs_gate *gates, int n_gates, int n, qs_dtype dt,
 }
 
 // Candidate shapes per dtype: (tile bits, register bits, run bits).
-static const int kCandC64[][3] = {{12, 4, 5}, {12, 4, 4}, {12, 3, 5}, {12, 3, 4}, {12, 3, 3}, {11, 3, 4},
+static const int kCandC64[][3] = {{12, 4, 4}, {12, 4, 5}, {12, 3, 5}, {12, 3, 4}, {12, 3, 3}, {11, 3, 4},
                                   {11, 2, 3}, {10, 2, 3}};
 static const int kCandC128[][3] = {{11, 3, 4}, {11, 3, 3}, {11, 2, 4}, {11, 2, 3}, {10, 2, 3}, {10, 1, 3}};
 
@@ -670,6 +670,12 @@ TrajLayout traj_layout(int n, qs_dtype dt, int T, int n_gates, const Plan &pl)
     L.jobs = take(std::max<size_t>(pl.prog.jobs.size(), 1) * sizeof(OuterJob));
     L.obits = take(std::max<size_t>(pl.prog.obits.size(), 1) * sizeof(int32_t));
     L.chains = take(std::max<size_t>(pl.prog.chain_gates.size() + pl.prog.chain_off.size(), 1) * sizeof(int32_t));
+    // per (slot, tile, outer job) phase products of the pass being run: at most 2^(n - K) tiles
+    {
+        const int tb = pl.fused && n > pl.prog.K ? n - pl.prog.K : 0;
+        const size_t entries = ((size_t)S << tb) * (size_t)std::max(pl.prog.max_jobs, 1);
+        L.wtab = take(entries * 2 * (dt == QS_C64 ? 4 : 8));
+    }
     L.rec = take((size_t)std::max(pl.prog.max_rec, 1) * S * 2 * (dt == QS_C64 ? 4 : 8));
     L.partials = take(reduce_partials_doubles(n, S) * sizeof(double));
     L.out = take((size_t)S * 5 * sizeof(double));
@@ -732,6 +738,8 @@ static TrajLayout prep_layout(const TrajPrep &prep, int T)
     pl.prog.chain_gates.resize(prep.prog.chain_gates.size());
     pl.prog.chain_off.resize(prep.prog.chain_off.size());
     pl.prog.max_rec = prep.prog.max_rec;
+    pl.prog.max_jobs = prep.prog.max_jobs;
+    pl.prog.K = prep.prog.K;
     return traj_layout(prep.n, prep.dt, T, (int)prep.hg.size(), pl);
 }
 
@@ -805,9 +813,12 @@ static qs_status enqueue_compute(const TrajPrep &prep, const TrajLayout &L, char
                        (const PrepRef *)(B + L.prefs), (const OuterJob *)(B + L.jobs),
                        (const int32_t *)(B + L.obits)};
         for (size_t p = 0; p < P.passes.size(); ++p) {
+            const int64_t init = p == 0 ? (int64_t)init_index : -1;
             QS_HIP(launch_pass_prep(dt, S, &P.passes[p], pdv, tab, gdev, B + L.rec, st));
-            QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (int)p, p == 0 ? (int64_t)init_index : -1,
-                                     (int64_t)init_index, pdv, B + L.rec, st, dyn));
+            QS_HIP(launch_pass_jobs(dt, n, S, &P.passes[p], pdv, B + L.rec, init, (int64_t)init_index, dyn,
+                                    B + L.wtab, st));
+            QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (int)p, init, (int64_t)init_index, pdv, B + L.rec,
+                                     B + L.wtab, st, dyn));
         }
     } else {
         for (int g = 0; g < n_gates; ++g) {
@@ -912,9 +923,9 @@ qs_status qs_traj_layout(const qs_gate *gates, int n_gates, int n, qs_dtype dt, 
     Plan pl;
     if ((v = resolve_plan(gates, n_gates, n, dt, T, plan, pl)) != QS_OK) return v;
     TrajLayout L = traj_layout(n, dt, T, n_gates, pl);
-    size_t vals[16] = {L.states, L.tab, L.gates, L.edev, L.passes, L.stages, L.rounds, L.ops, L.prefs,
-                       L.jobs, L.obits, L.chains, L.rec, L.partials, L.out, L.total};
-    for (int i = 0; i < 16; ++i) out[i] = vals[i];
+    size_t vals[17] = {L.states, L.tab, L.gates, L.edev, L.passes, L.stages, L.rounds, L.ops, L.prefs,
+                       L.jobs, L.obits, L.chains, L.wtab, L.rec, L.partials, L.out, L.total};
+    for (int i = 0; i < 17; ++i) out[i] = vals[i];
     return QS_OK;
 }
 
@@ -955,6 +966,7 @@ qs_status qs_plan_describe(const qs_gate *gates, int n_gates, int n, qs_dtype dt
     I("K", pl.prog.K);
     I("RB", pl.prog.RB);
     I("run_bits", pl.run_bits);
+    if (pl.fused) I("stage_rec_cap", stage_rec_cap(dt, pl.prog.K));
     {
         const double cost = pl.fused ? model_cost_fused(pl.prog, n, dt, kModelSlots, pl.run_bits)
                                      : model_cost_unfused(gates, n_gates, n, dt, kModelSlots);

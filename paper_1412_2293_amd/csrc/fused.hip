@@ -85,7 +85,8 @@ struct PhaseSet {
 };
 
 // grec: the block in global memory (uniform reads, held in scalar registers); lrec: the same
-// block staged in LDS (per-thread table lookups); wout: per-tile outer products in LDS.
+// block staged in LDS (per-thread table lookups); wout: this tile's products of the phases
+// conditioned on tile-number bits (global memory, uniform reads).
 // bits: whether the block has phases conditioned on register bits (else only w is used).
 template <typename R, int RB>
 __device__ __forceinline__ void load_phases(PhaseSet<R, RB> &ps, const cxf<R> *__restrict__ grec,
@@ -329,6 +330,38 @@ hipError_t launch_phase_chains(double *tab, int S, const int32_t *chain_gates, c
     return hipGetLastError();
 }
 
+// Per (slot, tile, outer job) of one pass: the product of the job's record entries whose
+// tile-number bit is set in the tile's index, in the order the planner listed them.  Tiles are
+// numbered as the fused kernel's blocks are (the walked tile-number bits, the others at their
+// basis values), so a block finds its products at wtab + blockIdx * jobs.
+template <typename R>
+__global__ void k_pass_jobs(int S, int n_jobs, int tiles_log, uint64_t walk, uint64_t fixed_bits, int rec_size,
+                            const OuterJob *__restrict__ jobs, const int32_t *__restrict__ obits,
+                            const cxf<R> *__restrict__ rec_all, const RunParams *dyn, uint64_t classical,
+                            cxf<R> *__restrict__ wtab)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ((int64_t)S << tiles_log) * n_jobs) return;
+    const int j = (int)(i % n_jobs);
+    const int64_t blk = i / n_jobs;
+    const int slot = (int)(blk >> tiles_log);
+    uint64_t t = (uint64_t)blk & ((1ull << tiles_log) - 1ull);
+    if (dyn) fixed_bits = (uint64_t)dyn->init & classical;
+    uint64_t outer = fixed_bits, m = walk;
+    while (m) {
+        const uint64_t low = m & (~m + 1ull);
+        if (t & 1ull) outer |= low;
+        t >>= 1;
+        m ^= low;
+    }
+    const OuterJob jb = jobs[j];
+    const cxf<R> *rec = rec_all + (size_t)slot * rec_size;
+    cxf<R> w = {(R)1, (R)0};
+    for (int k = 0; k < jb.n; ++k)
+        if ((outer >> obits[jb.bits_off + k]) & 1ull) w = mul(w, rec[jb.rec_off + k]);
+    wtab[i] = w;
+}
+
 template <typename R>
 __global__ void k_pass_prep(int S, int op_begin, int n_ops, int rec_size, ProgramDev prog,
                             const double *tab, const qs_gate *gates, cxf<R> *rec_all)
@@ -400,20 +433,13 @@ __global__ void k_pass_prep(int S, int op_begin, int n_ops, int rec_size, Progra
 template <typename R>
 struct StageLds {
     cxf<R> *rec;
-    cxf<R> *wout;
-    int32_t *obits;
 };
 
 template <typename R>
-__device__ __forceinline__ StageLds<R> stage_lds(unsigned char *smem, int K, int rec_cap)
+__device__ __forceinline__ StageLds<R> stage_lds(unsigned char *smem, int K)
 {
     StageLds<R> L;
-    size_t off = (size_t(1) << K) * sizeof(cxf<R>);
-    L.rec = reinterpret_cast<cxf<R> *>(smem + off);
-    off += sizeof(cxf<R>) * rec_cap;
-    L.wout = reinterpret_cast<cxf<R> *>(smem + off);
-    off += sizeof(cxf<R>) * kStageJobs;
-    L.obits = reinterpret_cast<int32_t *>(smem + off);
+    L.rec = reinterpret_cast<cxf<R> *>(smem + (size_t(1) << K) * sizeof(cxf<R>));
     return L;
 }
 
@@ -444,9 +470,8 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                                                   const StageDesc *__restrict__ g_stages,
                                                   const RoundDesc *__restrict__ g_rounds,
                                                   const OpDesc *__restrict__ g_ops,
-                                                  const OuterJob *__restrict__ g_jobs,
-                                                  const int32_t *__restrict__ g_obits,
-                                                  const cxf<R> *__restrict__ rec_all)
+                                                  const cxf<R> *__restrict__ rec_all,
+                                                  const cxf<R> *__restrict__ wtab)
 {
     // Descriptor arrays as separate read-only, non-aliasing arguments: their uniform reads
     // become scalar loads that do not wait on the tile's vector memory traffic.
@@ -455,16 +480,14 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
         const StageDesc *__restrict__ stages;
         const RoundDesc *__restrict__ rounds;
         const OpDesc *__restrict__ ops;
-        const OuterJob *__restrict__ jobs;
-        const int32_t *__restrict__ obits;
-    } prog = {g_passes, g_stages, g_rounds, g_ops, g_jobs, g_obits};
+    } prog = {g_passes, g_stages, g_rounds, g_ops};
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NR = 1 << RB;
     const PassDesc *pd = prog.passes + pass_index;
     const int K = pd->K;
     const int TB = K - RB;
     const uint32_t kmask = (1u << K) - 1u;
-    const StageLds<R> L = stage_lds<R>(smem, K, rec_cap);
+    const StageLds<R> L = stage_lds<R>(smem, K);
     // A run starts in the basis state |basis>, and a physical qubit no non-diagonal gate has
     // touched still holds its basis value (controlled phases only rescale), so only the tiles
     // that agree with it on the pass's classical bits hold amplitude, and inside a tile only the
@@ -484,6 +507,9 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     const uint64_t tile = (uint64_t)blockIdx.x & ((1ull << tiles_log) - 1ull);
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
     const cxf<R> *__restrict__ rec = rec_all + (size_t)slot * pd->rec_size;
+    // this tile's products of the phases conditioned on tile-number bits (one per outer job)
+    const cxf<R> *__restrict__ wout =
+        wtab + (size_t)blockIdx.x * (size_t)(pd->job_end - pd->job_begin);
 
     // Outer (tile-number) bits of the physical index.
     uint64_t outer = fill ? 0 : ((uint64_t)basis & pd->classical);
@@ -597,22 +623,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
         copy_words(reinterpret_cast<uint32_t *>(L.rec),
                    reinterpret_cast<const uint32_t *>(rec + sd.rec_begin),
                    (sd.rec_end - sd.rec_begin) * (int)(sizeof(cxf<R>) / 4), tid, nthr);
-        copy_words(reinterpret_cast<uint32_t *>(L.obits),
-                   reinterpret_cast<const uint32_t *>(prog.obits + sd.obits_begin),
-                   sd.obits_end - sd.obits_begin, tid, nthr);
         __syncthreads();
-        // per-tile products of the phases conditioned on tile-number bits
-        const int nj = sd.job_end - sd.job_begin;
-        for (int j = (int)tid; j < nj; j += (int)nthr) {
-            const OuterJob jb = prog.jobs[sd.job_begin + j];
-            cxf<R> w = {(R)1, (R)0};
-            for (int k = 0; k < jb.n; ++k)
-                if ((outer >> L.obits[jb.bits_off - sd.obits_begin + k]) & 1ull)
-                    w = mul(w, L.rec[jb.rec_off - sd.rec_begin + k]);
-            L.wout[j] = w;
-        }
-        if (nj > 0) __syncthreads();
-        const int job_shift = sd.job_begin - pd->job_begin;
 
         for (int ri = sd.round_begin; ri < sd.round_end; ++ri) {
             const RoundDesc *rd = prog.rounds + ri;
@@ -645,11 +656,11 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                     } else {
                         const bool bits = !(flags & OPF_PREW);
                         load_phases<R, RB>(pre, rec + prer, L.rec + (prer - sd.rec_begin), prer >= 0, bits,
-                                           prej < 0 ? -1 : prej - job_shift, L.wout, tid);
+                                           prej, wout, tid);
                         prekind = prer < 0 ? 0 : bits ? 2 : 1;
                     }
                     load_phases<R, RB>(post, rec + postr, L.rec + (postr - sd.rec_begin), postr >= 0, true,
-                                       postj < 0 ? -1 : postj - job_shift, L.wout, tid);
+                                       postj, wout, tid);
                     dispatch_u1<R, RB>(op->p0, (flags & OPF_REAL) != 0, prekind, a, m, pre, post);
                 } else if (type == OP_U2) {
                     cxf<R> m[16];
@@ -690,11 +701,6 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     }
 }
 
-static size_t stage_fixed_bytes(size_t cxs)
-{
-    return cxs * kStageJobs + sizeof(int32_t) * kStageObits;
-}
-
 // Record entries staged per stage: 8 KiB of records, or less when the tile leaves less room
 // under 40 KiB (complex<float> tiles of 32 KiB: four blocks per CU), 80 KiB (two blocks per CU)
 // or 160 KiB (one block per CU).
@@ -705,7 +711,7 @@ int stage_rec_cap(qs_dtype dt, int K)
     const size_t budget = (dt == QS_C64 && tile <= 32 * 1024) ? 40 * 1024
                           : tile <= 64 * 1024                 ? 80 * 1024
                                                               : 160 * 1024;
-    const size_t fixed = tile + stage_fixed_bytes(cxs);
+    const size_t fixed = tile;
     if (fixed >= budget) return 0;
     size_t cap = (budget - fixed) / cxs;
     const size_t want = 8192 / cxs;
@@ -715,7 +721,7 @@ int stage_rec_cap(qs_dtype dt, int K)
 size_t fused_lds_bytes(qs_dtype dt, int K)
 {
     const size_t cxs = dt == QS_C64 ? 8 : 16;
-    return (size_t(1) << K) * cxs + stage_fixed_bytes(cxs) + (size_t)stage_rec_cap(dt, K) * cxs;
+    return (size_t(1) << K) * cxs + (size_t)stage_rec_cap(dt, K) * cxs;
 }
 
 hipError_t launch_pass_prep(qs_dtype dt, int S, const PassDesc *h, ProgramDev prog,
@@ -732,6 +738,30 @@ hipError_t launch_pass_prep(qs_dtype dt, int S, const PassDesc *h, ProgramDev pr
     else
         hipLaunchKernelGGL(k_pass_prep<double>, dim3(blocks), dim3(128), 0, st, S, h->op_begin, n_ops,
                            h->rec_size, prog, tab, gates_dev, (cxf<double> *)rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass_jobs(qs_dtype dt, int n, int S, const PassDesc *h, ProgramDev prog, const void *rec,
+                            int64_t init, int64_t basis, const RunParams *dyn, void *wtab, hipStream_t st)
+{
+    const int n_jobs = h->job_end - h->job_begin;
+    if (n_jobs <= 0) return hipSuccess;
+    const bool fill = init >= 0 && h->zero_fill;
+    const uint64_t walk = fill ? h->outer_mask : (h->outer_mask & ~h->classical);
+    const int tiles_log = __builtin_popcountll(walk);
+    const uint64_t classical = fill ? 0 : h->classical;
+    const uint64_t fixed_bits = (uint64_t)basis & classical;
+    const int64_t tot = ((int64_t)S << tiles_log) * n_jobs;
+    TimedLaunch tl("jobs", (double)tot * (dt == QS_C64 ? 8 : 16), st);
+    const unsigned blocks = (unsigned)((tot + 255) / 256);
+    if (dt == QS_C64)
+        hipLaunchKernelGGL(k_pass_jobs<float>, dim3(blocks), dim3(256), 0, st, S, n_jobs, tiles_log, walk, fixed_bits,
+                           h->rec_size, prog.jobs + h->job_begin, prog.obits, (const cxf<float> *)rec, dyn,
+                           classical, (cxf<float> *)wtab);
+    else
+        hipLaunchKernelGGL(k_pass_jobs<double>, dim3(blocks), dim3(256), 0, st, S, n_jobs, tiles_log, walk,
+                           fixed_bits, h->rec_size, prog.jobs + h->job_begin, prog.obits, (const cxf<double> *)rec,
+                           dyn, classical, (cxf<double> *)wtab);
     return hipGetLastError();
 }
 
@@ -765,7 +795,7 @@ hipError_t fused_prepare_attributes()
 template <typename R, int RB>
 static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_index, int rec_cap,
                            int64_t init, int64_t basis, const RunParams *dyn, ProgramDev prog, const void *rec,
-                           size_t lds, hipStream_t st)
+                           const void *wtab, size_t lds, hipStream_t st)
 {
     const hipError_t attr = fused_attr<R, RB>();
     if (attr != hipSuccess) return attr;
@@ -775,14 +805,14 @@ static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_ind
     unsigned blocks = (unsigned)((uint64_t)S << free_bits);
     unsigned threads = 1u << (h.K - RB);
     hipLaunchKernelGGL((k_fused<R, RB>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index,
-                       rec_cap, init, basis, dyn, prog.passes, prog.stages, prog.rounds, prog.ops, prog.jobs, prog.obits,
-                       (const cxf<R> *)rec);
+                       rec_cap, init, basis, dyn, prog.passes, prog.stages, prog.rounds, prog.ops,
+                       (const cxf<R> *)rec, (const cxf<R> *)wtab);
     return hipGetLastError();
 }
 
 hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDesc *pass_host,
                              int pass_index, int64_t init, int64_t basis, ProgramDev prog, const void *rec,
-                             hipStream_t st, const RunParams *dyn)
+                             const void *wtab, hipStream_t st, const RunParams *dyn)
 {
     const PassDesc &h = *pass_host;
     size_t lds = fused_lds_bytes(dt, h.K);
@@ -798,18 +828,18 @@ hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDes
     if (dt == QS_C64) {
         float *p = (float *)psi;
         switch (h.RB) {
-        case 1: return launch_t<float, 1>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, lds, st);
-        case 2: return launch_t<float, 2>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, lds, st);
-        case 3: return launch_t<float, 3>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, lds, st);
-        case 4: return launch_t<float, 4>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, lds, st);
+        case 1: return launch_t<float, 1>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, lds, st);
+        case 2: return launch_t<float, 2>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, lds, st);
+        case 3: return launch_t<float, 3>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, lds, st);
+        case 4: return launch_t<float, 4>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, lds, st);
         }
     } else {
         double *p = (double *)psi;
         switch (h.RB) {
-        case 1: return launch_t<double, 1>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, lds, st);
-        case 2: return launch_t<double, 2>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, lds, st);
-        case 3: return launch_t<double, 3>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, lds, st);
-        case 4: return launch_t<double, 4>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, lds, st);
+        case 1: return launch_t<double, 1>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, lds, st);
+        case 2: return launch_t<double, 2>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, lds, st);
+        case 3: return launch_t<double, 3>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, lds, st);
+        case 4: return launch_t<double, 4>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, lds, st);
         }
     }
     return hipErrorInvalidValue;

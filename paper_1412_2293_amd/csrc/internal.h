@@ -233,9 +233,15 @@ hipError_t launch_pass_prep(qs_dtype dt, int S, const PassDesc *pass_host, Progr
 hipError_t fused_prepare_attributes();
 // init >= 0: the first pass of a run, which makes |init> instead of reading the state; basis:
 // the run's initial basis index (every pass, for the zero tiles of untouched qubits).
+// wtab: the pass's per-tile products of the phases conditioned on tile-number bits, written by
+// launch_pass_jobs (S * 2^(walked tile-number bits) * jobs entries).
 hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDesc *pass_host,
                              int pass_index, int64_t init, int64_t basis, ProgramDev prog, const void *rec,
-                             hipStream_t st, const RunParams *dyn = nullptr);
+                             const void *wtab, hipStream_t st, const RunParams *dyn = nullptr);
+// The per-tile products of a pass's outer jobs into wtab (after launch_pass_prep of the pass);
+// the same init / basis / dyn as the pass's launch_fused_pass.
+hipError_t launch_pass_jobs(qs_dtype dt, int n, int S, const PassDesc *pass_host, ProgramDev prog, const void *rec,
+                            int64_t init, int64_t basis, const RunParams *dyn, void *wtab, hipStream_t st);
 size_t fused_lds_bytes(qs_dtype dt, int K);
 // Record entries per stage that fit next to a tile of 2^K amplitudes (two tiles per CU).
 int stage_rec_cap(qs_dtype dt, int K);
@@ -277,6 +283,7 @@ struct Program {
     std::vector<int32_t> chain_gates, chain_off;
     int K = 0, RB = 0;
     int max_rec = 0;              // largest per-slot record block of a pass (complex entries)
+    int max_jobs = 0;             // most outer jobs of one pass
 };
 
 qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, int run_bits,

@@ -311,7 +311,9 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
             const PG &x = pg[i];
             rec_c = jobs_c = obits_c = 0;
             if (x.kind == QS_G_U1) {
-                rec_c = 4;
+                // the matrix, plus the uniform input phase of an inner chain member with no
+                // folded input block
+                rec_c = (chain_role[x.gate] == 1 && pre_att[i].empty()) ? 5 : 4;
                 for (int post = 0; post < 2; ++post) {
                     const auto &att = (post ? post_att : pre_att)[i];
                     if (att.empty()) continue;
@@ -535,6 +537,7 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         pd.job_end = (int)P.jobs.size();
         pd.rec_size = rec;
         max_rec = std::max(max_rec, rec);
+        P.max_jobs = std::max(P.max_jobs, pd.job_end - pd.job_begin);
         P.passes.push_back(pd);
     }
     // The first pass stores the zero tiles unless the last pass rewrites every amplitude (no

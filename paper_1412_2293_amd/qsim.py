@@ -341,11 +341,11 @@ def traj_layout(gates, n: int, dtype: int, n_traj: int, plan=None) -> dict:
     """Byte offsets of the regions of the run_trajectories buffer."""
     ga = gates if isinstance(gates, ctypes.Array) else gate_array(gates)
     p = _plan(plan)
-    out = np.zeros(16, np.uint64)
+    out = np.zeros(17, np.uint64)
     _check(lib().qs_traj_layout(ga, len(ga), n, dtype, n_traj, ctypes.byref(p) if p else None, _ptr(out)),
            "traj_layout")
     names = ["states", "tab", "gates", "edev", "passes", "stages", "rounds", "ops", "prefs", "jobs",
-             "obits", "chains", "rec", "partials", "out", "total"]
+             "obits", "chains", "wtab", "rec", "partials", "out", "total"]
     return {k: int(v) for k, v in zip(names, out)}
 
 

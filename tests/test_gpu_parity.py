@@ -12,8 +12,8 @@ import pytest
 
 import oracle
 from oracle import fixed_rank
-from workloads import (CP, FLIP, NOISE_PHASE, NOISE_ROT, U1, Circuit, Gate, grover, qft,
-                       random_layers, random_mixed_circuit)
+from workloads import (CP, FLIP, NOISE_PHASE, NOISE_ROT, U1, Circuit, Gate, chain_heavy_circuit, grover,
+                       qft, random_layers, random_mixed_circuit)
 
 from paper_forms import (eq10, first_layer_pairs, grover_p_ideal, pair_product_amplitudes,
                          pair_product_fidelity, qft_noisy_amplitudes)
@@ -583,44 +583,6 @@ def test_fixed_rank_unnormalised_never_exceeds_the_density_matrix():
     assert prev > 0.5 * p_dm   # r = 8 keeps most of it
     rho.close()
     w.close()
-
-
-def chain_heavy_circuit(n: int, n_gates: int, seed: int):
-    """Mostly complex one-qubit gates, so that long phase chains form, with every gate that a
-    chain crosses (controlled phases, sign flips, SWAPs, CNOT controls) or that ends one (real
-    gates, CNOT targets, dense two-qubit gates) in between, some of the one-qubit gates
-    noiseless and diagonal (T-like)."""
-    from workloads import CNOT, NOISE_NONE, SWAP, U2, _renumber_sites, haar_2x2, random_unitary
-    rng = np.random.default_rng(seed)
-    N = 1 << n
-    hm = np.array([[1, 1], [1, -1]], np.complex128) / math.sqrt(2.0)
-    gates = []
-    for _ in range(n_gates):
-        k = int(rng.integers(0, 20))
-        qa = int(rng.integers(0, n))
-        if k < 11:
-            gates.append(Gate(U1, q0=qa, m=haar_2x2(rng), noise=NOISE_ROT))
-        elif k == 11:
-            ph = np.exp(1j * rng.uniform(0, 2 * math.pi))
-            gates.append(Gate(U1, q0=qa, m=np.diag([1.0, ph]).astype(np.complex128), noise=NOISE_NONE))
-        elif k == 12:
-            gates.append(Gate(U1, q0=qa, m=hm, noise=NOISE_ROT))
-        elif k in (13, 14):
-            a, b = (int(v) for v in rng.choice(n, size=2, replace=False))
-            gates.append(Gate(CP, q0=a, q1=b, theta=float(rng.uniform(0, 2 * math.pi)), noise=NOISE_PHASE))
-        elif k == 15:
-            a, b = (int(v) for v in rng.choice(n, size=2, replace=False))
-            gates.append(Gate(SWAP, q0=a, q1=b))
-        elif k == 16:
-            a, b = (int(v) for v in rng.choice(n, size=2, replace=False))
-            gates.append(Gate(CNOT, q0=a, q1=b))
-        elif k == 17:
-            a, b = (int(v) for v in rng.choice(n, size=2, replace=False))
-            gates.append(Gate(U2, q0=a, q1=b, m=random_unitary(4, rng)))
-        else:
-            mask = int(rng.integers(0, N)) | (1 << qa)
-            gates.append(Gate(FLIP, mask=mask, value=int(rng.integers(0, N)) & mask))
-    return Circuit(n, _renumber_sites(gates), name=f"chains{n}", init_index=int(rng.integers(0, N)))
 
 
 @pytest.mark.parametrize("dtype", [q.C128, q.C64])

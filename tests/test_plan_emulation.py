@@ -9,8 +9,8 @@ import pytest
 
 import oracle
 import paper_1412_2293_amd as q
-from workloads import (CNOT, CP, FLIP, NOISE_PHASE, NOISE_ROT, SWAP, U1, U2, grover, qft,
-                       random_layers, random_mixed_circuit)
+from workloads import (CNOT, CP, FLIP, NOISE_PHASE, NOISE_ROT, SWAP, U1, U2, chain_heavy_circuit, grover,
+                       qft, random_layers, random_mixed_circuit)
 
 CNOT4 = np.array([[1, 0, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0], [0, 1, 0, 0]], np.complex128)
 
@@ -192,6 +192,7 @@ def circuits():
     yield qft(8, seed=3)
     yield grover(6, seed=4, iterations=3)
     yield random_layers(8, 5, seed=5, pairing="random")
+    yield chain_heavy_circuit(9, 140, seed=1)
 
 
 @pytest.mark.parametrize("plan", PLANS, ids=lambda p: "-".join(f"{k}{v}" for k, v in p.items()))
@@ -325,3 +326,23 @@ def test_phase_chains_follow_the_wire():
         psi, layout = emulate(c, prog, e, seed=5, traj=traj)
         ref = oracle.sv_run(c, e, seed=5, traj=traj)
         assert np.linalg.norm(unpermute(psi, layout, c.n) - ref) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", [q.C64, q.C128])
+def test_stage_records_fit_the_lds_stage(dtype):
+    """Every stage's records (matrices, uniform input phases of chain members, phase blocks)
+    fit the LDS area the kernel stages them in."""
+    cs = list(circuits()) + [chain_heavy_circuit(11, 160, 1), chain_heavy_circuit(13, 160, 2)]
+    for c in cs:
+        for plan in PLANS + [{"fuse": 1, "tile_bits": 9, "reg_bits": 3, "run_bits": 2}]:
+            if plan.get("tile_bits", 12) > c.n and plan.get("reg_bits", 3) > c.n:
+                continue
+            prog = q.plan_describe(c.gates, c.n, dtype, plan)
+            cap = prog["stage_rec_cap"]
+            for pas in prog["passes"]:
+                for st in pas["stages"]:
+                    assert st["rec_end"] - st["rec_begin"] <= cap, (c.name, plan)
+                    for rd in st["rounds"]:
+                        for op in rd["ops"]:
+                            size = {0: 5 if op["flags"] & 4 else 4, 1: 16, 2: 1}[op["type"]]
+                            assert st["rec_begin"] <= op["rec"] and op["rec"] + size <= st["rec_end"]
