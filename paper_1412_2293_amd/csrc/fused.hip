@@ -427,27 +427,10 @@ __global__ void k_pass_prep(int S, int op_begin, int n_ops, int rec_size, Progra
     }
 }
 
-// LDS of one block: the tile, then the current stage's records, per-tile outer products and
-// outer condition bits.  Op and round descriptors are read with scalar loads.
-
-template <typename R>
-struct StageLds {
-    cxf<R> *rec;
-};
-
-template <typename R>
-__device__ __forceinline__ StageLds<R> stage_lds(unsigned char *smem, int K)
-{
-    StageLds<R> L;
-    L.rec = reinterpret_cast<cxf<R> *>(smem + (size_t(1) << K) * sizeof(cxf<R>));
-    return L;
-}
-
-__device__ __forceinline__ void copy_words(uint32_t *dst, const uint32_t *src, int words, uint32_t tid,
-                                           uint32_t nthreads)
-{
-    for (int w = (int)tid; w < words; w += (int)nthreads) dst[w] = src[w];
-}
+// LDS of one block: the tile only.  Op and round descriptors, matrices and register-bit phase
+// factors are read with scalar loads; the per-thread phase tables of a folded block with vector
+// loads of the slot's records (a few KB, cache resident); the per-tile products of the phases
+// conditioned on tile-number bits come from the table written by k_pass_jobs.
 
 // Register tiles of 16 complex<float> or 8 complex<double> (and more) need more than 128
 // VGPRs: those tiles have at most 256 threads and may use the whole register file.
@@ -455,9 +438,9 @@ template <typename R, int RB>
 constexpr bool kWideTile = RB == 4 || (sizeof(R) == 8 && RB == 3);
 
 // Waves per SIMD the register allocation must allow.  complex<float> with 16-register tiles is
-// held to 128 VGPRs, so that four 256-thread blocks share a CU (their 32 KiB tiles plus records
-// fit the 160 KiB of LDS, see stage_rec_cap): more waves hide the tile loads and the LDS
-// exchanges better than the registers the compiler would otherwise keep for scheduling.
+// held to 128 VGPRs, so that four 256-thread blocks share a CU (their 32 KiB tiles fit the
+// 160 KiB of LDS): more waves hide the tile loads and the LDS exchanges better than the
+// registers the compiler would otherwise keep for scheduling.
 template <typename R, int RB>
 constexpr int kMinWaves = (sizeof(R) == 4 && RB == 4) ? 4 : 1;
 
@@ -487,7 +470,6 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     const int K = pd->K;
     const int TB = K - RB;
     const uint32_t kmask = (1u << K) - 1u;
-    const StageLds<R> L = stage_lds<R>(smem, K);
     // A run starts in the basis state |basis>, and a physical qubit no non-diagonal gate has
     // touched still holds its basis value (controlled phases only rescale), so only the tiles
     // that agree with it on the pass's classical bits hold amplitude, and inside a tile only the
@@ -619,12 +601,6 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
 
     for (int si = pd->stage_begin; si < pd->stage_end; ++si) {
         const StageDesc sd = prog.stages[si];
-        if (si != pd->stage_begin) __syncthreads();   // the previous stage's LDS readers are done
-        copy_words(reinterpret_cast<uint32_t *>(L.rec),
-                   reinterpret_cast<const uint32_t *>(rec + sd.rec_begin),
-                   (sd.rec_end - sd.rec_begin) * (int)(sizeof(cxf<R>) / 4), tid, nthr);
-        __syncthreads();
-
         for (int ri = sd.round_begin; ri < sd.round_end; ++ri) {
             const RoundDesc *rd = prog.rounds + ri;
             const uint32_t mask = rd->reg_mask;
@@ -655,11 +631,11 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                         prekind = 1;
                     } else {
                         const bool bits = !(flags & OPF_PREW);
-                        load_phases<R, RB>(pre, rec + prer, L.rec + (prer - sd.rec_begin), prer >= 0, bits,
+                        load_phases<R, RB>(pre, rec + prer, rec + prer, prer >= 0, bits,
                                            prej, wout, tid);
                         prekind = prer < 0 ? 0 : bits ? 2 : 1;
                     }
-                    load_phases<R, RB>(post, rec + postr, L.rec + (postr - sd.rec_begin), postr >= 0, true,
+                    load_phases<R, RB>(post, rec + postr, rec + postr, postr >= 0, true,
                                        postj, wout, tid);
                     dispatch_u1<R, RB>(op->p0, (flags & OPF_REAL) != 0, prekind, a, m, pre, post);
                 } else if (type == OP_U2) {
@@ -701,27 +677,19 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     }
 }
 
-// Record entries staged per stage: 8 KiB of records, or less when the tile leaves less room
-// under 40 KiB (complex<float> tiles of 32 KiB: four blocks per CU), 80 KiB (two blocks per CU)
-// or 160 KiB (one block per CU).
+// Record entries per stage: 8 KiB of records (a stage bounds the descriptor ranges the kernel
+// walks between two plan boundaries); 0 when the tile does not fit the 160 KiB of LDS.
 int stage_rec_cap(qs_dtype dt, int K)
 {
     const size_t cxs = dt == QS_C64 ? 8 : 16;
-    const size_t tile = (size_t(1) << K) * cxs;
-    const size_t budget = (dt == QS_C64 && tile <= 32 * 1024) ? 40 * 1024
-                          : tile <= 64 * 1024                 ? 80 * 1024
-                                                              : 160 * 1024;
-    const size_t fixed = tile;
-    if (fixed >= budget) return 0;
-    size_t cap = (budget - fixed) / cxs;
-    const size_t want = 8192 / cxs;
-    return (int)(cap > want ? want : cap);
+    if ((size_t(1) << K) * cxs > 160 * 1024) return 0;
+    return (int)(8192 / cxs);
 }
 
+// LDS of one block: its tile.
 size_t fused_lds_bytes(qs_dtype dt, int K)
 {
-    const size_t cxs = dt == QS_C64 ? 8 : 16;
-    return (size_t(1) << K) * cxs + (size_t)stage_rec_cap(dt, K) * cxs;
+    return (size_t(1) << K) * (dt == QS_C64 ? 8 : 16);
 }
 
 hipError_t launch_pass_prep(qs_dtype dt, int S, const PassDesc *h, ProgramDev prog,
