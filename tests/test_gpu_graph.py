@@ -49,3 +49,20 @@ def test_graph_of_grover_and_qft():
             got = g.launch(c.init_index, e=0.03, seed=7, marked=marked)
         ref = q.run_trajectories(c.gates, c.n, c.init_index, q.C64, T, e=0.03, seed=7, marked=marked)
         assert _same(got["F"], ref["F"]), c.name
+
+
+@pytest.mark.parametrize("dtype", [q.C64, q.C128])
+def test_qft_graph_with_new_initial_states(dtype):
+    """A QFT from a basis state leaves most tile-number bits untouched until its last pass, so
+    the passes walk only the tiles that agree with the initial index there, and the per-tile
+    phase products depend on it: one graph replayed from several initial indices matches eager
+    runs from the same indices."""
+    c = qft(15, 4)
+    T = 6
+    plan = {"fuse": 1, "tile_bits": 8, "reg_bits": 3, "run_bits": 2}
+    with q.TrajGraph(c.gates, c.n, dtype, T, plan=plan) as g:
+        for init in (c.init_index, 0, (1 << 15) - 1, 0x5A5A & 0x7FFF):
+            got = g.launch(init, e=0.04, seed=3)
+            ref = q.run_trajectories(c.gates, c.n, init, dtype, T, e=0.04, seed=3, plan=plan)
+            assert _same(got["F"], ref["F"]), init
+            assert _same(got["norm"], ref["norm"]), init
