@@ -143,7 +143,10 @@ qs_status qs_apply_gate(qs_state s, const qs_gate *g, const qs_noise *nz);
  * qubits `qubits` (< n); ops: n_ops host matrices of 2^k x 2^k complex doubles, row-major,
  * (re, im) interleaved, local index bit(qubits[0]) + 2 bit(qubits[1]).  The library forms the
  * superoperator sum_k E_k (x) conj(E_k) in FP64 and applies it in one sweep over the ket
- * bits qubits + n and the bra bits qubits. */
+ * bits qubits + n and the bra bits qubits (k = 2: a 16 x 16 update on four index bits, the
+ * superoperator uploaded through a pinned buffer of the handle; a call waits until the previous
+ * k = 2 call's upload has left that buffer).  Errors: k other than 1, 2 (QS_EUNSUPPORTED);
+ * qubits out of range or equal, n_ops outside 1..64, non-finite entries (QS_EINVAL). */
 qs_status qs_apply_kraus(qs_state rho, int k, const int32_t *qubits, int n_ops, const double *ops);
 
 /* One circuit gate on vec(rho) (Section 3): a ROT-tagged one-qubit gate U with e > 0 becomes

@@ -18,6 +18,7 @@ norm preservation, the Kraus channel against the Monte Carlo mean, eq. (10) for 
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -261,6 +262,29 @@ def kraus_phase(theta: float, e: float) -> np.ndarray:
     ph = np.exp(-1j * theta)
     E1 = np.diag([1.0, 1.0, 1.0, ph * np.sqrt(P)])
     E2 = np.diag([0.0, 0.0, 0.0, ph * np.sqrt(1.0 - P)])
+    return np.stack([E1, E2]).astype(np.complex128)
+
+
+def cp_mixing_f(e: float) -> float:
+    """The parameter f of eq. (13) for P = exp(-e^2): (sqrt(1 + 3P) - P - 1) / sqrt(P (1 - P)),
+    0 in the limit P -> 1 (no noise)."""
+    P = math.exp(-e * e)
+    if P >= 1.0:
+        return 0.0
+    return (math.sqrt(1.0 + 3.0 * P) - P - 1.0) / math.sqrt(P * (1.0 - P))
+
+
+def kraus_phase_improved(theta: float, e: float) -> np.ndarray:
+    """The noisy controlled phase with the Kraus operators of eq. (14): the eq. (9) pair mixed by
+    the unitary of eq. (13), {U_theta E~1, U_theta E~2}, with E~1 = diag(1, 1, 1, sqrt(P) +
+    f sqrt(1-P)) / sqrt(1+f^2) and E~2 = diag(-f, -f, -f, -f sqrt(P) + sqrt(1-P)) / sqrt(1+f^2).
+    A unitary mixture of Kraus operators describes the same channel."""
+    P = math.exp(-e * e)
+    f = cp_mixing_f(e)
+    c = 1.0 / math.sqrt(1.0 + f * f)
+    ph = np.exp(-1j * theta)
+    E1 = c * np.diag([1.0, 1.0, 1.0, ph * (math.sqrt(P) + f * math.sqrt(1.0 - P))])
+    E2 = c * np.diag([-f, -f, -f, ph * (-f * math.sqrt(P) + math.sqrt(1.0 - P))])
     return np.stack([E1, E2]).astype(np.complex128)
 
 

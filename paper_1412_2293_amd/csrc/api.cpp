@@ -104,8 +104,11 @@ struct qs_state_s {
     void *buf;
     size_t bytes;
     hipStream_t st;
-    double *scratch;     // device: table rows, reduction partials, outputs
+    double *scratch;     // device: table rows, reduction partials, outputs, and (last 512
+                         // doubles) the superoperator of a two-qubit Kraus set
     size_t scratch_doubles;
+    double *kraus_host = nullptr;     // pinned staging of that superoperator (first use)
+    hipEvent_t kraus_ev = nullptr;    // its last upload (the staging is reused after it)
 };
 
 struct qs_fr_s {
@@ -152,7 +155,7 @@ qs_status qs_sv_create(int n, qs_dtype dt, int T, void *buf, size_t bytes, void 
     s->bytes = bytes;
     s->st = (hipStream_t)stream;
     s->scratch_doubles = (size_t)T * 8 + reduce_partials_doubles(n, T) + 2 * reduce_partials_doubles(n, 1) + 64 +
-                         (size_t)T * 5 + 64;
+                         (size_t)T * 5 + 64 + 512;
     hipError_t e = hipMalloc(&s->scratch, s->scratch_doubles * sizeof(double));
     if (e != hipSuccess) {
         delete s;
@@ -168,6 +171,8 @@ qs_status qs_sv_destroy(qs_state s)
     if (!s) return QS_OK;
     (void)hipStreamSynchronize(s->st);
     (void)hipFree(s->scratch);
+    if (s->kraus_ev) (void)hipEventDestroy(s->kraus_ev);
+    if (s->kraus_host) (void)hipHostFree(s->kraus_host);
     delete s;
     return QS_OK;
 }
@@ -290,6 +295,47 @@ qs_status qs_apply_gate(qs_state s, const qs_gate *g, const qs_noise *nz)
     return sweep_gate(s->buf, s->dt, s->n, s->T, *g, nz, s->scratch, s->st);
 }
 
+}  // extern "C"
+
+// Two-qubit Kraus set on vec(rho): S = sum_o E_o (x) conj(E_o) on the four index bits
+// (bra q0, bra q1, ket q0 + n, ket q1 + n), local index l = b + 4 a for the ket local index
+// a = bit(q0 + n) + 2 bit(q1 + n) and the bra local index b = bit(q0) + 2 bit(q1):
+// S[(a, b), (c, d)] = sum_o E_o[a][c] conj(E_o[b][d]) (eq. 3; operators row-major on the local
+// index bit(q0) + 2 bit(q1)).  Built in FP64 on the host, staged through pinned memory.
+static qs_status apply_kraus2(qs_state rho, int n, const int32_t *q, int n_ops, const double *ops)
+{
+    if (!rho->kraus_host) {
+        QS_HIP(hipHostMalloc((void **)&rho->kraus_host, 512 * sizeof(double), hipHostMallocDefault));
+        QS_HIP(hipEventCreateWithFlags(&rho->kraus_ev, hipEventDisableTiming));
+    } else {
+        QS_HIP(hipEventSynchronize(rho->kraus_ev));   // the previous upload has read the staging
+    }
+    double *S = rho->kraus_host;
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b)
+            for (int c = 0; c < 4; ++c)
+                for (int d = 0; d < 4; ++d) {
+                    std::complex<double> v = 0;
+                    for (int o = 0; o < n_ops; ++o) {
+                        const double *E = ops + 32 * o;
+                        std::complex<double> eac(E[2 * (4 * a + c)], E[2 * (4 * a + c) + 1]);
+                        std::complex<double> ebd(E[2 * (4 * b + d)], E[2 * (4 * b + d) + 1]);
+                        v += eac * std::conj(ebd);
+                    }
+                    const int row = b + 4 * a, col = d + 4 * c;
+                    S[2 * (16 * row + col)] = v.real();
+                    S[2 * (16 * row + col) + 1] = v.imag();
+                }
+    double *m_dev = rho->scratch + rho->scratch_doubles - 512;
+    QS_HIP(hipMemcpyAsync(m_dev, S, 512 * sizeof(double), hipMemcpyHostToDevice, rho->st));
+    QS_HIP(hipEventRecord(rho->kraus_ev, rho->st));
+    const int bits[4] = {q[0], q[1], q[0] + n, q[1] + n};
+    QS_HIP(launch_sweep_4q(rho->buf, rho->dt, rho->n, bits, m_dev, rho->st));
+    return QS_OK;
+}
+
+extern "C" {
+
 qs_status qs_apply_kraus(qs_state rho, int k, const int32_t *qubits, int n_ops, const double *ops)
 {
     clear_error();
@@ -297,11 +343,15 @@ qs_status qs_apply_kraus(qs_state rho, int k, const int32_t *qubits, int n_ops, 
     if (rho->n % 2 != 0) return fail(QS_EINVAL, "apply_kraus: state must have 2n qubits (vec rho)");
     if (rho->T != 1) return fail(QS_EINVAL, "apply_kraus: density matrix state must hold one vector");
     const int n = rho->n / 2;
-    if (k != 1) return fail(QS_EUNSUPPORTED, "apply_kraus: one-qubit Kraus sets (k = 1) only");
-    if (qubits[0] < 0 || qubits[0] >= n) return fail(QS_EINVAL, "apply_kraus: qubit out of range");
+    if (k != 1 && k != 2) return fail(QS_EUNSUPPORTED, "apply_kraus: one- and two-qubit Kraus sets (k = 1, 2) only");
+    for (int i = 0; i < k; ++i)
+        if (qubits[i] < 0 || qubits[i] >= n) return fail(QS_EINVAL, "apply_kraus: qubit out of range");
+    if (k == 2 && qubits[0] == qubits[1]) return fail(QS_EINVAL, "apply_kraus: the two qubits must differ");
     if (n_ops < 1 || n_ops > 64) return fail(QS_EINVAL, "apply_kraus: n_ops must be in 1..64");
-    for (int i = 0; i < n_ops * 8; ++i)
+    const int dim = 1 << k;
+    for (int i = 0; i < n_ops * dim * dim * 2; ++i)
         if (!std::isfinite(ops[i])) return fail(QS_EINVAL, "apply_kraus: non-finite operator entry");
+    if (k == 2) return apply_kraus2(rho, n, qubits, n_ops, ops);
     // Superoperator S = sum_k E_k (x) conj(E_k) on (bra bit q, ket bit q + n): local index
     // bit(q) + 2 bit(q + n) = b + 2 a for ket bit a, bra bit b;
     // S[(a, b), (c, d)] = sum_k E_k[a][c] conj(E_k[b][d]).

@@ -195,6 +195,10 @@ hipError_t launch_sweep_cp(void *psi, qs_dtype dt, int n, int S, int qa, int qb,
 hipError_t launch_sweep_perm(void *psi, qs_dtype dt, int n, int S, int kind, int qa, int qb,
                              hipStream_t st);
 // m32: host 4x4 complex matrix (32 doubles), passed to the kernel by value.
+// Dense 16x16 (m_dev: 256 complex FP64, device memory) on index bits bits[0..3] of one
+// vector of nbits >= 4 qubits; local index bit k <-> index bit bits[k] (distinct).
+hipError_t launch_sweep_4q(void *psi, qs_dtype dt, int nbits, const int bits[4], const double *m_dev,
+                           hipStream_t st);
 hipError_t launch_sweep_2q(void *psi, qs_dtype dt, int n, int S, int qa, int qb,
                            const double *m32, hipStream_t st);
 // One gate's operator for S slots (as launch_noise_table for a single gate passed by value).

@@ -4,6 +4,8 @@
 // Sweeps are HBM-bound: every dense gate reads and writes each amplitude once.  Threads of a
 // block take consecutive 16-byte chunks so that each wave instruction touches one contiguous
 // 1 KiB range; a chunk is two complex<float> or one complex<double>.
+#include <algorithm>
+
 #include "internal.h"
 
 #include <cmath>
@@ -817,6 +819,66 @@ hipError_t launch_sweep_perm(void *psi, qs_dtype dt, int n, int S, int kind, int
     }
     if (dt == QS_C64) return sweep_2q_t<float, 2>((float *)psi, n, S, qa, qb, nullptr, nullptr, st);
     return sweep_2q_t<double, 2>((double *)psi, n, S, qa, qb, nullptr, nullptr, st);
+}
+
+// ---------------------------------------------------------------------------------------
+// Dense 16x16 update on four index bits (the superoperator of a two-qubit Kraus set on
+// vec(rho), eq. 3): for every index with those bits clear, the 16 entries whose local index
+// l = sum_k bit(k of l) << bits[k] are replaced by M times them.  M is 256 complex FP64 values
+// in device memory, row-major, read with uniform loads.
+// ---------------------------------------------------------------------------------------
+struct Bits4 {
+    int b[4];        // the four index bits, local bit k -> index bit b[k]
+    int sorted[4];   // the same, ascending (for inserting the zero bits)
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_4q(R *psi, Bits4 bits, const double *__restrict__ m, uint64_t total)
+{
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t base = g;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) base = ins0(base, bits.sorted[k]);
+        uint64_t idx[16];
+        cx<R> x[16];
+#pragma unroll
+        for (int l = 0; l < 16; ++l) {
+            uint64_t i = base;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if ((l >> k) & 1) i |= 1ull << bits.b[k];
+            idx[l] = i;
+            x[l] = sload(psi, i);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            cx<R> y = {(R)0, (R)0};
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const cx<R> mrc = {(R)m[2 * (16 * r + c)], (R)m[2 * (16 * r + c) + 1]};
+                y = cfma(mrc, x[c], y);
+            }
+            sstore(psi, idx[r], y);
+        }
+    }
+}
+
+hipError_t launch_sweep_4q(void *psi, qs_dtype dt, int nbits, const int bits[4], const double *m_dev,
+                           hipStream_t st)
+{
+    Bits4 b{};
+    for (int k = 0; k < 4; ++k) b.b[k] = b.sorted[k] = bits[k];
+    std::sort(b.sorted, b.sorted + 4);
+    const uint64_t total = 1ull << (nbits - 4);
+    TimedLaunch tl("sweep_4q", 2.0 * (double)(1ull << nbits) * amp_bytes(dt), st);
+    if (dt == QS_C64)
+        hipLaunchKernelGGL(k_4q<float>, dim3(blocks_for(total, 256)), dim3(256), 0, st, (float *)psi, b, m_dev,
+                           total);
+    else
+        hipLaunchKernelGGL(k_4q<double>, dim3(blocks_for(total, 256)), dim3(256), 0, st, (double *)psi, b, m_dev,
+                           total);
+    return hipGetLastError();
 }
 
 hipError_t launch_sweep_2q(void *psi, qs_dtype dt, int n, int S, int qa, int qb,

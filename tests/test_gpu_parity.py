@@ -335,6 +335,27 @@ def test_apply_kraus_random_sets(dtype):
 
 
 @pytest.mark.parametrize("dtype", [q.C128, q.C64])
+def test_apply_kraus_random_two_qubit_sets(dtype):
+    """Two-qubit Kraus sets (the 16 x 16 superoperator sweep on four index bits) against the
+    oracle's E rho E^dagger sums, for qubit pairs in both orders, adjacent and far apart."""
+    n = 7
+    rng = np.random.default_rng(18)
+    N = 1 << n
+    A = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    rho0 = A @ A.conj().T
+    rho0 /= np.trace(rho0)
+    sv = q.StateVector(2 * n, dtype, 1)
+    to_device_states(sv, rho0.reshape(1, -1))
+    ref = rho0
+    for pair in [(0, 3), (5, 1), (6, 2), (3, 4), (0, 6)]:
+        ops = (rng.standard_normal((3, 4, 4)) + 1j * rng.standard_normal((3, 4, 4))) / 3
+        q.apply_kraus(sv, list(pair), ops)
+        ref = oracle.dm_apply_kraus(ref, n, list(pair), ops)
+    got = from_device(sv)[0].reshape(N, N)
+    assert rel_err(got, ref) <= (1e-12 if dtype == q.C128 else 2e-5)
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
 @pytest.mark.parametrize("n", [10, 13])
 def test_fixed_rank_r1_grover_is_eq10(n, dtype):
     e = 0.02
@@ -606,3 +627,27 @@ def test_phase_chains_full_states(dtype, plan):
         for t in range(T):
             assert rel_err(unpermute(st[t + 1], res["layout"], n), states[t]) <= tol, (n, t)
         assert np.max(np.abs(res["F"] - F_ref)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+def test_dm_qft_with_the_improved_cp_kraus_set(dtype):
+    """The controlled phases of a noisy QFT on vec(rho) applied as the eq. (14) Kraus pair
+    through the general Kraus sweep give, entry by entry, the state of the eq. (9) path (the two
+    sets are one channel), and the oracle's."""
+    n, e = 6, 0.2
+    c = qft(n, seed=5)
+    a = q.StateVector(2 * n, dtype, 1)
+    b = q.StateVector(2 * n, dtype, 1)
+    for r in (a, b):
+        r.init_basis(c.init_index * ((1 << n) + 1))
+    for g in c.gates:
+        q.dm_apply_gate(a, g, e)
+        if g.kind == CP:
+            q.apply_kraus(b, [g.q0, g.q1], q.cp_kraus_improved(g.theta, e))
+        else:
+            q.dm_apply_gate(b, g, e)
+    ra = from_device(a)[0].reshape(1 << n, 1 << n)
+    rb = from_device(b)[0].reshape(1 << n, 1 << n)
+    tol = 1e-12 if dtype == q.C128 else 2e-5
+    assert rel_err(rb, ra) <= tol
+    assert rel_err(rb, oracle.dm_run(c, e)) <= tol

@@ -137,3 +137,40 @@ def test_kraus_sets_are_trace_preserving():
             np.testing.assert_allclose(sum(k.conj().T @ k for k in K), np.eye(2), atol=1e-15)
             K = oracle.kraus_phase(float(rng.uniform(0, 2 * math.pi)), e)
             np.testing.assert_allclose(sum(k.conj().T @ k for k in K), np.eye(4), atol=1e-15)
+
+
+def _superop(K):
+    return sum(np.kron(k, k.conj()) for k in K)
+
+
+def test_improved_cp_kraus_is_the_orthogonal_form_of_eq9():
+    """Eq. (14): the eq. (9) operators mixed by the unitary of eq. (13).  Same channel (equal
+    superoperators), complete, and Hilbert-Schmidt orthogonal with squared norms equal to the
+    squared singular values of the matrix of eq. (12) (its rows are the diagonals of the eq. (9)
+    operators), taken from numpy's SVD; those are the lambda_1,2 = 2 +- sqrt(1 + 3P) of the
+    text."""
+    rng = np.random.default_rng(4)
+    for e in [0.0, 0.01, 0.1, 0.3, 1.0, 2.0]:
+        P = math.exp(-e * e)
+        for theta in [0.0, math.pi, float(rng.uniform(0, 2 * math.pi))]:
+            K9 = oracle.kraus_phase(theta, e)
+            K14 = oracle.kraus_phase_improved(theta, e)
+            np.testing.assert_allclose(sum(k.conj().T @ k for k in K14), np.eye(4), atol=1e-14)
+            np.testing.assert_allclose(_superop(K14), _superop(K9), atol=1e-14)
+        K14 = oracle.kraus_phase_improved(0.0, e)
+        gram = np.array([[np.trace(a.conj().T @ b) for b in K14] for a in K14])
+        psi12 = np.array([[1, 1, 1, math.sqrt(P)], [0, 0, 0, math.sqrt(1 - P)]])
+        sv2 = np.linalg.svd(psi12, compute_uv=False) ** 2
+        np.testing.assert_allclose(gram, np.diag(sv2), atol=1e-13)
+        np.testing.assert_allclose(sv2, [2 + math.sqrt(1 + 3 * P), 2 - math.sqrt(1 + 3 * P)], atol=1e-13)
+
+
+def test_library_improved_cp_kraus_matches_the_oracle():
+    """The operators the library's callers pass to apply_kraus (package side) equal the
+    oracle's eq. (14) set."""
+    import paper_1412_2293_amd as q
+    rng = np.random.default_rng(9)
+    for e in [0.0, 0.02, 0.2, 1.5]:
+        for theta in [0.0, 1.0, float(rng.uniform(0, 2 * math.pi))]:
+            np.testing.assert_allclose(q.cp_kraus_improved(theta, e), oracle.kraus_phase_improved(theta, e),
+                                       atol=1e-15)
