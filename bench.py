@@ -529,14 +529,25 @@ def choi_bench(q, torch):
         F, tr = choi.relative_state_fidelity(w.shor_code(p), q.C128)
         shor.append({"p": p, "overlap": F, "sqrt_overlap": math.sqrt(max(F, 0.0)), "trace": tr,
                      "phase_code_overlap": 1 - 3 * p * p + 2 * p ** 3, "unprotected_overlap": 1 - p})
-    qft = []
+    qft, codes_relax = [], []
     for T1, T2 in ((10.0, 5.0), (30.0, 20.0), (100.0, 70.0), (300.0, 200.0), (1000.0, 700.0)):
         t1 = time.perf_counter()
         F, tr = choi.relative_state_fidelity(w.qft_relaxation(5, T1, T2), q.C128)
         qft.append({"T1": T1, "T2": T2, "overlap": F, "trace": tr, "wall_s": time.perf_counter() - t1})
+        Fp, _ = choi.relative_state_fidelity(w.phase_code_relaxation(T1, T2), q.C128)
+        Fs, _ = choi.relative_state_fidelity(w.shor_code_relaxation(T1, T2), q.C128)
+        # one unprotected qubit over the same time: sum_k |Tr E_k / 2|^2
+        g, pz = 1.0 - math.exp(-1.0 / T1), 0.5 * (1.0 - math.exp(-1.0 / T2))
+        s1 = math.sqrt(1.0 - g)
+        F1 = (1 - pz) * ((1 + s1) / 2) ** 2 + pz * ((1 - s1) / 2) ** 2
+        codes_relax.append({"T1": T1, "T2": T2, "phase_code_overlap": Fp, "shor_code_overlap": Fs,
+                            "unprotected_overlap": F1})
     return {"workload": "relative states on vec(rho) complex128: phase code (3 + 1 reference qubits), "
-                        "qft5 with relaxation after every gate (5 + 5 reference qubits, 2^20 entries)",
-            "phase_code": code, "shor_code": shor, "qft5": qft, "wall_s": time.perf_counter() - t0}
+                        "Shor's code (9 + 1), both under phase errors and under T1/T2 relaxation of "
+                        "one gate time, qft5 with relaxation after every gate (5 + 5 reference qubits, "
+                        "2^20 entries)",
+            "phase_code": code, "shor_code": shor, "codes_T1T2": codes_relax, "qft5": qft,
+            "wall_s": time.perf_counter() - t0}
 
 
 def fr24_bench(q, torch, iterations=10):

@@ -58,3 +58,22 @@ def test_shor_code_against_closed_form(dtype):
         tol = 1e-12 if dtype == q.C128 else 5e-6
         assert abs(F - (1 - 3 * qb * qb + 2 * qb ** 3)) <= tol, (p, F)
         assert abs(tr - 1.0) <= tol
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+def test_codes_under_relaxation_against_oracle(dtype):
+    """The three-qubit and Shor codes with amplitude and phase relaxation on every code qubit:
+    relative-state overlaps against the oracle's, and with T1 = inf the closed forms of the
+    phase-error codes (p from eq. 19)."""
+    tol = 1e-12 if dtype == q.C128 else 5e-6
+    for T1, T2 in ((30.0, 20.0), (10.0, 5.0)):
+        for build in (w.phase_code_relaxation, w.shor_code_relaxation):
+            prog = build(T1, T2)
+            F, tr = choi.relative_state_fidelity(prog, dtype)
+            F_ref, _ = oracle.choi_fidelity(prog)
+            assert abs(F - F_ref) <= tol, (prog.name, F, F_ref)
+            assert abs(tr - 1.0) <= tol
+    T2 = 12.0
+    p = 0.5 * (1.0 - math.exp(-1.0 / T2))
+    F, _ = choi.relative_state_fidelity(w.phase_code_relaxation(math.inf, T2), dtype)
+    assert abs(F - (1 - 3 * p * p + 2 * p ** 3)) <= tol

@@ -67,3 +67,27 @@ def test_shor_code_phase_errors():
     F, tr = oracle.choi_fidelity(w.shor_code(p))
     qb = 3 * p * (1 - p) ** 2 + p ** 3
     assert abs(F - (1 - 3 * qb * qb + 2 * qb ** 3)) < 1e-12 and abs(tr - 1.0) < 1e-12
+
+
+def test_codes_under_relaxation_reduce_to_the_phase_error_forms():
+    """With no amplitude relaxation (T1 = inf) the relaxation builders give the phase-error codes
+    with p from eq. (19), whose overlaps are 1 - 3p^2 + 2p^3 (three-qubit code) and
+    1 - 3q^2 + 2q^3, q = 3p(1-p)^2 + p^3 (Shor's code)."""
+    T2 = 12.0
+    p = 0.5 * (1.0 - math.exp(-1.0 / T2))
+    F, tr = oracle.choi_fidelity(w.phase_code_relaxation(math.inf, T2))
+    assert abs(F - (1 - 3 * p * p + 2 * p ** 3)) < 1e-13 and abs(tr - 1.0) < 1e-13
+    F, tr = oracle.choi_fidelity(w.shor_code_relaxation(math.inf, T2))
+    qb = 3 * p * (1 - p) ** 2 + p ** 3
+    assert abs(F - (1 - 3 * qb * qb + 2 * qb ** 3)) < 1e-12 and abs(tr - 1.0) < 1e-12
+
+
+def test_phase_code_under_relaxation_is_trace_preserving_and_monotone():
+    """Amplitude relaxation (which the phase code does not correct) only lowers the overlap, the
+    more the shorter T1; the trace stays 1."""
+    Fs = []
+    for T1 in (5.0, 20.0, 100.0, math.inf):
+        F, tr = oracle.choi_fidelity(w.phase_code_relaxation(T1, 50.0))
+        assert abs(tr - 1.0) < 1e-13
+        Fs.append(F)
+    assert Fs[0] < Fs[1] < Fs[2] < Fs[3] < 1.0

@@ -319,17 +319,35 @@ def toffoli_gates(c1: int, c2: int, t: int) -> List[Gate]:
             _u1(t, H_MATRIX), Gate(CNOT, q0=c1, q1=c2), _u1(c1, _T), _u1(c2, _TDG), Gate(CNOT, q0=c1, q1=c2)]
 
 
+def relaxation_channels(qubits, T1: float, T2: float, t: float = 1.0) -> List[Channel]:
+    """Amplitude then phase relaxation over time t on each of `qubits` (T1 or T2 = inf: none)."""
+    out: List[Channel] = []
+    for q in qubits:
+        out.append(Channel((q,), amplitude_damping(t, T1)))
+        out.append(Channel((q,), dephasing_from_T2(t, T2)))
+    return out
+
+
+def _phase_code(noise: list, name: str, meta: dict) -> ChoiProgram:
+    enc = [Gate(CNOT, q0=0, q1=1), Gate(CNOT, q0=0, q1=2)] + [_u1(q, H_MATRIX) for q in range(3)]
+    dec = [_u1(q, H_MATRIX) for q in range(3)] + [Gate(CNOT, q0=0, q1=1), Gate(CNOT, q0=0, q1=2)]
+    dec += toffoli_gates(1, 2, 0)
+    return ChoiProgram(3, [0], enc + noise + dec, [], ancillas=[1, 2], name=name, meta=meta)
+
+
 def phase_code(p: float) -> ChoiProgram:
     """Three-qubit phase-error code (Section 4.1) on the logical qubit 0: encode (CNOTs then
     Hadamards), a phase error with probability p on each code qubit, decode (Hadamards, CNOTs,
     and the majority correction as a Toffoli controlled by the syndrome qubits 1 and 2).  The
     target is the identity on the logical qubit; the syndrome qubits are traced out."""
-    enc = [Gate(CNOT, q0=0, q1=1), Gate(CNOT, q0=0, q1=2)] + [_u1(q, H_MATRIX) for q in range(3)]
-    noise = [Channel((q,), dephasing(p)) for q in range(3)]
-    dec = [_u1(q, H_MATRIX) for q in range(3)] + [Gate(CNOT, q0=0, q1=1), Gate(CNOT, q0=0, q1=2)]
-    dec += toffoli_gates(1, 2, 0)
-    return ChoiProgram(3, [0], enc + noise + dec, [], ancillas=[1, 2], name=f"phase_code p={p}",
-                       meta={"p": p})
+    return _phase_code([Channel((q,), dephasing(p)) for q in range(3)], f"phase_code p={p}", {"p": p})
+
+
+def phase_code_relaxation(T1: float, T2: float, t: float = 1.0) -> ChoiProgram:
+    """The three-qubit phase-error code with amplitude and phase relaxation (T1, T2 over a time t,
+    eq. 19 for the phase part) on each code qubit in place of the phase errors."""
+    return _phase_code(relaxation_channels(range(3), T1, T2, t), f"phase_code T1={T1} T2={T2}",
+                       {"T1": T1, "T2": T2, "t": t})
 
 
 def qft_relaxation(n: int, T1: float, T2: float, t: float = 1.0) -> ChoiProgram:
@@ -375,17 +393,26 @@ def shor_code(p: float) -> ChoiProgram:
     Toffoli controlled by b+1, b+2 onto b (bit correction), then Hadamards on 0, 3, 6, CNOTs
     0 -> 3, 6 and a Toffoli controlled by 3, 6 onto 0 (phase correction).  The target is the
     identity on the logical qubit; the other eight qubits are traced out."""
+    return _shor_code([Channel((q,), dephasing(p)) for q in range(9)], f"shor_code p={p}", {"p": p})
+
+
+def shor_code_relaxation(T1: float, T2: float, t: float = 1.0) -> ChoiProgram:
+    """Shor's nine-qubit code with amplitude and phase relaxation (T1, T2 over a time t) on each
+    code qubit in place of the phase errors."""
+    return _shor_code(relaxation_channels(range(9), T1, T2, t), f"shor_code T1={T1} T2={T2}",
+                      {"T1": T1, "T2": T2, "t": t})
+
+
+def _shor_code(noise: list, name: str, meta: dict) -> ChoiProgram:
     enc = [Gate(CNOT, q0=0, q1=3), Gate(CNOT, q0=0, q1=6)] + [_u1(b, H_MATRIX) for b in (0, 3, 6)]
     for b in (0, 3, 6):
         enc += [Gate(CNOT, q0=b, q1=b + 1), Gate(CNOT, q0=b, q1=b + 2)]
-    noise = [Channel((q,), dephasing(p)) for q in range(9)]
     dec = []
     for b in (0, 3, 6):
         dec += [Gate(CNOT, q0=b, q1=b + 1), Gate(CNOT, q0=b, q1=b + 2)] + toffoli_gates(b + 1, b + 2, b)
     dec += [_u1(b, H_MATRIX) for b in (0, 3, 6)] + [Gate(CNOT, q0=0, q1=3), Gate(CNOT, q0=0, q1=6)]
     dec += toffoli_gates(3, 6, 0)
-    return ChoiProgram(9, [0], enc + noise + dec, [], ancillas=list(range(1, 9)), name=f"shor_code p={p}",
-                       meta={"p": p})
+    return ChoiProgram(9, [0], enc + noise + dec, [], ancillas=list(range(1, 9)), name=name, meta=meta)
 
 
 def chain_heavy_circuit(n: int, n_gates: int, seed: int):
