@@ -87,9 +87,11 @@ struct PassDesc {
     int32_t reserved;
 };
 
-// A stage: consecutive rounds whose op descriptors, records, outer jobs and outer bits are
-// copied into LDS together (record and job offsets of ops are relative to the pass; stage
-// ranges are absolute except rec_*, which are relative to the pass's record block).
+// A stage: consecutive rounds whose records, outer jobs and outer bits stay within the
+// per-stage bounds below (record and job offsets of ops are relative to the pass; stage ranges
+// are absolute except rec_*, which are relative to the pass's record block).  The fused kernel
+// walks stages as plain ranges of rounds; the bounds keep the descriptor tables of one stage
+// small.
 struct StageDesc {
     int32_t round_begin, round_end;
     int32_t op_begin, op_end;
