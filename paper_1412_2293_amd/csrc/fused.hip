@@ -340,12 +340,16 @@ __global__ void k_pass_jobs(int S, int n_jobs, int tiles_log, uint64_t walk, uin
                             const cxf<R> *__restrict__ rec_all, const RunParams *dyn, uint64_t classical,
                             cxf<R> *__restrict__ wtab)
 {
+    // thread order (slot, job, tile): the threads of a wave share the job, so its descriptor,
+    // condition bits and factors are uniform loads
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ((int64_t)S << tiles_log) * n_jobs) return;
-    const int j = (int)(i % n_jobs);
-    const int64_t blk = i / n_jobs;
-    const int slot = (int)(blk >> tiles_log);
-    uint64_t t = (uint64_t)blk & ((1ull << tiles_log) - 1ull);
+    const int64_t per_slot = (int64_t)n_jobs << tiles_log;
+    if (i >= (int64_t)S * per_slot) return;
+    const int slot = (int)(i / per_slot);
+    const int64_t rem = i - (int64_t)slot * per_slot;
+    const int j = (int)(rem >> tiles_log);
+    uint64_t t = (uint64_t)rem & ((1ull << tiles_log) - 1ull);
+    const uint64_t tile = t;
     if (dyn) fixed_bits = (uint64_t)dyn->init & classical;
     uint64_t outer = fixed_bits, m = walk;
     while (m) {
@@ -359,7 +363,7 @@ __global__ void k_pass_jobs(int S, int n_jobs, int tiles_log, uint64_t walk, uin
     cxf<R> w = {(R)1, (R)0};
     for (int k = 0; k < jb.n; ++k)
         if ((outer >> obits[jb.bits_off + k]) & 1ull) w = mul(w, rec[jb.rec_off + k]);
-    wtab[i] = w;
+    wtab[(((int64_t)slot << tiles_log) + (int64_t)tile) * n_jobs + j] = w;
 }
 
 template <typename R>

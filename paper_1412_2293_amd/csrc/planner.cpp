@@ -299,7 +299,7 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         const uint32_t load_mask = ((1u << RB) - 1u) << (K - RB);
         const RoundDesc load_rd = make_round(load_mask, K);
 
-        // greedy register rounds, closed also when the current LDS stage is full
+        // greedy register rounds, closed also when the current stage reaches its bounds
         auto fill = [&](uint32_t need) {
             uint32_t m = need;
             for (int j = K - 1; j >= 0 && __builtin_popcount(m) < RB; --j)
