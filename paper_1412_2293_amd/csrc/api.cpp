@@ -720,11 +720,12 @@ TrajLayout traj_layout(int n, qs_dtype dt, int T, int n_gates, const Plan &pl)
     L.jobs = take(std::max<size_t>(pl.prog.jobs.size(), 1) * sizeof(OuterJob));
     L.obits = take(std::max<size_t>(pl.prog.obits.size(), 1) * sizeof(int32_t));
     L.chains = take(std::max<size_t>(pl.prog.chain_gates.size() + pl.prog.chain_off.size(), 1) * sizeof(int32_t));
-    // per (slot, tile, outer job) phase products of the pass being run: at most 2^(n - K) tiles
+    // the tiles' outer index bits (at most 2^(n - K) tiles), then the per (slot, tile, outer job)
+    // phase products of the pass being run
     {
         const int tb = pl.fused && n > pl.prog.K ? n - pl.prog.K : 0;
         const size_t entries = ((size_t)S << tb) * (size_t)std::max(pl.prog.max_jobs, 1);
-        L.wtab = take(entries * 2 * (dt == QS_C64 ? 4 : 8));
+        L.wtab = take(align256((size_t(1) << tb) * sizeof(uint64_t)) + entries * 2 * (dt == QS_C64 ? 4 : 8));
     }
     L.rec = take((size_t)std::max(pl.prog.max_rec, 1) * S * 2 * (dt == QS_C64 ? 4 : 8));
     L.partials = take(reduce_partials_doubles(n, S) * sizeof(double));
@@ -864,11 +865,13 @@ static qs_status enqueue_compute(const TrajPrep &prep, const TrajLayout &L, char
                        (const int32_t *)(B + L.obits)};
         for (size_t p = 0; p < P.passes.size(); ++p) {
             const int64_t init = p == 0 ? (int64_t)init_index : -1;
+            uint64_t *otab = (uint64_t *)(B + L.wtab);
+            char *wtab = B + L.wtab + align256((size_t(1) << (n > P.K ? n - P.K : 0)) * sizeof(uint64_t));
             QS_HIP(launch_pass_prep(dt, S, &P.passes[p], pdv, tab, gdev, B + L.rec, st));
             QS_HIP(launch_pass_jobs(dt, n, S, &P.passes[p], pdv, B + L.rec, init, (int64_t)init_index, dyn,
-                                    B + L.wtab, st));
+                                    wtab, otab, st));
             QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (int)p, init, (int64_t)init_index, pdv, B + L.rec,
-                                     B + L.wtab, st, dyn));
+                                     wtab, otab, st, dyn));
         }
     } else {
         for (int g = 0; g < n_gates; ++g) {

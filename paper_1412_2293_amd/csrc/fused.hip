@@ -334,16 +334,18 @@ hipError_t launch_phase_chains(double *tab, int S, const int32_t *chain_gates, c
 // tile-number bit is set in the tile's index, in the order the planner listed them.  Tiles are
 // numbered as the fused kernel's blocks are (the walked tile-number bits, the others at their
 // basis values), so a block finds its products at wtab + blockIdx * jobs.
+// Also writes otab[tile]: the tile's tile-number bits of the physical index (the walked bits
+// from the tile number, the others at the basis values), from the threads of slot 0, job 0.
 template <typename R>
 __global__ void k_pass_jobs(int S, int n_jobs, int tiles_log, uint64_t walk, uint64_t fixed_bits, int rec_size,
                             const OuterJob *__restrict__ jobs, const int32_t *__restrict__ obits,
                             const cxf<R> *__restrict__ rec_all, const RunParams *dyn, uint64_t classical,
-                            cxf<R> *__restrict__ wtab)
+                            cxf<R> *__restrict__ wtab, uint64_t *__restrict__ otab)
 {
     // thread order (slot, job, tile): the threads of a wave share the job, so its descriptor,
-    // condition bits and factors are uniform loads
+    // condition bits and factors are uniform loads (n_jobs == 0: one row of threads for otab)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t per_slot = (int64_t)n_jobs << tiles_log;
+    const int64_t per_slot = (int64_t)(n_jobs > 0 ? n_jobs : 1) << tiles_log;
     if (i >= (int64_t)S * per_slot) return;
     const int slot = (int)(i / per_slot);
     const int64_t rem = i - (int64_t)slot * per_slot;
@@ -358,6 +360,8 @@ __global__ void k_pass_jobs(int S, int n_jobs, int tiles_log, uint64_t walk, uin
         t >>= 1;
         m ^= low;
     }
+    if (slot == 0 && j == 0) otab[tile] = outer;
+    if (n_jobs == 0) return;
     const OuterJob jb = jobs[j];
     const cxf<R> *rec = rec_all + (size_t)slot * rec_size;
     cxf<R> w = {(R)1, (R)0};
@@ -451,14 +455,15 @@ constexpr int kMinWaves = (sizeof(R) == 4 && RB == 4) ? 4 : 1;
 template <typename R, int RB>
 __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     __attribute__((amdgpu_waves_per_eu(kMinWaves<R, RB>, 8))) k_fused(R *__restrict__ psi, int n, int S, int pass_index,
-                                                  int rec_cap, int64_t init, int64_t basis,
+                                                  int rec_cap, int64_t init, int64_t basis, uint32_t blocal,
                                                   const RunParams *__restrict__ dyn,
                                                   const PassDesc *__restrict__ g_passes,
                                                   const StageDesc *__restrict__ g_stages,
                                                   const RoundDesc *__restrict__ g_rounds,
                                                   const OpDesc *__restrict__ g_ops,
                                                   const cxf<R> *__restrict__ rec_all,
-                                                  const cxf<R> *__restrict__ wtab)
+                                                  const cxf<R> *__restrict__ wtab,
+                                                  const uint64_t *__restrict__ otab)
 {
     // Descriptor arrays as separate read-only, non-aliasing arguments: their uniform reads
     // become scalar loads that do not wait on the tile's vector memory traffic.
@@ -497,35 +502,23 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     const cxf<R> *__restrict__ wout =
         wtab + (size_t)blockIdx.x * (size_t)(pd->job_end - pd->job_begin);
 
-    // Outer (tile-number) bits of the physical index.
-    uint64_t outer = fill ? 0 : ((uint64_t)basis & pd->classical);
-    {
-        uint64_t m = walk, t = tile;
-        while (m) {
-            uint64_t low = m & (~m + 1ull);
-            if (t & 1ull) outer |= low;
-            t >>= 1;
-            m ^= low;
-        }
-    }
+    // Outer (tile-number) bits of the physical index, written for this launch by k_pass_jobs.
+    const uint64_t outer = otab[tile];
     // Load layout: thread bits = tile-local bits 0..TB-1, register bits = TB..K-1.
     uint64_t gthr = outer;
     for (int j = 0; j < TB; ++j)
         if ((tid >> j) & 1u) gthr |= 1ull << pd->q_pos[j];
     uint64_t greg[NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        uint64_t g = 0;
-#pragma unroll
-        for (int k = 0; k < RB; ++k)
-            if (r & (1 << k)) g |= 1ull << pd->q_pos[TB + k];
-        greg[r] = g;
-    }
+    for (int r = 0; r < NR; ++r) greg[r] = pd->reg_off[r];
     R *base = psi + ((uint64_t)slot << (n + 1));
-    // the basis index's bits at the tile-local positions
-    uint32_t blocal = 0;
-    for (int j = 0; j < K; ++j)
-        if (((uint64_t)basis >> pd->q_pos[j]) & 1ull) blocal |= 1u << j;
+    // the basis index's bits at the tile-local positions (from the host, or here when the
+    // basis comes from the device block)
+    if (dyn) {
+        blocal = 0;
+        for (int j = 0; j < K; ++j)
+            if (((uint64_t)basis >> pd->q_pos[j]) & 1ull) blocal |= 1u << j;
+    }
     tv<R> a[NR];
     if (fill && ((outer ^ (uint64_t)basis) & pd->classical) != 0) {
         // a tile of the first pass outside the support: zeros (uniform per block)
@@ -666,11 +659,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     if (cur != load_mask) exchange_to(load_mask, pd->load_round);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        uint64_t g = 0;
-#pragma unroll
-        for (int k = 0; k < RB; ++k)
-            if (r & (1 << k)) g |= 1ull << pd->q_pos[TB + k];
-        uint64_t i = gthr | g;
+        uint64_t i = gthr | pd->reg_off[r];
         if constexpr (sizeof(R) == 4) {
             typedef float f2 __attribute__((ext_vector_type(2)));
             __builtin_nontemporal_store(a[r], reinterpret_cast<f2 *>(base + 2 * i));
@@ -714,26 +703,26 @@ hipError_t launch_pass_prep(qs_dtype dt, int S, const PassDesc *h, ProgramDev pr
 }
 
 hipError_t launch_pass_jobs(qs_dtype dt, int n, int S, const PassDesc *h, ProgramDev prog, const void *rec,
-                            int64_t init, int64_t basis, const RunParams *dyn, void *wtab, hipStream_t st)
+                            int64_t init, int64_t basis, const RunParams *dyn, void *wtab, uint64_t *otab,
+                            hipStream_t st)
 {
     const int n_jobs = h->job_end - h->job_begin;
-    if (n_jobs <= 0) return hipSuccess;
     const bool fill = init >= 0 && h->zero_fill;
     const uint64_t walk = fill ? h->outer_mask : (h->outer_mask & ~h->classical);
     const int tiles_log = __builtin_popcountll(walk);
     const uint64_t classical = fill ? 0 : h->classical;
     const uint64_t fixed_bits = (uint64_t)basis & classical;
-    const int64_t tot = ((int64_t)S << tiles_log) * n_jobs;
-    TimedLaunch tl("jobs", (double)tot * (dt == QS_C64 ? 8 : 16), st);
+    const int64_t tot = ((int64_t)S << tiles_log) * (n_jobs > 0 ? n_jobs : 1);
+    TimedLaunch tl("jobs", (double)((int64_t)S << tiles_log) * n_jobs * (dt == QS_C64 ? 8 : 16), st);
     const unsigned blocks = (unsigned)((tot + 255) / 256);
     if (dt == QS_C64)
         hipLaunchKernelGGL(k_pass_jobs<float>, dim3(blocks), dim3(256), 0, st, S, n_jobs, tiles_log, walk, fixed_bits,
                            h->rec_size, prog.jobs + h->job_begin, prog.obits, (const cxf<float> *)rec, dyn,
-                           classical, (cxf<float> *)wtab);
+                           classical, (cxf<float> *)wtab, otab);
     else
         hipLaunchKernelGGL(k_pass_jobs<double>, dim3(blocks), dim3(256), 0, st, S, n_jobs, tiles_log, walk,
                            fixed_bits, h->rec_size, prog.jobs + h->job_begin, prog.obits, (const cxf<double> *)rec,
-                           dyn, classical, (cxf<double> *)wtab);
+                           dyn, classical, (cxf<double> *)wtab, otab);
     return hipGetLastError();
 }
 
@@ -767,7 +756,7 @@ hipError_t fused_prepare_attributes()
 template <typename R, int RB>
 static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_index, int rec_cap,
                            int64_t init, int64_t basis, const RunParams *dyn, ProgramDev prog, const void *rec,
-                           const void *wtab, size_t lds, hipStream_t st)
+                           const void *wtab, const uint64_t *otab, size_t lds, hipStream_t st)
 {
     const hipError_t attr = fused_attr<R, RB>();
     if (attr != hipSuccess) return attr;
@@ -776,15 +765,18 @@ static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_ind
     const int free_bits = n - h.K - (fill ? 0 : __builtin_popcountll(h.classical));
     unsigned blocks = (unsigned)((uint64_t)S << free_bits);
     unsigned threads = 1u << (h.K - RB);
+    uint32_t blocal = 0;
+    for (int j = 0; j < h.K; ++j)
+        if (((uint64_t)basis >> h.q_pos[j]) & 1ull) blocal |= 1u << j;
     hipLaunchKernelGGL((k_fused<R, RB>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index,
-                       rec_cap, init, basis, dyn, prog.passes, prog.stages, prog.rounds, prog.ops,
-                       (const cxf<R> *)rec, (const cxf<R> *)wtab);
+                       rec_cap, init, basis, blocal, dyn, prog.passes, prog.stages, prog.rounds, prog.ops,
+                       (const cxf<R> *)rec, (const cxf<R> *)wtab, otab);
     return hipGetLastError();
 }
 
 hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDesc *pass_host,
                              int pass_index, int64_t init, int64_t basis, ProgramDev prog, const void *rec,
-                             const void *wtab, hipStream_t st, const RunParams *dyn)
+                             const void *wtab, const uint64_t *otab, hipStream_t st, const RunParams *dyn)
 {
     const PassDesc &h = *pass_host;
     size_t lds = fused_lds_bytes(dt, h.K);
@@ -800,18 +792,18 @@ hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDes
     if (dt == QS_C64) {
         float *p = (float *)psi;
         switch (h.RB) {
-        case 1: return launch_t<float, 1>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, lds, st);
-        case 2: return launch_t<float, 2>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, lds, st);
-        case 3: return launch_t<float, 3>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, lds, st);
-        case 4: return launch_t<float, 4>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, lds, st);
+        case 1: return launch_t<float, 1>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st);
+        case 2: return launch_t<float, 2>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st);
+        case 3: return launch_t<float, 3>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st);
+        case 4: return launch_t<float, 4>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st);
         }
     } else {
         double *p = (double *)psi;
         switch (h.RB) {
-        case 1: return launch_t<double, 1>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, lds, st);
-        case 2: return launch_t<double, 2>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, lds, st);
-        case 3: return launch_t<double, 3>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, lds, st);
-        case 4: return launch_t<double, 4>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, lds, st);
+        case 1: return launch_t<double, 1>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st);
+        case 2: return launch_t<double, 2>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st);
+        case 3: return launch_t<double, 3>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st);
+        case 4: return launch_t<double, 4>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st);
         }
     }
     return hipErrorInvalidValue;

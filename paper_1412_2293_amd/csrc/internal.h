@@ -85,6 +85,8 @@ struct PassDesc {
     int32_t zero_fill;            // first pass: store the tiles outside the support as zeros
                                   // (needed unless the last pass rewrites every amplitude)
     int32_t reserved;
+    uint64_t reg_off[16];         // load layout: physical index bits of register r (its RB bits
+                                  // are the top RB tile-local bits)
 };
 
 // A stage: consecutive rounds whose records, outer jobs and outer bits stay within the
@@ -241,13 +243,17 @@ hipError_t fused_prepare_attributes();
 // the run's initial basis index (every pass, for the zero tiles of untouched qubits).
 // wtab: the pass's per-tile products of the phases conditioned on tile-number bits, written by
 // launch_pass_jobs (S * 2^(walked tile-number bits) * jobs entries).
+// otab: the tile-number bits of each tile's physical index (2^(walked bits) entries), also
+// written by launch_pass_jobs.
 hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDesc *pass_host,
                              int pass_index, int64_t init, int64_t basis, ProgramDev prog, const void *rec,
-                             const void *wtab, hipStream_t st, const RunParams *dyn = nullptr);
-// The per-tile products of a pass's outer jobs into wtab (after launch_pass_prep of the pass);
-// the same init / basis / dyn as the pass's launch_fused_pass.
+                             const void *wtab, const uint64_t *otab, hipStream_t st, const RunParams *dyn = nullptr);
+// The per-tile products of a pass's outer jobs into wtab and the tiles' outer index bits into
+// otab (after launch_pass_prep of the pass); the same init / basis / dyn as the pass's
+// launch_fused_pass.
 hipError_t launch_pass_jobs(qs_dtype dt, int n, int S, const PassDesc *pass_host, ProgramDev prog, const void *rec,
-                            int64_t init, int64_t basis, const RunParams *dyn, void *wtab, hipStream_t st);
+                            int64_t init, int64_t basis, const RunParams *dyn, void *wtab, uint64_t *otab,
+                            hipStream_t st);
 size_t fused_lds_bytes(qs_dtype dt, int K);
 // Record entries per stage that fit next to a tile of 2^K amplitudes (two tiles per CU).
 int stage_rec_cap(qs_dtype dt, int K);

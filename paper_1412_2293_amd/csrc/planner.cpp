@@ -294,6 +294,12 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         for (int j = 0; j < K; ++j)
             if (!((touched >> Q[j]) & 1ull)) pd.lclassical |= 1u << j;
         for (int q : pb.targets) touched |= 1ull << q;
+        for (int r = 0; r < 16; ++r) {
+            uint64_t off = 0;
+            for (int k = 0; k < RB; ++k)
+                if (r < (1 << RB) && ((r >> k) & 1)) off |= 1ull << Q[K - RB + k];
+            pd.reg_off[r] = off;
+        }
         uint32_t lcls = pd.lclassical;   // tile-local bits untouched so far in this pass
         const uint32_t kmask = (1u << K) - 1u;
         const uint32_t load_mask = ((1u << RB) - 1u) << (K - RB);
