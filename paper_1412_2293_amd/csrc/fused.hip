@@ -589,7 +589,19 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
         const RoundDesc *rd = prog.rounds + ri;
         cur = to;
         cur_ri = ri;
-        lthr = (uint32_t)rd->tlo[tid & 31u] | (uint32_t)rd->thi[(tid >> 5) & 15u];
+        // the thread id deposited into the tile-local bits outside the registers: a zero bit
+        // inserted at each register bit, lowest first (arithmetic, no table load to wait on)
+        {
+            uint32_t x = tid, m = to;
+#pragma unroll
+            for (int k = 0; k < RB; ++k) {
+                const uint32_t b = (uint32_t)__builtin_ctz(m);
+                const uint32_t lo = x & ((1u << b) - 1u);
+                x = ((x ^ lo) << 1) | lo;
+                m &= m - 1u;
+            }
+            lthr = x;
+        }
         uint32_t sw = swz(lthr) * CXS;
         asm volatile("" : "+v"(sw));
 #pragma unroll

@@ -239,6 +239,9 @@ def test_program_ranges_are_consistent():
                     assert st["op_begin"] == op_at and st["round_begin"] == round_at
                     assert st["job_begin"] == job_at and st["rec_begin"] == rec_at
                     for rd in st["rounds"]:
+                        # every register layout holds exactly RB tile-local bits (the kernel
+                        # inserts one zero bit per register bit to place the thread id)
+                        assert bin(rd["reg_mask"]).count("1") == prog["RB"] and rd["reg_mask"] < (1 << K)
                         for op in rd["ops"]:
                             assert op["rec"] >= rec_at
                         op_at += len(rd["ops"])
