@@ -216,9 +216,10 @@ qs_status qs_traj_graph_destroy(qs_traj_graph g);
 /* Byte offsets, inside the qs_run_trajectories buffer, of its regions (for inspection):
  * out[0] states, [1] noise table (per gate and slot: 8 doubles), [2] device gates, [3] per-slot
  * noise strengths, [4] pass, [5] stage, [6] round, [7] op, [8] phase-reference, [9] outer-job,
- * [10] outer-bit descriptors, [11] phase chains, [12] per-tile phase products of the last
- * pass, [13] per-slot records of the last pass, [14] reduction partials, [15] results, [16]
- * total (out holds 17 values).  No device work. */
+ * [10] outer-bit descriptors, [11] phase chains, [12] per-tile tables of the last pass (the
+ * tiles' index bits, then the phase products of its outer jobs), [13] per-slot records of the
+ * last pass, [14] reduction partials, [15] results, [16] total (out holds 17 values).  No
+ * device work. */
 qs_status qs_traj_layout(const qs_gate *gates, int n_gates, int n_qubits, qs_dtype dt, int n_traj,
                          const qs_plan *plan, size_t *out);
 
