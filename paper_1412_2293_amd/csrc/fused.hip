@@ -88,9 +88,11 @@ struct PhaseSet {
 // block staged in LDS (per-thread table lookups); wout: this tile's products of the phases
 // conditioned on tile-number bits (global memory, uniform reads).
 // bits: whether the block has phases conditioned on register bits (else only w is used).
+// uni: no factor of the block depends on a thread-id bit, so every entry of the thread tables
+// equals their first (uniform reads instead of per-thread lookups).
 template <typename R, int RB>
 __device__ __forceinline__ void load_phases(PhaseSet<R, RB> &ps, const cxf<R> *__restrict__ grec,
-                                            const cxf<R> *lrec, bool present, bool bits, int job,
+                                            const cxf<R> *lrec, bool present, bool bits, bool uni, int job,
                                             const cxf<R> *wout, uint32_t tid)
 {
     ps.any = present;
@@ -99,7 +101,8 @@ __device__ __forceinline__ void load_phases(PhaseSet<R, RB> &ps, const cxf<R> *_
 #pragma unroll
         for (int k = 0; k < RB; ++k) ps.bit[k] = grec[k];
     }
-    ps.w = mul(lrec[4 + (tid & 31u)], lrec[36 + ((tid >> 5) & 15u)]);
+    if (uni) ps.w = grec[4];
+    else ps.w = mul(lrec[4 + (tid & 31u)], lrec[36 + ((tid >> 5) & 15u)]);
     if (job >= 0) ps.w = mul(ps.w, wout[job]);
 }
 
@@ -452,7 +455,10 @@ constexpr bool kWideTile = RB == 4 || (sizeof(R) == 8 && RB == 3);
 template <typename R, int RB>
 constexpr int kMinWaves = (sizeof(R) == 4 && RB == 4) ? 4 : 1;
 
-template <typename R, int RB>
+// UNI: whether blocks whose factors do not depend on thread-id bits take their per-thread factor
+// with a uniform load (the host picks this variant for passes where most blocks are such; the
+// other keeps the per-thread lookups branch-free, which schedules better when few are).
+template <typename R, int RB, bool UNI>
 __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     __attribute__((amdgpu_waves_per_eu(kMinWaves<R, RB>, 8))) k_fused(R *__restrict__ psi, int n, int S, int pass_index,
                                                   int rec_cap, int64_t init, int64_t basis, uint32_t blocal,
@@ -641,11 +647,11 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                     } else {
                         const bool bits = !(flags & OPF_PREW);
                         load_phases<R, RB>(pre, rec + prer, rec + prer, prer >= 0, bits,
-                                           prej, wout, tid);
+                                           UNI && (flags & OPF_PRE_UNI) != 0, prej, wout, tid);
                         prekind = prer < 0 ? 0 : bits ? 2 : 1;
                     }
                     load_phases<R, RB>(post, rec + postr, rec + postr, postr >= 0, true,
-                                       postj, wout, tid);
+                                       UNI && (flags & OPF_POST_UNI) != 0, postj, wout, tid);
                     dispatch_u1<R, RB>(op->p0, (flags & OPF_REAL) != 0, prekind, a, m, pre, post);
                 } else if (type == OP_U2) {
                     cxf<R> m[16];
@@ -739,19 +745,26 @@ hipError_t launch_pass_jobs(qs_dtype dt, int n, int S, const PassDesc *h, Progra
 }
 
 // thread-safe one-time opt-in to the full 160 KiB of LDS
-template <typename R, int RB>
-static hipError_t fused_attr()
+template <typename R, int RB, bool UNI>
+static hipError_t fused_attr_one()
 {
     static const hipError_t attr = [] {
         // the kernel addresses its tile at LDS address 0: it must have no static LDS
         hipFuncAttributes fa;
-        hipError_t e = hipFuncGetAttributes(&fa, (const void *)k_fused<R, RB>);
+        hipError_t e = hipFuncGetAttributes(&fa, (const void *)k_fused<R, RB, UNI>);
         if (e != hipSuccess) return e;
         if (fa.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
-        return hipFuncSetAttribute((const void *)k_fused<R, RB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        return hipFuncSetAttribute((const void *)k_fused<R, RB, UNI>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    160 * 1024);
     }();
     return attr;
+}
+
+template <typename R, int RB>
+static hipError_t fused_attr()
+{
+    const hipError_t e = fused_attr_one<R, RB, false>();
+    return e != hipSuccess ? e : fused_attr_one<R, RB, true>();
 }
 
 hipError_t fused_prepare_attributes()
@@ -780,9 +793,14 @@ static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_ind
     uint32_t blocal = 0;
     for (int j = 0; j < h.K; ++j)
         if (((uint64_t)basis >> h.q_pos[j]) & 1ull) blocal |= 1u << j;
-    hipLaunchKernelGGL((k_fused<R, RB>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index,
-                       rec_cap, init, basis, blocal, dyn, prog.passes, prog.stages, prog.rounds, prog.ops,
-                       (const cxf<R> *)rec, (const cxf<R> *)wtab, otab);
+    if (h.uni_kernel)
+        hipLaunchKernelGGL((k_fused<R, RB, true>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index,
+                           rec_cap, init, basis, blocal, dyn, prog.passes, prog.stages, prog.rounds, prog.ops,
+                           (const cxf<R> *)rec, (const cxf<R> *)wtab, otab);
+    else
+        hipLaunchKernelGGL((k_fused<R, RB, false>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index,
+                           rec_cap, init, basis, blocal, dyn, prog.passes, prog.stages, prog.rounds, prog.ops,
+                           (const cxf<R> *)rec, (const cxf<R> *)wtab, otab);
     return hipGetLastError();
 }
 

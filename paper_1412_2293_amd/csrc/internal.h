@@ -84,7 +84,8 @@ struct PassDesc {
                                   // basis index there can be nonzero, and only those are read
     int32_t zero_fill;            // first pass: store the tiles outside the support as zeros
                                   // (needed unless the last pass rewrites every amplitude)
-    int32_t reserved;
+    int32_t uni_kernel;           // run the kernel variant with uniform factors for blocks
+                                  // without thread-conditioned phases (most blocks are such)
     uint64_t reg_off[16];         // load layout: physical index bits of register r (its RB bits
                                   // are the top RB tile-local bits)
 };
@@ -115,7 +116,11 @@ enum PrepKind : int32_t { PR_REG = 0, PR_THREAD = 1, PR_OUTER = 2 };
 // written by the chain kernel).  OPF_UPHASE: the op has no folded input block, and its input
 // phase is the uniform record entry rec + 4.  OPF_PREW: the op's input phase does not depend
 // on register bits (a per-thread or uniform factor only).
-enum OpFlags : int32_t { OPF_REAL = 1, OPF_CHAIN = 2, OPF_UPHASE = 4, OPF_PREW = 8 };
+// OPF_PRE_UNI / OPF_POST_UNI: the folded input / output block has no phase conditioned on a
+// thread-id bit, so its per-thread factor is the same for every thread of a block.
+enum OpFlags : int32_t {
+    OPF_REAL = 1, OPF_CHAIN = 2, OPF_UPHASE = 4, OPF_PREW = 8, OPF_PRE_UNI = 16, OPF_POST_UNI = 32
+};
 
 struct OpDesc {
     int32_t type;

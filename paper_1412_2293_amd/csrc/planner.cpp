@@ -483,6 +483,12 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                                 if (local_of[at.cond] >= 0 && reg_index[local_of[at.cond]] >= 0) reg = true;
                             if (!reg) op.flags |= OPF_PREW;
                         }
+                        {
+                            bool thr = false;
+                            for (auto &at : att)
+                                if (local_of[at.cond] >= 0 && reg_index[local_of[at.cond]] < 0) thr = true;
+                            if (!thr) op.flags |= post ? OPF_POST_UNI : OPF_PRE_UNI;
+                        }
                         if (n_outer > 0) {
                             OuterJob jb{};
                             jb.op = (int)P.ops.size();
@@ -528,6 +534,22 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
             }
             R.op_end = (int)P.ops.size();
             P.rounds.push_back(R);
+        }
+        {
+            // the uniform-factor kernel variant when most of the pass's blocks can use it
+            int blocks = 0, uni = 0;
+            for (int oi = pd.op_begin; oi < (int)P.ops.size(); ++oi) {
+                const OpDesc &o = P.ops[oi];
+                if (o.pre_rec >= 0) {
+                    ++blocks;
+                    uni += (o.flags & OPF_PRE_UNI) != 0;
+                }
+                if (o.post_rec >= 0) {
+                    ++blocks;
+                    uni += (o.flags & OPF_POST_UNI) != 0;
+                }
+            }
+            pd.uni_kernel = blocks > 0 && 2 * uni > blocks;
         }
         {
             StageDesc &last = P.stages.back();

@@ -651,3 +651,25 @@ def test_dm_qft_with_the_improved_cp_kraus_set(dtype):
     tol = 1e-12 if dtype == q.C128 else 2e-5
     assert rel_err(rb, ra) <= tol
     assert rel_err(rb, oracle.dm_run(c, e)) <= tol
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+@pytest.mark.parametrize("plan", [{"fuse": 1}, {"fuse": 1, "tile_bits": 8, "reg_bits": 3, "run_bits": 3}],
+                         ids=["default", "t8r3"])
+def test_random_layers_uniform_factor_variant_full_states(dtype, plan):
+    """Random layers, whose folded CZ phases are mostly conditioned on register or tile-number
+    bits, run most passes in the kernel variant that reads those blocks' factors uniformly:
+    every amplitude of every trajectory against the oracle."""
+    n = 14
+    c = random_layers(n, 5, seed=6, pairing="brickwork")
+    desc = q.plan_describe(c.gates, n, dtype, plan)
+    assert any(p["uni_kernel"] for p in desc["passes"]) and not all(p["uni_kernel"] for p in desc["passes"])
+    T, e, s = 3, 0.1, 12
+    res = q.run_trajectories(c.gates, n, c.init_index, dtype, T, e=e, seed=s, plan=plan)
+    F_ref, _, ideal, states = oracle.run_trajectories(c, e, s, range(T), keep_states=True)
+    st = q.trajectory_states(res, n, dtype, T).cpu().numpy().astype(np.complex128)
+    tol = 1e-12 if dtype == q.C128 else 3e-5
+    assert rel_err(unpermute(st[0], res["layout"], n), ideal) <= tol
+    for t in range(T):
+        assert rel_err(unpermute(st[t + 1], res["layout"], n), states[t]) <= tol, t
+    assert np.max(np.abs(res["F"] - F_ref)) <= TOL[dtype]

@@ -140,6 +140,10 @@ def emulate(circuit, prog, e=0.0, seed=0, traj=0):
                                     cond = np.full(l0.size, (outer >> bit) & 1)
                                 w[post] = w[post] * np.where(cond == 1, ops[cpg], 1.0)
                             M = ops[op["gate"]]
+                            # a block flagged uniform has no thread-conditioned phase
+                            for post, flag in ((0, 16), (1, 32)):
+                                if op["flags"] & flag:
+                                    assert not any(ph[0] == 1 and ph[1] == post for ph in op["phases"])
                             assert bool(op["flags"] & 2) == isinstance(M, tuple)
                             if op["flags"] & 2:
                                 # inner chain member: a real matrix after a uniform input phase
