@@ -673,3 +673,20 @@ def test_random_layers_uniform_factor_variant_full_states(dtype, plan):
     for t in range(T):
         assert rel_err(unpermute(st[t + 1], res["layout"], n), states[t]) <= tol, t
     assert np.max(np.abs(res["F"] - F_ref)) <= TOL[dtype]
+
+
+def test_apply_kraus_rejects_bad_sets_before_device_work():
+    """k outside 1..2 is unsupported; equal or out-of-range qubits and non-finite entries are
+    invalid; the density matrix is left untouched."""
+    n = 3
+    sv = q.StateVector(2 * n, q.C128, 1)
+    sv.init_basis(0)
+    before = from_device(sv).copy()
+    ops2 = np.stack([np.eye(4, dtype=np.complex128)])
+    for qubits, ops, code in (([0, 1, 2], np.stack([np.eye(8, dtype=np.complex128)]), -4),
+                              ([1, 1], ops2, -1), ([0, 3], ops2, -1),
+                              ([0, 1], np.full((1, 4, 4), np.nan, np.complex128), -1)):
+        with pytest.raises(q.QsimError) as ei:
+            q.apply_kraus(sv, qubits, ops)
+        assert f"({code})" in str(ei.value), str(ei.value)
+    assert np.array_equal(from_device(sv), before)
