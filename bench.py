@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=150,
                     help="requests of the seeded serving stream to replay (0: skip)")
     ap.add_argument("--serving-inflight", type=int, default=4)
+    ap.add_argument("--leg", default="",
+                    help="run only this side measurement (large_state_n32, graph_replay, dm13, dm_qft13, "
+                         "fr24, fr_vs_dm12, choi, sweeps_n28) and print its JSON (profiling runs)")
     return ap.parse_args()
 
 
@@ -72,7 +75,18 @@ def main():
     import paper_1412_2293_amd as q
     from workloads import qft
 
+    leg_names = ("large_state_n32", "graph_replay", "dm13", "dm_qft13", "fr24", "fr_vs_dm12", "choi", "sweeps_n28")
+    if a.leg and a.leg not in leg_names:
+        print(f"unknown leg {a.leg}; one of {', '.join(leg_names)}", file=sys.stderr)
+        sys.exit(2)
     torch.cuda.set_device(0)
+    if a.leg:
+        legs = {"large_state_n32": lambda: large_state_bench(q, torch), "graph_replay": lambda: graph_bench(q, torch),
+                "dm13": lambda: dm13_bench(q, torch), "dm_qft13": lambda: dm_qft13_bench(q, torch),
+                "fr24": lambda: fr24_bench(q, torch), "fr_vs_dm12": lambda: fr_vs_dm12_bench(q, torch),
+                "choi": lambda: choi_bench(q, torch), "sweeps_n28": lambda: sweeps(q)}
+        print(json.dumps({a.leg: legs[a.leg]()}), flush=True)
+        return
     n, Te = a.n, a.traj_per_e
     T = 2 * Te
     es = np.array([0.001] * Te + [0.01] * Te)
