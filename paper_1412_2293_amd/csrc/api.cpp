@@ -728,7 +728,15 @@ TrajLayout traj_layout(int n, qs_dtype dt, int T, int n_gates, const Plan &pl)
         L.wtab = take(align256((size_t(1) << tb) * sizeof(uint64_t)) + entries * 2 * (dt == QS_C64 ? 4 : 8));
     }
     L.rec = take((size_t)std::max(pl.prog.max_rec, 1) * S * 2 * (dt == QS_C64 ? 4 : 8));
-    L.partials = take(reduce_partials_doubles(n, S) * sizeof(double));
+    {
+        // the fused runs' per (slot, tile) overlap partials of their last pass
+        size_t d = reduce_partials_doubles(n, S);
+        if (pl.fused) {
+            const int tb = n > pl.prog.K ? n - pl.prog.K : 0;
+            d = std::max(d, ((size_t)S << tb) * 3);
+        }
+        L.partials = take(d * sizeof(double));
+    }
     L.out = take((size_t)S * 5 * sizeof(double));
     L.dyn = take(sizeof(RunParams));
     L.total = off;
@@ -870,8 +878,21 @@ static qs_status enqueue_compute(const TrajPrep &prep, const TrajLayout &L, char
             QS_HIP(launch_pass_prep(dt, S, &P.passes[p], pdv, tab, gdev, B + L.rec, st));
             QS_HIP(launch_pass_jobs(dt, n, S, &P.passes[p], pdv, B + L.rec, init, (int64_t)init_index, dyn,
                                     wtab, otab, st));
+            if (p + 1 < P.passes.size()) {
+                QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (int)p, init, (int64_t)init_index, pdv,
+                                         B + L.rec, wtab, otab, st, dyn));
+                continue;
+            }
+            // the last pass also forms the overlaps with slot 0: slot 0 first, then the others
+            double *part = (double *)(B + L.partials);
             QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (int)p, init, (int64_t)init_index, pdv, B + L.rec,
-                                     wtab, otab, st, dyn));
+                                     wtab, otab, st, dyn, part, 0, 1));
+            if (S > 1)
+                QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (int)p, init, (int64_t)init_index, pdv,
+                                         B + L.rec, wtab, otab, st, dyn, part, 1, S - 1));
+            QS_HIP(launch_overlap_final(psi, dt, n, S, fused_walked_bits(n, &P.passes[p], init), pmarked, part,
+                                        (double *)(B + L.out), st, dyn));
+            return QS_OK;
         }
     } else {
         for (int g = 0; g < n_gates; ++g) {

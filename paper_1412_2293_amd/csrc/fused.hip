@@ -469,7 +469,8 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                                                   const OpDesc *__restrict__ g_ops,
                                                   const cxf<R> *__restrict__ rec_all,
                                                   const cxf<R> *__restrict__ wtab,
-                                                  const uint64_t *__restrict__ otab)
+                                                  const uint64_t *__restrict__ otab,
+                                                  double *__restrict__ ovl, int slot_base, int slots)
 {
     // Descriptor arrays as separate read-only, non-aliasing arguments: their uniform reads
     // become scalar loads that do not wait on the tile's vector memory traffic.
@@ -500,13 +501,25 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     const bool fill = first && pd->zero_fill;
     const uint64_t walk = fill ? pd->outer_mask : (pd->outer_mask & ~pd->classical);
     const int tiles_log = __builtin_popcountll(walk);
-    const int slot = (int)(blockIdx.x >> tiles_log);
-    const uint64_t tile = (uint64_t)blockIdx.x & ((1ull << tiles_log) - 1ull);
+    // Block order: slot-major, so that the blocks in flight share one slot's records.  When the
+    // pass also forms the overlaps with slot 0 (slots [slot_base, slot_base + slots)), tile-major
+    // with the slot fastest: all slots of a tile run together and read slot 0's tile from the
+    // caches.  (Measured against groups of 2^10 tiles, group-major, and against slot groups of 8
+    // with one slot per XCD: both slower, as slot 0's tiles are then reused from further away.)
+    int slot;
+    uint64_t tile;
+    if (ovl) {
+        slot = slot_base + (int)(blockIdx.x % (unsigned)slots);
+        tile = blockIdx.x / (unsigned)slots;
+    } else {
+        slot = (int)(blockIdx.x >> tiles_log);
+        tile = (uint64_t)blockIdx.x & ((1ull << tiles_log) - 1ull);
+    }
+    const uint64_t bidx = ((uint64_t)slot << tiles_log) | tile;
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
     const cxf<R> *__restrict__ rec = rec_all + (size_t)slot * pd->rec_size;
     // this tile's products of the phases conditioned on tile-number bits (one per outer job)
-    const cxf<R> *__restrict__ wout =
-        wtab + (size_t)blockIdx.x * (size_t)(pd->job_end - pd->job_begin);
+    const cxf<R> *__restrict__ wout = wtab + bidx * (size_t)(pd->job_end - pd->job_begin);
 
     // Outer (tile-number) bits of the physical index, written for this launch by k_pass_jobs.
     const uint64_t outer = otab[tile];
@@ -531,6 +544,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
 #pragma unroll
         for (int r = 0; r < NR; ++r)
             __builtin_nontemporal_store(tv<R>{(R)0, (R)0}, reinterpret_cast<tv<R> *>(base + 2 * (gthr | greg[r])));
+        if (ovl && tid < 3) ovl[bidx * 3 + tid] = 0.0;
         return;
     }
     if (init >= 0) {
@@ -686,6 +700,42 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
             __builtin_nontemporal_store(a[r], reinterpret_cast<d2 *>(base + 2 * i));
         }
     }
+    if (ovl) {
+        // This tile's share of <psi_0|psi_slot> and <psi_slot|psi_slot> in FP64: the same sums
+        // as the separate overlap reduction, one partial per (slot, tile).
+        const R *ref = psi;
+        double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const uint64_t i = gthr | pd->reg_off[r];
+            const tv<R> e = slot == 0 ? a[r] : *reinterpret_cast<const tv<R> *>(ref + 2 * i);
+            const double ar = e.x, ai = e.y, br = a[r].x, bi = a[r].y;
+            v[0] += ar * br + ai * bi;
+            v[1] += ar * bi - ai * br;
+            v[2] += br * br + bi * bi;
+        }
+        // wave sums (a block of fewer than 64 threads is one partial wave: sum over its lanes)
+        const int width = nthr < 64u ? (int)nthr : 64;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            for (int off = width >> 1; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, width);
+        if (nthr <= 64u) {
+            if (tid == 0)
+                for (int k = 0; k < 3; ++k) ovl[bidx * 3 + k] = v[k];
+        } else {
+            // the tile's LDS (at least 2 KiB here) is free once every wave has left the last exchange
+            __syncthreads();
+            double *sh = reinterpret_cast<double *>(smem);
+            if ((tid & 63u) == 0)
+                for (int k = 0; k < 3; ++k) sh[(tid >> 6) * 3 + k] = v[k];
+            __syncthreads();
+            if (tid < 3) {
+                double t = 0.0;
+                for (uint32_t w = 0; w < (nthr >> 6); ++w) t += sh[w * 3 + tid];
+                ovl[bidx * 3 + tid] = t;
+            }
+        }
+    }
 }
 
 // Record entries per stage: 8 KiB of records (a stage bounds the descriptor ranges the kernel
@@ -781,14 +831,15 @@ hipError_t fused_prepare_attributes()
 template <typename R, int RB>
 static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_index, int rec_cap,
                            int64_t init, int64_t basis, const RunParams *dyn, ProgramDev prog, const void *rec,
-                           const void *wtab, const uint64_t *otab, size_t lds, hipStream_t st)
+                           const void *wtab, const uint64_t *otab, size_t lds, hipStream_t st,
+                           double *ovl, int slot_base, int slots)
 {
     const hipError_t attr = fused_attr<R, RB>();
     if (attr != hipSuccess) return attr;
     // the first pass may store every tile; otherwise a pass runs over the tiles that hold amplitude
     const bool fill = init >= 0 && h.zero_fill;
     const int free_bits = n - h.K - (fill ? 0 : __builtin_popcountll(h.classical));
-    unsigned blocks = (unsigned)((uint64_t)S << free_bits);
+    unsigned blocks = (unsigned)((uint64_t)(ovl ? slots : S) << free_bits);
     unsigned threads = 1u << (h.K - RB);
     uint32_t blocal = 0;
     for (int j = 0; j < h.K; ++j)
@@ -796,44 +847,57 @@ static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_ind
     if (h.uni_kernel)
         hipLaunchKernelGGL((k_fused<R, RB, true>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index,
                            rec_cap, init, basis, blocal, dyn, prog.passes, prog.stages, prog.rounds, prog.ops,
-                           (const cxf<R> *)rec, (const cxf<R> *)wtab, otab);
+                           (const cxf<R> *)rec, (const cxf<R> *)wtab, otab, ovl, slot_base, slots);
     else
         hipLaunchKernelGGL((k_fused<R, RB, false>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index,
                            rec_cap, init, basis, blocal, dyn, prog.passes, prog.stages, prog.rounds, prog.ops,
-                           (const cxf<R> *)rec, (const cxf<R> *)wtab, otab);
+                           (const cxf<R> *)rec, (const cxf<R> *)wtab, otab, ovl, slot_base, slots);
     return hipGetLastError();
+}
+
+int fused_walked_bits(int n, const PassDesc *pass_host, int64_t init)
+{
+    const bool fill = init >= 0 && pass_host->zero_fill;
+    return n - pass_host->K - (fill ? 0 : __builtin_popcountll(pass_host->classical));
 }
 
 hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDesc *pass_host,
                              int pass_index, int64_t init, int64_t basis, ProgramDev prog, const void *rec,
-                             const void *wtab, const uint64_t *otab, hipStream_t st, const RunParams *dyn)
+                             const void *wtab, const uint64_t *otab, hipStream_t st, const RunParams *dyn,
+                             double *ovl, int slot_base, int slots)
 {
     const PassDesc &h = *pass_host;
     size_t lds = fused_lds_bytes(dt, h.K);
     const int rec_cap = stage_rec_cap(dt, h.K);
     if (lds > 160 * 1024 || rec_cap <= 0 || basis < 0) return hipErrorInvalidValue;
+    if (ovl && (slots < 1 || slot_base < 0 || slot_base + slots > S)) return hipErrorInvalidValue;
+    const int S_run = ovl ? slots : S;
     // Algorithmic bytes: a pass writes the tiles that can hold amplitude (a 2^-popcount(classical)
     // share; every tile when the first pass stores the zeros) and reads, except the first pass,
     // the amplitudes of the support inside them (a further 2^-popcount(lclassical) share).
     const bool fill_all = init >= 0 && h.zero_fill;
     const double tiles_share = fill_all ? 1.0 : std::ldexp(1.0, -__builtin_popcountll(h.classical));
     const double read_share = init >= 0 ? 0.0 : std::ldexp(1.0, -__builtin_popcount(h.lclassical));
-    TimedLaunch tl("fused", (1.0 + read_share) * tiles_share * (double)((uint64_t)S << n) * amp_bytes(dt), st);
+    // with the overlaps: slot 0's tiles once more (read from HBM once, by the first slot of a tile)
+    const double ref_share = ovl && slot_base > 0 ? 1.0 : 0.0;
+    TimedLaunch tl("fused",
+                   ((1.0 + read_share) * (double)S_run + ref_share) * tiles_share * std::ldexp(1.0, n) * amp_bytes(dt),
+                   st);
     if (dt == QS_C64) {
         float *p = (float *)psi;
         switch (h.RB) {
-        case 1: return launch_t<float, 1>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st);
-        case 2: return launch_t<float, 2>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st);
-        case 3: return launch_t<float, 3>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st);
-        case 4: return launch_t<float, 4>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st);
+        case 1: return launch_t<float, 1>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st, ovl, slot_base, slots);
+        case 2: return launch_t<float, 2>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st, ovl, slot_base, slots);
+        case 3: return launch_t<float, 3>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st, ovl, slot_base, slots);
+        case 4: return launch_t<float, 4>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st, ovl, slot_base, slots);
         }
     } else {
         double *p = (double *)psi;
         switch (h.RB) {
-        case 1: return launch_t<double, 1>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st);
-        case 2: return launch_t<double, 2>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st);
-        case 3: return launch_t<double, 3>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st);
-        case 4: return launch_t<double, 4>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st);
+        case 1: return launch_t<double, 1>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st, ovl, slot_base, slots);
+        case 2: return launch_t<double, 2>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st, ovl, slot_base, slots);
+        case 3: return launch_t<double, 3>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st, ovl, slot_base, slots);
+        case 4: return launch_t<double, 4>(p, n, S, h, pass_index, rec_cap, init, basis, dyn, prog, rec, wtab, otab, lds, st, ovl, slot_base, slots);
         }
     }
     return hipErrorInvalidValue;

@@ -220,6 +220,10 @@ hipError_t launch_scale_pattern(void *psi, qs_dtype dt, int n, int S, uint64_t m
 // Per-slot (Re <ref|psi_s>, Im <ref|psi_s>, <psi_s|psi_s>, Re psi_s[marked], Im psi_s[marked])
 // with ref = slot ref_slot of ref_psi; out has S * 5 doubles.  partials: reduce_partials_size.
 size_t reduce_partials_doubles(int n, int S);
+// Sums per-slot partials (2^log_blocks per slot, 3 doubles each) into out[slot * 5 ...] as
+// launch_overlaps does (with the marked amplitude of psi).
+hipError_t launch_overlap_final(const void *psi, qs_dtype dt, int n, int S, int log_blocks, int64_t marked,
+                                const double *partials, double *out, hipStream_t st, const RunParams *dyn);
 hipError_t launch_overlaps(const void *ref_psi, int ref_slot, const void *psi, qs_dtype dt, int n,
                            int S, int64_t marked, double *partials, double *out, hipStream_t st,
                            const RunParams *dyn = nullptr);
@@ -252,7 +256,14 @@ hipError_t fused_prepare_attributes();
 // written by launch_pass_jobs.
 hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDesc *pass_host,
                              int pass_index, int64_t init, int64_t basis, ProgramDev prog, const void *rec,
-                             const void *wtab, const uint64_t *otab, hipStream_t st, const RunParams *dyn = nullptr);
+                             const void *wtab, const uint64_t *otab, hipStream_t st, const RunParams *dyn = nullptr,
+                             double *ovl = nullptr, int slot_base = 0, int slots = 0);
+// ovl (non-null): the pass runs only the slots [slot_base, slot_base + slots), tile-major, and
+// also writes each (slot, tile) block's FP64 sums Re/Im <psi_0|psi_slot> and <psi_slot|psi_slot>
+// to ovl[((slot << walked bits) | tile) * 3 ...]; slot 0's tiles must be final before a launch
+// with slot_base > 0 (run slot 0 alone first).  Finished by launch_overlap_final.
+// Walked tile-number bits of a pass launch (the tiles its blocks cover).
+int fused_walked_bits(int n, const PassDesc *pass_host, int64_t init);
 // The per-tile products of a pass's outer jobs into wtab and the tiles' outer index bits into
 // otab (after launch_pass_prep of the pass); the same init / basis / dyn as the pass's
 // launch_fused_pass.

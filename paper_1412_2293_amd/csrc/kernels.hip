@@ -928,6 +928,19 @@ size_t reduce_partials_doubles(int n, int S)
     return a > b ? a : b;
 }
 
+hipError_t launch_overlap_final(const void *psi, qs_dtype dt, int n, int S, int log_blocks, int64_t marked,
+                                const double *partials, double *out, hipStream_t st, const RunParams *dyn)
+{
+    TimedLaunch tl("reduce", (double)((uint64_t)S << log_blocks) * 3 * sizeof(double), st);
+    if (dt == QS_C64)
+        hipLaunchKernelGGL(k_overlap_final<float>, dim3(S), dim3(kRedThreads), 0, st, (const float *)psi, n,
+                           log_blocks, marked, partials, out, dyn);
+    else
+        hipLaunchKernelGGL(k_overlap_final<double>, dim3(S), dim3(kRedThreads), 0, st, (const double *)psi, n,
+                           log_blocks, marked, partials, out, dyn);
+    return hipGetLastError();
+}
+
 hipError_t launch_overlaps(const void *ref_psi, int ref_slot, const void *psi, qs_dtype dt, int n,
                            int S, int64_t marked, double *partials, double *out, hipStream_t st,
                            const RunParams *dyn)

@@ -12,8 +12,8 @@ import pytest
 
 import oracle
 from oracle import fixed_rank
-from workloads import (CP, FLIP, NOISE_PHASE, NOISE_ROT, U1, Circuit, Gate, chain_heavy_circuit, grover,
-                       qft, random_layers, random_mixed_circuit)
+from workloads import (CP, FLIP, H_MATRIX, NOISE_PHASE, NOISE_ROT, U1, Circuit, Gate, chain_heavy_circuit,
+                       grover, qft, random_layers, random_mixed_circuit)
 
 from paper_forms import (eq10, first_layer_pairs, grover_p_ideal, pair_product_amplitudes,
                          pair_product_fidelity, qft_noisy_amplitudes)
@@ -690,3 +690,34 @@ def test_apply_kraus_rejects_bad_sets_before_device_work():
             q.apply_kraus(sv, qubits, ops)
         assert f"({code})" in str(ei.value), str(ei.value)
     assert np.array_equal(from_device(sv), before)
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+@pytest.mark.parametrize("T", [1, 6, 9])
+def test_fused_last_pass_overlaps_edge_cases(dtype, T):
+    """The fused runs form the overlaps with the ideal slot inside their last pass (the ideal
+    slot alone first, then the others tile-major); the unfused runs keep the separate reduction.
+    Covered: one noisy trajectory, slot counts that are not powers of two, programs whose only
+    pass is also the first (zero tiles outside the support), a marked amplitude."""
+    n = 9
+    circuits = [
+        Circuit(n, [Gate(U1, q0=3, m=H_MATRIX.copy(), noise=NOISE_ROT)], name="one-h", init_index=5),
+        Circuit(n, [Gate(U1, q0=q, m=H_MATRIX.copy(), noise=NOISE_ROT) for q in range(n)] +
+                [Gate(CP, q0=0, q1=4, theta=0.7, noise=NOISE_PHASE)], name="h-layer"),
+        qft(n, seed=3),
+    ]
+    marked = 13   # inside the support of the one-gate circuit (|5> and |13>)
+    for c in circuits:
+        c.marked = marked
+        F_ref, p_ref, ideal, states = oracle.run_trajectories(c, 0.1, 4, range(T), keep_states=True)
+        out = {}
+        for fuse in (0, 1):
+            out[fuse] = q.run_trajectories(c.gates, n, c.init_index, dtype, T, e=0.1, seed=4, marked=marked,
+                                           plan={"fuse": fuse, "tile_bits": 6, "reg_bits": 2, "run_bits": 2}
+                                           if fuse else {"fuse": 0})
+        for fuse, res in out.items():
+            assert np.max(np.abs(res["F"] - F_ref)) <= TOL[dtype], (c.name, fuse)
+            assert np.max(np.abs(res["p"] - p_ref)) <= TOL[dtype], (c.name, fuse)
+            norms = [np.vdot(s, s).real for s in states]
+            assert np.max(np.abs(res["norm"] - norms)) <= TOL[dtype] * 10, (c.name, fuse)
+        assert np.max(np.abs(out[1]["F"] - out[0]["F"])) <= TOL[dtype]
