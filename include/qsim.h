@@ -51,7 +51,15 @@ typedef enum {
     QS_EBUSY = -5         /* serving: admission refused (no free memory or slot)             */
 } qs_status;
 
-typedef enum { QS_C64 = 0, QS_C128 = 1 } qs_dtype;
+/* Amplitude type.  The two range markers make every 32-bit int a value of the type, so a
+ * caller's out-of-range value reaches the library's validation (QS_EINVAL, or 0 bytes) as a
+ * well-defined value; they are not valid arguments. */
+typedef enum {
+    QS_C64 = 0,
+    QS_C128 = 1,
+    QS_DTYPE_RANGE_MIN_ = -0x7fffffff - 1,
+    QS_DTYPE_RANGE_MAX_ = 0x7fffffff
+} qs_dtype;
 
 /* Gate kinds. */
 typedef enum {
@@ -158,6 +166,19 @@ qs_status qs_apply_kraus(qs_state rho, int k, const int32_t *qubits, int n_ops, 
  * where b = 1 when both qubits of the row (column) index are 1.
  * Asynchronous. */
 qs_status qs_dm_apply_gate(qs_state rho, const qs_gate *g, double e);
+
+/* Kraus pair of the noisy controlled phase theta with phase-noise strength e (Section 3.3),
+ * each operator times the ideal gate diag(1, 1, 1, exp(-i theta)), written to ops_out as two
+ * 4x4 complex matrices (64 doubles, row-major, (re, im) interleaved, local index
+ * bit(q0) + 2 bit(q1); the operators are diagonal).  With P = exp(-e^2):
+ *   improved = 0: eq. (9), E1 = diag(1, 1, 1, sqrt(P)), E2 = diag(0, 0, 0, sqrt(1 - P));
+ *   improved = 1: eq. (14), the eq. (9) pair mixed by the unitary of eq. (13) with
+ *     f = (sqrt(1 + 3P) - 1 - P) / sqrt(P (1 - P)) (0 at P = 1):
+ *     E1 = diag(1, 1, 1, sqrt(P) + f sqrt(1 - P)) / sqrt(1 + f^2),
+ *     E2 = diag(-f, -f, -f, sqrt(1 - P) - f sqrt(P)) / sqrt(1 + f^2).
+ * Both describe the same channel.  Errors: NULL ops_out, non-finite theta or e, e < 0, improved
+ * other than 0 or 1 (QS_EINVAL).  Host only, no device work. */
+qs_status qs_kraus_cp(double theta, double e, int improved, double *ops_out);
 
 /* F = |<a_ta|b_tb>|^2 / (<a|a><b|b>) in FP64 (Section 2, Fig. 1 uses 1 - F); both states must
  * have the same n and dtype.  overlap (nullable) receives <a|b> as two doubles.  Blocks. */
@@ -274,9 +295,19 @@ qs_status qs_fr_apply_gate(qs_fr fr, const qs_gate *g);
  * the new rank.  Blocks (the eigen-decomposition runs on the host). */
 qs_status qs_fr_apply_kraus(qs_fr fr, int q, int n_ops, const double *ops, double tau,
                             double zero_tol, int *rank_out);
+/* Two-qubit Kraus set (Section 3.2 with the two-qubit channels of Section 3.3, eq. 9 and
+ * eq. 14): n_ops <= 4 host 4x4 complex matrices, row-major, (re, im) interleaved, local index
+ * bit(q0) + 2 bit(q1), on the distinct qubits q0, q1.  The same step as qs_fr_apply_kraus over
+ * the 4r quarter-columns of the columns (Gram 32 x 32 in FP64, one read of the columns; the
+ * recombination in one read and one write).  Errors as qs_fr_apply_kraus; q0 == q1 is
+ * QS_EINVAL.  Blocks. */
+qs_status qs_fr_apply_kraus2(qs_fr fr, int q0, int q1, int n_ops, const double *ops, double tau,
+                             double zero_tol, int *rank_out);
 /* One circuit gate in the fixed-rank form: a ROT-tagged one-qubit gate U with e > 0 is the
- * Kraus step of qs_fr_apply_kraus with {U E1, U E2} of eq. (6); any other gate (noise
- * ignored) is qs_fr_apply_gate.  rank_out (nullable) gets the rank afterwards. */
+ * Kraus step of qs_fr_apply_kraus with {U E1, U E2} of eq. (6); a PHASE-tagged controlled
+ * phase with e > 0 is the two-qubit Kraus step of qs_fr_apply_kraus2 with the eq. (9) pair of
+ * qs_kraus_cp (improved = 0); any other gate (noise ignored) is qs_fr_apply_gate.  rank_out
+ * (nullable) gets the rank afterwards. */
 qs_status qs_fr_apply_noisy_gate(qs_fr fr, const qs_gate *g, double e, double tau,
                                  double zero_tol, int *rank_out);
 /* <psi|rho|psi>: f_unnorm = exp(log_trace) f_norm, f_norm with the stored unit-trace rho. */

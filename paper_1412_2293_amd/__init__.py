@@ -4,4 +4,4 @@ The work runs in the HIP kernels of libqsim.so behind the C ABI declared in incl
 this package only marshals arguments.  torch provides device memory and streams.
 """
 from .qsim import *  # noqa: F401,F403
-from .kraus import cp_kraus_improved, cp_mixing  # noqa: F401,E402
+from .kraus import cp_kraus, cp_kraus_improved  # noqa: F401,E402

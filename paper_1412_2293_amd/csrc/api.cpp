@@ -119,8 +119,12 @@ struct qs_fr_s {
     double log_trace;
     double *scratch;     // device: gram partials | gram out | coef | overlap partials | out | table
     size_t off_gram, off_coef, off_ovp, off_ovo, off_tab;
-    double *host;        // pinned staging: gram (512) + coef (512)
+    double *host;        // pinned staging: gram, then coef (kFrHostGram doubles each)
 };
+
+// Doubles of one Gram or coefficient matrix: 32 x 32 complex (two-qubit Kraus sets; a
+// one-qubit set uses the leading 16 x 16).
+constexpr size_t kFrHostGram = 32 * 32 * 2;
 
 static size_t state_bytes(int n, qs_dtype dt, int T) { return ((size_t)T << n) * amp_bytes(dt); }
 
@@ -1218,8 +1222,9 @@ qs_status qs_traj_graph_create(const qs_gate *gates, int n_gates, int n, qs_dtyp
     g->T = T;
     g->L = qs::prep_layout(g->prep, T);
     if (buf_bytes < g->L.total) {
+        const size_t need = g->L.total;
         delete g;
-        return fail(QS_EINVAL, "traj_graph_create: buffer too small (need " + std::to_string(g->L.total) + " bytes)");
+        return fail(QS_EINVAL, "traj_graph_create: buffer too small (need " + std::to_string(need) + " bytes)");
     }
     g->buf = (char *)dev_buf;
     const int S = T + 1;
@@ -1404,9 +1409,9 @@ qs_status qs_fr_create(int n, int r, qs_dtype dt, void *buf, size_t bytes, void 
     size_t off = 0;
     off += align256(fr_gram_partials_doubles(n, r) * 8) / 8;
     f->off_gram = off;
-    off += 512;
+    off += kFrHostGram;
     f->off_coef = off;
-    off += 512;
+    off += kFrHostGram;
     f->off_ovp = off;
     off += align256(reduce_partials_doubles(n, 8) * 8) / 8;
     f->off_ovo = off;
@@ -1418,7 +1423,7 @@ qs_status qs_fr_create(int n, int r, qs_dtype dt, void *buf, size_t bytes, void 
         delete f;
         return hip_fail(e, "fr_create: hipMalloc scratch");
     }
-    e = hipHostMalloc(&f->host, 1024 * sizeof(double), hipHostMallocDefault);
+    e = hipHostMalloc(&f->host, 2 * kFrHostGram * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
         (void)hipFree(f->scratch);
         delete f;
@@ -1460,45 +1465,49 @@ qs_status qs_fr_apply_gate(qs_fr f, const qs_gate *g)
     return sweep_gate(f->V, f->dt, f->n, f->rank, *g, nullptr, f->scratch + f->off_tab, f->st);
 }
 
-qs_status qs_fr_apply_kraus(qs_fr f, int q, int n_ops, const double *ops, double tau, double zero_tol,
-                            int *rank_out)
+}  // extern "C"
+
+// One Kraus step of the fixed-rank form (Section 3.2) for a set on k = 1 or 2 qubits: the Gram
+// matrix of the 2^k r sub-columns on the device, G = W^dagger W on the host, its FP64
+// eigen-decomposition, the truncation rule, and the recombination of the kept eigenvectors.
+static qs_status fr_kraus_step(qs_fr f, int k, const int32_t *qb, int n_ops, const double *ops, double tau,
+                               double zero_tol, int *rank_out, const char *who)
 {
-    clear_error();
-    if (!f || !ops) return fail(QS_EINVAL, "fr_apply_kraus: NULL argument");
-    if (f->rank < 1) return fail(QS_EINVAL, "fr_apply_kraus: call fr_init_basis first");
-    if (q < 0 || q >= f->n) return fail(QS_EINVAL, "fr_apply_kraus: qubit out of range");
-    if (n_ops < 1 || n_ops > 4) return fail(QS_EINVAL, "fr_apply_kraus: n_ops must be in 1..4");
-    if (!(tau >= 0) || !(zero_tol >= 0)) return fail(QS_EINVAL, "fr_apply_kraus: tau and zero_tol must be >= 0");
-    for (int i = 0; i < 8 * n_ops; ++i)
-        if (!std::isfinite(ops[i])) return fail(QS_EINVAL, "fr_apply_kraus: non-finite operator entry");
+    const int d = 1 << k;            // operator dimension
+    const int G = d * 8;             // sub-columns of the Gram matrix (column c < rank at x * 8 + c)
     const int rin = f->rank;
     double *gram_dev = f->scratch + f->off_gram;
-    QS_HIP(launch_fr_gram(f->V, f->dt, f->n, rin, q, f->scratch, gram_dev, f->st));
-    QS_HIP(hipMemcpyAsync(f->host, gram_dev, 512 * sizeof(double), hipMemcpyDeviceToHost, f->st));
+    if (k == 1) QS_HIP(launch_fr_gram(f->V, f->dt, f->n, rin, qb[0], f->scratch, gram_dev, f->st));
+    else QS_HIP(launch_fr_gram2(f->V, f->dt, f->n, rin, qb[0], qb[1], f->scratch, gram_dev, f->st));
+    QS_HIP(hipMemcpyAsync(f->host, gram_dev, (size_t)G * G * 2 * sizeof(double), hipMemcpyDeviceToHost, f->st));
     QS_HIP(hipStreamSynchronize(f->st));
-    // Gamma[(x, c), (y, d)] at index (x * 8 + c) * 16 + (y * 8 + d)
-    auto Gam = [&](int x, int c, int y, int d) {
-        size_t i = (size_t)(x * 8 + c) * 16 + (y * 8 + d);
+    // Gamma[(x, c), (y, d)] at index (x * 8 + c) * G + (y * 8 + d)
+    auto Gam = [&](int x, int c, int y, int dd) {
+        size_t i = (size_t)(x * 8 + c) * G + (y * 8 + dd);
         return cd(f->host[2 * i], f->host[2 * i + 1]);
     };
-    auto E = [&](int a, int r, int c) { return cd(ops[8 * a + 2 * (2 * r + c)], ops[8 * a + 2 * (2 * r + c) + 1]); };
+    const int dd2 = d * d;
+    auto E = [&](int a, int r, int c) {
+        const size_t i = (size_t)dd2 * a + (size_t)d * r + c;
+        return cd(ops[2 * i], ops[2 * i + 1]);
+    };
     const int m = n_ops * rin;
     std::vector<cd> GW((size_t)m * m);
+    std::vector<cd> C((size_t)dd2);   // (E_a^dagger E_b)[x][y]
     for (int a = 0; a < n_ops; ++a)
         for (int b = 0; b < n_ops; ++b) {
-            cd C[2][2];   // (E_a^dagger E_b)[x][y]
-            for (int x = 0; x < 2; ++x)
-                for (int y = 0; y < 2; ++y) {
-                    cd s = 0;
-                    for (int z = 0; z < 2; ++z) s += std::conj(E(a, z, x)) * E(b, z, y);
-                    C[x][y] = s;
+            for (int x = 0; x < d; ++x)
+                for (int y = 0; y < d; ++y) {
+                    cd acc = 0;
+                    for (int z = 0; z < d; ++z) acc += std::conj(E(a, z, x)) * E(b, z, y);
+                    C[(size_t)x * d + y] = acc;
                 }
             for (int c = 0; c < rin; ++c)
-                for (int d = 0; d < rin; ++d) {
-                    cd s = 0;
-                    for (int x = 0; x < 2; ++x)
-                        for (int y = 0; y < 2; ++y) s += C[x][y] * Gam(x, c, y, d);
-                    GW[(size_t)(a * rin + c) * m + (b * rin + d)] = s;
+                for (int e2 = 0; e2 < rin; ++e2) {
+                    cd acc = 0;
+                    for (int x = 0; x < d; ++x)
+                        for (int y = 0; y < d; ++y) acc += C[(size_t)x * d + y] * Gam(x, c, y, e2);
+                    GW[(size_t)(a * rin + c) * m + (b * rin + e2)] = acc;
                 }
         }
     std::vector<double> w;
@@ -1508,38 +1517,119 @@ qs_status qs_fr_apply_kraus(qs_fr f, int q, int n_ops, const double *ops, double
     for (int i = 0; i < m; ++i) order[i] = i;
     std::sort(order.begin(), order.end(), [&](int i, int j) { return w[i] > w[j]; });
     const double mu_max = w[order[0]];
-    if (!(mu_max > 0)) return fail(QS_EINVAL, "fr_apply_kraus: the Kraus step annihilated the state");
+    if (!(mu_max > 0)) return fail(QS_EINVAL, std::string(who) + ": the Kraus step annihilated the state");
     int nz = 0;
     for (int i = 0; i < m; ++i)
         if (w[order[i]] > zero_tol * mu_max) ++nz;
     int keep = std::min(nz, f->r);
     if (nz > f->r)
         while (keep > 0 && w[order[keep - 1]] - w[order[keep]] <= tau * mu_max) --keep;
-    if (keep < 1) return fail(QS_EINVAL, "fr_apply_kraus: tie cluster covers every kept eigenvalue");
+    if (keep < 1) return fail(QS_EINVAL, std::string(who) + ": tie cluster covers every kept eigenvalue");
     double kept = 0;
     for (int i = 0; i < keep; ++i) kept += w[order[i]];
     const double scale = 1.0 / std::sqrt(kept);
     // coef[(x' * 8 + k'), (y * 8 + c)] = sum_a Q[(a, c), k'] E_a[x'][y] / sqrt(kept)
-    double *coef = f->host + 512;
-    std::memset(coef, 0, 512 * sizeof(double));
-    for (int xo = 0; xo < 2; ++xo)
+    double *coef = f->host + kFrHostGram;
+    std::memset(coef, 0, (size_t)G * G * 2 * sizeof(double));
+    for (int xo = 0; xo < d; ++xo)
         for (int ko = 0; ko < keep; ++ko)
-            for (int y = 0; y < 2; ++y)
+            for (int y = 0; y < d; ++y)
                 for (int c = 0; c < rin; ++c) {
-                    cd s = 0;
-                    for (int a = 0; a < n_ops; ++a) s += Q[(size_t)(a * rin + c) * m + order[ko]] * E(a, xo, y);
-                    s *= scale;
-                    size_t i = (size_t)(xo * 8 + ko) * 16 + (y * 8 + c);
-                    coef[2 * i] = s.real();
-                    coef[2 * i + 1] = s.imag();
+                    cd acc = 0;
+                    for (int a = 0; a < n_ops; ++a) acc += Q[(size_t)(a * rin + c) * m + order[ko]] * E(a, xo, y);
+                    acc *= scale;
+                    size_t i = (size_t)(xo * 8 + ko) * G + (y * 8 + c);
+                    coef[2 * i] = acc.real();
+                    coef[2 * i + 1] = acc.imag();
                 }
     double *coef_dev = f->scratch + f->off_coef;
-    QS_HIP(hipMemcpyAsync(coef_dev, coef, 512 * sizeof(double), hipMemcpyHostToDevice, f->st));
-    QS_HIP(launch_fr_recombine(f->V, f->dt, f->n, rin, keep, q, coef_dev, f->st));
+    QS_HIP(hipMemcpyAsync(coef_dev, coef, (size_t)G * G * 2 * sizeof(double), hipMemcpyHostToDevice, f->st));
+    if (k == 1) QS_HIP(launch_fr_recombine(f->V, f->dt, f->n, rin, keep, qb[0], coef_dev, f->st));
+    else QS_HIP(launch_fr_recombine2(f->V, f->dt, f->n, rin, keep, qb[0], qb[1], coef_dev, f->st));
+    // the staging buffer is next written after the next step's synchronisation, which orders it
+    // after this upload
     f->rank = keep;
     f->log_trace += std::log(kept);
     if (rank_out) *rank_out = keep;
     return QS_OK;
+}
+
+static qs_status fr_check_kraus(qs_fr f, int k, const int32_t *qb, int n_ops, const double *ops, double tau,
+                                double zero_tol, const char *who)
+{
+    if (!f || !ops) return fail(QS_EINVAL, std::string(who) + ": NULL argument");
+    if (f->rank < 1) return fail(QS_EINVAL, std::string(who) + ": call fr_init_basis first");
+    for (int i = 0; i < k; ++i)
+        if (qb[i] < 0 || qb[i] >= f->n) return fail(QS_EINVAL, std::string(who) + ": qubit out of range");
+    if (k == 2 && qb[0] == qb[1]) return fail(QS_EINVAL, std::string(who) + ": the two qubits must differ");
+    if (n_ops < 1 || n_ops > 4) return fail(QS_EINVAL, std::string(who) + ": n_ops must be in 1..4");
+    if (!(tau >= 0) || !(zero_tol >= 0))
+        return fail(QS_EINVAL, std::string(who) + ": tau and zero_tol must be >= 0");
+    const int words = 2 * (1 << (2 * k)) * n_ops;
+    for (int i = 0; i < words; ++i)
+        if (!std::isfinite(ops[i])) return fail(QS_EINVAL, std::string(who) + ": non-finite operator entry");
+    return QS_OK;
+}
+
+// The noisy controlled phase's Kraus pair: eq. (9), or eq. (14) (the same channel, its operators
+// mixed by the unitary of eq. (13)), each times the ideal phase diag(1, 1, 1, e^{-i theta}).
+// P = exp(-e^2); f = (sqrt(1 + 3P) - 1 - P) / sqrt(P (1 - P)), 0 in the limit P -> 1.
+static void kraus_cp_ops(double theta, double e, int improved, double *out)
+{
+    std::memset(out, 0, 64 * sizeof(double));
+    const double P = std::exp(-e * e);
+    const cd u11(std::cos(theta), -std::sin(theta));
+    auto put = [&](int a, int i, cd v) {
+        out[32 * a + 2 * (5 * i)] = v.real();
+        out[32 * a + 2 * (5 * i) + 1] = v.imag();
+    };
+    if (!improved) {
+        for (int i = 0; i < 3; ++i) put(0, i, 1.0);
+        put(0, 3, u11 * std::sqrt(P));
+        put(1, 3, u11 * std::sqrt(1.0 - P));
+        return;
+    }
+    const double f = P >= 1.0 ? 0.0 : (std::sqrt(1.0 + 3.0 * P) - 1.0 - P) / std::sqrt(P * (1.0 - P));
+    const double norm = 1.0 / std::sqrt(1.0 + f * f);
+    for (int i = 0; i < 3; ++i) {
+        put(0, i, norm);
+        put(1, i, -f * norm);
+    }
+    put(0, 3, u11 * ((std::sqrt(P) + f * std::sqrt(1.0 - P)) * norm));
+    put(1, 3, u11 * ((std::sqrt(1.0 - P) - f * std::sqrt(P)) * norm));
+}
+
+extern "C" {
+
+qs_status qs_kraus_cp(double theta, double e, int improved, double *ops_out)
+{
+    clear_error();
+    if (!ops_out) return fail(QS_EINVAL, "kraus_cp: ops_out is NULL");
+    if (!std::isfinite(theta) || !std::isfinite(e) || e < 0)
+        return fail(QS_EINVAL, "kraus_cp: theta must be finite and e finite and >= 0");
+    if (improved != 0 && improved != 1) return fail(QS_EINVAL, "kraus_cp: improved must be 0 or 1");
+    kraus_cp_ops(theta, e, improved, ops_out);
+    return QS_OK;
+}
+
+qs_status qs_fr_apply_kraus(qs_fr f, int q, int n_ops, const double *ops, double tau, double zero_tol,
+                            int *rank_out)
+{
+    clear_error();
+    const int32_t qb[2] = {q, 0};
+    qs_status v = fr_check_kraus(f, 1, qb, n_ops, ops, tau, zero_tol, "fr_apply_kraus");
+    if (v != QS_OK) return v;
+    return fr_kraus_step(f, 1, qb, n_ops, ops, tau, zero_tol, rank_out, "fr_apply_kraus");
+}
+
+qs_status qs_fr_apply_kraus2(qs_fr f, int q0, int q1, int n_ops, const double *ops, double tau,
+                             double zero_tol, int *rank_out)
+{
+    clear_error();
+    const int32_t qb[2] = {q0, q1};
+    qs_status v = fr_check_kraus(f, 2, qb, n_ops, ops, tau, zero_tol, "fr_apply_kraus2");
+    if (v != QS_OK) return v;
+    return fr_kraus_step(f, 2, qb, n_ops, ops, tau, zero_tol, rank_out, "fr_apply_kraus2");
 }
 
 qs_status qs_fr_apply_noisy_gate(qs_fr f, const qs_gate *g, double e, double tau, double zero_tol,
@@ -1554,6 +1644,11 @@ qs_status qs_fr_apply_noisy_gate(qs_fr f, const qs_gate *g, double e, double tau
         double ops[16];
         kraus_rot_ops(g->m, e, ops);
         return qs_fr_apply_kraus(f, g->q0, 2, ops, tau, zero_tol, rank_out);
+    }
+    if (g->kind == QS_G_CP && e > 0 && g->noise == QS_NOISE_PHASE) {
+        double ops[64];
+        kraus_cp_ops(g->theta, e, 0, ops);
+        return qs_fr_apply_kraus2(f, g->q0, g->q1, 2, ops, tau, zero_tol, rank_out);
     }
     v = qs_fr_apply_gate(f, g);
     if (v == QS_OK && rank_out) *rank_out = f->rank;

@@ -280,6 +280,13 @@ hipError_t launch_fr_gram(const void *V, qs_dtype dt, int n, int r, int q, doubl
                           double *gram_out, hipStream_t st);
 hipError_t launch_fr_recombine(void *V, qs_dtype dt, int n, int r_in, int r_out, int q,
                                const double *coef_dev, hipStream_t st);
+// Two-qubit Kraus sets: Gram of the 4r quarter-columns on (q0, q1) (32 x 32 complex, entry
+// (x * 8 + c, y * 8 + d) with x = bit q0 + 2 bit q1) and the recombination with a 32 x 32
+// coefficient matrix.
+hipError_t launch_fr_gram2(const void *V, qs_dtype dt, int n, int r, int q0, int q1, double *partials,
+                           double *gram_out, hipStream_t st);
+hipError_t launch_fr_recombine2(void *V, qs_dtype dt, int n, int r_in, int r_out, int q0, int q1,
+                                const double *coef_dev, hipStream_t st);
 
 // ---------------------------------------------------------------------------------------
 // Kernel timing (HIP events around each launch while enabled).

@@ -24,7 +24,7 @@ __all__ = ["QsimError", "lib", "Gate", "Noise", "Plan", "C64", "C128", "gate_arr
            "sv_bytes_required", "StateVector", "apply_gate", "apply_kraus", "fidelity",
            "dm_fidelity", "dm_apply_gate", "noise_draw", "traj_bytes_required", "run_trajectories",
            "timing_enable", "timing_read", "plan_describe", "plan_choose", "traj_layout", "timing_reset", "copy", "FixedRank", "trajectory_states",
-           "fr_bytes_required", "TrajGraph", "Server", "SrvConfig", "SrvJobInfo", "SrvStats", "LIB_PATH"]
+           "fr_bytes_required", "kraus_cp", "TrajGraph", "Server", "SrvConfig", "SrvJobInfo", "SrvStats", "LIB_PATH"]
 
 
 class QsimError(RuntimeError):
@@ -114,6 +114,8 @@ def lib():
         "qs_fr_init_basis": ([P, u64], st),
         "qs_fr_apply_gate": ([P, ctypes.POINTER(Gate)], st),
         "qs_fr_apply_kraus": ([P, i32, i32, P, dbl, dbl, P], st),
+        "qs_fr_apply_kraus2": ([P, i32, i32, i32, P, dbl, dbl, P], st),
+        "qs_kraus_cp": ([dbl, dbl, i32, P], st),
         "qs_fr_fidelity": ([P, P, i32, P, P, P], st),
         "qs_fr_info": ([P, P, P, P], st),
         "qs_traj_graph_bytes_required": ([P, i32, i32, i32, i32, ctypes.POINTER(Plan), ctypes.POINTER(sz)], st),
@@ -391,6 +393,14 @@ def copy(dst, src, nbytes: int, stream=None):
     _check(lib().qs_copy(_ptr(dst), _ptr(src), int(nbytes), _stream(stream)), "copy")
 
 
+def kraus_cp(theta: float, e: float, improved: bool = False) -> np.ndarray:
+    """(2, 4, 4) complex128: the noisy controlled phase's Kraus pair built by the library
+    (qs_kraus_cp: eq. 9, or eq. 14 when improved)."""
+    out = np.zeros((2, 4, 4), np.complex128)
+    _check(lib().qs_kraus_cp(float(theta), float(e), int(improved), _ptr(out.view(np.float64))), "kraus_cp")
+    return out
+
+
 def fr_bytes_required(n: int, r: int, dtype: int) -> int:
     return int(lib().qs_fr_bytes_required(n, r, dtype))
 
@@ -433,6 +443,13 @@ class FixedRank:
         rank = ctypes.c_int()
         _check(lib().qs_fr_apply_kraus(self.h, int(q), ops.shape[0], _ptr(ops.view(np.float64)),
                                        float(tau), float(zero_tol), ctypes.byref(rank)), "fr_apply_kraus")
+        return rank.value
+
+    def apply_kraus2(self, q0: int, q1: int, ops, tau: float = 1e-9, zero_tol: float = 1e-13) -> int:
+        ops = np.ascontiguousarray(np.asarray(ops, np.complex128))
+        rank = ctypes.c_int()
+        _check(lib().qs_fr_apply_kraus2(self.h, int(q0), int(q1), ops.shape[0], _ptr(ops.view(np.float64)),
+                                        float(tau), float(zero_tol), ctypes.byref(rank)), "fr_apply_kraus2")
         return rank.value
 
     def apply_noisy_gate(self, g, e: float, tau: float = 1e-9, zero_tol: float = 1e-13) -> int:

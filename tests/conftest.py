@@ -8,6 +8,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+# A host-sanitizer run (tests/test_host_sanitizers.py) points the binding at the ASan/UBSan
+# build of the library.
+if os.environ.get("QSIM_TEST_LIB"):
+    import paper_1412_2293_amd.qsim as _qsim
+    _qsim.LIB_PATH = os.environ["QSIM_TEST_LIB"]
+
+
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")

@@ -177,15 +177,25 @@ def test_per_trajectory_noise_strength():
 # Full-size QFT (n = 26, 64 trajectories per e in one launch): the per-trajectory product
 # closed form, evaluated with the oracle's noise draws, pins every fidelity and sampled
 # amplitudes.
-@pytest.mark.parametrize("dtype", [q.C64, q.C128])
-def test_qft26_full_size_against_closed_form(dtype):
+#
+# The unfused cases (one sweep kernel per gate) use enough slots that the sweeps' grids reach
+# their 2^21-block cap and every thread block walks the state in its grid-stride loop: the dense
+# one-qubit sweep takes 512 work items per block, 2^25 (complex<double>) or 2^24
+# (complex<float>, two amplitudes per item) per slot, so 41 and 73 slots need 41 * 2^16 and
+# 73 * 2^15 blocks; the two-qubit sweeps (256 items per block, 2^24 or 2^23 per slot) the same.
+@pytest.mark.parametrize("dtype,fuse,T", [(q.C64, 1, 128), (q.C128, 1, 16), (q.C64, 0, 72), (q.C128, 0, 40)],
+                         ids=["c64-fused", "c128-fused", "c64-unfused", "c128-unfused"])
+def test_qft26_full_size_against_closed_form(dtype, fuse, T):
     n = 26
     c = qft(n, seed=1)
-    T = 128 if dtype == q.C64 else 16
     es = np.array([0.001] * (T // 2) + [0.01] * (T // 2))
     seed = 1
-    print(f"qft26 {NAMES[dtype]} T={T}", flush=True)
-    res = q.run_trajectories(c.gates, n, c.init_index, dtype, T, e=es, seed=seed, plan={"fuse": 1})
+    if fuse == 0:
+        items_per_block = 512
+        per_slot = (1 << (n - 1)) // (2 if dtype == q.C64 else 1)
+        assert (T + 1) * per_slot // items_per_block > (1 << 21)   # the grid-stride loop runs
+    print(f"qft26 {NAMES[dtype]} fuse={fuse} T={T}", flush=True)
+    res = q.run_trajectories(c.gates, n, c.init_index, dtype, T, e=es, seed=seed, plan={"fuse": fuse})
     sites = [g.site for g in c.gates]
     xi = oracle.normals(seed, sites, np.arange(T, dtype=np.uint32))
     st = q.trajectory_states(res, n, dtype, T)
@@ -201,7 +211,7 @@ def test_qft26_full_size_against_closed_form(dtype):
             assert abs(res["F"][t] - F_cf) <= 1e-12 * F_cf, (t, res["F"][t], F_cf)
         else:
             assert abs(res["F"][t] - F_cf) <= 1e-5, (t, res["F"][t], F_cf)
-        if t % 16 == 0:
+        if t % 16 == 0 or t == T - 1:
             amps = st[t + 1].index_select(0, phys_t).cpu().numpy().astype(np.complex128)
             ref = amp_cf
             assert np.max(np.abs(amps - ref)) <= (1e-14 if dtype == q.C128 else 2e-8) , t
@@ -442,13 +452,10 @@ def test_fixed_rank_r8_against_oracle(dtype):
 @pytest.mark.parametrize("dtype", [q.C128, q.C64])
 def test_fixed_rank_complex_amplitudes_against_oracle(dtype):
     """Haar-random one-qubit gates make every amplitude complex, so the imaginary part of the
-    Gram matrix (and its orientation) matters; Grover alone stays real."""
-    from workloads import NOISE_NONE
+    Gram matrix (and its orientation) matters; Grover alone stays real.  The CZs keep their
+    phase noise: each is a two-qubit Kraus step (eq. 9) with truncation."""
     n, e, r = 9, 0.05, 8
     c = random_layers(n, 3, seed=12, pairing="random")
-    for g in c.gates:
-        if g.kind == CP:
-            g.noise = NOISE_NONE      # the fixed-rank form takes Kraus steps on one-qubit gates
     tau = 1e-9
     zt = 1e-13 if dtype == q.C128 else 1e-6
     fr = q.FixedRank(n, r, dtype)

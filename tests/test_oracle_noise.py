@@ -166,11 +166,19 @@ def test_improved_cp_kraus_is_the_orthogonal_form_of_eq9():
 
 
 def test_library_improved_cp_kraus_matches_the_oracle():
-    """The operators the library's callers pass to apply_kraus (package side) equal the
-    oracle's eq. (14) set."""
+    """The operators the library builds behind the C ABI (qs_kraus_cp, host-only) equal the
+    oracle's eq. (9) and eq. (14) sets."""
     import paper_1412_2293_amd as q
     rng = np.random.default_rng(9)
     for e in [0.0, 0.02, 0.2, 1.5]:
         for theta in [0.0, 1.0, float(rng.uniform(0, 2 * math.pi))]:
             np.testing.assert_allclose(q.cp_kraus_improved(theta, e), oracle.kraus_phase_improved(theta, e),
                                        atol=1e-15)
+            np.testing.assert_allclose(q.cp_kraus(theta, e), oracle.kraus_phase(theta, e), atol=1e-15)
+
+
+def test_library_cp_kraus_rejects_bad_arguments():
+    import paper_1412_2293_amd as q
+    for args in [(math.nan, 0.1, 0), (0.0, -0.1, 0), (0.0, math.inf, 1), (0.0, 0.1, 2)]:
+        with pytest.raises(q.QsimError):
+            q.kraus_cp(args[0], args[1], args[2])

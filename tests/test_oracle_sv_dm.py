@@ -190,6 +190,16 @@ def test_fixed_rank_full_rank_equals_exact_dm():
     np.testing.assert_allclose(fr.rho(), oracle.dm_run(c, e), atol=1e-12)
 
 
+def test_fixed_rank_full_rank_noisy_qft_equals_exact_dm():
+    """Every controlled phase a two-qubit Kraus step (eq. 9), every Hadamard a one-qubit one
+    (eq. 6): at a rank bound above the reachable rank nothing is truncated, so the factored rho
+    is the exact density matrix (which the closed-form QFT noise average pins)."""
+    c = qft(4, seed=1)
+    fr = fixed_rank.run_circuit(c, 0.3, r=256)
+    np.testing.assert_allclose(fr.rho(), oracle.dm_run(c, 0.3), atol=1e-13)
+    assert max(fr.ranks) > 2
+
+
 @pytest.mark.parametrize("n,e", [(5, 0.2), (8, 0.05), (10, 0.01)])
 def test_fixed_rank_rank1_grover_is_eq10(n, e):
     c = grover(n, seed=2)
