@@ -184,6 +184,20 @@ qs_status qs_kraus_cp(double theta, double e, int improved, double *ops_out);
  * have the same n and dtype.  overlap (nullable) receives <a|b> as two doubles.  Blocks. */
 qs_status qs_fidelity(qs_state a, int ta, qs_state b, int tb, double *f, double *overlap);
 
+/* Allocation-free form of qs_fidelity's reductions, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no handle, no hipMalloc or hipFree, no allocating library call.  a_dev and b_dev are two
+ * caller-owned device state vectors of n_qubits (1..34) qubits in dtype dt; out_dev (device,
+ * 4 doubles, caller-owned) receives Re <a|b>, Im <a|b>, <a|a>, <b|b> in FP64, the same sums in the
+ * same order as qs_fidelity (F = |<a|b>|^2 / (<a|a> <b|b>)).  The partial sums live in a fixed
+ * 16.1 KiB device array of the library (one copy per GPU, held until the process ends); a call
+ * enqueues on hip_stream and returns without waiting.  Calls that overlap on one GPU (other
+ * streams or host threads) race on that array; calls on one stream are ordered.  Errors:
+ * NULL pointers, unknown dtype, n_qubits outside 1..34 (QS_EINVAL), a failed HIP call
+ * (QS_EDEVICE). */
+qs_status qs_fidelity_noalloc(const void *a_dev, const void *b_dev, int n_qubits, qs_dtype dt,
+                              void *hip_stream, double *out_dev);
+
 /* <psi|rho|psi> = sum_ij conj(psi_i) rho_ij psi_j and Tr rho, FP64 (Section 3).  rho as in
  * qs_apply_kraus, psi trajectory tpsi of an n-qubit state of the same dtype.  Blocks. */
 qs_status qs_dm_fidelity(qs_state rho, qs_state psi, int tpsi, double *f, double *trace);

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqsim.so")
 
-SOURCES = ["kernels.hip", "fused.hip", "fr.hip", "api.cpp", "planner.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "fused.hip", "fr.hip", "noalloc.hip", "api.cpp", "planner.cpp", "serve.cpp"]
 ARCH = "gfx950"
 
 

@@ -22,7 +22,7 @@ NOISE_NONE, NOISE_ROT, NOISE_PHASE = 0, 1, 2
 
 __all__ = ["QsimError", "lib", "Gate", "Noise", "Plan", "C64", "C128", "gate_array",
            "sv_bytes_required", "StateVector", "apply_gate", "apply_kraus", "fidelity",
-           "dm_fidelity", "dm_apply_gate", "noise_draw", "traj_bytes_required", "run_trajectories",
+           "dm_fidelity", "fidelity_noalloc", "dm_apply_gate", "noise_draw", "traj_bytes_required", "run_trajectories",
            "timing_enable", "timing_read", "plan_describe", "plan_choose", "traj_layout", "timing_reset", "copy", "FixedRank", "trajectory_states",
            "fr_bytes_required", "kraus_cp", "TrajGraph", "Server", "SrvConfig", "SrvJobInfo", "SrvStats", "LIB_PATH"]
 
@@ -116,6 +116,7 @@ def lib():
         "qs_fr_apply_kraus": ([P, i32, i32, P, dbl, dbl, P], st),
         "qs_fr_apply_kraus2": ([P, i32, i32, i32, P, dbl, dbl, P], st),
         "qs_kraus_cp": ([dbl, dbl, i32, P], st),
+        "qs_fidelity_noalloc": ([P, P, i32, i32, P, P], st),
         "qs_fr_fidelity": ([P, P, i32, P, P, P], st),
         "qs_fr_info": ([P, P, P, P], st),
         "qs_traj_graph_bytes_required": ([P, i32, i32, i32, i32, ctypes.POINTER(Plan), ctypes.POINTER(sz)], st),
@@ -260,6 +261,13 @@ def fidelity(a: StateVector, ta: int, b: StateVector, tb: int):
     ov = np.zeros(2)
     _check(lib().qs_fidelity(a.h, ta, b.h, tb, ctypes.byref(f), _ptr(ov)), "fidelity")
     return f.value, complex(ov[0], ov[1])
+
+
+def fidelity_noalloc(a, b, n: int, dtype: int, out, stream=None):
+    """qs_fidelity_noalloc on device buffers a, b (torch tensors of one state each) into the
+    device tensor out (4 float64: Re <a|b>, Im <a|b>, <a|a>, <b|b>); asynchronous."""
+    _check(lib().qs_fidelity_noalloc(_ptr(a), _ptr(b), int(n), int(dtype), _stream(stream), _ptr(out)),
+           "fidelity_noalloc")
 
 
 def dm_fidelity(rho: StateVector, psi: StateVector, tpsi: int = 0):
