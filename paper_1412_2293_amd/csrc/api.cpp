@@ -4,6 +4,7 @@
 #include <atomic>
 #include <cmath>
 #include <complex>
+#include <memory>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -762,6 +763,30 @@ qs_status check_circuit(const qs_gate *gates, int n_gates, int n)
 
 namespace qs {
 
+// Prepared runs of recently seen circuits: the plan choice and the fused program are pure
+// functions of (gates, n, dtype, plan request), so a repeated call reuses them instead of
+// planning again.  Keyed by those inputs byte for byte; a small first-in first-out set.
+namespace {
+struct PrepCache {
+    std::mutex mu;
+    std::vector<std::pair<std::string, std::shared_ptr<const TrajPrep>>> entries;
+    static constexpr size_t kMax = 16;
+};
+PrepCache &prep_cache()
+{
+    static PrepCache c;
+    return c;
+}
+std::string prep_key(const qs_gate *gates, int n_gates, int n, qs_dtype dt, const qs_plan *plan)
+{
+    const qs_plan pl = plan ? *plan : qs_plan{-1, 0, 0, 0};
+    const int32_t head[8] = {n, (int32_t)dt, n_gates, pl.fuse, pl.tile_bits, pl.reg_bits, pl.run_bits, plan ? 1 : 0};
+    std::string k((const char *)head, sizeof head);
+    if (n_gates > 0) k.append((const char *)gates, sizeof(qs_gate) * (size_t)n_gates);
+    return k;
+}
+}  // namespace
+
 qs_status traj_prepare(const qs_gate *gates, int n_gates, int n, qs_dtype dt, const qs_plan *plan,
                        TrajPrep &prep)
 {
@@ -769,6 +794,30 @@ qs_status traj_prepare(const qs_gate *gates, int n_gates, int n, qs_dtype dt, co
     if (dt != QS_C64 && dt != QS_C128) return fail(QS_EINVAL, "run_trajectories: unknown dtype");
     qs_status v = check_circuit(gates, n_gates, n);
     if (v != QS_OK) return v;
+    const std::string key = prep_key(gates, n_gates, n, dt, plan);
+    {
+        PrepCache &c = prep_cache();
+        std::lock_guard<std::mutex> lk(c.mu);
+        for (auto &e : c.entries)
+            if (e.first == key) {
+                prep = *e.second;
+                return QS_OK;
+            }
+    }
+    v = traj_prepare_uncached(gates, n_gates, n, dt, plan, prep);
+    if (v != QS_OK) return v;
+    auto shared = std::make_shared<const TrajPrep>(prep);
+    PrepCache &c = prep_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (c.entries.size() >= PrepCache::kMax) c.entries.erase(c.entries.begin());
+    c.entries.emplace_back(key, std::move(shared));
+    return QS_OK;
+}
+
+qs_status traj_prepare_uncached(const qs_gate *gates, int n_gates, int n, qs_dtype dt, const qs_plan *plan,
+                                TrajPrep &prep)
+{
+    qs_status v;
     Plan pl;
     if ((v = resolve_plan(gates, n_gates, n, dt, 1, plan, pl)) != QS_OK) return v;
     prep.n = n;
@@ -1077,6 +1126,8 @@ qs_status qs_plan_describe(const qs_gate *gates, int n_gates, int n, qs_dtype dt
         I("rec_size", pd.rec_size);
         I("load_round", pd.load_round);
         I("load_reg_mask", P.rounds[pd.load_round].reg_mask);
+        I("store_round", pd.store_round);
+        I("store_reg_mask", P.rounds[pd.store_round].reg_mask);
         I("round_begin", pd.round_begin);
         I("round_end", pd.round_end);
         I("op_begin", pd.op_begin);

@@ -135,9 +135,13 @@ __device__ constexpr int quad_base(int k)
 }
 
 // PRE: input phase kind (0 none, 1 one factor per thread, 2 with register-bit factors); POST:
-// whether the folded output block is present.  They are uniform per op, so each combination
-// is its own straight-line code behind a scalar branch, with no work for an absent block.
-template <typename R, int RB, int P, int PRE, bool POST>
+// whether the folded output block is present.  ZIN: which input of every pair is known to be
+// zero (0 neither; 1 the |1> input, 2 the |0> input) -- the target qubit has not been touched by
+// any earlier gate of the run and still holds the basis bit 0 (1), so that half of the tile is
+// exactly zero and its products are left out (the result is the same: a product with zero
+// added to a value leaves the value).  They are uniform per op, so each combination is its own
+// straight-line code behind a scalar branch, with no work for an absent block.
+template <typename R, int RB, int P, int PRE, bool POST, int ZIN>
 __device__ __forceinline__ void apply_u1(tv<R> (&a)[1 << RB], const cxf<R> (&m)[4],
                                          const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
@@ -146,9 +150,20 @@ __device__ __forceinline__ void apply_u1(tv<R> (&a)[1 << RB], const cxf<R> (&m)[
         const int r = pair_base<P>(k);
         const int r1 = r | (1 << P);
         cxf<R> x0 = cx<R>(a[r]), x1 = cx<R>(a[r1]);
-        if constexpr (PRE > 0) x1 = mul(pair_phase<R, RB, P, PRE == 2>(pre, r), x1);
-        cxf<R> y0 = fma_c(m[1], x1, mul(m[0], x0));
-        cxf<R> y1 = fma_c(m[3], x1, mul(m[2], x0));
+        cxf<R> y0, y1;
+        if constexpr (ZIN == 1) {
+            y0 = mul(m[0], x0);
+            y1 = mul(m[2], x0);
+        } else {
+            if constexpr (PRE > 0) x1 = mul(pair_phase<R, RB, P, PRE == 2>(pre, r), x1);
+            if constexpr (ZIN == 2) {
+                y0 = mul(m[1], x1);
+                y1 = mul(m[3], x1);
+            } else {
+                y0 = fma_c(m[1], x1, mul(m[0], x0));
+                y1 = fma_c(m[3], x1, mul(m[2], x0));
+            }
+        }
         if constexpr (POST) y1 = mul(pair_phase<R, RB, P, true>(post, r), y1);
         a[r] = tvec(y0);
         a[r1] = tvec(y1);
@@ -156,7 +171,7 @@ __device__ __forceinline__ void apply_u1(tv<R> (&a)[1 << RB], const cxf<R> (&m)[
 }
 
 // The same update with a real matrix (m[k].im == 0): half the multiplications.
-template <typename R, int RB, int P, int PRE, bool POST>
+template <typename R, int RB, int P, int PRE, bool POST, int ZIN>
 __device__ __forceinline__ void apply_u1_real(tv<R> (&a)[1 << RB], const cxf<R> (&m)[4],
                                               const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
@@ -166,9 +181,20 @@ __device__ __forceinline__ void apply_u1_real(tv<R> (&a)[1 << RB], const cxf<R> 
         const int r = pair_base<P>(k);
         const int r1 = r | (1 << P);
         cxf<R> x0 = cx<R>(a[r]), x1 = cx<R>(a[r1]);
-        if constexpr (PRE > 0) x1 = mul(pair_phase<R, RB, P, PRE == 2>(pre, r), x1);
-        cxf<R> y0 = {m0 * x0.re + m1 * x1.re, m0 * x0.im + m1 * x1.im};
-        cxf<R> y1 = {m2 * x0.re + m3 * x1.re, m2 * x0.im + m3 * x1.im};
+        cxf<R> y0, y1;
+        if constexpr (ZIN == 1) {
+            y0 = {m0 * x0.re, m0 * x0.im};
+            y1 = {m2 * x0.re, m2 * x0.im};
+        } else {
+            if constexpr (PRE > 0) x1 = mul(pair_phase<R, RB, P, PRE == 2>(pre, r), x1);
+            if constexpr (ZIN == 2) {
+                y0 = {m1 * x1.re, m1 * x1.im};
+                y1 = {m3 * x1.re, m3 * x1.im};
+            } else {
+                y0 = {m0 * x0.re + m1 * x1.re, m0 * x0.im + m1 * x1.im};
+                y1 = {m2 * x0.re + m3 * x1.re, m2 * x0.im + m3 * x1.im};
+            }
+        }
         if constexpr (POST) y1 = mul(pair_phase<R, RB, P, true>(post, r), y1);
         a[r] = tvec(y0);
         a[r1] = tvec(y1);
@@ -202,37 +228,52 @@ __device__ __forceinline__ void apply_u2(tv<R> (&a)[1 << RB], const cxf<R> (&m)[
 // Dispatch on the target register bit.  There is no pass-through branch (the last position
 // is the fall-back): every path rewrites the register tile, which lets the register allocator
 // keep the tile in the same registers across ops instead of copying it at each merge.
-template <typename R, int RB, int PRE, bool POST>
+template <typename R, int RB, int PRE, bool POST, int ZIN>
 __device__ __forceinline__ void dispatch_u1_pp(int p, bool real, tv<R> (&a)[1 << RB], const cxf<R> (&m)[4],
                                                const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
     if (real) {
-        if (RB > 1 && p == 0) apply_u1_real<R, RB, 0, PRE, POST>(a, m, pre, post);
-        else if (RB > 2 && p == 1) apply_u1_real<R, RB, 1 % RB, PRE, POST>(a, m, pre, post);
-        else if (RB > 3 && p == 2) apply_u1_real<R, RB, 2 % RB, PRE, POST>(a, m, pre, post);
-        else apply_u1_real<R, RB, RB - 1, PRE, POST>(a, m, pre, post);
+        if (RB > 1 && p == 0) apply_u1_real<R, RB, 0, PRE, POST, ZIN>(a, m, pre, post);
+        else if (RB > 2 && p == 1) apply_u1_real<R, RB, 1 % RB, PRE, POST, ZIN>(a, m, pre, post);
+        else if (RB > 3 && p == 2) apply_u1_real<R, RB, 2 % RB, PRE, POST, ZIN>(a, m, pre, post);
+        else apply_u1_real<R, RB, RB - 1, PRE, POST, ZIN>(a, m, pre, post);
         return;
     }
-    if (RB > 1 && p == 0) apply_u1<R, RB, 0, PRE, POST>(a, m, pre, post);
-    else if (RB > 2 && p == 1) apply_u1<R, RB, 1 % RB, PRE, POST>(a, m, pre, post);
-    else if (RB > 3 && p == 2) apply_u1<R, RB, 2 % RB, PRE, POST>(a, m, pre, post);
-    else apply_u1<R, RB, RB - 1, PRE, POST>(a, m, pre, post);
+    if (RB > 1 && p == 0) apply_u1<R, RB, 0, PRE, POST, ZIN>(a, m, pre, post);
+    else if (RB > 2 && p == 1) apply_u1<R, RB, 1 % RB, PRE, POST, ZIN>(a, m, pre, post);
+    else if (RB > 3 && p == 2) apply_u1<R, RB, 2 % RB, PRE, POST, ZIN>(a, m, pre, post);
+    else apply_u1<R, RB, RB - 1, PRE, POST, ZIN>(a, m, pre, post);
 }
 
+// zin: 0 general, 1 the |1> inputs are zero (no input phase to apply), 2 the |0> inputs are zero.
 template <typename R, int RB>
-__device__ __forceinline__ void dispatch_u1(int p, bool real, int prekind, tv<R> (&a)[1 << RB],
+__device__ __forceinline__ void dispatch_u1(int p, bool real, int prekind, int zin, tv<R> (&a)[1 << RB],
                                             const cxf<R> (&m)[4], const PhaseSet<R, RB> &pre,
                                             const PhaseSet<R, RB> &post)
 {
-    if (prekind == 2) {
-        if (post.any) dispatch_u1_pp<R, RB, 2, true>(p, real, a, m, pre, post);
-        else dispatch_u1_pp<R, RB, 2, false>(p, real, a, m, pre, post);
+    if (zin == 1) {
+        if (post.any) dispatch_u1_pp<R, RB, 0, true, 1>(p, real, a, m, pre, post);
+        else dispatch_u1_pp<R, RB, 0, false, 1>(p, real, a, m, pre, post);
+    } else if (zin == 2) {
+        if (prekind == 2) {
+            if (post.any) dispatch_u1_pp<R, RB, 2, true, 2>(p, real, a, m, pre, post);
+            else dispatch_u1_pp<R, RB, 2, false, 2>(p, real, a, m, pre, post);
+        } else if (prekind == 1) {
+            if (post.any) dispatch_u1_pp<R, RB, 1, true, 2>(p, real, a, m, pre, post);
+            else dispatch_u1_pp<R, RB, 1, false, 2>(p, real, a, m, pre, post);
+        } else {
+            if (post.any) dispatch_u1_pp<R, RB, 0, true, 2>(p, real, a, m, pre, post);
+            else dispatch_u1_pp<R, RB, 0, false, 2>(p, real, a, m, pre, post);
+        }
+    } else if (prekind == 2) {
+        if (post.any) dispatch_u1_pp<R, RB, 2, true, 0>(p, real, a, m, pre, post);
+        else dispatch_u1_pp<R, RB, 2, false, 0>(p, real, a, m, pre, post);
     } else if (prekind == 1) {
-        if (post.any) dispatch_u1_pp<R, RB, 1, true>(p, real, a, m, pre, post);
-        else dispatch_u1_pp<R, RB, 1, false>(p, real, a, m, pre, post);
+        if (post.any) dispatch_u1_pp<R, RB, 1, true, 0>(p, real, a, m, pre, post);
+        else dispatch_u1_pp<R, RB, 1, false, 0>(p, real, a, m, pre, post);
     } else {
-        if (post.any) dispatch_u1_pp<R, RB, 0, true>(p, real, a, m, pre, post);
-        else dispatch_u1_pp<R, RB, 0, false>(p, real, a, m, pre, post);
+        if (post.any) dispatch_u1_pp<R, RB, 0, true, 0>(p, real, a, m, pre, post);
+        else dispatch_u1_pp<R, RB, 0, false, 0>(p, real, a, m, pre, post);
     }
 }
 
@@ -484,8 +525,6 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     constexpr int NR = 1 << RB;
     const PassDesc *pd = prog.passes + pass_index;
     const int K = pd->K;
-    const int TB = K - RB;
-    const uint32_t kmask = (1u << K) - 1u;
     // A run starts in the basis state |basis>, and a physical qubit no non-diagonal gate has
     // touched still holds its basis value (controlled phases only rescale), so only the tiles
     // that agree with it on the pass's classical bits hold amplitude, and inside a tile only the
@@ -523,10 +562,24 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
 
     // Outer (tile-number) bits of the physical index, written for this launch by k_pass_jobs.
     const uint64_t outer = otab[tile];
-    // Load layout: thread bits = tile-local bits 0..TB-1, register bits = TB..K-1.
+    // Load (and store) layout: the register bits are the tile-local bits of its round
+    // descriptor's mask, the thread id fills the others, lowest first.  lthr0: the thread's
+    // tile-local index bits in that layout (a zero bit inserted at each register bit).
+    const uint32_t load_mask = prog.rounds[pd->load_round].reg_mask;
     uint64_t gthr = outer;
-    for (int j = 0; j < TB; ++j)
-        if ((tid >> j) & 1u) gthr |= 1ull << pd->q_pos[j];
+    uint32_t lthr0 = tid;
+    {
+        uint32_t m = load_mask;
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            const uint32_t b = (uint32_t)__builtin_ctz(m);
+            const uint32_t lo = lthr0 & ((1u << b) - 1u);
+            lthr0 = ((lthr0 ^ lo) << 1) | lo;
+            m &= m - 1u;
+        }
+        for (int j = 0; j < K; ++j)
+            if ((lthr0 >> j) & 1u) gthr |= 1ull << pd->q_pos[j];
+    }
     uint64_t greg[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) greg[r] = pd->reg_off[r];
@@ -553,15 +606,15 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
 #pragma unroll
         for (int r = 0; r < NR; ++r) a[r] = tv<R>{(gthr | greg[r]) == (uint64_t)init ? (R)1 : (R)0, (R)0};
     } else {
-        // read only the amplitudes that can be nonzero: tile-local index tid | r << TB agrees
+        // read only the amplitudes that can be nonzero: tile-local index lthr0 | roff[r] agrees
         // with the basis index on the tile-local classical bits (thread part per lane, register
         // part uniform)
         const uint32_t lc = pd->lclassical;
-        const uint32_t tmask = (1u << TB) - 1u;
-        const bool tok = ((tid ^ blocal) & lc & tmask) == 0;
+        const bool tok = ((lthr0 ^ blocal) & lc & ~load_mask) == 0;
+        const RoundDesc *ld = prog.rounds + pd->load_round;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const bool rok = ((((uint32_t)r << TB) ^ blocal) & lc & ~tmask) == 0;
+            const bool rok = ((ld->roff[r] ^ blocal) & lc & load_mask) == 0;
             a[r] = tv<R>{(R)0, (R)0};
             if (rok && tok) {
                 const uint64_t i = gthr | greg[r];
@@ -571,8 +624,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     }
 
     // Register layout: tile-local index of register r of this thread = lthr | roff[r], with
-    // roff from the current round's descriptor (cur_ri; the load layout has the thread id in the
-    // low bits).  LDS addresses: swz(lthr | roff[r]) = swz(lthr) ^ swz(roff[r]); the register
+    // roff from the current round's descriptor (cur_ri; at first the load layout's).  LDS addresses: swz(lthr | roff[r]) = swz(lthr) ^ swz(roff[r]); the register
     // part is the descriptor's sroff (one scalar load of 16 words), so each access costs one
     // XOR.  The tile sits at the start of the dynamic LDS, addressed directly.
     constexpr uint32_t CXS = sizeof(cxf<R>);
@@ -587,12 +639,11 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
         const v2 v = *reinterpret_cast<const lds_v2 *>((size_t)byte);
         return cxf<R>{v.x, v.y};
     };
-    const uint32_t load_mask = (((1u << RB) - 1u) << TB) & kmask;
     uint32_t cur = load_mask;
     // current register layout as an index into the rounds array: loads through the kernel
     // argument with a uniform index stay scalar
     int cur_ri = pd->load_round;
-    uint32_t lthr = tid;
+    uint32_t lthr = lthr0;
 
     auto exchange_to = [&](uint32_t to, int ri) {
         __syncthreads();
@@ -646,9 +697,12 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                     const int prer = op->pre_rec, postr = op->post_rec;
                     const int prej = op->pre_job, postj = op->post_job;
                     // a target qubit no earlier gate has touched holds the basis bit: when that
-                    // bit is 0 every |1> input is zero, and its input phase has nothing to do
-                    const bool zero_in = ((op->creg >> op->p0) & 1u) &&
-                                         !(blocal & prog.rounds[cur_ri].roff[1 << op->p0]);
+                    // bit is 0 every |1> input is zero (and its input phase has nothing to do),
+                    // when it is 1 every |0> input
+                    const bool untouched = ((op->creg >> op->p0) & 1u) != 0;
+                    const bool bit1 = (blocal & prog.rounds[cur_ri].roff[1 << op->p0]) != 0;
+                    const bool zero_in = untouched && !bit1;
+                    const int zin = untouched ? (bit1 ? 2 : 1) : 0;
                     int prekind;
                     if (zero_in) {
                         pre.any = false;
@@ -666,7 +720,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                     }
                     load_phases<R, RB>(post, rec + postr, rec + postr, postr >= 0, true,
                                        UNI && (flags & OPF_POST_UNI) != 0, postj, wout, tid);
-                    dispatch_u1<R, RB>(op->p0, (flags & OPF_REAL) != 0, prekind, a, m, pre, post);
+                    dispatch_u1<R, RB>(op->p0, (flags & OPF_REAL) != 0, prekind, zin, a, m, pre, post);
                 } else if (type == OP_U2) {
                     cxf<R> m[16];
 #pragma unroll
@@ -688,10 +742,37 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
             }
         }
     }
-    if (cur != load_mask) exchange_to(load_mask, pd->load_round);
+    // Slot 0's amplitudes for the overlaps, loaded before the last exchange so that their latency
+    // overlaps it (slot 0 is final before a launch of the other slots; these loads precede this
+    // block's own stores).
+    // The tile is stored in the pass's store layout: the last round's when the planner chose
+    // it (no exchange back), else the load layout.
+    const int st_ri = pd->store_round;
+    uint64_t gst = gthr;
+    if (st_ri != pd->load_round) {
+        uint32_t x = tid, m = prog.rounds[st_ri].reg_mask;
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            const uint32_t b = (uint32_t)__builtin_ctz(m);
+            const uint32_t lo = x & ((1u << b) - 1u);
+            x = ((x ^ lo) << 1) | lo;
+            m &= m - 1u;
+        }
+        gst = outer;
+        for (int j = 0; j < K; ++j)
+            if ((x >> j) & 1u) gst |= 1ull << pd->q_pos[j];
+    }
+    tv<R> refv[NR];
+    const bool pre_ref = ovl != nullptr && slot != 0;
+    if (pre_ref) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            refv[r] = *reinterpret_cast<const tv<R> *>(psi + 2 * (gst | pd->store_off[r]));
+    }
+    if (cur != prog.rounds[st_ri].reg_mask) exchange_to(prog.rounds[st_ri].reg_mask, st_ri);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        uint64_t i = gthr | pd->reg_off[r];
+        uint64_t i = gst | pd->store_off[r];
         if constexpr (sizeof(R) == 4) {
             typedef float f2 __attribute__((ext_vector_type(2)));
             __builtin_nontemporal_store(a[r], reinterpret_cast<f2 *>(base + 2 * i));
@@ -703,36 +784,58 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     if (ovl) {
         // This tile's share of <psi_0|psi_slot> and <psi_slot|psi_slot> in FP64: the same sums
         // as the separate overlap reduction, one partial per (slot, tile).
-        const R *ref = psi;
         double v[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const uint64_t i = gthr | pd->reg_off[r];
-            const tv<R> e = slot == 0 ? a[r] : *reinterpret_cast<const tv<R> *>(ref + 2 * i);
+            const tv<R> e = pre_ref ? refv[r] : a[r];
             const double ar = e.x, ai = e.y, br = a[r].x, bi = a[r].y;
             v[0] += ar * br + ai * bi;
             v[1] += ar * bi - ai * br;
             v[2] += br * br + bi * bi;
         }
-        // wave sums (a block of fewer than 64 threads is one partial wave: sum over its lanes)
-        const int width = nthr < 64u ? (int)nthr : 64;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            for (int off = width >> 1; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, width);
-        if (nthr <= 64u) {
-            if (tid == 0)
-                for (int k = 0; k < 3; ++k) ovl[bidx * 3 + k] = v[k];
-        } else {
-            // the tile's LDS (at least 2 KiB here) is free once every wave has left the last exchange
+        // Block sums.  With more than one wave, every thread leaves its three sums in the LDS
+        // (the tile's LDS, free once every wave has left the last exchange, holds three doubles
+        // per thread when a thread keeps at least 16 bytes of amplitudes) and the first wave adds
+        // them up, so the other waves finish without any cross-lane work.  A block of at most
+        // one wave (or with too little LDS per thread) sums over its lanes, then over waves.
+        constexpr bool kLdsSums = (sizeof(R) << (RB + 1)) >= 3 * sizeof(double);
+        if (kLdsSums && nthr > 64u) {
             __syncthreads();
             double *sh = reinterpret_cast<double *>(smem);
-            if ((tid & 63u) == 0)
-                for (int k = 0; k < 3; ++k) sh[(tid >> 6) * 3 + k] = v[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) sh[k * nthr + tid] = v[k];
             __syncthreads();
-            if (tid < 3) {
-                double t = 0.0;
-                for (uint32_t w = 0; w < (nthr >> 6); ++w) t += sh[w * 3 + tid];
-                ovl[bidx * 3 + tid] = t;
+            if (tid < 64u) {
+                double t[3] = {0.0, 0.0, 0.0};
+                for (uint32_t j = tid; j < nthr; j += 64u)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) t[k] += sh[k * nthr + j];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    for (int off = 32; off > 0; off >>= 1) t[k] += __shfl_xor(t[k], off, 64);
+                if (tid == 0)
+                    for (int k = 0; k < 3; ++k) ovl[bidx * 3 + k] = t[k];
+            }
+        } else {
+            // wave sums (a block of fewer than 64 threads is one partial wave: sum over its lanes)
+            const int width = nthr < 64u ? (int)nthr : 64;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                for (int off = width >> 1; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, width);
+            if (nthr <= 64u) {
+                if (tid == 0)
+                    for (int k = 0; k < 3; ++k) ovl[bidx * 3 + k] = v[k];
+            } else {
+                __syncthreads();
+                double *sh = reinterpret_cast<double *>(smem);
+                if ((tid & 63u) == 0)
+                    for (int k = 0; k < 3; ++k) sh[(tid >> 6) * 3 + k] = v[k];
+                __syncthreads();
+                if (tid < 3) {
+                    double t = 0.0;
+                    for (uint32_t w = 0; w < (nthr >> 6); ++w) t += sh[w * 3 + tid];
+                    ovl[bidx * 3 + tid] = t;
+                }
             }
         }
     }

@@ -55,12 +55,15 @@ struct RoundDesc {
     uint16_t thi[16];             // tile-local bits of thread-id bits 5..8, indexed by tid >> 5
 };
 
-// LDS slot of tile-local index l: the low five bits are xor-ed with a fold of the higher bits,
-// a bijection that spreads strided accesses over the banks.  It is linear over XOR, so for
+// LDS slot of tile-local index l: the low four bits are xor-ed with the higher nibbles of l, a
+// bijection (the high bits are unchanged) that spreads the accesses of a register layout over
+// the banks: a 64-bit access serves 16 lanes per cycle, whose slots differ in the low four bits
+// whenever the layout's four lowest thread bits lie in different positions of their nibbles
+// (every layout of a contiguous register run, for instance).  It is linear over XOR, so for
 // disjoint thread and register bits lds_swizzle(t | r) = lds_swizzle(t) ^ lds_swizzle(r).
 __host__ __device__ inline uint32_t lds_swizzle(uint32_t l)
 {
-    return l ^ (((l >> 5) ^ (l >> 10)) & 31u);
+    return l ^ ((l >> 4) & 15u) ^ ((l >> 8) & 15u) ^ ((l >> 12) & 15u);
 }
 
 struct PassDesc {
@@ -86,8 +89,12 @@ struct PassDesc {
                                   // (needed unless the last pass rewrites every amplitude)
     int32_t uni_kernel;           // run the kernel variant with uniform factors for blocks
                                   // without thread-conditioned phases (most blocks are such)
-    uint64_t reg_off[16];         // load layout: physical index bits of register r (its RB bits
-                                  // are the top RB tile-local bits)
+    uint64_t reg_off[16];         // load layout: physical index bits of register r
+    int32_t store_round;          // index in the rounds array of the layout the tile is stored
+                                  // in: the pass's last round when its layout keeps the low run
+                                  // bits in the thread id, else the load layout
+    int32_t reserved2;
+    uint64_t store_off[16];       // store layout: physical index bits of register r
 };
 
 // A stage: consecutive rounds whose records, outer jobs and outer bits stay within the
@@ -335,6 +342,10 @@ struct TrajPrep {
     std::vector<qs_gate> hg;       // device image of the gates (CNOT carries its 4x4 matrix)
     std::vector<int32_t> layout;   // logical qubit -> physical bit after the SWAP relabelling
 };
+// Validate and plan a trajectory run (cached per circuit, dtype and plan request);
+// traj_prepare_uncached always plans.
+qs_status traj_prepare_uncached(const qs_gate *gates, int n_gates, int n, qs_dtype dt, const qs_plan *plan,
+                                TrajPrep &prep);
 
 // One enqueued batch: `host` receives S*5 doubles (per slot: Re and Im of the overlap with the
 // ideal slot, squared norm, Re and Im of the marked amplitude) when the stream reaches the copy.

@@ -294,16 +294,11 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         for (int j = 0; j < K; ++j)
             if (!((touched >> Q[j]) & 1ull)) pd.lclassical |= 1u << j;
         for (int q : pb.targets) touched |= 1ull << q;
-        for (int r = 0; r < 16; ++r) {
-            uint64_t off = 0;
-            for (int k = 0; k < RB; ++k)
-                if (r < (1 << RB) && ((r >> k) & 1)) off |= 1ull << Q[K - RB + k];
-            pd.reg_off[r] = off;
-        }
         uint32_t lcls = pd.lclassical;   // tile-local bits untouched so far in this pass
         const uint32_t kmask = (1u << K) - 1u;
-        const uint32_t load_mask = ((1u << RB) - 1u) << (K - RB);
-        const RoundDesc load_rd = make_round(load_mask, K);
+        // register layout the rounds are padded towards (the top tile-local bits)
+        const uint32_t top_mask = ((1u << RB) - 1u) << (K - RB);
+        const uint32_t load_mask = top_mask;
 
         // greedy register rounds, closed also when the current stage reaches its bounds
         auto fill = [&](uint32_t need) {
@@ -377,6 +372,32 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         }
         for (auto &rd : rounds)
             if (!rd.forced) rd.forced = fill(rd.need);
+        // The layout the tile is loaded and stored in: the first round's, or else the last
+        // round's, when it keeps the low run bits in the thread id (so that consecutive lanes
+        // still read and write contiguous rows of 2^run_bits amplitudes); that saves the exchange
+        // into the first round or out of the last.  Otherwise the top tile-local bits.
+        // The tile is stored from the last round's layout under the same condition, which saves
+        // the exchange back.
+        uint32_t io_mask = top_mask;
+        const uint32_t run_mask = whole ? 0u : ((1u << std::min(run_bits, K)) - 1u);
+        const bool last_ok = (rounds.back().forced & run_mask) == 0;
+        if ((rounds.front().forced & run_mask) == 0) io_mask = rounds.front().forced;
+        else if (last_ok) io_mask = rounds.back().forced;
+        const uint32_t st_mask = last_ok ? rounds.back().forced : io_mask;
+        const RoundDesc load_rd = make_round(io_mask, K);
+        auto phys_offsets = [&](uint32_t mask, uint64_t (&off)[16]) {
+            int regpos[16], nr = 0;
+            for (int j = 0; j < K; ++j)
+                if ((mask >> j) & 1u) regpos[nr++] = j;
+            for (int r = 0; r < 16; ++r) {
+                uint64_t o = 0;
+                for (int k = 0; k < nr; ++k)
+                    if (r < (1 << RB) && ((r >> k) & 1)) o |= 1ull << Q[regpos[k]];
+                off[r] = o;
+            }
+        };
+        phys_offsets(io_mask, pd.reg_off);
+        phys_offsets(st_mask, pd.store_off);
         pd.stage_begin = (int)P.stages.size();
         pd.load_round = (int)P.rounds.size();
         P.rounds.push_back(load_rd);
@@ -561,6 +582,7 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         }
         pd.stage_end = (int)P.stages.size();
         pd.round_end = (int)P.rounds.size();
+        pd.store_round = st_mask == io_mask ? pd.load_round : pd.round_end - 1;
         pd.op_end = (int)P.ops.size();
         pd.job_end = (int)P.jobs.size();
         pd.rec_size = rec;

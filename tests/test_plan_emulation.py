@@ -233,8 +233,23 @@ def test_program_ranges_are_consistent():
                 # the pass's load layout is the rounds-array entry just before its rounds
                 assert pas["load_round"] == round_at
                 K = len(pas["q_pos"])
-                rb = bin(pas["load_reg_mask"]).count("1")
-                assert rb >= 1 and pas["load_reg_mask"] == ((1 << rb) - 1) << (K - rb)
+                # the load/store layout: RB register bits, none of them among the low run bits
+                # (consecutive lanes cover contiguous rows), and the first or the last round's
+                # layout when that one qualifies
+                lm = pas["load_reg_mask"]
+                assert bin(lm).count("1") == prog["RB"] and lm < (1 << K)
+                whole = K == c.n
+                run_mask = 0 if whole else (1 << min(prog["run_bits"], K)) - 1
+                assert lm & run_mask == 0
+                rmasks = [rd["reg_mask"] for st in pas["stages"] for rd in st["rounds"]]
+                if rmasks[0] & run_mask == 0:
+                    assert lm == rmasks[0]
+                elif rmasks[-1] & run_mask == 0:
+                    assert lm == rmasks[-1]
+                # stored from the last round's layout when that one qualifies, else the load one
+                sm = pas["store_reg_mask"]
+                assert sm & run_mask == 0
+                assert sm == (rmasks[-1] if rmasks[-1] & run_mask == 0 else lm)
                 round_at += 1
                 assert pas["op_begin"] == op_at and pas["round_begin"] == round_at
                 assert pas["job_begin"] == job_at
