@@ -75,7 +75,8 @@ def main():
     import paper_1412_2293_amd as q
     from workloads import qft
 
-    leg_names = ("large_state_n32", "graph_replay", "dm13", "dm_qft13", "fr24", "fr_vs_dm12", "choi", "sweeps_n28")
+    leg_names = ("large_state_n32", "graph_replay", "dm13", "dm_qft13", "fr24", "fr_vs_dm12", "choi", "sweeps_n28",
+                 "grover12_dynamics", "grover10_c1", "serving_full_range", "fr24_full")
     if a.leg and a.leg not in leg_names:
         print(f"unknown leg {a.leg}; one of {', '.join(leg_names)}", file=sys.stderr)
         sys.exit(2)
@@ -84,7 +85,11 @@ def main():
         legs = {"large_state_n32": lambda: large_state_bench(q, torch), "graph_replay": lambda: graph_bench(q, torch),
                 "dm13": lambda: dm13_bench(q, torch), "dm_qft13": lambda: dm_qft13_bench(q, torch),
                 "fr24": lambda: fr24_bench(q, torch), "fr_vs_dm12": lambda: fr_vs_dm12_bench(q, torch),
-                "choi": lambda: choi_bench(q, torch), "sweeps_n28": lambda: sweeps(q)}
+                "choi": lambda: choi_bench(q, torch), "sweeps_n28": lambda: sweeps(q),
+                "grover12_dynamics": lambda: grover12_dynamics_bench(q, torch),
+                "grover10_c1": lambda: grover10_c1_bench(q, torch),
+                "serving_full_range": lambda: serving_full_range_bench(q, torch),
+                "fr24_full": lambda: fr24_bench(q, torch, iterations=None)}
         print(json.dumps({a.leg: legs[a.leg]()}), flush=True)
         return
     n, Te = a.n, a.traj_per_e
@@ -189,10 +194,16 @@ def main():
         torch.cuda.empty_cache()
         out["fr_vs_dm12"] = fr_vs_dm12_bench(q, torch)
         torch.cuda.empty_cache()
+        out["grover12_dynamics"] = grover12_dynamics_bench(q, torch)
+        torch.cuda.empty_cache()
         out["choi"] = choi_bench(q, torch)
+        torch.cuda.empty_cache()
+        out["grover10_c1"] = grover10_c1_bench(q, torch)
         torch.cuda.empty_cache()
         if a.serving_requests > 0:
             out["serving"] = serving_bench(q, torch, a.serving_requests, a.serving_inflight)
+            torch.cuda.empty_cache()
+            out["serving_full_range"] = serving_full_range_bench(q, torch)
             torch.cuda.empty_cache()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c)
@@ -521,6 +532,83 @@ def fr_vs_dm12_bench(q, torch, ranks=(1, 2, 4, 8)):
             "trace_dm": tr, "dm_wall_s": t_dm, "by_rank": rows}
 
 
+def grover_dynamics(q, n, e, seed, ranks=(1, 2, 4, 8), T=256, keep=8):
+    """The marked-state probability after every Grover iteration (Section 3.2, the comparison of
+    the paper's 12-qubit figure): the exact density matrix (vec(rho), every noisy Hadamard its
+    eq. (6) Kraus channel), the fixed-rank form at several ranks (unnormalised and normalised),
+    and Monte Carlo trajectories (eq. 1), whose state after iteration k is the same circuit cut
+    after that iteration (the noise counters are the gates' positions, so a prefix replays the
+    trajectory's first k iterations exactly).  Beside them eq. (10), lambda_1^(n + 2nk) times the
+    ideal probability, which rank 1 reproduces."""
+    import math
+
+    import numpy as np
+    from workloads import grover
+    c = grover(n, seed=seed)
+    j = c.meta["iterations"]
+    per = 2 * n + 2
+    ends = [n + k * per for k in range(j + 1)]     # gate count after iteration k (k = 0: after H^n)
+    ga = q.gate_array(c.gates)
+    w = q.StateVector(n, q.C128, 1)
+    w.init_basis(c.marked)
+    lam1 = 0.5 * (1.0 + math.exp(-2.0 * e * e))
+    p_ideal = [math.sin((2 * k + 1) * math.asin(2.0 ** (-n / 2))) ** 2 for k in range(j + 1)]
+    eq10 = [lam1 ** (n + 2 * n * k) * p_ideal[k] for k in range(j + 1)]
+    t0 = time.perf_counter()
+    rho = q.StateVector(2 * n, q.C128, 1)
+    rho.init_basis(0)
+    p_dm, g0 = [], 0
+    for end in ends:
+        for g in ga[g0:end]:
+            q.dm_apply_gate(rho, g, e)
+        g0 = end
+        p_dm.append(q.dm_fidelity(rho, w, 0)[0])
+    rho.close()
+    t_dm = time.perf_counter() - t0
+    fr_rows = []
+    for r in ranks:
+        fr = q.FixedRank(n, r, q.C128)
+        fr.init_basis(0)
+        pu, pn, g0 = [], [], 0
+        for end in ends:
+            for g in ga[g0:end]:
+                fr.apply_noisy_gate(g, e)
+            g0 = end
+            fu, fn, _ = fr.fidelity(w)
+            pu.append(fu)
+            pn.append(fn)
+        fr_rows.append({"r": r, "p_unnormalised": pu, "p_normalised": pn})
+        fr.close()
+    w.close()
+    t0 = time.perf_counter()
+    mc_mean, mc_sem, mc_traj = [], [], []
+    for end in ends:
+        res = q.run_trajectories(ga[:end], n, c.init_index, q.C128, T, e=e, seed=seed, marked=c.marked)
+        p = np.asarray(res["p"])
+        mc_mean.append(float(p.mean()))
+        mc_sem.append(float(p.std(ddof=1) / math.sqrt(T)))
+        mc_traj.append([float(x) for x in p[:keep]])
+    t_mc = time.perf_counter() - t0
+    return {"n": n, "e": e, "iterations": j, "marked": c.marked, "p_ideal": p_ideal, "eq10": eq10,
+            "p_dm": p_dm, "fixed_rank": fr_rows, "mc_trajectories": T, "mc_mean": mc_mean, "mc_sem": mc_sem,
+            "mc_first_trajectories": [list(x) for x in zip(*mc_traj)], "dm_wall_s": t_dm, "mc_wall_s": t_mc}
+
+
+def grover12_dynamics_bench(q, torch):
+    """grover_dynamics on the paper's case: n = 12, e = 0.01, r = 1, 2, 4, 8, 256 trajectories."""
+    log("[bench] grover12 dynamics")
+    d = grover_dynamics(q, 12, 0.01, seed=12)
+    last = d["iterations"]
+    d["summary"] = {
+        "final_p_dm": d["p_dm"][last], "final_mc_mean": d["mc_mean"][last], "final_eq10": d["eq10"][last],
+        "final_fixed_rank": {row["r"]: [row["p_unnormalised"][last], row["p_normalised"][last]]
+                             for row in d["fixed_rank"]},
+        "max_unnormalised_minus_dm": max(u - p for row in d["fixed_rank"]
+                                         for u, p in zip(row["p_unnormalised"], d["p_dm"])),
+    }
+    return d
+
+
 def choi_bench(q, torch):
     """Choi-Jamiolkowski relative states (Section 4) on the density-matrix path: the three-qubit
     phase-error code against the phase-error probability p, with eq. (18) beside it (the paper
@@ -591,7 +679,8 @@ def fr24_bench(q, torch, iterations=10):
     steps = sum(1 for g in c.gates if g.kind == 0)
     full_steps = n + 2 * n * grover_iterations(n)
     per_step = (t1 - t0) / steps
-    out = {"workload": f"grover{n} prefix: {iterations} iterations, r={r}, complex64 columns, e={e}",
+    part = "full circuit" if iterations is None else f"prefix: {iterations} iterations"
+    out = {"workload": f"grover{n} {part} (j={c.meta['iterations']}), r={r}, complex64 columns, e={e}",
            "kraus_steps": steps, "wall_s": t1 - t0, "ms_per_kraus_step": per_step * 1e3,
            "max_rank": max(ranks), "p_marked_unnormalised": fu, "p_marked_normalised": fn,
            "log_trace": lt, "full_circuit_kraus_steps": full_steps,
@@ -602,12 +691,15 @@ def fr24_bench(q, torch, iterations=10):
             out[k] = {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"], "GB/s": round(gbs, 1),
                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
     if kr["fr_gram"]["launches"]:
-        # Gram of the 2r half-columns: 1088 FP64 flops per amplitude index at r = 8 (the 136
-        # independent entries of a Hermitian 16 x 16, 4 real multiply-adds each), FP64 matrix peak
+        # Gram of the 2r half-columns on the FP64 matrix cores: three real 16 x 16 x 4 products
+        # per four pairs, 768 flops per amplitude index executed (mfma_frac against the FP64
+        # matrix peak); the method's own count is 544 (the 136 independent entries of a
+        # Hermitian 16 x 16, four real multiply-adds each, per pair of indices)
         g = kr["fr_gram"]
-        tf = 1088.0 * (1 << n) / (g["ms"] / g["launches"] / 1e3) / 1e12
-        out["fr_gram"].update({"alg_TFLOPs": round(tf, 2), "fp64_peak_TFLOPs": FP64_PEAK_TFLOPS,
-                               "mfma_frac": round(tf / FP64_PEAK_TFLOPS, 4)})
+        sec = g["ms"] / g["launches"] / 1e3
+        tf = 768.0 * (1 << n) / sec / 1e12
+        out["fr_gram"].update({"mfma_TFLOPs": round(tf, 2), "alg_TFLOPs": round(544.0 * (1 << n) / sec / 1e12, 2),
+                               "fp64_peak_TFLOPs": FP64_PEAK_TFLOPS, "mfma_frac": round(tf / FP64_PEAK_TFLOPS, 4)})
     fr.close()
     w.close()
     return out
@@ -649,6 +741,90 @@ def serving_bench(q, torch, n_requests, inflight):
     return out
 
 
+def grover10_c1_bench(q, torch, T=200, runs=10):
+    """The plain method at CPU size (Fig. 1): Grover n = 10 (marked index from seed 0, 25
+    iterations), 200 noisy trajectories with the eq. (1) rotation after every Hadamard (e = 0.01,
+    Philox seed 0) and the ideal circuit in one launch (the whole state sits in one tile), in
+    complex<double>.  Median of `runs` timed runs after 3 warm-ups; the distribution of 1 - F
+    over the trajectories, eq. (10) and the rigorous lower bound lambda_1^(n + 2nj) beside the
+    mean marked probability."""
+    import math
+
+    import numpy as np
+    from workloads import grover
+    c = grover(10, seed=0)
+    ga = q.gate_array(c.gates)
+    e, seed = 0.01, 0
+    plan = {"fuse": -1}
+    chosen = q.plan_choose(ga, c.n, q.C128)[0]
+    need = q.traj_bytes_required(ga, c.n, q.C128, T, plan)
+    buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+    log("[bench] grover10 C1 (200 trajectories)")
+    for _ in range(3):
+        q.run_trajectories(ga, c.n, c.init_index, q.C128, T, e=e, seed=seed, plan=plan, marked=c.marked, buf=buf)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        res = q.run_trajectories(ga, c.n, c.init_index, q.C128, T, e=e, seed=seed, plan=plan, marked=c.marked,
+                                 buf=buf)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    F, p = np.asarray(res["F"]), np.asarray(res["p"])
+    j = c.meta["iterations"]
+    lam1 = 0.5 * (1.0 + math.exp(-2.0 * e * e))
+    p_ideal = math.sin((2 * j + 1) * math.asin(2.0 ** (-c.n / 2))) ** 2
+    hist, edges = np.histogram(1.0 - F, bins=12)
+    return {"workload": f"grover10 (j={j}, marked {c.marked}), {T} trajectories + ideal, e={e}, complex128, one launch",
+            "plan": chosen, "median_s": dt, "trajectories_per_s": T / dt,
+            "amplitude_updates_per_s": c.amplitude_updates() * T / dt,
+            "F_mean": float(F.mean()), "p_mean": float(p.mean()), "p_ideal": p_ideal,
+            "eq10": lam1 ** (c.n + 2 * c.n * j) * p_ideal, "lower_bound_lambda1_pow": lam1 ** (c.n + 2 * c.n * j),
+            "one_minus_F_hist": {"counts": hist.tolist(), "edges": [float(x) for x in edges]}}
+
+
+def serving_full_range_bench(q, torch, inflight=4, first=60, max_model_s=1.0, pool_gib=32):
+    """The serving stream over its full qubit range [12, 28]: of the first `first` requests of the
+    seeded stream (seed 3, in arrival order) every one whose modelled time (the library's cost
+    model, qs_plan_choose, times its T + 1 slots) is under max_model_s; the others (Grover and
+    random layers at n >= 22, up to minutes each) are listed.  The pool is small enough that the
+    large requests split into batches and wait for memory (admission waits)."""
+    from paper_1412_2293_amd import serving
+    from workloads import serving_stream
+    reqs = serving_stream(seed=3)[:first]
+    keep, skipped, model_total = [], [], 0.0
+    for r in reqs:
+        c = r.circuit()
+        s = q.plan_choose(q.gate_array(c.gates), c.n, q.C64)[1] * (r.T + 1)
+        if s <= max_model_s:
+            keep.append(r)
+            model_total += s
+        else:
+            skipped.append({"index": r.index, "kind": r.kind, "n": r.n, "T": r.T, "model_s": round(s, 1)})
+    log(f"[bench] serving full range: {len(keep)} of {first} requests (n up to 28), pool {pool_gib} GiB")
+    P = serving.prepare(keep, q.C64)
+    pool_bytes = pool_gib << 30
+    pool = torch.empty(pool_bytes, dtype=torch.uint8, device="cuda")
+    cfg = dict(pool_bytes=pool_bytes, dtype=q.C64, max_inflight=inflight, max_chunk_traj=256, pool=pool)
+    with q.Server(**cfg) as srv:
+        serving.replay(srv, P[:4], rate=None)
+    with q.Server(**cfg) as srv:
+        cal = serving.replay(srv, P, rate=None)["summary"]
+    rate = cal["requests_per_s"]
+    with q.Server(**cfg) as srv:
+        main = serving.replay(srv, P, rate=0.8 * rate)
+    del pool
+    recs = main["records"]
+    return {"workload": f"requests of the first {first} of the seeded serving stream (seed 3, n uniform in [12, 28]) "
+                        f"with modelled time <= {max_model_s} s: {len(keep)} kept, n up to {max(r.n for r in keep)}, "
+                        "Poisson arrivals at 0.8x the sustainable rate, complex64, FP64 fidelities",
+            "pool_bytes": pool_bytes, "max_inflight": inflight, "modelled_s": model_total, "skipped": skipped,
+            "calibration": cal, "arrival_rate_per_s": 0.8 * rate, "summary": main["summary"],
+            "largest": sorted(({"n": r["n"], "kind": r["kind"], "T": r["T"], "chunks": r["chunks"],
+                                "latency_s": round(r["latency_s"], 3), "queue_s": round(r["queue_s"], 3)}
+                               for r in recs), key=lambda x: -x["n"])[:6]}
+
+
 def cpu_baseline(c, prefix=None):
     """The CPU oracle, single thread, on a bounded sample of the workload: one noisy trajectory
     (e = 0.01) of the same circuit (all gates unless `prefix` is given), run as one oracle
@@ -666,6 +842,7 @@ def cpu_baseline(c, prefix=None):
     oracle.sv_run(part, 0.01, seed=1, traj=64)
     dt = time.perf_counter() - t0
     return {"value": updates / dt, "unit": "amplitude-updates/s", "cores": 1, "kind": "oracle",
+            "host_cores": os.cpu_count(),
             "sample": f"qft{n} trajectory 64 (e=0.01): first {prefix} of {len(c.gates)} gates "
                       f"({part.count(0)} H, {part.count(1)} controlled phases), complex128 plain "
                       f"loops, {dt:.1f} s"}
