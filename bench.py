@@ -76,7 +76,7 @@ def main():
     from workloads import qft
 
     leg_names = ("large_state_n32", "graph_replay", "dm13", "dm_qft13", "fr24", "fr_vs_dm12", "choi", "sweeps_n28",
-                 "grover12_dynamics", "grover10_c1", "serving_full_range", "fr24_full")
+                 "grover12_dynamics", "grover10_c1", "serving_full_range", "fr24_full", "block_rounds_n30")
     if a.leg and a.leg not in leg_names:
         print(f"unknown leg {a.leg}; one of {', '.join(leg_names)}", file=sys.stderr)
         sys.exit(2)
@@ -89,7 +89,8 @@ def main():
                 "grover12_dynamics": lambda: grover12_dynamics_bench(q, torch),
                 "grover10_c1": lambda: grover10_c1_bench(q, torch),
                 "serving_full_range": lambda: serving_full_range_bench(q, torch),
-                "fr24_full": lambda: fr24_bench(q, torch, iterations=None)}
+                "fr24_full": lambda: fr24_bench(q, torch, iterations=None),
+                "block_rounds_n30": lambda: block_rounds_bench(q, torch)}
         print(json.dumps({a.leg: legs[a.leg]()}), flush=True)
         return
     n, Te = a.n, a.traj_per_e
@@ -306,58 +307,105 @@ def sweeps(q):
     return out
 
 
-def large_state_bench(q, torch, prefix_layers=2):
+def large_state_bench(q, torch, prefixes=(2, 4)):
     """One large state: n = 32 complex64 (32 GiB per slot), 40 layers of Haar one-qubit gates
-    and brickwork CZ, e = 0.005, 4 trajectories + ideal (160 GiB), automatic plan, run in full.
-    Beside it the first `prefix_layers` layers as per-gate sweeps and as fused passes, which
-    gives the per-layer speed-up without a 100-second unfused run."""
+    and brickwork CZ, e = 0.005, 4 trajectories + ideal (160 GiB), run in full twice: fused passes
+    op by op on the vector ALUs (automatic plan) and fused passes whose register rounds run as
+    dense 16 x 16 blocks on the FP32 matrix cores (mfma = 1).  Beside them the first 2 and 4
+    layers as per-gate sweeps and as fused passes: the difference of the two prefixes is the
+    per-layer time past the first layers (where a basis-state start still leaves tiles empty),
+    whose ratio is the steady-state speed-up of fusion over per-gate sweeps."""
     import numpy as np
     from workloads import Circuit, random_layers
     n, depth, T, e, seed = 32, 40, 4, 0.005, 4
     c = random_layers(n, depth, seed, pairing="brickwork")
     ga = q.gate_array(c.gates)
     plan = q.plan_choose(ga, n, q.C64)[0]
-    need = q.traj_bytes_required(ga, n, q.C64, T)
+    need = q.traj_bytes_required(ga, n, q.C64, T, {"fuse": 1, "mfma": 1})
+    need = max(need, q.traj_bytes_required(ga, n, q.C64, T))
     log(f"[bench] large state n={n}: {len(c.gates)} gates, {need / 2**30:.1f} GiB")
     buf = torch.empty(need, dtype=torch.uint8, device="cuda")
-    q.timing_reset()
-    q.timing_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = q.run_trajectories(ga, n, 0, q.C64, T, e=e, seed=seed, buf=buf)
-    t1 = time.perf_counter()
-    q.timing_enable(False)
-    fz = q.timing_read("fused")
-    F = res["F"].tolist()
-    norms = res["norm"].tolist()
-    per_layer = len(c.gates) // depth
-    pre = Circuit(n, c.gates[:prefix_layers * per_layer], name="prefix")
-    pga = q.gate_array(pre.gates)
-    times = {}
-    for name, pl in (("fused", {"fuse": -1}), ("unfused", {"fuse": 0})):
+    runs = {}
+    for name, pl in (("valu", {"fuse": -1}), ("mfma", {"fuse": 1, "mfma": 1})):
         q.timing_reset()
         q.timing_enable(True)
         torch.cuda.synchronize()
-        a0 = time.perf_counter()
-        r = q.run_trajectories(pga, n, 0, q.C64, T, e=e, seed=seed, plan=pl, buf=buf)
-        times[name] = time.perf_counter() - a0
+        t0 = time.perf_counter()
+        res = q.run_trajectories(ga, n, 0, q.C64, T, e=e, seed=seed, plan=pl, buf=buf)
+        t1 = time.perf_counter()
         q.timing_enable(False)
-        if name == "fused":
-            Fp = r["F"].copy()
-        else:
-            sw = q.timing_read("sweep_u1")
-            Fu = r["F"].copy()
+        fz = q.timing_read("fused")
+        runs[name] = {"plan": pl if name == "mfma" else plan, "wall_s": t1 - t0, "passes": fz["launches"],
+                      "fused_avg_ms": fz["ms"] / max(fz["launches"], 1),
+                      "fused_GBps": round(fz["alg_bytes"] / (fz["ms"] / 1e3) / 1e9, 1),
+                      "F": res["F"].tolist(), "norm": res["norm"].tolist()}
+        del res
+    runs["mfma"]["max_abs_dF_vs_valu"] = float(np.max(np.abs(np.array(runs["mfma"]["F"]) - np.array(runs["valu"]["F"]))))
+    per_layer = len(c.gates) // depth
+    pref = {}
+    for L in prefixes:
+        pre = Circuit(n, c.gates[:L * per_layer], name="prefix")
+        pga = q.gate_array(pre.gates)
+        for name, pl in (("fused", {"fuse": -1}), ("unfused", {"fuse": 0})):
+            q.timing_reset()
+            q.timing_enable(True)
+            torch.cuda.synchronize()
+            a0 = time.perf_counter()
+            r = q.run_trajectories(pga, n, 0, q.C64, T, e=e, seed=seed, plan=pl, buf=buf)
+            pref[(L, name)] = (time.perf_counter() - a0, r["F"].copy())
+            q.timing_enable(False)
+            if name == "unfused":
+                sw = q.timing_read("sweep_u1")
+            del r
     del buf
+    a, b = prefixes
     u1_gbs = sw["alg_bytes"] / (sw["ms"] / 1e3) / 1e9 if sw["ms"] else 0.0
+    steady_fused = (pref[(b, "fused")][0] - pref[(a, "fused")][0]) / (b - a)
+    steady_unfused = (pref[(b, "unfused")][0] - pref[(a, "unfused")][0]) / (b - a)
+    v = runs["valu"]
     return {"workload": f"random{n}x{depth} brickwork, complex64, {T} trajectories + ideal, e={e}",
-            "bytes": need, "plan": plan, "passes": fz["launches"], "wall_s": t1 - t0,
-            "fused_avg_ms": fz["ms"] / max(fz["launches"], 1),
-            "fused_GBps": round(fz["alg_bytes"] / (fz["ms"] / 1e3) / 1e9, 1),
-            "F": F, "norm": norms,
-            "prefix_layers": prefix_layers, "prefix_fused_s": times["fused"], "prefix_unfused_s": times["unfused"],
-            "prefix_speedup": times["unfused"] / times["fused"],
-            "prefix_max_abs_dF_fused_vs_unfused": float(np.max(np.abs(Fp - Fu))),
+            "bytes": need, "plan": plan, "passes": v["passes"], "wall_s": v["wall_s"],
+            "fused_avg_ms": v["fused_avg_ms"], "fused_GBps": v["fused_GBps"], "F": v["F"], "norm": v["norm"],
+            "mfma": runs["mfma"],
+            "prefix_s": {f"{L}_{name}": t for (L, name), (t, _) in pref.items()},
+            "prefix_speedup": pref[(a, "unfused")][0] / pref[(a, "fused")][0],
+            "steady_state_s_per_layer": {"fused": steady_fused, "unfused": steady_unfused},
+            "steady_state_speedup": steady_unfused / steady_fused,
+            "prefix_max_abs_dF_fused_vs_unfused": float(max(np.max(np.abs(pref[(L, "fused")][1] - pref[(L, "unfused")][1]))
+                                                            for L in prefixes)),
             "unfused_u1_GBps": round(u1_gbs, 1), "unfused_u1_hbm_frac": round(u1_gbs / HBM_PEAK_GBS, 4)}
+
+
+def block_rounds_bench(q, torch, n=30, depth=8, T=4):
+    """Random layers (Haar one-qubit gates, noisy brickwork CZ, e = 0.005) on n = 30 complex64
+    (8 GiB per slot), T trajectories + ideal, fused op by op on the vector ALUs and with every
+    register round as a dense 16 x 16 block on the FP32 matrix cores (mfma = 1): time per pass
+    and |dF| between the two.  A short run for counter profiles of both kernel variants."""
+    import numpy as np
+    from workloads import random_layers
+    c = random_layers(n, depth, 4, pairing="brickwork")
+    ga = q.gate_array(c.gates)
+    out = {"workload": f"random{n}x{depth} brickwork, complex64, {T} trajectories + ideal, e=0.005"}
+    F = {}
+    for name, pl in (("valu", {"fuse": 1}), ("mfma", {"fuse": 1, "mfma": 1})):
+        need = q.traj_bytes_required(ga, n, q.C64, T, pl)
+        buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+        q.run_trajectories(ga, n, 0, q.C64, T, e=0.005, seed=4, plan=pl, buf=buf)   # warm-up
+        torch.cuda.synchronize()
+        q.timing_reset()
+        q.timing_enable(True)
+        t0 = time.perf_counter()
+        res = q.run_trajectories(ga, n, 0, q.C64, T, e=0.005, seed=4, plan=pl, buf=buf)
+        t1 = time.perf_counter()
+        q.timing_enable(False)
+        fz = q.timing_read("fused")
+        F[name] = res["F"].copy()
+        out[name] = {"wall_s": t1 - t0, "passes": fz["launches"], "fused_avg_ms": fz["ms"] / max(fz["launches"], 1),
+                     "fused_GBps": round(fz["alg_bytes"] / (fz["ms"] / 1e3) / 1e9, 1)}
+        del res, buf
+        torch.cuda.empty_cache()
+    out["max_abs_dF"] = float(np.max(np.abs(F["mfma"] - F["valu"])))
+    return out
 
 
 def graph_bench(q, torch, reps=20):

@@ -114,6 +114,11 @@ typedef struct {
     int32_t reg_bits;  /* fused: amplitudes per thread = 2^reg_bits (0 = library picks)     */
     int32_t run_bits;  /* fused: the 2^run_bits lowest-index amplitudes of a tile are one
                           contiguous row (coalescing); 0 = library picks                   */
+    int32_t mfma;      /* fused, complex<float>, 4 register bits: 1 runs each register round of
+                          three or more one-qubit ops as one dense 16 x 16 complex block (the
+                          ops and their phases conditioned on register bits multiplied
+                          together) on the FP32 matrix cores, as a real 32 x 32 product;
+                          0 = op by op on the vector ALUs.  Ignored otherwise.              */
 } qs_plan;
 
 typedef struct qs_state_s *qs_state;

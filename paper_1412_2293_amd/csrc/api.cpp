@@ -552,12 +552,13 @@ struct TrajLayout {
 
 struct Plan {
     bool fused = false;
+    bool mfma = false;
     int K = 0, RB = 0, run_bits = 0;
     qs::Program prog;
 };
 
 qs_status fused_plan_for(const qs_gate *gates, int n_gates, int n, qs_dtype dt, int K, int RB, int run,
-                         Plan &out)
+                         Plan &out, bool mfma = false)
 {
     out.fused = true;
     if (K > kMaxTileBits) return fail(QS_EINVAL, "plan: tile_bits too large");
@@ -576,7 +577,8 @@ qs_status fused_plan_for(const qs_gate *gates, int n_gates, int n, qs_dtype dt, 
     out.run_bits = run;
     int rec_cap = stage_rec_cap(dt, K);
     if (rec_cap < 256) return fail(QS_EINVAL, "plan: tile leaves too little LDS for the gate records");
-    return plan_fused(gates, n_gates, n, K, RB, run, rec_cap, out.prog);
+    out.mfma = mfma && dt == QS_C64 && RB == 4;
+    return plan_fused(gates, n_gates, n, K, RB, run, rec_cap, out.prog, out.mfma);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -601,6 +603,11 @@ static double row_efficiency(int run_bits, qs_dtype dt)
     return bytes >= 128 ? 1.0 : bytes >= 64 ? 0.8 : bytes >= 32 ? 0.45 : 0.3;
 }
 
+// A dense 16 x 16 block on the FP32 matrix cores: 64 products of 16 x 16 x 4 per 1024 amplitudes
+// (one wave's tile), 32 cycles each on one SIMD's matrix unit: 2 cycles per amplitude, the
+// vector-ALU equivalent of 2 x 16 lane-instructions per amplitude at the model's issue rate.
+constexpr double kModelBlockValuEq = 32.0;
+
 double model_cost_fused(const Program &P, int n, qs_dtype dt, int S, int run_bits)
 {
     const double N = std::ldexp(1.0, n), amp = (double)amp_bytes(dt);
@@ -611,6 +618,21 @@ double model_cost_fused(const Program &P, int n, qs_dtype dt, int S, int run_bit
         const PassDesc &pd = P.passes[pi];
         double per_amp = 20.0;                                  // load/store, tile set-up
         per_amp += 6.0 * (pd.round_end - pd.round_begin + 1);   // LDS exchanges
+        if (pd.blocks) {
+            // block rounds: the matrix-core time, the lane exchanges around each block (4 per
+            // amplitude) and the phases applied outside the block (5 per folded block)
+            for (int ri = pd.round_begin; ri < pd.round_end; ++ri) {
+                per_amp += kModelBlockValuEq + 4.0;
+                for (int oi = P.rounds[ri].op_begin; oi < P.rounds[ri].op_end; ++oi) {
+                    const OpDesc &op = P.ops[oi];
+                    per_amp += 5.0 * ((op.pre_rec >= 0) + (op.post_rec >= 0));
+                }
+            }
+            const double mem = (pi == 0 ? 1.0 : 2.0) * N * amp / (kModelHbm * eff);
+            const double alu = N * per_amp / kModelValu;
+            total += std::max(mem, alu) + 0.5 * std::min(mem, alu);
+            continue;
+        }
         for (int oi = pd.op_begin; oi < pd.op_end; ++oi) {
             const OpDesc &op = P.ops[oi];
             if (op.type == OP_U1) {
@@ -665,15 +687,18 @@ qs_status autotune_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, i
     for (int c = 0; c < ncand; ++c) {
         const int *k = dt == QS_C64 ? kCandC64[c] : kCandC128[c];
         if (two_qubit_dense && k[1] < 2) continue;
-        Plan cand;
-        if (fused_plan_for(gates, n_gates, n, dt, k[0], k[1], k[2], cand) != QS_OK) {
-            clear_error();
-            continue;
-        }
-        const double cost = model_cost_fused(cand.prog, n, dt, S, cand.run_bits);
-        if (cost < best * 0.999) {
-            best = cost;
-            out = std::move(cand);
+        // complex<float> shapes with 16 registers also as block-round plans (matrix cores)
+        for (int mf = 0; mf <= (dt == QS_C64 && k[1] == 4 ? 1 : 0); ++mf) {
+            Plan cand;
+            if (fused_plan_for(gates, n_gates, n, dt, k[0], k[1], k[2], cand, mf == 1) != QS_OK) {
+                clear_error();
+                continue;
+            }
+            const double cost = model_cost_fused(cand.prog, n, dt, S, cand.run_bits);
+            if (cost < best * 0.999) {
+                best = cost;
+                out = std::move(cand);
+            }
         }
     }
     if (cost_out) *cost_out = best;
@@ -700,7 +725,8 @@ qs_status resolve_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, in
     int K = (p && p->tile_bits > 0) ? p->tile_bits : (dt == QS_C64 ? 12 : 11);
     int RB = (p && p->reg_bits > 0) ? p->reg_bits : (dt == QS_C64 ? 4 : 3);
     int run = (p && p->run_bits > 0) ? p->run_bits : (dt == QS_C64 ? 4 : 3);
-    return fused_plan_for(gates, n_gates, n, dt, K, RB, run, out);
+    if (p && (p->mfma < 0 || p->mfma > 1)) return fail(QS_EINVAL, "plan: mfma must be 0 or 1");
+    return fused_plan_for(gates, n_gates, n, dt, K, RB, run, out, p && p->mfma == 1);
 }
 
 TrajLayout traj_layout(int n, qs_dtype dt, int T, int n_gates, const Plan &pl)
@@ -779,8 +805,9 @@ PrepCache &prep_cache()
 }
 std::string prep_key(const qs_gate *gates, int n_gates, int n, qs_dtype dt, const qs_plan *plan)
 {
-    const qs_plan pl = plan ? *plan : qs_plan{-1, 0, 0, 0};
-    const int32_t head[8] = {n, (int32_t)dt, n_gates, pl.fuse, pl.tile_bits, pl.reg_bits, pl.run_bits, plan ? 1 : 0};
+    const qs_plan pl = plan ? *plan : qs_plan{-1, 0, 0, 0, 0};
+    const int32_t head[9] = {n, (int32_t)dt, n_gates, pl.fuse, pl.tile_bits, pl.reg_bits, pl.run_bits, pl.mfma,
+                             plan ? 1 : 0};
     std::string k((const char *)head, sizeof head);
     if (n_gates > 0) k.append((const char *)gates, sizeof(qs_gate) * (size_t)n_gates);
     return k;
@@ -929,6 +956,10 @@ static qs_status enqueue_compute(const TrajPrep &prep, const TrajLayout &L, char
             uint64_t *otab = (uint64_t *)(B + L.wtab);
             char *wtab = B + L.wtab + align256((size_t(1) << (n > P.K ? n - P.K : 0)) * sizeof(uint64_t));
             QS_HIP(launch_pass_prep(dt, S, &P.passes[p], pdv, tab, gdev, B + L.rec, st));
+            bool blocks = false;
+            for (int ri = P.passes[p].round_begin; ri < P.passes[p].round_end; ++ri)
+                blocks = blocks || P.rounds[ri].block_rec >= 0;
+            if (blocks) QS_HIP(launch_block_prep(dt, S, &P.passes[p], pdv, B + L.rec, st));
             QS_HIP(launch_pass_jobs(dt, n, S, &P.passes[p], pdv, B + L.rec, init, (int64_t)init_index, dyn,
                                     wtab, otab, st));
             if (p + 1 < P.passes.size()) {
@@ -1072,6 +1103,7 @@ qs_status qs_plan_choose(const qs_gate *gates, int n_gates, int n, qs_dtype dt, 
     out->tile_bits = pl.fused ? pl.K : 0;
     out->reg_bits = pl.fused ? pl.RB : 0;
     out->run_bits = pl.fused ? pl.run_bits : 0;
+    out->mfma = pl.fused && pl.mfma ? 1 : 0;
     if (model_s_per_slot) *model_s_per_slot = cost;
     return QS_OK;
 }
@@ -1092,6 +1124,7 @@ qs_status qs_plan_describe(const qs_gate *gates, int n_gates, int n, qs_dtype dt
     I("fused", pl.fused ? 1 : 0);
     I("K", pl.prog.K);
     I("RB", pl.prog.RB);
+    I("mfma", pl.mfma ? 1 : 0);
     I("run_bits", pl.run_bits);
     if (pl.fused) I("stage_rec_cap", stage_rec_cap(dt, pl.prog.K));
     {
@@ -1127,6 +1160,7 @@ qs_status qs_plan_describe(const qs_gate *gates, int n_gates, int n, qs_dtype dt
         I("load_round", pd.load_round);
         I("load_reg_mask", P.rounds[pd.load_round].reg_mask);
         I("store_round", pd.store_round);
+        I("blocks", pd.blocks);
         I("store_reg_mask", P.rounds[pd.store_round].reg_mask);
         I("round_begin", pd.round_begin);
         I("round_end", pd.round_end);
@@ -1150,6 +1184,7 @@ qs_status qs_plan_describe(const qs_gate *gates, int n_gates, int n, qs_dtype dt
                 const RoundDesc &rd = P.rounds[ri];
                 o += ri != sd.round_begin ? ",{" : "{";
                 I("reg_mask", rd.reg_mask);
+                I("block_rec", rd.block_rec);
                 o += "\"ops\":[";
                 for (int oi = rd.op_begin; oi < rd.op_end; ++oi) {
                     const OpDesc &op = P.ops[oi];

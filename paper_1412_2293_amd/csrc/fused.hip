@@ -294,6 +294,94 @@ __device__ __forceinline__ void dispatch_u2(int p0, int p1, tv<R> (&a)[1 << RB],
 }
 
 // ---------------------------------------------------------------------------------------
+// Dense 16 x 16 blocks on the FP32 matrix cores (rounds the planner marks with a block record).
+// In a round the 16 registers of a thread are the 16 states of the round's four qubits (register
+// index = block index) and the thread id numbers the columns.  A 16 x 16 x 4 product takes its
+// K index from lane bits 4, 5 and a chunk index, so register bits 0, 1 are first exchanged with
+// lane bits 4, 5 (one lane-half swap per register pair and component); then register
+// g + 4c of lane group j holds block state j + 4c of column group g.  With the block as the real
+// 32 x 32 matrix [[Re U, -Im U], [Im U, Re U]] acting on [Re x; Im x], eight products of four
+// rows each give the real and imaginary output rows of one column group.  Output register i of
+// lane group j holds row 4j + i; it is stored at register g + 4i, and after the exchange back
+// the register index is j + 4i.  The operand table holds the block with its rows permuted by
+// P(4j + i) = 4i + j, so that register j + 4i ends with output state j + 4i.
+// ---------------------------------------------------------------------------------------
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+// (lo, hi): the same register pair of a lane half; exchange the upper 16 lanes of each 32 of lo
+// with the lower 16 of hi (a transpose of register bit and lane bit 4).
+__device__ __forceinline__ void lane_swap16(tv<float> &lo, tv<float> &hi)
+{
+    const auto x = __builtin_amdgcn_permlane16_swap(__float_as_uint(lo.x), __float_as_uint(hi.x), false, false);
+    const auto y = __builtin_amdgcn_permlane16_swap(__float_as_uint(lo.y), __float_as_uint(hi.y), false, false);
+    lo = tv<float>{__uint_as_float(x[0]), __uint_as_float(y[0])};
+    hi = tv<float>{__uint_as_float(x[1]), __uint_as_float(y[1])};
+}
+
+// The same for lane bit 5 (upper 32 lanes of lo with the lower 32 of hi).
+__device__ __forceinline__ void lane_swap32(tv<float> &lo, tv<float> &hi)
+{
+    const auto x = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo.x), __float_as_uint(hi.x), false, false);
+    const auto y = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo.y), __float_as_uint(hi.y), false, false);
+    lo = tv<float>{__uint_as_float(x[0]), __uint_as_float(y[0])};
+    hi = tv<float>{__uint_as_float(x[1]), __uint_as_float(y[1])};
+}
+
+__device__ __forceinline__ void swap_reg01_lane45(tv<float> (&a)[16])
+{
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (!(r & 1)) lane_swap16(a[r], a[r | 1]);
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (!(r & 2)) lane_swap32(a[r], a[r | 2]);
+}
+
+// y = U x for every column of the register tile (64 products); tab: this lane's 16 operand
+// values, entry ob * 8 + c = row block ob (real, imaginary outputs) and K chunk c (rows 4c..4c+3
+// of [Re x; Im x]).
+__device__ __forceinline__ void block_apply(tv<float> (&a)[16], const float (&A)[16])
+{
+    swap_reg01_lane45(a);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        mf4 re = {0.f, 0.f, 0.f, 0.f}, im = re;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            re = __builtin_amdgcn_mfma_f32_16x16x4f32(A[c], a[g + 4 * c].x, re, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f32_16x16x4f32(A[8 + c], a[g + 4 * c].x, im, 0, 0, 0);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            re = __builtin_amdgcn_mfma_f32_16x16x4f32(A[4 + c], a[g + 4 * c].y, re, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f32_16x16x4f32(A[12 + c], a[g + 4 * c].y, im, 0, 0, 0);
+        }
+        // column group g's inputs are consumed: its outputs take their registers
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[g + 4 * i] = tv<float>{re[i], im[i]};
+    }
+    swap_reg01_lane45(a);
+}
+
+// a[r] *= w for the registers whose bit P is set (a phase on the |1> state of register bit P).
+template <typename R, int RB, int P>
+__device__ __forceinline__ void phase_on_bit(tv<R> (&a)[1 << RB], cxf<R> w)
+{
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r)
+        if ((r >> P) & 1) a[r] = tvec(mul(w, cx<R>(a[r])));
+}
+
+template <typename R, int RB>
+__device__ __forceinline__ void dispatch_phase_on_bit(int p, tv<R> (&a)[1 << RB], cxf<R> w)
+{
+    if (RB > 1 && p == 0) phase_on_bit<R, RB, 0>(a, w);
+    else if (RB > 2 && p == 1) phase_on_bit<R, RB, 1 % RB>(a, w);
+    else if (RB > 3 && p == 2) phase_on_bit<R, RB, 2 % RB>(a, w);
+    else phase_on_bit<R, RB, RB - 1>(a, w);
+}
+
+// ---------------------------------------------------------------------------------------
 // Per-slot records of one pass (one thread per op and slot; FP64 products rounded once).
 // ---------------------------------------------------------------------------------------
 __device__ __forceinline__ double2 dmul(double2 a, double2 b)
@@ -308,6 +396,65 @@ __device__ __forceinline__ double2 dunit(double2 a)
 {
     const double h = hypot(a.x, a.y);
     return h > 0.0 ? make_double2(a.x / h, a.y / h) : make_double2(1.0, 0.0);
+}
+
+// Per (slot, block round, column): column `col` of the round's block U (the ops applied in order
+// to the basis state col, in FP64: each op's phases conditioned on register bits on its |1> input,
+// its 2 x 2 matrix, the same on its output), written into the operand table with rows permuted
+// as block_apply expects.  The matrices and register-bit factors come from the slot's records,
+// written by k_pass_prep before.
+template <typename R>
+__global__ void k_block_prep(int S, int round_begin, int n_rounds, int rec_size, ProgramDev prog,
+                             cxf<R> *__restrict__ rec_all)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)S * n_rounds * 16) return;
+    const int col = (int)(t & 15);
+    const int rr = (int)((t >> 4) % n_rounds);
+    const int slot = (int)((t >> 4) / n_rounds);
+    const RoundDesc &rd = prog.rounds[round_begin + rr];
+    if (rd.block_rec < 0) return;
+    cxf<R> *rec = rec_all + (size_t)slot * rec_size;
+    double2 v[16];
+    for (int b = 0; b < 16; ++b) v[b] = make_double2(b == col ? 1.0 : 0.0, 0.0);
+    auto ld = [&](int e) { return make_double2((double)rec[e].re, (double)rec[e].im); };
+    auto bit_phases = [&](int block, int p) {
+        if (block < 0) return;
+        double2 f[4];
+        for (int k = 0; k < 4; ++k) f[k] = ld(block + k);
+        for (int b = 0; b < 16; ++b) {
+            if (!((b >> p) & 1)) continue;
+            double2 w = make_double2(1.0, 0.0);
+            for (int k = 0; k < 4; ++k)
+                if (k != p && ((b >> k) & 1)) w = dmul(w, f[k]);
+            v[b] = dmul(w, v[b]);
+        }
+    };
+    for (int oi = rd.op_begin; oi < rd.op_end; ++oi) {
+        const OpDesc &op = prog.ops[oi];
+        const int p = op.p0;
+        bit_phases(op.pre_rec, p);
+        const double2 m0 = ld(op.rec), m1 = ld(op.rec + 1), m2 = ld(op.rec + 2), m3 = ld(op.rec + 3);
+        for (int b = 0; b < 16; ++b) {
+            if ((b >> p) & 1) continue;
+            const double2 x0 = v[b], x1 = v[b | (1 << p)];
+            const double2 y0 = dmul(m0, x0), y0b = dmul(m1, x1), y1 = dmul(m2, x0), y1b = dmul(m3, x1);
+            v[b] = make_double2(y0.x + y0b.x, y0.y + y0b.y);
+            v[b | (1 << p)] = make_double2(y1.x + y1b.x, y1.y + y1b.y);
+        }
+        bit_phases(op.post_rec, p);
+    }
+    // U[g][col] = v[g] goes to row P(g) of the permuted block; real form entries
+    // (r, c) -> lane (r % 16) + 16 (c % 4), entry (r / 16) * 8 + c / 4 of the lane's 16
+    R *tab = reinterpret_cast<R *>(rec + rd.block_rec);
+    auto put = [&](int r, int c, double x) { tab[((r & 15) + 16 * (c & 3)) * 16 + (r >> 4) * 8 + (c >> 2)] = (R)x; };
+    for (int g = 0; g < 16; ++g) {
+        const int r = ((g & 3) << 2) | (g >> 2);
+        put(r, col, v[g].x);
+        put(r, 16 + col, -v[g].y);
+        put(16 + r, col, v[g].y);
+        put(16 + r, 16 + col, v[g].x);
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -499,7 +646,7 @@ constexpr int kMinWaves = (sizeof(R) == 4 && RB == 4) ? 4 : 1;
 // UNI: whether blocks whose factors do not depend on thread-id bits take their per-thread factor
 // with a uniform load (the host picks this variant for passes where most blocks are such; the
 // other keeps the per-thread lookups branch-free, which schedules better when few are).
-template <typename R, int RB, bool UNI>
+template <typename R, int RB, bool UNI, bool BLK>
 __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     __attribute__((amdgpu_waves_per_eu(kMinWaves<R, RB>, 8))) k_fused(R *__restrict__ psi, int n, int S, int pass_index,
                                                   int rec_cap, int64_t init, int64_t basis, uint32_t blocal,
@@ -685,6 +832,45 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
             const RoundDesc *rd = prog.rounds + ri;
             const uint32_t mask = rd->reg_mask;
             if (mask != cur) exchange_to(mask, ri);
+            if constexpr (BLK && sizeof(R) == 4 && RB == 4) {
+                // every round of a block pass is a block (the planner makes it all or none), so
+                // this variant carries no op-by-op path
+                {
+                    // the round as one dense block: the ops' phases conditioned outside the
+                    // registers before and after it (per op, on its target's |1> states)
+                    const float *tp = reinterpret_cast<const float *>(rec + rd->block_rec) + (tid & 63u) * 16;
+                    float A[16];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float4 q4 = *reinterpret_cast<const float4 *>(tp + 4 * k);
+                        A[4 * k] = q4.x;
+                        A[4 * k + 1] = q4.y;
+                        A[4 * k + 2] = q4.z;
+                        A[4 * k + 3] = q4.w;
+                    }
+                    for (int oi = rd->op_begin; oi < rd->op_end; ++oi) {
+                        const OpDesc *op = prog.ops + oi;
+                        const int flags = op->flags;
+                        if (op->pre_rec >= 0 && (!(flags & OPF_PRE_UNI) || op->pre_job >= 0)) {
+                            PhaseSet<R, RB> pre;
+                            load_phases<R, RB>(pre, rec + op->pre_rec, rec + op->pre_rec, true, false,
+                                               UNI && (flags & OPF_PRE_UNI) != 0, op->pre_job, wout, tid);
+                            dispatch_phase_on_bit<R, RB>(op->p0, a, pre.w);
+                        }
+                    }
+                    block_apply(a, A);
+                    for (int oi = rd->op_begin; oi < rd->op_end; ++oi) {
+                        const OpDesc *op = prog.ops + oi;
+                        const int flags = op->flags;
+                        if (op->post_rec >= 0 && (!(flags & OPF_POST_UNI) || op->post_job >= 0)) {
+                            PhaseSet<R, RB> post;
+                            load_phases<R, RB>(post, rec + op->post_rec, rec + op->post_rec, true, false,
+                                               UNI && (flags & OPF_POST_UNI) != 0, op->post_job, wout, tid);
+                            dispatch_phase_on_bit<R, RB>(op->p0, a, post.w);
+                        }
+                    }
+                }
+            } else {
             const int oe = rd->op_end;
             for (int oi = rd->op_begin; oi < oe; ++oi) {
                 const OpDesc *op = prog.ops + oi;
@@ -739,6 +925,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                         a[r] = hit ? y : a[r];
                     }
                 }
+            }
             }
         }
     }
@@ -873,6 +1060,17 @@ hipError_t launch_pass_prep(qs_dtype dt, int S, const PassDesc *h, ProgramDev pr
     return hipGetLastError();
 }
 
+hipError_t launch_block_prep(qs_dtype dt, int S, const PassDesc *h, ProgramDev prog, void *rec, hipStream_t st)
+{
+    const int n_rounds = h->round_end - h->round_begin;
+    const int64_t tot = (int64_t)S * n_rounds * 16;
+    if (tot == 0 || dt != QS_C64) return hipSuccess;
+    TimedLaunch tl("prep", (double)S * n_rounds * kBlockRecEntries * 8.0, st);
+    hipLaunchKernelGGL(k_block_prep<float>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, S, h->round_begin,
+                       n_rounds, h->rec_size, prog, (cxf<float> *)rec);
+    return hipGetLastError();
+}
+
 hipError_t launch_pass_jobs(qs_dtype dt, int n, int S, const PassDesc *h, ProgramDev prog, const void *rec,
                             int64_t init, int64_t basis, const RunParams *dyn, void *wtab, uint64_t *otab,
                             hipStream_t st)
@@ -898,26 +1096,35 @@ hipError_t launch_pass_jobs(qs_dtype dt, int n, int S, const PassDesc *h, Progra
 }
 
 // thread-safe one-time opt-in to the full 160 KiB of LDS
-template <typename R, int RB, bool UNI>
+template <typename R, int RB, bool UNI, bool BLK>
 static hipError_t fused_attr_one()
 {
     static const hipError_t attr = [] {
         // the kernel addresses its tile at LDS address 0: it must have no static LDS
         hipFuncAttributes fa;
-        hipError_t e = hipFuncGetAttributes(&fa, (const void *)k_fused<R, RB, UNI>);
+        hipError_t e = hipFuncGetAttributes(&fa, (const void *)k_fused<R, RB, UNI, BLK>);
         if (e != hipSuccess) return e;
         if (fa.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
-        return hipFuncSetAttribute((const void *)k_fused<R, RB, UNI>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   160 * 1024);
+        return hipFuncSetAttribute((const void *)k_fused<R, RB, UNI, BLK>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     }();
     return attr;
 }
 
+// the block-round variants (matrix-core rounds) exist for complex<float> with 16 registers only
+template <typename R, int RB>
+constexpr bool kBlockVariant = sizeof(R) == 4 && RB == 4;
+
 template <typename R, int RB>
 static hipError_t fused_attr()
 {
-    const hipError_t e = fused_attr_one<R, RB, false>();
-    return e != hipSuccess ? e : fused_attr_one<R, RB, true>();
+    hipError_t e = fused_attr_one<R, RB, false, false>();
+    if (e == hipSuccess) e = fused_attr_one<R, RB, true, false>();
+    if constexpr (kBlockVariant<R, RB>) {
+        if (e == hipSuccess) e = fused_attr_one<R, RB, false, true>();
+        if (e == hipSuccess) e = fused_attr_one<R, RB, true, true>();
+    }
+    return e;
 }
 
 hipError_t fused_prepare_attributes()
@@ -947,14 +1154,21 @@ static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_ind
     uint32_t blocal = 0;
     for (int j = 0; j < h.K; ++j)
         if (((uint64_t)basis >> h.q_pos[j]) & 1ull) blocal |= 1u << j;
-    if (h.uni_kernel)
-        hipLaunchKernelGGL((k_fused<R, RB, true>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index,
-                           rec_cap, init, basis, blocal, dyn, prog.passes, prog.stages, prog.rounds, prog.ops,
-                           (const cxf<R> *)rec, (const cxf<R> *)wtab, otab, ovl, slot_base, slots);
-    else
-        hipLaunchKernelGGL((k_fused<R, RB, false>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index,
-                           rec_cap, init, basis, blocal, dyn, prog.passes, prog.stages, prog.rounds, prog.ops,
-                           (const cxf<R> *)rec, (const cxf<R> *)wtab, otab, ovl, slot_base, slots);
+#define QS_FUSED_LAUNCH(UNI, BLK)                                                                              \
+    hipLaunchKernelGGL((k_fused<R, RB, UNI, BLK>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index,   \
+                       rec_cap, init, basis, blocal, dyn, prog.passes, prog.stages, prog.rounds, prog.ops,         \
+                       (const cxf<R> *)rec, (const cxf<R> *)wtab, otab, ovl, slot_base, slots)
+    if constexpr (kBlockVariant<R, RB>) {
+        if (h.blocks) {
+            if (h.uni_kernel) QS_FUSED_LAUNCH(true, true);
+            else QS_FUSED_LAUNCH(false, true);
+            return hipGetLastError();
+        }
+    }
+    if (h.blocks) return hipErrorInvalidValue;   // no block-round variant for this tile shape
+    if (h.uni_kernel) QS_FUSED_LAUNCH(true, false);
+    else QS_FUSED_LAUNCH(false, false);
+#undef QS_FUSED_LAUNCH
     return hipGetLastError();
 }
 

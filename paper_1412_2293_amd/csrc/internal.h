@@ -48,7 +48,9 @@ struct RoundDesc {
     uint32_t reg_mask;            // tile-local bits held in registers during this round
     int32_t op_begin;
     int32_t op_end;
-    int32_t reserved;
+    int32_t block_rec;            // -1: the ops run one by one; else the round runs as one dense
+                                  // 16 x 16 block on the matrix cores, whose operand table (per
+                                  // slot, 1024 floats in lane order) starts at this record entry
     uint32_t roff[16];            // tile-local offset of register r (32-bit: scalar loads)
     uint32_t sroff[16];           // lds_swizzle(roff[r])
     uint16_t tlo[32];             // tile-local bits of thread-id bits 0..4, indexed by tid & 31
@@ -93,7 +95,7 @@ struct PassDesc {
     int32_t store_round;          // index in the rounds array of the layout the tile is stored
                                   // in: the pass's last round when its layout keeps the low run
                                   // bits in the thread id, else the load layout
-    int32_t reserved2;
+    int32_t blocks;               // some round of the pass runs as a dense block (matrix cores)
     uint64_t store_off[16];       // store layout: physical index bits of register r
 };
 
@@ -271,6 +273,10 @@ hipError_t launch_fused_pass(void *psi, qs_dtype dt, int n, int S, const PassDes
 // with slot_base > 0 (run slot 0 alone first).  Finished by launch_overlap_final.
 // Walked tile-number bits of a pass launch (the tiles its blocks cover).
 int fused_walked_bits(int n, const PassDesc *pass_host, int64_t init);
+// The operand tables of the pass's block rounds (after launch_pass_prep of the pass; complex<float>
+// plans only).
+hipError_t launch_block_prep(qs_dtype dt, int S, const PassDesc *pass_host, ProgramDev prog, void *rec,
+                             hipStream_t st);
 // The per-tile products of a pass's outer jobs into wtab and the tiles' outer index bits into
 // otab (after launch_pass_prep of the pass); the same init / basis / dyn as the pass's
 // launch_fused_pass.
@@ -328,8 +334,13 @@ struct Program {
     int max_jobs = 0;             // most outer jobs of one pass
 };
 
+// mfma: run eligible register rounds as dense blocks on the matrix cores (RB = 4 only); phase
+// chains are then not formed.
 qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, int run_bits,
-                     int rec_cap, Program &out);
+                     int rec_cap, Program &out, bool mfma = false);
+
+// Complex entries of one block round's operand table per slot (1024 floats).
+constexpr int kBlockRecEntries = 512;
 
 // A circuit validated and planned once; every batch of its trajectories reuses it.  The host
 // arrays stay alive while any batch that copies from them is in flight.

@@ -46,6 +46,7 @@ RoundDesc make_round(uint32_t m, int K)
 {
     RoundDesc R{};
     R.reg_mask = m;
+    R.block_rec = -1;
     std::vector<int> regpos, tpos;
     for (int j = 0; j < K; ++j) ((m >> j) & 1u ? regpos : tpos).push_back(j);
     for (int r = 0; r < 16; ++r) {
@@ -80,7 +81,7 @@ int find_pos(const std::vector<int> &v, int x)
 }  // namespace
 
 qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, int run_bits,
-                     int rec_cap, Program &P)
+                     int rec_cap, Program &P, bool mfma)
 {
     if (K > n) K = n;
     if (K > kMaxTileBits) K = kMaxTileBits;
@@ -181,7 +182,8 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         };
         for (const PG &x : pg) {
             if (x.kind == QS_G_U1) {
-                if (chainable(gates[x.gate])) open[x.a].push_back(x.gate);
+                // block rounds take each gate's full complex matrix: no chains then
+                if (!mfma && chainable(gates[x.gate])) open[x.a].push_back(x.gate);
                 else close(x.a);
             } else if (x.kind == QS_G_CNOT) {
                 close(x.b);
@@ -554,6 +556,34 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                 P.ops.push_back(op);
             }
             R.op_end = (int)P.ops.size();
+            // A round of one-qubit ops (at least three) on the four register bits runs as one dense
+            // 16 x 16 block on the matrix cores: the ops' matrices and their phases conditioned on
+            // register bits multiply into the block, in order.  A phase conditioned on a bit
+            // outside the registers is diagonal on the op's target and commutes with the other
+            // targets' ops, so it is applied before the block (an input phase) when no earlier op
+            // of the round acts on that target, and after it (an output phase) when no later one
+            // does; otherwise the round runs op by op.
+            if (mfma && RB == 4 && K - RB >= 6 && R.op_end - R.op_begin >= 3) {
+                bool ok = true;
+                for (int oi = R.op_begin; ok && oi < R.op_end; ++oi) {
+                    const OpDesc &o = P.ops[oi];
+                    if (o.type != OP_U1 || (o.flags & (OPF_CHAIN | OPF_UPHASE))) {
+                        ok = false;
+                        break;
+                    }
+                    bool ext_pre = false, ext_post = false;
+                    for (int k = o.pref_begin; k < o.pref_end; ++k)
+                        if (P.prefs[k].kind != PR_REG) (P.prefs[k].post ? ext_post : ext_pre) = true;
+                    for (int oj = R.op_begin; oj < R.op_end; ++oj) {
+                        if (oj == oi || P.ops[oj].p0 != o.p0) continue;
+                        if ((ext_pre && oj < oi) || (ext_post && oj > oi)) ok = false;
+                    }
+                }
+                if (ok) {
+                    R.block_rec = rec;
+                    rec += kBlockRecEntries;
+                }
+            }
             P.rounds.push_back(R);
         }
         {
@@ -583,6 +613,15 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         pd.stage_end = (int)P.stages.size();
         pd.round_end = (int)P.rounds.size();
         pd.store_round = st_mask == io_mask ? pd.load_round : pd.round_end - 1;
+        // a pass runs its rounds either all as blocks or all op by op (the kernel variants)
+        {
+            bool all = pd.round_end > pd.round_begin;
+            for (int ri = pd.round_begin; ri < pd.round_end; ++ri)
+                if (P.rounds[ri].block_rec < 0) all = false;
+            if (!all)
+                for (int ri = pd.round_begin; ri < pd.round_end; ++ri) P.rounds[ri].block_rec = -1;
+            pd.blocks = all ? 1 : 0;
+        }
         pd.op_end = (int)P.ops.size();
         pd.job_end = (int)P.jobs.size();
         pd.rec_size = rec;

@@ -45,7 +45,7 @@ class Noise(ctypes.Structure):
 
 class Plan(ctypes.Structure):
     _fields_ = [("fuse", ctypes.c_int32), ("tile_bits", ctypes.c_int32),
-                ("reg_bits", ctypes.c_int32), ("run_bits", ctypes.c_int32)]
+                ("reg_bits", ctypes.c_int32), ("run_bits", ctypes.c_int32), ("mfma", ctypes.c_int32)]
 
 
 class SrvConfig(ctypes.Structure):
@@ -297,6 +297,7 @@ def _plan(plan):
     p.tile_bits = int(plan.get("tile_bits", 0))
     p.reg_bits = int(plan.get("reg_bits", 0))
     p.run_bits = int(plan.get("run_bits", 0))
+    p.mfma = int(plan.get("mfma", 0))
     return p
 
 
@@ -365,7 +366,10 @@ def plan_choose(gates, n: int, dtype: int):
     p = Plan()
     cost = ctypes.c_double()
     _check(lib().qs_plan_choose(ga, len(ga), n, dtype, ctypes.byref(p), ctypes.byref(cost)), "plan_choose")
-    return {"fuse": p.fuse, "tile_bits": p.tile_bits, "reg_bits": p.reg_bits, "run_bits": p.run_bits}, cost.value
+    out = {"fuse": p.fuse, "tile_bits": p.tile_bits, "reg_bits": p.reg_bits, "run_bits": p.run_bits}
+    if p.mfma:
+        out["mfma"] = 1
+    return out, cost.value
 
 
 def plan_describe(gates, n: int, dtype: int, plan=None) -> dict:

@@ -32,7 +32,7 @@ def test_struct_sizes_match_header_layout():
     # qs_gate: 4 int32 + 2 uint32 + double + 2 uint64 + 32 doubles
     assert ctypes.sizeof(q.Gate) == 16 + 8 + 8 + 16 + 256
     assert ctypes.sizeof(q.Noise) == 8 + 8 + 4 + 4 + 8
-    assert ctypes.sizeof(q.Plan) == 16
+    assert ctypes.sizeof(q.Plan) == 20
 
 
 def _c_layout(structs):

@@ -66,6 +66,45 @@ def chain_operators(ops, chains):
     return out
 
 
+def block_round(v, rnd, regbits, tbits, ar, outer, ops):
+    """A round run as one dense block (the kernel's matrix-core path): every op's phases
+    conditioned outside the registers on its target's |1> states first, then the ops in order with
+    their phases conditioned on register bits (the block), then the outside output phases."""
+    def cond_of(kind, bit, idx):
+        if kind == 0:
+            return (idx >> regbits[bit]) & 1
+        if kind == 1:
+            return (idx >> tbits[bit]) & 1
+        return np.full(idx.size, (outer >> bit) & 1)
+
+    def phases(v, op, post, inside):
+        j = regbits[op["p0"]]
+        l1 = ar[((ar >> j) & 1) == 1]
+        w = np.ones(l1.size, np.complex128)
+        for kind, pst, bit, cpg in op["phases"]:
+            if pst == post and (kind == 0) == inside:
+                w = w * np.where(cond_of(kind, bit, l1) == 1, ops[cpg], 1.0)
+        v[l1] *= w
+
+    v = v.copy()
+    for op in rnd["ops"]:
+        assert op["type"] == 0 and not (op["flags"] & 2)
+        phases(v, op, 0, False)
+    for op in rnd["ops"]:
+        phases(v, op, 0, True)
+        j = regbits[op["p0"]]
+        l0 = ar[((ar >> j) & 1) == 0]
+        l1 = l0 | (1 << j)
+        M = ops[op["gate"]]
+        x0, x1 = v[l0].copy(), v[l1].copy()
+        v[l0] = M[0, 0] * x0 + M[0, 1] * x1
+        v[l1] = M[1, 0] * x0 + M[1, 1] * x1
+        phases(v, op, 1, True)
+    for op in rnd["ops"]:
+        phases(v, op, 1, False)
+    return v
+
+
 def emulate(circuit, prog, e=0.0, seed=0, traj=0):
     """Run the program the way the kernel does, on memory that starts as garbage (NaN): the
     first pass makes the basis state in its tile, a pass works only on the tiles that can hold
@@ -119,6 +158,9 @@ def emulate(circuit, prog, e=0.0, seed=0, traj=0):
                     m = rnd["reg_mask"]
                     regbits = [j for j in range(K) if (m >> j) & 1]
                     tbits = [j for j in range(K) if not (m >> j) & 1]
+                    if rnd.get("block_rec", -1) >= 0:
+                        v = block_round(v, rnd, regbits, tbits, ar, outer, ops)
+                        continue
                     for op in rnd["ops"]:
                         if op["type"] == 0:
                             # creg: register bits no earlier gate touched; amplitudes that
@@ -210,6 +252,29 @@ def test_planner_program_matches_oracle(plan):
             ref = oracle.sv_run(c, e, seed=7, traj=traj)
             err = np.linalg.norm(unpermute(psi, layout, c.n) - ref)
             assert err < 1e-12, (c.name, plan, e, err)
+
+
+MFMA_PLANS = [{"fuse": 1, "mfma": 1},
+              {"fuse": 1, "tile_bits": 10, "reg_bits": 4, "run_bits": 2, "mfma": 1}]
+
+
+@pytest.mark.parametrize("plan", MFMA_PLANS, ids=["default", "t10r4"])
+def test_block_rounds_match_oracle(plan):
+    """Rounds run as dense blocks: the outside phases moved before and after the block, the ops
+    and their register-conditioned phases in order inside it; against the oracle."""
+    cases = [random_layers(12, 4, seed=21, pairing="random"), random_layers(13, 3, seed=22),
+             random_mixed_circuit(12, 160, seed=23), qft(12, seed=24)]
+    blocks = 0
+    for c in cases:
+        prog = q.plan_describe(c.gates, c.n, q.C64, plan)
+        assert prog["mfma"] == 1 and not prog["chains"]
+        blocks += sum(1 for pas in prog["passes"] for st in pas["stages"] for rd in st["rounds"]
+                      if rd["block_rec"] >= 0)
+        for e, traj in ((0.0, 0), (0.2, 5)):
+            psi, layout = emulate(c, prog, e, seed=9, traj=traj)
+            ref = oracle.sv_run(c, e, seed=9, traj=traj)
+            assert np.linalg.norm(unpermute(psi, layout, c.n) - ref) < 1e-12, (c.name, plan, e)
+    assert blocks >= 6
 
 
 def test_stages_split_long_passes():
