@@ -471,16 +471,56 @@ def dm13_bench(q, torch):
     k = q.timing_read("sweep_2q")
     sweeps = k["launches"]
     gbs = k["alg_bytes"] / (k["ms"] / 1e3) / 1e9 if k["ms"] else 0.0
+    rho.close()
+    torch.cuda.empty_cache()
+    # the same channel through the fused passes: the superoperator circuit on vec(rho) run as one
+    # slot of the trajectory machinery (plan picked by the library, and two fixed shapes)
+    fused = {}
+    sg = q.dm_superop(ga, n, e)
+    for dt, dname in ((q.C128, "c128"), (q.C64, "c64")):
+        ideal_d = ideal if dt == q.C128 else q.StateVector(n, q.C64, 1)
+        if dt == q.C64:
+            ideal_d.amplitudes().copy_(ideal.amplitudes().to(torch.complex64))
+        plans = [("auto", None)]
+        if dt == q.C128:
+            plans += [("t11r3", {"fuse": 1, "tile_bits": 11, "reg_bits": 3, "run_bits": 3}),
+                      ("t12r4", {"fuse": 1, "tile_bits": 12, "reg_bits": 4, "run_bits": 3})]
+        for pname, plan in plans:
+            need = q.dm_run_bytes_required(ga, n, dt, e, plan)
+            buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+            q.dm_run(ga, n, c.init_index, dt, ideal_d, e=e, plan=plan, buf=buf)      # warm-up (plan cache)
+            torch.cuda.synchronize()
+            q.timing_reset()
+            q.timing_enable(True)
+            t2 = time.perf_counter()
+            r = q.dm_run(ga, n, c.init_index, dt, ideal_d, e=e, plan=plan, buf=buf)
+            t3 = time.perf_counter()
+            q.timing_enable(False)
+            kf = q.timing_read("fused")
+            desc = q.plan_describe(sg, 2 * n, dt, plan)
+            fgbs = kf["alg_bytes"] / (kf["ms"] / 1e3) / 1e9 if kf["ms"] else 0.0
+            fused[f"{dname}_{pname}"] = {
+                "plan": {"fused": desc["fused"], "tile_bits": desc["K"], "reg_bits": desc["RB"],
+                         "run_bits": desc["run_bits"]},
+                "passes": len(desc["passes"]), "wall_s": t3 - t2, "fused_ms": kf["ms"],
+                "pass_avg_ms": kf["ms"] / max(kf["launches"], 1), "pass_GBps": round(fgbs, 1),
+                "pass_hbm_frac": round(fgbs / HBM_PEAK_GBS, 4), "fidelity": r["F"], "trace": r["trace"],
+                "fidelity_minus_sweeps": r["F"] - f}
+            log(f"[bench] dm13 fused {dname} {pname}: {t3 - t2:.4f} s, {len(desc['passes'])} passes, "
+                f"F = {r['F']:.12f}")
+            del buf, r
+            torch.cuda.empty_cache()
+        if dt == q.C64:
+            ideal_d.close()
     res = q.run_trajectories(ga, n, c.init_index, q.C128, 2048, e=e, seed=11)
     mc = float(np.mean(res["F"]))
     mc_err = float(np.std(res["F"]) / np.sqrt(2048))
     out = {"workload": f"grover{n} (j={c.meta['iterations']}), vec(rho) complex128, e={e}",
-           "gates": len(c.gates), "superoperator_sweeps": sweeps, "wall_s": t1 - t0,
-           "sweep_avg_ms": k["ms"] / max(sweeps, 1), "sweep_GBps": round(gbs, 1),
+           "gates": len(c.gates), "superoperator_gates": len(sg), "superoperator_sweeps": sweeps,
+           "wall_s": t1 - t0, "sweep_avg_ms": k["ms"] / max(sweeps, 1), "sweep_GBps": round(gbs, 1),
            "sweep_hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "fidelity": f, "trace": tr,
-           "mc_mean_fidelity_T2048": mc, "mc_stderr": mc_err,
+           "fused": fused, "mc_mean_fidelity_T2048": mc, "mc_stderr": mc_err,
            "dm_minus_mc_in_stderr": (f - mc) / mc_err if mc_err > 0 else None}
-    rho.close()
     ideal.close()
     return out
 

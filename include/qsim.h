@@ -68,7 +68,11 @@ typedef enum {
     QS_G_SWAP = 2, /* exchange qubits q0, q1                                                  */
     QS_G_CNOT = 3, /* control q0, target q1                                                   */
     QS_G_U2 = 4,   /* dense two-qubit gate m (4x4), local index bit(q0) + 2 bit(q1)           */
-    QS_G_FLIP = 5  /* negate every amplitude i with (i & mask) == value                       */
+    QS_G_FLIP = 5, /* negate every amplitude i with (i & mask) == value                       */
+    QS_G_DIAG = 6  /* multiply every amplitude i with (i & mask) == value by the complex factor
+                      m[0] + i m[1] (a diagonal gate on the masked bits: a sign flip, a
+                      controlled phase with any number of controls, or one of the non-unitary
+                      diagonal factors of an averaged channel on vec(rho)); noiseless          */
 } qs_gate_kind;
 
 /* Noise tags (Section 2). */
@@ -206,6 +210,46 @@ qs_status qs_fidelity_noalloc(const void *a_dev, const void *b_dev, int n_qubits
 /* <psi|rho|psi> = sum_ij conj(psi_i) rho_ij psi_j and Tr rho, FP64 (Section 3).  rho as in
  * qs_apply_kraus, psi trajectory tpsi of an n-qubit state of the same dtype.  Blocks. */
 qs_status qs_dm_fidelity(qs_state rho, qs_state psi, int tpsi, double *f, double *trace);
+
+/* ------------------------------------------------------------------------------------------
+ * Density-matrix circuit runs (Section 3) through the fused passes: the noisy n-qubit circuit
+ * becomes a noiseless circuit on vec(rho) (2n qubits, entry rho_ij at index i 2^n + j), which
+ * the trajectory machinery runs as one slot, tile by tile, many channels per pass.
+ * ---------------------------------------------------------------------------------------- */
+
+/* The superoperator circuit of gates with noise strength e, written to out (host, cap
+ * entries; out NULL: only *n_out is set).  Every output gate is noiseless:
+ *   - ROT-tagged one-qubit U with e > 0: its eq. (6) Kraus pair {U E1, U E2} as one U2 gate on
+ *     (q0 = q, q1 = q + n) with m[b + 2a][b' + 2a'] = sum_k K_k[a][a'] conj(K_k[b][b'])
+ *     (a, a': row bit; b, b': column bit);
+ *   - PHASE-tagged CP with e > 0: its eq. (9) average as three DIAG gates, rows with both
+ *     qubits 1 by exp(-i theta) exp(-e^2/2), columns with both by exp(i theta) exp(-e^2/2),
+ *     entries with all four by exp(e^2);
+ *   - any other gate G: G on the row bits (qubits + n, masks << n), then conj(G) on the column
+ *     bits (CP with -theta, U1/U2/DIAG with conjugated entries).
+ * Errors: n_qubits outside 1..17, e < 0 or not finite, an invalid gate, cap too small
+ * (QS_EINVAL).  Host only. */
+qs_status qs_dm_superop(const qs_gate *gates, int n_gates, int n_qubits, double e, qs_gate *out, int cap,
+                        int *n_out);
+
+/* Bytes of dev_buf needed by qs_dm_run (0 on invalid arguments). */
+size_t qs_dm_run_bytes_required(const qs_gate *gates, int n_gates, int n_qubits, qs_dtype dt, double e,
+                                const qs_plan *plan);
+
+/* rho = the channel of the noisy circuit applied to |init><init| (Section 3: ROT noise as the
+ * eq. (6) Kraus pair, PHASE noise as the eq. (9) average), computed by running the
+ * qs_dm_superop circuit under `plan` (as in qs_run_trajectories: fused passes or per-gate
+ * sweeps, chosen by the library for fuse = -1).  f_out (host) = <psi|rho|psi> =
+ * sum_ij conj(psi_i) rho_ij psi_j and trace_out (host, nullable) = Tr rho, in FP64, with psi_dev
+ * a caller-owned device state of n_qubits qubits in dtype dt and logical qubit order (the ideal
+ * state, normally).  vec(rho) stays in dev_buf at byte offset 0 with row bit q at physical bit
+ * layout_out[q] + n and column bit q at layout_out[q] (layout_out: nullable, n entries;
+ * SWAPs relabel both halves alike).  Blocks until the results are on the host.  Errors as
+ * qs_dm_superop, plus init_index out of range, NULL psi_dev or f_out, an unaligned or small
+ * buffer (QS_EINVAL), a failed HIP call (QS_EDEVICE). */
+qs_status qs_dm_run(const qs_gate *gates, int n_gates, int n_qubits, uint64_t init_index, qs_dtype dt, double e,
+                    const qs_plan *plan, const void *psi_dev, void *dev_buf, size_t buf_bytes, void *hip_stream,
+                    double *f_out, double *trace_out, int32_t *layout_out);
 
 /* Device noise draws for testing: out_dev[t * n_sites + s] = xi for (sites_dev[s],
  * traj_base + t) on Philox stream `stream` (FP64, device memory).  Asynchronous. */

@@ -85,6 +85,12 @@ class FixedRank:
         for v in self.V:
             v[sel] = -v[sel]
 
+    def apply_diag(self, mask: int, value: int, f: complex):
+        idx = np.arange(1 << self.n, dtype=np.uint64)
+        sel = (idx & np.uint64(mask)) == np.uint64(value)
+        for v in self.V:
+            v[sel] = v[sel] * f
+
     def apply_kraus(self, qubits, ops):
         W = [_apply_op(v, self.n, qubits, K) for K in ops for v in self.V]
         Wm = np.stack(W, axis=1)                      # N x (m * rank)
@@ -141,4 +147,6 @@ def run_circuit(circuit, e: float, r: int, tau: float = 1e-9, zero_tol: float = 
             fr.apply_unitary([g.q0, g.q1], np.asarray(g.m))
         elif g.kind == 5:
             fr.apply_flip(g.mask, g.value)
+        elif g.kind == 6:
+            fr.apply_diag(g.mask, g.value, complex(np.asarray(g.m).reshape(-1)[0]))
     return fr

@@ -195,7 +195,7 @@ void or_normals(uint64_t seed, uint32_t request, uint32_t stream, int64_t n_site
 /* ------------------------------------------------------------------------------------ */
 /* State-vector level (Section 2).                                                       */
 /* ------------------------------------------------------------------------------------ */
-enum { K_U1 = 0, K_CP = 1, K_SWAP = 2, K_CNOT = 3, K_U2 = 4, K_FLIP = 5 };
+enum { K_U1 = 0, K_CP = 1, K_SWAP = 2, K_CNOT = 3, K_U2 = 4, K_FLIP = 5, K_DIAG = 6 };
 enum { N_NONE = 0, N_ROT = 1, N_PHASE = 2 };
 
 /* b_{..0..} = u00 a_{..0..} + u01 a_{..1..},  b_{..1..} = u10 a_{..0..} + u11 a_{..1..} */
@@ -273,6 +273,15 @@ static void sv_flip(cplx *psi, int n, uint64_t mask, uint64_t value)
             psi[i] = -psi[i];
 }
 
+/* The diagonal gate D = I + (f - 1) sum_{i & mask == value} |i><i|. */
+static void sv_diag(cplx *psi, int n, uint64_t mask, uint64_t value, cplx f)
+{
+    uint64_t N = 1ull << n;
+    for (uint64_t i = 0; i < N; ++i)
+        if ((i & mask) == value)
+            psi[i] *= f;
+}
+
 static void load_u1(const double *m, cplx u[2][2])
 {
     for (int r = 0; r < 2; ++r)
@@ -344,6 +353,9 @@ static void sv_run_circuit(cplx *psi, int n, const or_circuit *c, double e, uint
         }
         case K_FLIP:
             sv_flip(psi, n, c->mask[g], c->value[g]);
+            break;
+        case K_DIAG:
+            sv_diag(psi, n, c->mask[g], c->value[g], m[0] + I * m[1]);
             break;
         default:
             break;
@@ -565,6 +577,19 @@ int or_dm_run(int n, int64_t n_gates, const int32_t *kind, const int32_t *q0, co
                     int cj = (j & mask[g]) == value[g];
                     if (ri != cj)
                         rho[i * N + j] = -rho[i * N + j];
+                }
+            break;
+        }
+        case K_DIAG: {
+            /* D rho D^dagger: entry (i, j) times f when row i is selected, times conj(f) when
+               column j is. */
+            cplx f = m[0] + I * m[1];
+            for (uint64_t i = 0; i < N; ++i)
+                for (uint64_t j = 0; j < N; ++j) {
+                    if ((i & mask[g]) == value[g])
+                        rho[i * N + j] *= f;
+                    if ((j & mask[g]) == value[g])
+                        rho[i * N + j] *= conj(f);
                 }
             break;
         }

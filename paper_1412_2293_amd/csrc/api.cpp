@@ -218,8 +218,10 @@ static qs_status check_gate(const qs_gate &g, int n, int idx)
         if (g.kind != QS_G_CP && g.noise != QS_NOISE_NONE) return bad("noise only on U1 and CP");
         break;
     case QS_G_FLIP:
-        if (g.mask & ~nmask) return bad("FLIP mask beyond n bits");
-        if (g.value & ~g.mask) return bad("FLIP value outside its mask");
+    case QS_G_DIAG:
+        if (g.mask & ~nmask) return bad("FLIP/DIAG mask beyond n bits");
+        if (g.value & ~g.mask) return bad("FLIP/DIAG value outside its mask");
+        if (g.noise != QS_NOISE_NONE) return bad("noise only on U1 and CP");
         break;
     default:
         return bad("unknown gate kind");
@@ -265,6 +267,8 @@ static qs_status sweep_gate(void *psi, qs_dtype dt, int n, int S, const qs_gate 
         QS_HIP(launch_sweep_2q(psi, dt, n, S, g.q0, g.q1, g.m, st));
     } else if (g.kind == QS_G_FLIP) {
         QS_HIP(launch_flip(psi, dt, n, S, g.mask, g.value, st));
+    } else if (g.kind == QS_G_DIAG) {
+        QS_HIP(launch_scale_pattern(psi, dt, n, S, g.mask, g.value, g.m[0], g.m[1], st));
     }
     return QS_OK;
 }
@@ -406,6 +410,13 @@ qs_status qs_dm_apply_gate(qs_state rho, const qs_gate *g, double e)
     if (g->kind == QS_G_FLIP) {
         QS_HIP(launch_flip(rho->buf, rho->dt, rho->n, 1, g->mask << n, g->value << n, rho->st));
         QS_HIP(launch_flip(rho->buf, rho->dt, rho->n, 1, g->mask, g->value, rho->st));
+        return QS_OK;
+    }
+    if (g->kind == QS_G_DIAG) {
+        // the factor on the selected rows, its conjugate on the selected columns
+        QS_HIP(launch_scale_pattern(rho->buf, rho->dt, rho->n, 1, g->mask << n, g->value << n, g->m[0], g->m[1],
+                                    rho->st));
+        QS_HIP(launch_scale_pattern(rho->buf, rho->dt, rho->n, 1, g->mask, g->value, g->m[0], -g->m[1], rho->st));
         return QS_OK;
     }
     if (g->kind == QS_G_CP && e > 0 && g->noise == QS_NOISE_PHASE) {
@@ -661,7 +672,8 @@ double model_cost_unfused(const qs_gate *gates, int n_gates, int n, qs_dtype dt,
         switch (gates[g].kind) {
         case QS_G_CP: frac = 0.5; break;   // touches N/4 amplitudes in lines of half the state
         case QS_G_SWAP: frac = 1.0; break;
-        case QS_G_FLIP: frac = 0.0; break;
+        case QS_G_FLIP:
+        case QS_G_DIAG: frac = 0.0; break;
         default: frac = 1.0;
         }
         t += 2.0 * frac * N * amp / kModelHbm + 4e-6 / std::max(S, 1);
@@ -989,6 +1001,7 @@ static qs_status enqueue_compute(const TrajPrep &prep, const TrajLayout &L, char
             case QS_G_CNOT: QS_HIP(launch_sweep_perm(psi, dt, n, S, G.kind, G.q0, G.q1, st)); break;
             case QS_G_U2: QS_HIP(launch_sweep_2q(psi, dt, n, S, G.q0, G.q1, G.m, st)); break;
             case QS_G_FLIP: QS_HIP(launch_flip(psi, dt, n, S, G.mask, G.value, st)); break;
+            case QS_G_DIAG: QS_HIP(launch_scale_pattern(psi, dt, n, S, G.mask, G.value, G.m[0], G.m[1], st)); break;
             }
         }
     }
@@ -1246,6 +1259,233 @@ qs_status qs_run_trajectories(const qs_gate *gates, int n_gates, int n, uint64_t
     qs::traj_finalize(prep, run, fid_out, p_out, norm_out, layout_out);
     return QS_OK;
 }
+
+// ---------------------------------------------------------------------------------------
+// Density-matrix runs (Section 3) through the trajectory machinery
+// ---------------------------------------------------------------------------------------
+namespace qs {
+namespace {
+
+// The gates of a noisy n-qubit circuit as a noiseless circuit on vec(rho) (2n qubits, entry
+// rho_ij at index i 2^n + j): the circuit's channels one after another, each as a gate list
+// on the row bits (q + n) and the column bits (q).
+//   * one-qubit U with ROT noise and e > 0: its eq. (6) Kraus pair {U E1, U E2} as one dense
+//     two-qubit gate on (column bit q, row bit q + n), M[b + 2a][b' + 2a'] =
+//     sum_k K_k[a][a'] conj(K_k[b][b']);
+//   * controlled phase with PHASE noise and e > 0: the averaged channel of eq. (9), entry rho_ij
+//     times exp(-i theta (b_i - b_j)) exp(-e^2 (b_i - b_j)^2 / 2) (b = both qubits 1), as three
+//     diagonal patterns: rows with b_i = 1 by exp(-i theta) exp(-e^2/2), columns with b_j = 1
+//     by exp(i theta) exp(-e^2/2), entries with both by exp(e^2);
+//   * every other gate G (and the noisy ones at e = 0): G on the row bits, conj(G) on the
+//     column bits (SWAP, CNOT and FLIP are real).
+void dm_superop_gates(const qs_gate *gates, int n_gates, int n, double e, std::vector<qs_gate> &out)
+{
+    out.clear();
+    out.reserve((size_t)n_gates * 2);
+    for (int gi = 0; gi < n_gates; ++gi) {
+        const qs_gate &G = gates[gi];
+        qs_gate ket = G, bra = G;
+        ket.noise = bra.noise = QS_NOISE_NONE;
+        if (G.kind == QS_G_U1 && e > 0 && G.noise == QS_NOISE_ROT) {
+            double ops[16];
+            kraus_rot_ops(G.m, e, ops);
+            qs_gate s{};
+            s.kind = QS_G_U2;
+            s.q0 = G.q0;
+            s.q1 = G.q0 + n;
+            s.site = G.site;
+            for (int l = 0; l < 4; ++l)
+                for (int lp = 0; lp < 4; ++lp) {
+                    const int b = l & 1, a = l >> 1, bp = lp & 1, ap = lp >> 1;
+                    std::complex<double> v = 0;
+                    for (int k = 0; k < 2; ++k) {
+                        const double *K = ops + 8 * k;
+                        std::complex<double> ka(K[4 * a + 2 * ap], K[4 * a + 2 * ap + 1]);
+                        std::complex<double> kb(K[4 * b + 2 * bp], K[4 * b + 2 * bp + 1]);
+                        v += ka * std::conj(kb);
+                    }
+                    s.m[2 * (4 * l + lp)] = v.real();
+                    s.m[2 * (4 * l + lp) + 1] = v.imag();
+                }
+            out.push_back(s);
+            continue;
+        }
+        if (G.kind == QS_G_CP && e > 0 && G.noise == QS_NOISE_PHASE) {
+            const uint64_t cm = (1ull << G.q0) | (1ull << G.q1);
+            const double sp = std::exp(-0.5 * e * e);
+            qs_gate d{};
+            d.kind = QS_G_DIAG;
+            d.site = G.site;
+            d.mask = d.value = cm << n;
+            d.m[0] = std::cos(G.theta) * sp;
+            d.m[1] = -std::sin(G.theta) * sp;
+            out.push_back(d);
+            d.mask = d.value = cm;
+            d.m[1] = -d.m[1];
+            out.push_back(d);
+            d.mask = d.value = cm | (cm << n);
+            d.m[0] = std::exp(e * e);
+            d.m[1] = 0.0;
+            out.push_back(d);
+            continue;
+        }
+        switch (G.kind) {
+        case QS_G_U1:
+            ket.q0 += n;
+            for (int k = 1; k < 8; k += 2) bra.m[k] = -G.m[k];
+            break;
+        case QS_G_CP:
+            ket.q0 += n;
+            ket.q1 += n;
+            bra.theta = -G.theta;
+            break;
+        case QS_G_SWAP:
+        case QS_G_CNOT:
+            ket.q0 += n;
+            ket.q1 += n;
+            break;
+        case QS_G_U2:
+            ket.q0 += n;
+            ket.q1 += n;
+            for (int k = 1; k < 32; k += 2) bra.m[k] = -G.m[k];
+            break;
+        case QS_G_FLIP:
+            ket.mask <<= n;
+            ket.value <<= n;
+            break;
+        case QS_G_DIAG:
+            ket.mask <<= n;
+            ket.value <<= n;
+            bra.m[1] = -G.m[1];
+            break;
+        }
+        out.push_back(ket);
+        out.push_back(bra);
+    }
+}
+
+// Buffer of a density-matrix run: the trajectory layout of the superoperator circuit with
+// one slot (vec(rho)), then psi in the run's physical bit order, the expectation partials and
+// its four output doubles.
+struct DmLayout {
+    TrajLayout L;
+    size_t psi, partials, out, total;
+};
+
+DmLayout dm_layout(const TrajPrep &prep, int n)
+{
+    DmLayout D{};
+    D.L = prep_layout(prep, 0);
+    size_t off = D.L.total;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    D.psi = take(state_bytes(n, prep.dt, 1));
+    D.partials = take(reduce_partials_doubles(n, 1) * sizeof(double));
+    D.out = take(16 * sizeof(double));
+    D.total = off;
+    return D;
+}
+
+qs_status dm_prepare(const qs_gate *gates, int n_gates, int n, qs_dtype dt, double e, const qs_plan *plan,
+                     TrajPrep &prep)
+{
+    if (n < 1 || 2 * n > 34) return fail(QS_EINVAL, "dm_run: n_qubits must be in 1..17");
+    if (!std::isfinite(e) || e < 0) return fail(QS_EINVAL, "dm_run: e must be finite and >= 0");
+    qs_status v = check_circuit(gates, n_gates, n);
+    if (v != QS_OK) return v;
+    std::vector<qs_gate> sg;
+    dm_superop_gates(gates, n_gates, n, e, sg);
+    return traj_prepare(sg.data(), (int)sg.size(), 2 * n, dt, plan, prep);
+}
+
+}  // namespace
+}  // namespace qs
+
+extern "C" {
+
+qs_status qs_dm_superop(const qs_gate *gates, int n_gates, int n_qubits, double e, qs_gate *out, int cap,
+                        int *n_out)
+{
+    clear_error();
+    if (!n_out) return fail(QS_EINVAL, "dm_superop: n_out is NULL");
+    *n_out = 0;
+    if (n_qubits < 1 || 2 * n_qubits > 34) return fail(QS_EINVAL, "dm_superop: n_qubits must be in 1..17");
+    if (!std::isfinite(e) || e < 0) return fail(QS_EINVAL, "dm_superop: e must be finite and >= 0");
+    qs_status v = check_circuit(gates, n_gates, n_qubits);
+    if (v != QS_OK) return v;
+    std::vector<qs_gate> sg;
+    qs::dm_superop_gates(gates, n_gates, n_qubits, e, sg);
+    *n_out = (int)sg.size();
+    if (!out) return QS_OK;
+    if (cap < (int)sg.size())
+        return fail(QS_EINVAL, "dm_superop: cap below the " + std::to_string(sg.size()) + " gates of the result");
+    std::copy(sg.begin(), sg.end(), out);
+    return QS_OK;
+}
+
+size_t qs_dm_run_bytes_required(const qs_gate *gates, int n_gates, int n_qubits, qs_dtype dt, double e,
+                                const qs_plan *plan)
+{
+    clear_error();
+    qs::TrajPrep prep;
+    if (qs::dm_prepare(gates, n_gates, n_qubits, dt, e, plan, prep) != QS_OK) return 0;
+    return qs::dm_layout(prep, n_qubits).total;
+}
+
+qs_status qs_dm_run(const qs_gate *gates, int n_gates, int n_qubits, uint64_t init_index, qs_dtype dt, double e,
+                    const qs_plan *plan, const void *psi_dev, void *dev_buf, size_t buf_bytes, void *hip_stream,
+                    double *f_out, double *trace_out, int32_t *layout_out)
+{
+    clear_error();
+    if (!psi_dev || !f_out) return fail(QS_EINVAL, "dm_run: psi_dev and f_out must be non-NULL");
+    if (!dev_buf || !qs::aligned256(dev_buf))
+        return fail(QS_EINVAL, "dm_run: buffer must be non-NULL and 256-byte aligned");
+    const int n = n_qubits;
+    qs::TrajPrep prep;
+    qs_status v = qs::dm_prepare(gates, n_gates, n, dt, e, plan, prep);
+    if (v != QS_OK) return v;
+    if (init_index >= (1ull << n)) return fail(QS_EINVAL, "dm_run: init_index out of range");
+    const qs::DmLayout D = qs::dm_layout(prep, n);
+    if (buf_bytes < D.total)
+        return fail(QS_EINVAL, "dm_run: buffer too small (need " + std::to_string(D.total) + " bytes)");
+    // SWAPs act on the row and the column bits alike, so the relabelling keeps the two halves
+    // apart and permutes them the same way
+    std::vector<int32_t> sigma(n);
+    bool identity = true;
+    for (int q = 0; q < n; ++q) {
+        sigma[q] = prep.layout[q];
+        if (prep.layout[q + n] != prep.layout[q] + n || prep.layout[q] < 0 || prep.layout[q] >= n)
+            return fail(QS_EUNSUPPORTED, "dm_run: the plan's relabelling mixes row and column bits");
+        identity = identity && sigma[q] == q;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    char *B = (char *)dev_buf;
+    if ((v = qs::upload_program(prep, D.L, B, st)) != QS_OK) return v;
+    const double zero = 0.0;
+    QS_HIP(hipMemcpyAsync(B + D.L.edev, &zero, sizeof zero, hipMemcpyHostToDevice, st));
+    const uint64_t init = (init_index << n) | init_index;
+    if ((v = qs::enqueue_compute(prep, D.L, B, 1, init, -1, nullptr, nullptr, st)) != QS_OK) return v;
+    const void *psi_phys = psi_dev;
+    if (!identity) {
+        QS_HIP(qs::launch_permute_bits(B + D.psi, psi_dev, dt, n, sigma.data(), st));
+        psi_phys = B + D.psi;
+    }
+    QS_HIP(qs::launch_dm_expect(B + D.L.states, psi_phys, dt, n, (double *)(B + D.partials),
+                                (double *)(B + D.out), st));
+    double h[4];
+    QS_HIP(hipMemcpyAsync(h, B + D.out, sizeof h, hipMemcpyDeviceToHost, st));
+    QS_HIP(hipStreamSynchronize(st));
+    *f_out = h[0];
+    if (trace_out) *trace_out = h[2];
+    if (layout_out)
+        for (int q = 0; q < n; ++q) layout_out[q] = sigma[q];
+    return QS_OK;
+}
+
+}  // extern "C"
 
 // ---------------------------------------------------------------------------------------
 // Captured trajectory runs

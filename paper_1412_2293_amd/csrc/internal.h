@@ -240,6 +240,10 @@ hipError_t launch_overlaps(const void *ref_psi, int ref_slot, const void *psi, q
 hipError_t launch_dm_expect(const void *rho, const void *psi, qs_dtype dt, int n,
                             double *partials, double *out, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
+// dst[sigma(i)] = src[i] for the 2^n indices of one state, sigma moving index bit q to bit
+// perm[q] (perm: host array of n distinct bits, n <= 40).
+hipError_t launch_permute_bits(void *dst, const void *src, qs_dtype dt, int n, const int32_t *perm,
+                               hipStream_t st);
 
 struct ProgramDev {
     const PassDesc *passes;

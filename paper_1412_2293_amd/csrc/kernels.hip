@@ -266,6 +266,11 @@ __device__ void noisy_operator(const qs_gate &G, int s, const NoiseArgs &na, dou
         o[0] = cs;
         o[1] = -sn;
         for (int k = 2; k < 8; ++k) o[k] = 0.0;
+    } else if (G.kind == QS_G_DIAG) {
+        // the pattern's factor (noiseless)
+        o[0] = G.m[0];
+        o[1] = G.m[1];
+        for (int k = 2; k < 8; ++k) o[k] = 0.0;
     } else {
         for (int k = 0; k < 8; ++k) o[k] = 0.0;
     }
@@ -977,6 +982,43 @@ hipError_t launch_dm_expect(const void *rho, const void *psi, qs_dtype dt, int n
         hipLaunchKernelGGL(k_dm_expect_partial<double>, dim3(1u << lb), dim3(kRedThreads), 0, st,
                            (const double *)rho, (const double *)psi, n, lb, partials);
     hipLaunchKernelGGL(k_sum4_final, dim3(1), dim3(kRedThreads), 0, st, partials, 1 << lb, out);
+    return hipGetLastError();
+}
+
+// dst[sigma(i)] = src[i] over the n-bit indices i, sigma moving bit q of i to bit perm[q] (one
+// state vector; sigma must be a permutation of 0..n-1).
+struct BitPerm {
+    int8_t p[40];
+};
+
+template <typename R>
+__global__ void k_permute_bits(R *dst, const R *src, int n, BitPerm bp, uint64_t total)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t j = 0;
+        for (int q = 0; q < n; ++q)
+            if ((i >> q) & 1ull) j |= 1ull << bp.p[q];
+        dst[2 * j] = src[2 * i];
+        dst[2 * j + 1] = src[2 * i + 1];
+    }
+}
+
+hipError_t launch_permute_bits(void *dst, const void *src, qs_dtype dt, int n, const int32_t *perm,
+                               hipStream_t st)
+{
+    if (n < 1 || n > 40) return hipErrorInvalidValue;
+    BitPerm bp{};
+    for (int q = 0; q < n; ++q) bp.p[q] = (int8_t)perm[q];
+    const uint64_t total = 1ull << n;
+    TimedLaunch tl("copy", 2.0 * (double)total * amp_bytes(dt), st);
+    unsigned blocks = (unsigned)std::min<uint64_t>(blocks_for(total, 256), 256u * 64u);
+    if (dt == QS_C64)
+        hipLaunchKernelGGL(k_permute_bits<float>, dim3(blocks), dim3(256), 0, st, (float *)dst,
+                           (const float *)src, n, bp, total);
+    else
+        hipLaunchKernelGGL(k_permute_bits<double>, dim3(blocks), dim3(256), 0, st, (double *)dst,
+                           (const double *)src, n, bp, total);
     return hipGetLastError();
 }
 

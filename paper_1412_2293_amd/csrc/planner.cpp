@@ -125,11 +125,12 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         }
         PG x;
         x.kind = G.kind;
-        x.a = (G.kind == QS_G_FLIP) ? 0 : perm[G.q0];
+        const bool pattern = G.kind == QS_G_FLIP || G.kind == QS_G_DIAG;
+        x.a = pattern ? 0 : perm[G.q0];
         x.b = (G.kind == QS_G_CP || G.kind == QS_G_U2 || G.kind == QS_G_CNOT) ? perm[G.q1] : -1;
         x.gate = g;
         x.mask = x.value = 0;
-        if (G.kind == QS_G_FLIP) {
+        if (pattern) {
             x.mask = map_mask(G.mask);
             x.value = map_mask(G.value);
         }
@@ -234,7 +235,7 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
     for (size_t i = 0; i < pg.size(); ++i) {
         const PG &x = pg[i];
         if (x.kind != QS_G_CP) {
-            if (x.kind == QS_G_FLIP) standalone[i] = true;
+            if (x.kind == QS_G_FLIP || x.kind == QS_G_DIAG) standalone[i] = true;
             continue;
         }
         auto next_of = [&](int q) {
@@ -534,6 +535,10 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                     uint64_t mask, value;
                     if (x.kind == QS_G_FLIP) {
                         op.diag_kind = DIAG_NEGATE;
+                        mask = x.mask;
+                        value = x.value;
+                    } else if (x.kind == QS_G_DIAG) {
+                        op.diag_kind = DIAG_PHASE;   // the factor comes from the gate's table row
                         mask = x.mask;
                         value = x.value;
                     } else {

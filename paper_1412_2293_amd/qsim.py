@@ -17,14 +17,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqsim.so")
 
 C64, C128 = 0, 1
-U1, CP, SWAP, CNOT, U2, FLIP = 0, 1, 2, 3, 4, 5
+U1, CP, SWAP, CNOT, U2, FLIP, DIAG = 0, 1, 2, 3, 4, 5, 6
 NOISE_NONE, NOISE_ROT, NOISE_PHASE = 0, 1, 2
 
 __all__ = ["QsimError", "lib", "Gate", "Noise", "Plan", "C64", "C128", "gate_array",
            "sv_bytes_required", "StateVector", "apply_gate", "apply_kraus", "fidelity",
            "dm_fidelity", "fidelity_noalloc", "dm_apply_gate", "noise_draw", "traj_bytes_required", "run_trajectories",
            "timing_enable", "timing_read", "plan_describe", "plan_choose", "traj_layout", "timing_reset", "copy", "FixedRank", "trajectory_states",
-           "fr_bytes_required", "kraus_cp", "TrajGraph", "Server", "SrvConfig", "SrvJobInfo", "SrvStats", "LIB_PATH"]
+           "fr_bytes_required", "kraus_cp", "dm_superop", "dm_run_bytes_required", "dm_run", "dm_state", "TrajGraph", "Server", "SrvConfig", "SrvJobInfo", "SrvStats", "LIB_PATH"]
 
 
 class QsimError(RuntimeError):
@@ -117,6 +117,9 @@ def lib():
         "qs_fr_apply_kraus2": ([P, i32, i32, i32, P, dbl, dbl, P], st),
         "qs_kraus_cp": ([dbl, dbl, i32, P], st),
         "qs_fidelity_noalloc": ([P, P, i32, i32, P, P], st),
+        "qs_dm_superop": ([P, i32, i32, dbl, P, i32, ctypes.POINTER(ctypes.c_int)], st),
+        "qs_dm_run_bytes_required": ([P, i32, i32, i32, dbl, ctypes.POINTER(Plan)], sz),
+        "qs_dm_run": ([P, i32, i32, u64, i32, dbl, ctypes.POINTER(Plan), P, P, sz, P, P, P, P], st),
         "qs_fr_fidelity": ([P, P, i32, P, P, P], st),
         "qs_fr_info": ([P, P, P, P], st),
         "qs_traj_graph_bytes_required": ([P, i32, i32, i32, i32, ctypes.POINTER(Plan), ctypes.POINTER(sz)], st),
@@ -336,6 +339,55 @@ def run_trajectories(gates, n: int, init_index: int, dtype: int, n_traj: int, e=
            "run_trajectories")
     del keep
     return {"F": F, "p": P if marked >= 0 else None, "norm": norms, "layout": layout, "buf": buf}
+
+
+def dm_superop(gates, n: int, e: float = 0.0) -> ctypes.Array:
+    """The noiseless 2n-qubit circuit on vec(rho) that the library builds for a density-matrix
+    run of the noisy circuit (qs_dm_superop)."""
+    ga = gates if isinstance(gates, ctypes.Array) else gate_array(gates)
+    cnt = ctypes.c_int(0)
+    _check(lib().qs_dm_superop(ga, len(ga), n, float(e), None, 0, ctypes.byref(cnt)), "dm_superop")
+    out = (Gate * max(cnt.value, 1))()
+    _check(lib().qs_dm_superop(ga, len(ga), n, float(e), out, len(out), ctypes.byref(cnt)), "dm_superop")
+    return (Gate * cnt.value).from_buffer(out) if cnt.value else (Gate * 0)()
+
+
+def dm_run_bytes_required(gates, n: int, dtype: int, e: float = 0.0, plan=None) -> int:
+    ga = gates if isinstance(gates, ctypes.Array) else gate_array(gates)
+    p = _plan(plan)
+    return int(lib().qs_dm_run_bytes_required(ga, len(ga), n, dtype, float(e), ctypes.byref(p) if p else None))
+
+
+def dm_run(gates, n: int, init_index: int, dtype: int, psi, e: float = 0.0, plan=None, buf=None, stream=None):
+    """Density-matrix run of the noisy circuit (qs_dm_run): returns a dict with F =
+    <psi|rho|psi>, trace, layout and the device buffer whose first 4^n amplitudes are vec(rho)
+    (row bit q at layout[q] + n, column bit q at layout[q]).  psi: the n-qubit state (device
+    tensor or StateVector, logical order) to take the expectation with."""
+    import torch
+    ga = gates if isinstance(gates, ctypes.Array) else gate_array(gates)
+    p = _plan(plan)
+    need = int(lib().qs_dm_run_bytes_required(ga, len(ga), n, dtype, float(e), ctypes.byref(p) if p else None))
+    if need == 0:
+        raise QsimError("dm_run_bytes_required rejected the arguments: " + lib().qs_last_error().decode())
+    if buf is None:
+        buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+    psi_ptr = ctypes.c_void_p(psi.buf.data_ptr()) if isinstance(psi, StateVector) else _ptr(psi)
+    f = ctypes.c_double(0.0)
+    tr = ctypes.c_double(0.0)
+    layout = np.zeros(n, np.int32)
+    _check(lib().qs_dm_run(ga, len(ga), n, int(init_index), dtype, float(e), ctypes.byref(p) if p else None,
+                           psi_ptr, _ptr(buf), buf.numel() * buf.element_size(), _stream(stream),
+                           ctypes.byref(f), ctypes.byref(tr), _ptr(layout)), "dm_run")
+    return {"F": f.value, "trace": tr.value, "layout": layout, "buf": buf}
+
+
+def dm_state(res, n: int, dtype: int):
+    """vec(rho) of a dm_run result as a complex torch tensor view [4^n] (physical order)."""
+    import torch
+    ft = torch.float32 if dtype == C64 else torch.float64
+    N = 1 << (2 * n)
+    nbytes = N * (8 if dtype == C64 else 16)
+    return torch.view_as_complex(res["buf"][:nbytes].view(ft).view(N, 2))
 
 
 def trajectory_states(res, n: int, dtype: int, n_traj: int):

@@ -15,6 +15,8 @@ Conventions (shared vocabulary of the circuit description):
   * U2    dense two-qubit gate, 4x4 complex matrix, local index bit(q0) + 2*bit(q1);
   * FLIP  negate every amplitude whose index i satisfies (i & mask) == value
           (the Grover oracle and the reflection about |0>, both noiseless);
+  * DIAG  multiply every amplitude whose index i satisfies (i & mask) == value by the
+          complex factor m[0] (noiseless; a phase on any set of controls);
   * noise tag ROT   : the gate becomes U * V(e*xi) with V of eq. (1);
     noise tag PHASE : theta -> theta + e*xi on the |11> element (Section 2, after eq. (2)).
 """
@@ -26,8 +28,8 @@ from typing import List, Optional
 
 import numpy as np
 
-U1, CP, SWAP, CNOT, U2, FLIP = 0, 1, 2, 3, 4, 5
-KIND_NAMES = {U1: "U1", CP: "CP", SWAP: "SWAP", CNOT: "CNOT", U2: "U2", FLIP: "FLIP"}
+U1, CP, SWAP, CNOT, U2, FLIP, DIAG = 0, 1, 2, 3, 4, 5, 6
+KIND_NAMES = {U1: "U1", CP: "CP", SWAP: "SWAP", CNOT: "CNOT", U2: "U2", FLIP: "FLIP", DIAG: "DIAG"}
 NOISE_NONE, NOISE_ROT, NOISE_PHASE = 0, 1, 2
 
 H_MATRIX = np.array([[1.0, 1.0], [1.0, -1.0]], dtype=np.complex128) / math.sqrt(2.0)
@@ -42,8 +44,8 @@ class Gate:
     theta: float = 0.0                  # CP angle
     noise: int = NOISE_NONE
     site: int = 0                       # Philox counter word 0 for this gate's noise draw
-    mask: int = 0                       # FLIP
-    value: int = 0                      # FLIP
+    mask: int = 0                       # FLIP, DIAG
+    value: int = 0                      # FLIP, DIAG
 
 
 @dataclass
@@ -76,7 +78,7 @@ class Circuit:
                 tot += N // 4
             elif g.kind in (SWAP, CNOT):
                 tot += N // 2
-            elif g.kind == FLIP:
+            elif g.kind in (FLIP, DIAG):
                 tot += N >> bin(g.mask).count("1")
         return tot
 
