@@ -684,7 +684,8 @@ double model_cost_unfused(const qs_gate *gates, int n_gates, int n, qs_dtype dt,
 // Candidate shapes per dtype: (tile bits, register bits, run bits).
 static const int kCandC64[][3] = {{12, 4, 4}, {12, 4, 5}, {12, 3, 5}, {12, 3, 4}, {12, 3, 3}, {11, 3, 4},
                                   {11, 2, 3}, {10, 2, 3}};
-static const int kCandC128[][3] = {{11, 3, 4}, {11, 3, 3}, {11, 2, 4}, {11, 2, 3}, {10, 2, 3}, {10, 1, 3}};
+static const int kCandC128[][3] = {{11, 3, 4}, {11, 3, 3}, {11, 2, 4}, {11, 2, 3}, {10, 2, 3}, {10, 1, 3},
+                                   {12, 4, 3}, {12, 4, 4}};
 
 qs_status autotune_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, int S, Plan &out,
                         double *cost_out)
@@ -695,7 +696,8 @@ qs_status autotune_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, i
     double best = model_cost_unfused(gates, n_gates, n, dt, S);
     out = Plan();
     out.fused = false;
-    const int ncand = dt == QS_C64 ? 8 : 6;
+    const int ncand = dt == QS_C64 ? (int)(sizeof kCandC64 / sizeof kCandC64[0])
+                                   : (int)(sizeof kCandC128 / sizeof kCandC128[0]);
     for (int c = 0; c < ncand; ++c) {
         const int *k = dt == QS_C64 ? kCandC64[c] : kCandC128[c];
         if (two_qubit_dense && k[1] < 2) continue;
@@ -730,13 +732,12 @@ qs_status resolve_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, in
     if (fuse == -1) fuse = 1;
     out.fused = fuse == 1;
     if (!out.fused) return QS_OK;
-    // defaults: 2^12-amplitude tiles of 16 registers per thread (complex<float>), 2^11 of 8
-    // (complex<double>), both 256 threads: the largest register tiles that stay out of scratch
-    // memory; rows of 128 B, the shortest that still stream at full rate (fewer register rounds
-    // than longer rows), the fastest measured
-    int K = (p && p->tile_bits > 0) ? p->tile_bits : (dt == QS_C64 ? 12 : 11);
-    int RB = (p && p->reg_bits > 0) ? p->reg_bits : (dt == QS_C64 ? 4 : 3);
-    int run = (p && p->run_bits > 0) ? p->run_bits : (dt == QS_C64 ? 4 : 3);
+    // defaults: 2^12-amplitude tiles of 16 registers per thread over 256 threads, the largest
+    // register tiles that stay out of scratch memory (complex<double> at two waves per SIMD);
+    // rows of 16 amplitudes (128 B, 256 B), the fastest measured
+    int K = (p && p->tile_bits > 0) ? p->tile_bits : 12;
+    int RB = (p && p->reg_bits > 0) ? p->reg_bits : 4;
+    int run = (p && p->run_bits > 0) ? p->run_bits : 4;
     if (p && (p->mfma < 0 || p->mfma > 1)) return fail(QS_EINVAL, "plan: mfma must be 0 or 1");
     return fused_plan_for(gates, n_gates, n, dt, K, RB, run, out, p && p->mfma == 1);
 }
