@@ -59,7 +59,8 @@ def parse():
     ap.add_argument("--serving-inflight", type=int, default=4)
     ap.add_argument("--leg", default="",
                     help="run only this side measurement (large_state_n32, graph_replay, dm13, dm_qft13, "
-                         "fr24, fr_vs_dm12, choi, sweeps_n28) and print its JSON (profiling runs)")
+                         "fr24, fr_vs_dm12, choi, sweeps_n28, sweeps_n30, grover12_dynamics, grover10_c1, "
+                         "serving_full_range, fr24_full, block_rounds_n30) and print its JSON")
     return ap.parse_args()
 
 
@@ -75,7 +76,7 @@ def main():
     import paper_1412_2293_amd as q
     from workloads import qft
 
-    leg_names = ("large_state_n32", "graph_replay", "dm13", "dm_qft13", "fr24", "fr_vs_dm12", "choi", "sweeps_n28",
+    leg_names = ("large_state_n32", "graph_replay", "dm13", "dm_qft13", "fr24", "fr_vs_dm12", "choi", "sweeps_n28", "sweeps_n30",
                  "grover12_dynamics", "grover10_c1", "serving_full_range", "fr24_full", "block_rounds_n30")
     if a.leg and a.leg not in leg_names:
         print(f"unknown leg {a.leg}; one of {', '.join(leg_names)}", file=sys.stderr)
@@ -86,12 +87,15 @@ def main():
                 "dm13": lambda: dm13_bench(q, torch), "dm_qft13": lambda: dm_qft13_bench(q, torch),
                 "fr24": lambda: fr24_bench(q, torch), "fr_vs_dm12": lambda: fr_vs_dm12_bench(q, torch),
                 "choi": lambda: choi_bench(q, torch), "sweeps_n28": lambda: sweeps(q),
+                "sweeps_n30": lambda: sweeps(q, 30),
                 "grover12_dynamics": lambda: grover12_dynamics_bench(q, torch),
                 "grover10_c1": lambda: grover10_c1_bench(q, torch),
                 "serving_full_range": lambda: serving_full_range_bench(q, torch),
                 "fr24_full": lambda: fr24_bench(q, torch, iterations=None),
                 "block_rounds_n30": lambda: block_rounds_bench(q, torch)}
         print(json.dumps({a.leg: legs[a.leg]()}), flush=True)
+        if a.copy_calibration:
+            copy_calibration(q, torch)
         return
     n, Te = a.n, a.traj_per_e
     T = 2 * Te
@@ -170,12 +174,7 @@ def main():
     out["hbm_frac_step"] = round(step_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     del res
     if a.copy_calibration:
-        nb = 1 << 30
-        src = torch.empty(nb, dtype=torch.uint8, device="cuda")
-        dst = torch.empty(nb, dtype=torch.uint8, device="cuda")
-        q.copy(dst, src, nb, stream)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration(q, torch)
 
     if not a.no_extras:
         del buf
@@ -183,6 +182,8 @@ def main():
         out["fp64_unfused"] = fp64_unfused(q, c, ga, n, T, es, seed, F_c64, value)
         torch.cuda.empty_cache()
         out["sweeps_n28"] = sweeps(q)
+        torch.cuda.empty_cache()
+        out["sweeps_n30"] = sweeps(q, 30)
         torch.cuda.empty_cache()
         out["large_state_n32"] = large_state_bench(q, torch)
         torch.cuda.empty_cache()
@@ -269,25 +270,53 @@ def fp64_unfused(q, c, ga, n, T, es, seed, F_c64, fused_value):
             "max_abs_dF_f32_fused_vs_f64_unfused": dF, "kernels": sweeps_, "fused_f64": fused64}
 
 
-def sweeps(q):
-    """Unfused sweep kernels on n = 28 (one state + 1 more trajectory), every regime."""
+def copy_calibration(q, torch):
+    """One plain copy of 1 GiB (the library's copy kernel): 1 GiB read and 1 GiB written, the
+    reference for scaling the HBM byte counters of a profiled run."""
+    nb = 1 << 30
+    src = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    q.copy(dst, src, nb, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def sweeps(q, n=28):
+    """Unfused sweep kernels on one state + 1 more trajectory of n qubits, both dtypes: dense
+    one-qubit gates on low, middle and top qubits; controlled phases, SWAPs, CNOTs and dense
+    two-qubit gates on low pairs (runs of 2^lo contiguous amplitudes: short rows) and on high
+    pairs (long rows).  Algorithmic bytes: what the gate must read and write (N amplitudes for
+    dense gates, N/4 for a controlled phase, N/2 for a SWAP or CNOT)."""
     import torch
-    from workloads import CP, Gate, SWAP, U1, haar_2x2
+    from workloads import CNOT, CP, Gate, SWAP, U1, U2, haar_2x2
     import numpy as np
-    log("[bench] unfused sweeps at n=28")
+    log(f"[bench] unfused sweeps at n={n}")
     rng = np.random.default_rng(0)
+
+    def haar4():
+        z = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+        qm, r = np.linalg.qr(z)
+        return qm * (np.diag(r) / np.abs(np.diag(r)))
+
     out = {}
-    n, T = 28, 2
+    T = 2
+    top = n - 1
     for dt, name in ((q.C64, "c64"), (q.C128, "c128")):
         sv = q.StateVector(n, dt, T)
         sv.init_basis(0)
         res = {}
         cases = [("u1_q0", Gate(U1, q0=0, m=haar_2x2(rng))), ("u1_q1", Gate(U1, q0=1, m=haar_2x2(rng))),
                  ("u1_q6", Gate(U1, q0=6, m=haar_2x2(rng))), ("u1_q14", Gate(U1, q0=14, m=haar_2x2(rng))),
-                 ("u1_q27", Gate(U1, q0=27, m=haar_2x2(rng))), ("cp_3_20", Gate(CP, q0=3, q1=20, theta=0.3)),
-                 ("swap_2_25", Gate(SWAP, q0=2, q1=25))]
+                 (f"u1_q{top}", Gate(U1, q0=top, m=haar_2x2(rng))),
+                 ("cp_3_20", Gate(CP, q0=3, q1=20, theta=0.3)), ("swap_2_25", Gate(SWAP, q0=2, q1=25)),
+                 ("u2_3_20", Gate(U2, q0=3, q1=20, m=haar4())),
+                 (f"cp_18_{top}", Gate(CP, q0=18, q1=top, theta=0.3)),
+                 (f"swap_20_{top}", Gate(SWAP, q0=20, q1=top)),
+                 (f"cnot_19_{top - 1}", Gate(CNOT, q0=19, q1=top - 1)),
+                 (f"u2_20_{top}", Gate(U2, q0=20, q1=top, m=haar4()))]
         for label, g in cases:
-            kname = {U1: "sweep_u1", CP: "sweep_cp", SWAP: "sweep_swap"}[g.kind]
+            kname = {U1: "sweep_u1", CP: "sweep_cp", SWAP: "sweep_swap", CNOT: "sweep_swap",
+                     U2: "sweep_2q"}[g.kind]
             q.apply_gate(sv, g)
             torch.cuda.synchronize()
             q.timing_reset()
