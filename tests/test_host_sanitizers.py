@@ -21,8 +21,12 @@ def test_abi_and_planner_under_host_sanitizers(tmp_path):
     from paper_1412_2293_amd import build
     lib = build.build(sanitize=True)
     env = dict(os.environ)
+    # the ASan runtime must come first; whatever the environment already preloads stays after it
+    preload = build.asan_runtime()
+    if env.get("LD_PRELOAD"):
+        preload += ":" + env["LD_PRELOAD"]
     env.update({
-        "LD_PRELOAD": build.asan_runtime(),
+        "LD_PRELOAD": preload,
         "ASAN_OPTIONS": "detect_leaks=0:verify_asan_link_order=0:abort_on_error=1",
         "UBSAN_OPTIONS": "print_stacktrace=1:halt_on_error=1",
         "QSIM_TEST_LIB": lib,
