@@ -76,7 +76,7 @@ def main():
     import paper_1412_2293_amd as q
     from workloads import qft
 
-    leg_names = ("large_state_n32", "graph_replay", "dm13", "dm_qft13", "fr24", "fr_vs_dm12", "choi", "sweeps_n28", "sweeps_n30",
+    leg_names = ("large_state_n32", "graph_replay", "dm13", "dm_qft13", "dm_qft17", "fr24", "fr_vs_dm12", "choi", "sweeps_n28", "sweeps_n30",
                  "grover12_dynamics", "grover10_c1", "serving_full_range", "fr24_full", "block_rounds_n30")
     if a.leg and a.leg not in leg_names:
         print(f"unknown leg {a.leg}; one of {', '.join(leg_names)}", file=sys.stderr)
@@ -85,6 +85,7 @@ def main():
     if a.leg:
         legs = {"large_state_n32": lambda: large_state_bench(q, torch), "graph_replay": lambda: graph_bench(q, torch),
                 "dm13": lambda: dm13_bench(q, torch), "dm_qft13": lambda: dm_qft13_bench(q, torch),
+                "dm_qft17": lambda: dm_qft17_bench(q, torch),
                 "fr24": lambda: fr24_bench(q, torch), "fr_vs_dm12": lambda: fr_vs_dm12_bench(q, torch),
                 "choi": lambda: choi_bench(q, torch), "sweeps_n28": lambda: sweeps(q),
                 "sweeps_n30": lambda: sweeps(q, 30),
@@ -166,6 +167,16 @@ def main():
                    "plan": plan, "plan_chosen": chosen},
         "trajectories_per_s": T / (ms_step / 1e3),
         "hbm_frac_step": None,
+        # the paper's figures, with their hardware: context only (it gives no runtimes)
+        "paper_figures": [
+            {"what": "largest state-vector simulation", "value": "39 qubits",
+             "hardware": "Lomonosov, MVS-100K and MVS-10P supercomputers (distributed state)"},
+            {"what": "speed-up of the active-message programming model", "value": "about 10x",
+             "hardware": "the same supercomputers (baseline not stated)"},
+            {"what": "largest Kraus-operator (density-matrix) simulation", "value": "17 qubits",
+             "hardware": "Lomonosov"},
+            {"what": "here, on one MI355X", "value": "state vectors up to 34 qubits (complex64, 128 GiB per "
+             "slot; 33 checked against a closed form), density matrices up to 17 qubits (the dm_qft17 leg)"}],
         "roofline": roofline,
         "kernels_ms_per_step": {k: v["ms"] / a.steps for k, v in kernels.items()},
     }
@@ -191,6 +202,8 @@ def main():
         out["dm13"] = dm13_bench(q, torch)
         torch.cuda.empty_cache()
         out["dm_qft13"] = dm_qft13_bench(q, torch)
+        torch.cuda.empty_cache()
+        out["dm_qft17"] = dm_qft17_bench(q, torch)
         torch.cuda.empty_cache()
         out["fr24"] = fr24_bench(q, torch)
         torch.cuda.empty_cache()
@@ -551,6 +564,58 @@ def dm13_bench(q, torch):
            "fused": fused, "mc_mean_fidelity_T2048": mc, "mc_stderr": mc_err,
            "dm_minus_mc_in_stderr": (f - mc) / mc_err if mc_err > 0 else None}
     ideal.close()
+    return out
+
+
+def dm_qft17_bench(q, torch, e=0.01):
+    """The largest density matrix the library takes: a QFT on n = 17 qubits, vec(rho) of 2^34
+    complex64 entries (128 GiB), noisy Hadamards (eq. 6) and noisy controlled phases (eq. 9),
+    through the fused density-matrix run (automatic plan); the exact fidelity beside its closed
+    form, the noise average of the trajectory fidelity prod_t (1 + exp(-2e^2) exp(-e^2 m_t/2))/2."""
+    import math
+
+    import numpy as np
+    from workloads import qft
+    n = 17
+    c = qft(n, seed=17)
+    x = c.init_index
+    N = 1 << n
+    ex = np.zeros(N, np.complex128)
+    ex[x] = 1.0
+    psi = np.fft.fft(ex) / math.sqrt(N)
+    ideal = q.StateVector(n, q.C64, 1)
+    ideal.amplitudes().copy_(torch.as_tensor(psi[None, :].astype(np.complex64)).to("cuda"))
+    ga = q.gate_array(c.gates)
+    need = q.dm_run_bytes_required(ga, n, q.C64, e)
+    log(f"[bench] dm_qft17: vec(rho) of 2^{2 * n} complex64 entries ({need / 2**30:.1f} GiB buffer)")
+    buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+    q.dm_run(ga, n, x, q.C64, ideal, e=e, buf=buf)      # warm-up (plan cache)
+    torch.cuda.synchronize()
+    q.timing_reset()
+    q.timing_enable(True)
+    t0 = time.perf_counter()
+    r = q.dm_run(ga, n, x, q.C64, ideal, e=e, buf=buf)
+    t1 = time.perf_counter()
+    q.timing_enable(False)
+    kf = q.timing_read("fused")
+    gbs = kf["alg_bytes"] / (kf["ms"] / 1e3) / 1e9 if kf["ms"] else 0.0
+    F = 1.0
+    for t in range(n):
+        m = bin(x & ((1 << t) - 1)).count("1")
+        F *= 0.5 * (1.0 + math.exp(-2 * e * e) * math.exp(-e * e * m / 2))
+    sg = q.dm_superop(ga, n, e)
+    desc = q.plan_describe(sg, 2 * n, q.C64, None)
+    out = {"workload": f"qft{n} (x={x}) on vec(rho) of 2^{2 * n} entries, complex64, e={e}, noisy H (eq. 6) "
+                       "and controlled phases (eq. 9), fused density-matrix run",
+           "gates": len(c.gates), "superoperator_gates": len(sg), "passes": len(desc["passes"]),
+           "plan": {"tile_bits": desc["K"], "reg_bits": desc["RB"], "run_bits": desc["run_bits"]},
+           "wall_s": t1 - t0, "fused_ms": kf["ms"], "pass_GBps": round(gbs, 1),
+           "pass_hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "fidelity": r["F"], "fidelity_closed_form": F,
+           "abs_dF": abs(r["F"] - F), "trace": r["trace"],
+           "paper": "17-qubit Kraus-operator simulation on the Lomonosov supercomputer (no runtime given)"}
+    del buf, r
+    ideal.close()
+    torch.cuda.empty_cache()
     return out
 
 
@@ -942,27 +1007,46 @@ def serving_full_range_bench(q, torch, inflight=4, first=60, max_model_s=1.0, po
                                for r in recs), key=lambda x: -x["n"])[:6]}
 
 
-def cpu_baseline(c, prefix=None):
-    """The CPU oracle, single thread, on a bounded sample of the workload: one noisy trajectory
-    (e = 0.01) of the same circuit (all gates unless `prefix` is given), run as one oracle
-    call (about 15 s on one host core)."""
-    import oracle
+def cpu_baseline(c, prefix=None, workers=None):
+    """The CPU oracle on a bounded sample of the workload: one noisy trajectory (e = 0.01) of the
+    same circuit (all gates unless `prefix` is given) per host core, each an oracle call in a
+    child process of its own (about 15 s each), all cores at once.  Value: the amplitude updates
+    of all of them over the wall time; beside it the single-core rate (mean over the children)."""
+    import numpy as np
     from workloads import Circuit
-    log("[bench] cpu baseline (oracle, 1 thread)")
-    oracle.lib()
+    if workers is None:
+        # the host's CPU share for one GPU is 16 cores, whatever the machine reports
+        workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    log(f"[bench] cpu baseline (oracle, {workers} processes, one thread each)")
     n = c.n
     N = 1 << n
     prefix = len(c.gates) if prefix is None else prefix
     part = Circuit(n, c.gates[:prefix], init_index=c.init_index)
     updates = sum({0: N, 1: N // 4, 2: N // 2}.get(g.kind, N) for g in part.gates)
+    child = ("import sys, time; sys.path.insert(0, {root!r}); import oracle; from workloads import qft, Circuit; "
+             "c = qft({n}, seed={seed}); p = Circuit({n}, c.gates[:{prefix}], init_index=c.init_index); "
+             "oracle.lib(); t0 = time.perf_counter(); oracle.sv_run(p, 0.01, seed=1, traj={traj}); "
+             "print(time.perf_counter() - t0)")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
     t0 = time.perf_counter()
-    oracle.sv_run(part, 0.01, seed=1, traj=64)
-    dt = time.perf_counter() - t0
-    return {"value": updates / dt, "unit": "amplitude-updates/s", "cores": 1, "kind": "oracle",
-            "host_cores": os.cpu_count(),
-            "sample": f"qft{n} trajectory 64 (e=0.01): first {prefix} of {len(c.gates)} gates "
-                      f"({part.count(0)} H, {part.count(1)} controlled phases), complex128 plain "
-                      f"loops, {dt:.1f} s"}
+    procs = [subprocess.Popen([sys.executable, "-c", child.format(root=ROOT, n=n, seed=c.meta.get("seed", 1),
+                                                                   prefix=prefix, traj=64 + k)],
+                              stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+             for k in range(workers)]
+    times = []
+    for pr in procs:
+        out, err = pr.communicate()
+        if pr.returncode != 0:
+            raise RuntimeError(f"cpu baseline child failed ({pr.returncode}): {err[-400:]}")
+        times.append(float(out.strip().split()[-1]))
+    wall = time.perf_counter() - t0
+    return {"value": workers * updates / wall, "unit": "amplitude-updates/s", "cores": workers,
+            "kind": "oracle", "host_cores": os.cpu_count(),
+            "single_core_value": float(np.mean([updates / t for t in times])),
+            "sample": f"qft{n}: {workers} noisy trajectories (e=0.01, trajectory counters 64..{63 + workers}), one "
+                      f"per process and core, each the first {prefix} of {len(c.gates)} gates "
+                      f"({part.count(0)} H, {part.count(1)} controlled phases) in complex128 plain loops; "
+                      f"wall {wall:.1f} s, per process {min(times):.1f}-{max(times):.1f} s"}
 
 
 if __name__ == "__main__":
