@@ -318,8 +318,8 @@ def sweeps(q, n=28):
         sv = q.StateVector(n, dt, T)
         sv.init_basis(0)
         res = {}
-        cases = [("u1_q0", Gate(U1, q0=0, m=haar_2x2(rng))), ("u1_q1", Gate(U1, q0=1, m=haar_2x2(rng))),
-                 ("u1_q6", Gate(U1, q0=6, m=haar_2x2(rng))), ("u1_q14", Gate(U1, q0=14, m=haar_2x2(rng))),
+        cases = [(f"u1_q{k}", Gate(U1, q0=k, m=haar_2x2(rng))) for k in range(8)]
+        cases += [("u1_q14", Gate(U1, q0=14, m=haar_2x2(rng))),
                  (f"u1_q{top}", Gate(U1, q0=top, m=haar_2x2(rng))),
                  ("cp_3_20", Gate(CP, q0=3, q1=20, theta=0.3)), ("swap_2_25", Gate(SWAP, q0=2, q1=25)),
                  ("u2_3_20", Gate(U2, q0=3, q1=20, m=haar4())),

@@ -389,6 +389,47 @@ __global__ void __launch_bounds__(256) k_u1(R *psi, int n, int q, const double *
   }
 }
 
+// Dense one-qubit sweep with the target among the index bits that a wavefront's 64 lanes span:
+// every lane loads its own 16-byte vector (consecutive lanes hold consecutive vectors, so each
+// access of a wave is one contiguous 1 KiB) and takes its pair partner from lane l ^ 2^LB with a
+// cross-lane permute, LB = q for complex<double> (one amplitude per vector) and q - 1 for
+// complex<float> (two).  Each lane then forms its own half of the pair update: with target bit
+// 0, m00 a + m01 partner; with 1, m11 a + m10 partner.  Items (vectors) per slot are a multiple
+// of 256 U, so every lane of a wave takes part in each permute.
+template <typename R, int U>
+__global__ void __launch_bounds__(256) k_u1_lane(R *psi, int n, int lb, const double *tab_row, int log_items,
+                                                 uint64_t total)
+{
+  constexpr int VEC = kVec<R>;
+  const int lmask = 1 << lb;
+  for (uint64_t blk = blockIdx.x; blk * (256 * U) < total; blk += gridDim.x) {
+    const uint64_t base_item = blk * (256 * U) + threadIdx.x;
+    cx<R> a[U][VEC];
+    int slots[U];
+    uint64_t cs[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint64_t it = base_item + (uint64_t)u * 256;
+        slots[u] = (int)(it >> log_items);
+        cs[u] = it & ((1ull << log_items) - 1);
+        vload_nt(psi + ((uint64_t)slots[u] << (n + 1)), cs[u] * VEC, a[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const double *t = tab_row + (uint64_t)slots[u] * 8;
+        const bool one = (cs[u] >> lb) & 1;
+        const cx<R> ca = tab_c<R>(t, one ? 3 : 0), cp = tab_c<R>(t, one ? 2 : 1);
+        cx<R> b[VEC];
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+            const cx<R> pr = {__shfl_xor(a[u][k].re, lmask), __shfl_xor(a[u][k].im, lmask)};
+            b[k] = cfma(cp, pr, cmul(ca, a[u][k]));
+        }
+        vstore_nt(psi + ((uint64_t)slots[u] << (n + 1)), cs[u] * VEC, b);
+    }
+  }
+}
+
 // Generic one-amplitude-pair-per-thread fallback for small states.
 template <typename R>
 __global__ void k_u1_small(R *psi, int n, int q, const double *tab_row, uint64_t total)
@@ -751,13 +792,28 @@ hipError_t launch_init_basis(void *psi, qs_dtype dt, int n, int S, uint64_t inde
     return hipGetLastError();
 }
 
+// Target bits below which the one-qubit sweep exchanges pair partners between lanes (of the
+// six lane bits of a wave's vectors).
+#ifndef QS_LANE_TARGET_BITS
+#define QS_LANE_TARGET_BITS 6
+#endif
+constexpr int kLaneTargetBits = QS_LANE_TARGET_BITS;
+
 template <typename R>
 static hipError_t sweep_u1_t(R *psi, int n, int S, int q, const double *tab_row, hipStream_t st)
 {
     constexpr int VEC = kVec<R>;
     constexpr int U = 2;
     const uint64_t N = 1ull << n;
-    if (q >= (VEC == 2 ? 1 : 0) && (N / 2) / VEC >= 256 * U) {
+    // targets among the bits of a wave's 64 consecutive vectors (except complex<float> q = 0,
+    // whose pair is one vector): lanes exchange partners instead of striding in memory
+    const int lb = q - (VEC == 2 ? 1 : 0);
+    if (lb >= 0 && lb < kLaneTargetBits && N / VEC >= 256 * U) {
+        int log_items = n - (VEC == 2 ? 1 : 0);
+        uint64_t total = (uint64_t)S << log_items;
+        hipLaunchKernelGGL((k_u1_lane<R, U>), dim3(blocks_for(total, 256 * U)), dim3(256), 0, st, psi, n, lb,
+                           tab_row, log_items, total);
+    } else if (q >= (VEC == 2 ? 1 : 0) && (N / 2) / VEC >= 256 * U) {
         int log_items = n - 1 - (VEC == 2 ? 1 : 0);
         uint64_t total = (uint64_t)S << log_items;
         hipLaunchKernelGGL((k_u1<R, 0, U>), dim3(blocks_for(total, 256 * U)), dim3(256), 0, st, psi,
