@@ -531,6 +531,49 @@ __global__ void __launch_bounds__(256) k_2q(R *psi, int n, int qa, int qb, const
   }
 }
 
+// Dense two-qubit sweep with the lower qubit among a wave's lane bits and the upper one above
+// the vectors a wave spans: each lane loads its vector in both halves of the upper qubit (two
+// contiguous 1 KiB accesses per wave), takes the partner lane's two vectors (lane l ^ 2^LB,
+// LB = lower qubit - log2(amplitudes per vector)) with cross-lane permutes, and forms the two
+// outputs of its own lower-qubit value b: y(b, h) = sum over (b', h') of
+// m[b + 2h][b' + 2h'] x(b', h') (the host orders m with the lower qubit as the low local bit).
+// Items per slot (vectors with the upper qubit clear) are a multiple of 256, so every lane
+// takes part in each permute.
+template <typename R>
+__global__ void __launch_bounds__(256) k_2q_lane(R *psi, int n, int lb, int hb, M32 m32, int log_items,
+                                                 uint64_t total)
+{
+  constexpr int VEC = kVec<R>;
+  const int lmask = 1 << lb;
+  cx<R> m[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) m[k] = {(R)m32.v[2 * k], (R)m32.v[2 * k + 1]};
+  for (uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+       it += (uint64_t)gridDim.x * blockDim.x) {
+    const int slot = (int)(it >> log_items);
+    const uint64_t c = it & ((1ull << log_items) - 1);
+    const uint64_t v0 = ins0(c, hb), v1 = v0 | (1ull << hb);
+    R *p = psi + ((uint64_t)slot << (n + 1));
+    cx<R> A[VEC], B[VEC];
+    vload_nt(p, v0 * VEC, A);
+    vload_nt(p, v1 * VEC, B);
+    const bool b = (c >> lb) & 1;
+    // rows b (upper 0) and b + 2 (upper 1); columns: own lower value, partner's, in both halves
+    const cx<R> k00 = b ? m[5] : m[0], k01 = b ? m[4] : m[1], k02 = b ? m[7] : m[2], k03 = b ? m[6] : m[3];
+    const cx<R> k10 = b ? m[13] : m[8], k11 = b ? m[12] : m[9], k12 = b ? m[15] : m[10], k13 = b ? m[14] : m[11];
+    cx<R> Y0[VEC], Y1[VEC];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+        const cx<R> Ap = {__shfl_xor(A[k].re, lmask), __shfl_xor(A[k].im, lmask)};
+        const cx<R> Bp = {__shfl_xor(B[k].re, lmask), __shfl_xor(B[k].im, lmask)};
+        Y0[k] = cfma(k03, Bp, cfma(k02, B[k], cfma(k01, Ap, cmul(k00, A[k]))));
+        Y1[k] = cfma(k13, Bp, cfma(k12, B[k], cfma(k11, Ap, cmul(k10, A[k]))));
+    }
+    vstore_nt(p, v0 * VEC, Y0);
+    vstore_nt(p, v1 * VEC, Y1);
+  }
+}
+
 // Sign flip of every amplitude i with (i & mask) == value: the free bits of ~mask are
 // enumerated by depositing the item index into them.
 template <typename R>
@@ -942,10 +985,39 @@ hipError_t launch_sweep_4q(void *psi, qs_dtype dt, int nbits, const int bits[4],
     return hipGetLastError();
 }
 
+// The lane form of the dense two-qubit sweep when the lower qubit is among a wave's lane bits
+// and the upper one above the wave's vectors; false when it does not apply.
+template <typename R>
+static bool sweep_2q_lane(R *psi, int n, int S, int qa, int qb, const double *m32_host, hipStream_t st)
+{
+    constexpr int VEC = kVec<R>;
+    constexpr int vbits = VEC == 2 ? 1 : 0;
+    const int lo = qa < qb ? qa : qb, hi = qa < qb ? qb : qa;
+    const int lb = lo - vbits, hb = hi - vbits;
+    if (lb < 0 || lb >= kLaneTargetBits || hb < 6 || n - vbits - 1 < 8) return false;
+    // the kernel takes the lower qubit as the low local bit: when qa is the upper one, swap the
+    // two bits of both local indices (local index bit(qa) + 2 bit(qb))
+    M32 m{};
+    auto sw = [&](int l) { return qa == lo ? l : ((l & 1) << 1) | (l >> 1); };
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+            m.v[2 * (4 * sw(r) + sw(c))] = m32_host[2 * (4 * r + c)];
+            m.v[2 * (4 * sw(r) + sw(c)) + 1] = m32_host[2 * (4 * r + c) + 1];
+        }
+    const int log_items = n - vbits - 1;
+    const uint64_t total = (uint64_t)S << log_items;
+    hipLaunchKernelGGL(k_2q_lane<R>, dim3(blocks_for(total, 256)), dim3(256), 0, st, psi, n, lb, hb, m,
+                       log_items, total);
+    return true;
+}
+
 hipError_t launch_sweep_2q(void *psi, qs_dtype dt, int n, int S, int qa, int qb,
                            const double *m32, hipStream_t st)
 {
     TimedLaunch tl("sweep_2q", 2.0 * (double)((uint64_t)S << n) * amp_bytes(dt), st);
+    if (dt == QS_C64 ? sweep_2q_lane((float *)psi, n, S, qa, qb, m32, st)
+                     : sweep_2q_lane((double *)psi, n, S, qa, qb, m32, st))
+        return hipGetLastError();
     if (dt == QS_C64) return sweep_2q_t<float, 3>((float *)psi, n, S, qa, qb, nullptr, m32, st);
     return sweep_2q_t<double, 3>((double *)psi, n, S, qa, qb, nullptr, m32, st);
 }
