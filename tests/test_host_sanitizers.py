@@ -2,8 +2,8 @@
 plan choice, layouts, error paths) under AddressSanitizer and UndefinedBehaviorSanitizer.
 
 The library is rebuilt with the host compilation instrumented (the kernels as usual) and the
-CPU-side suites that call through the C ABI without a GPU -- the ABI checks and the plan
-emulation -- run against it in a child process that preloads the ASan runtime.  Any report
+CPU-side suites that call through the C ABI without a GPU -- the ABI checks, the plan
+emulation, the plan choice and the density-matrix circuit builder -- run against it in a child process that preloads the ASan runtime.  Any report
 aborts the child, so the test fails with the sanitizer's stack trace in its output.
 """
 import os
@@ -34,7 +34,7 @@ def test_abi_and_planner_under_host_sanitizers(tmp_path):
     })
     cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-m", "not gpu", "-p", "no:cacheprovider",
            os.path.join(ROOT, "tests", "test_abi.py"), os.path.join(ROOT, "tests", "test_plan_emulation.py"),
-           os.path.join(ROOT, "tests", "test_autotune.py")]
+           os.path.join(ROOT, "tests", "test_autotune.py"), os.path.join(ROOT, "tests", "test_dm_superop.py")]
     r = subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
     out = r.stdout[-6000:] + r.stderr[-6000:]
     assert r.returncode == 0, out
