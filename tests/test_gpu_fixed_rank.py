@@ -115,3 +115,26 @@ def test_fixed_rank_kraus2_rejects_bad_arguments():
     with pytest.raises(q.QsimError):
         fr.apply_kraus2(0, 1, bad)
     assert fr.info()[0] == 1
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64], ids=["c128", "c64"])
+def test_fixed_rank_mixed_circuit_with_diagonal_gates(dtype):
+    """Every gate kind in the fixed-rank form (unitary steps on each column, Kraus steps with
+    truncation for the noisy ones), including diagonal patterns with complex factors, against the
+    numpy oracle."""
+    from workloads import DIAG, Circuit, random_mixed_circuit
+    n, e, r = 7, 0.1, 8
+    c = random_mixed_circuit(n, 70, seed=21)
+    rng = np.random.default_rng(21)
+    gates = list(c.gates)
+    for _ in range(6):
+        mask = int(rng.integers(1, 1 << n))
+        f = complex(np.exp(1j * rng.uniform(0, 2 * np.pi)))
+        gates.insert(int(rng.integers(0, len(gates) + 1)),
+                     Gate(DIAG, m=np.array([f]), mask=mask, value=int(rng.integers(0, 1 << n)) & mask))
+    c = Circuit(n, gates, name="mixed7+diag", init_index=c.init_index)
+    fr = q.FixedRank(n, r, dtype)
+    fr.init_basis(c.init_index)
+    ranks = [fr.apply_noisy_gate(g, e, tau=1e-9, zero_tol=_zero_tol(dtype)) for g in c.gates]
+    ref = fixed_rank.run_circuit(c, e, r, tau=1e-9, zero_tol=1e-13)
+    _check(fr, ref, oracle.sv_run(c, 0.0), dtype, ranks)
