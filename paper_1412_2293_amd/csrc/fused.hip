@@ -201,7 +201,9 @@ __device__ __forceinline__ void apply_u1_real(tv<R> (&a)[1 << RB], const cxf<R> 
     }
 }
 
-template <typename R, int RB, int P0, int P1>
+// REAL: the 4 x 4 matrix is real (a permutation, or the superoperator of a real Kraus set on
+// vec(rho)): two multiply-adds per product instead of four.
+template <typename R, int RB, int P0, int P1, bool REAL>
 __device__ __forceinline__ void apply_u2(tv<R> (&a)[1 << RB], const cxf<R> (&m)[16])
 {
 #pragma unroll
@@ -212,11 +214,17 @@ __device__ __forceinline__ void apply_u2(tv<R> (&a)[1 << RB], const cxf<R> (&m)[
         cxf<R> y[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            cxf<R> s = mul(m[4 * i], x0);
-            s = fma_c(m[4 * i + 1], x1, s);
-            s = fma_c(m[4 * i + 2], x2, s);
-            s = fma_c(m[4 * i + 3], x3, s);
-            y[i] = s;
+            if constexpr (REAL) {
+                const R c0 = m[4 * i].re, c1 = m[4 * i + 1].re, c2 = m[4 * i + 2].re, c3 = m[4 * i + 3].re;
+                y[i] = {c0 * x0.re + c1 * x1.re + c2 * x2.re + c3 * x3.re,
+                        c0 * x0.im + c1 * x1.im + c2 * x2.im + c3 * x3.im};
+            } else {
+                cxf<R> s = mul(m[4 * i], x0);
+                s = fma_c(m[4 * i + 1], x1, s);
+                s = fma_c(m[4 * i + 2], x2, s);
+                s = fma_c(m[4 * i + 3], x3, s);
+                y[i] = s;
+            }
         }
         a[r0] = tvec(y[0]);
         a[r1] = tvec(y[1]);
@@ -277,13 +285,13 @@ __device__ __forceinline__ void dispatch_u1(int p, bool real, int prekind, int z
     }
 }
 
-template <typename R, int RB>
-__device__ __forceinline__ void dispatch_u2(int p0, int p1, tv<R> (&a)[1 << RB], const cxf<R> (&m)[16])
+template <typename R, int RB, bool REAL>
+__device__ __forceinline__ void dispatch_u2_t(int p0, int p1, tv<R> (&a)[1 << RB], const cxf<R> (&m)[16])
 {
     if constexpr (RB >= 2) {
         switch (p0 * 4 + p1) {
 #define QS_U2_CASE(A, B) \
-    case (A) * 4 + (B): if constexpr ((A) < RB && (B) < RB) apply_u2<R, RB, (A) % RB, (B) % RB>(a, m); break;
+    case (A) * 4 + (B): if constexpr ((A) < RB && (B) < RB) apply_u2<R, RB, (A) % RB, (B) % RB, REAL>(a, m); break;
         QS_U2_CASE(0, 1) QS_U2_CASE(1, 0) QS_U2_CASE(0, 2) QS_U2_CASE(2, 0)
         QS_U2_CASE(0, 3) QS_U2_CASE(3, 0) QS_U2_CASE(1, 2) QS_U2_CASE(2, 1)
         QS_U2_CASE(1, 3) QS_U2_CASE(3, 1) QS_U2_CASE(2, 3) QS_U2_CASE(3, 2)
@@ -291,6 +299,13 @@ __device__ __forceinline__ void dispatch_u2(int p0, int p1, tv<R> (&a)[1 << RB],
         default: break;
         }
     }
+}
+
+template <typename R, int RB>
+__device__ __forceinline__ void dispatch_u2(int p0, int p1, bool real, tv<R> (&a)[1 << RB], const cxf<R> (&m)[16])
+{
+    if (real) dispatch_u2_t<R, RB, true>(p0, p1, a, m);
+    else dispatch_u2_t<R, RB, false>(p0, p1, a, m);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -911,7 +926,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                     cxf<R> m[16];
 #pragma unroll
                     for (int k = 0; k < 16; ++k) m[k] = orec[k];
-                    dispatch_u2<R, RB>(op->p0, op->p1, a, m);
+                    dispatch_u2<R, RB>(op->p0, op->p1, (op->flags & OPF_REAL) != 0, a, m);
                 } else {
                     // no early exit when the tile-number condition fails: a pass-through path
                     // would make the register tile move between registers

@@ -120,7 +120,8 @@ enum OpType : int32_t { OP_U1 = 0, OP_U2 = 1, OP_DIAG = 2 };
 enum DiagKind : int32_t { DIAG_NEGATE = 0, DIAG_PHASE = 1 };
 enum PrepKind : int32_t { PR_REG = 0, PR_THREAD = 1, PR_OUTER = 2 };
 
-// OPF_REAL: the one-qubit matrix the kernel applies is real in every slot.  OPF_CHAIN: the gate
+// OPF_REAL: the one-qubit matrix the kernel applies is real in every slot (for a two-qubit op:
+// its 4 x 4 matrix is real).  OPF_CHAIN: the gate
 // is an inner member of a phase chain (its table rows hold a real matrix and an input phase,
 // written by the chain kernel).  OPF_UPHASE: the op has no folded input block, and its input
 // phase is the uniform record entry rec + 4.  OPF_PREW: the op's input phase does not depend

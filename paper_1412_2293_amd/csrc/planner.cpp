@@ -528,6 +528,14 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                     op.type = OP_U2;
                     op.p0 = reg_index[local_of[x.a]];
                     op.p1 = reg_index[local_of[x.b]];
+                    {
+                        // a CNOT is a permutation; a dense gate is real when every entry is
+                        bool real = true;
+                        if (x.kind == QS_G_U2)
+                            for (int k = 1; k < 32; k += 2)
+                                if (gates[x.gate].m[k] != 0.0) real = false;
+                        if (real) op.flags |= OPF_REAL;
+                    }
                     lcls &= ~((1u << local_of[x.a]) | (1u << local_of[x.b]));
                     rec += 16;
                 } else {
