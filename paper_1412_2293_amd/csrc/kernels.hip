@@ -471,9 +471,10 @@ __global__ void __launch_bounds__(256) k_2q(R *psi, int n, int qa, int qb, const
     uint64_t base = ins0(ins0(c * V, lo), hi);
     const uint64_t ba = 1ull << qa, bb = 1ull << qb;
     // 16-byte vectors (two complex<float> or one complex<double>); streaming accesses for the
-    // phase and dense kinds when the runs of contiguous amplitudes are at least 4 long (the
-    // permutations measured slower with them)
-    const bool nt = (KIND == 0 || KIND == 3) && lo >= 2;
+    // phase and dense kinds when the runs of contiguous amplitudes are at least 4 long, for the
+    // permutations when they are at least 64 long (at n = 28, SWAP and CNOT on high pairs: 62-72%
+    // -> 77-79% of HBM; with runs of 4 they measured slower with them)
+    const bool nt = (KIND == 0 || KIND == 3) ? lo >= 2 : lo >= 6;
     auto ld = [&](uint64_t i, cx<R> *a) {
         if constexpr (V == kVec<R>) {
             if (nt) vload_nt(p, i, a);
