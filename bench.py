@@ -77,7 +77,7 @@ def main():
     from workloads import qft
 
     leg_names = ("large_state_n32", "graph_replay", "dm13", "dm_qft13", "dm_qft17", "fr24", "fr_vs_dm12", "choi", "sweeps_n28", "sweeps_n30",
-                 "grover12_dynamics", "grover10_c1", "serving_full_range", "fr24_full", "block_rounds_n30")
+                 "grover12_dynamics", "grover10_c1", "grover20", "serving_full_range", "fr24_full", "block_rounds_n30")
     if a.leg and a.leg not in leg_names:
         print(f"unknown leg {a.leg}; one of {', '.join(leg_names)}", file=sys.stderr)
         sys.exit(2)
@@ -91,6 +91,7 @@ def main():
                 "sweeps_n30": lambda: sweeps(q, 30),
                 "grover12_dynamics": lambda: grover12_dynamics_bench(q, torch),
                 "grover10_c1": lambda: grover10_c1_bench(q, torch),
+                "grover20": lambda: grover20_bench(q, torch),
                 "serving_full_range": lambda: serving_full_range_bench(q, torch),
                 "fr24_full": lambda: fr24_bench(q, torch, iterations=None),
                 "block_rounds_n30": lambda: block_rounds_bench(q, torch)}
@@ -214,6 +215,8 @@ def main():
         out["choi"] = choi_bench(q, torch)
         torch.cuda.empty_cache()
         out["grover10_c1"] = grover10_c1_bench(q, torch)
+        torch.cuda.empty_cache()
+        out["grover20"] = grover20_bench(q, torch)
         torch.cuda.empty_cache()
         if a.serving_requests > 0:
             out["serving"] = serving_bench(q, torch, a.serving_requests, a.serving_inflight)
@@ -405,7 +408,8 @@ def large_state_bench(q, torch, prefixes=(2, 4)):
     v = runs["valu"]
     return {"workload": f"random{n}x{depth} brickwork, complex64, {T} trajectories + ideal, e={e}",
             "bytes": need, "plan": plan, "passes": v["passes"], "wall_s": v["wall_s"],
-            "fused_avg_ms": v["fused_avg_ms"], "fused_GBps": v["fused_GBps"], "F": v["F"], "norm": v["norm"],
+            "fused_avg_ms": v["fused_avg_ms"], "fused_GBps": v["fused_GBps"],
+            "fused_hbm_frac": round(v["fused_GBps"] / HBM_PEAK_GBS, 4), "F": v["F"], "norm": v["norm"],
             "mfma": runs["mfma"],
             "prefix_s": {f"{L}_{name}": t for (L, name), (t, _) in pref.items()},
             "prefix_speedup": pref[(a, "unfused")][0] / pref[(a, "fused")][0],
@@ -966,6 +970,43 @@ def grover10_c1_bench(q, torch, T=200, runs=10):
             "F_mean": float(F.mean()), "p_mean": float(p.mean()), "p_ideal": p_ideal,
             "eq10": lam1 ** (c.n + 2 * c.n * j) * p_ideal, "lower_bound_lambda1_pow": lam1 ** (c.n + 2 * c.n * j),
             "one_minus_F_hist": {"counts": hist.tolist(), "edges": [float(x) for x in edges]}}
+
+
+def grover20_bench(q, torch, T=64):
+    """Grover at a size bound by HBM: n = 20 (marked index from seed 20, 804 iterations, every
+    Hadamard noisy with e = 0.01), 64 trajectories + ideal in complex<float> (FP64 reductions),
+    automatic plan; amplitude-updates/s, trajectories/s, the fused passes' algorithmic bandwidth
+    against the HBM peak, and the mean marked probability beside eq. (10)."""
+    import math
+
+    import numpy as np
+    from workloads import grover
+    c = grover(20, seed=20)
+    ga = q.gate_array(c.gates)
+    e = 0.01
+    need = q.traj_bytes_required(ga, c.n, q.C64, T, None)
+    buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+    log(f"[bench] grover20 ({len(c.gates)} gates, {T} trajectories)")
+    q.run_trajectories(ga, c.n, c.init_index, q.C64, T, e=e, seed=20, marked=c.marked, buf=buf)
+    torch.cuda.synchronize()
+    q.timing_reset()
+    q.timing_enable(True)
+    t0 = time.perf_counter()
+    res = q.run_trajectories(ga, c.n, c.init_index, q.C64, T, e=e, seed=20, marked=c.marked, buf=buf)
+    t1 = time.perf_counter()
+    q.timing_enable(False)
+    fz = q.timing_read("fused")
+    gbs = fz["alg_bytes"] / (fz["ms"] / 1e3) / 1e9 if fz["ms"] else 0.0
+    j = c.meta["iterations"]
+    lam1 = 0.5 * (1.0 + math.exp(-2.0 * e * e))
+    p_ideal = math.sin((2 * j + 1) * math.asin(2.0 ** (-c.n / 2))) ** 2
+    out = {"workload": f"grover20 (j={j}), {T} trajectories + ideal, e={e}, complex64, FP64 reductions",
+           "plan": q.plan_choose(ga, c.n, q.C64)[0], "wall_s": t1 - t0, "passes": fz["launches"],
+           "amplitude_updates_per_s": c.amplitude_updates() * T / (t1 - t0), "trajectories_per_s": T / (t1 - t0),
+           "fused_GBps": round(gbs, 1), "fused_hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+           "p_mean": float(np.mean(res["p"])), "eq10": lam1 ** (c.n + 2 * c.n * j) * p_ideal, "p_ideal": p_ideal}
+    del buf, res
+    return out
 
 
 def serving_full_range_bench(q, torch, inflight=4, first=60, max_model_s=1.0, pool_gib=32):
