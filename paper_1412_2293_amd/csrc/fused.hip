@@ -661,10 +661,10 @@ constexpr int kMinWaves = (sizeof(R) == 4 && RB == 4) ? 4 : 1;
 // UNI: whether blocks whose factors do not depend on thread-id bits take their per-thread factor
 // with a uniform load (the host picks this variant for passes where most blocks are such; the
 // other keeps the per-thread lookups branch-free, which schedules better when few are).
-// ZV: whether the pass has one-qubit ops on targets that still hold their basis bit (the
-// zero-input updates); passes without any take the variant without those code paths, whose
-// smaller op dispatch measured 2% faster on random layers.
-template <typename R, int RB, bool UNI, bool BLK, bool ZV>
+// ZV: which one-qubit ops act on a target that still holds its basis bit (the zero-input
+// updates): 0 none, 1 some, 2 all.  Variants 0 and 2 leave out the code paths they cannot take
+// (the op dispatch of variant 1 is the largest; without it random layers measured 2-3% faster).
+template <typename R, int RB, bool UNI, bool BLK, int ZV>
 __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     __attribute__((amdgpu_waves_per_eu(kMinWaves<R, RB>, 8))) k_fused(R *__restrict__ psi, int n, int S, int pass_index,
                                                   int rec_cap, int64_t init, int64_t basis, uint32_t blocal,
@@ -903,7 +903,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                     // a target qubit no earlier gate has touched holds the basis bit: when that
                     // bit is 0 every |1> input is zero (and its input phase has nothing to do),
                     // when it is 1 every |0> input
-                    const bool untouched = ZV && ((op->creg >> op->p0) & 1u) != 0;
+                    const bool untouched = ZV == 2 || (ZV == 1 && ((op->creg >> op->p0) & 1u) != 0);
                     const bool bit1 = (blocal & prog.rounds[cur_ri].roff[1 << op->p0]) != 0;
                     const bool zero_in = untouched && !bit1;
                     const int zin = untouched ? (bit1 ? 2 : 1) : 0;
@@ -1114,7 +1114,7 @@ hipError_t launch_pass_jobs(qs_dtype dt, int n, int S, const PassDesc *h, Progra
 }
 
 // thread-safe one-time opt-in to the full 160 KiB of LDS
-template <typename R, int RB, bool UNI, bool BLK, bool ZV>
+template <typename R, int RB, bool UNI, bool BLK, int ZV>
 static hipError_t fused_attr_one()
 {
     static const hipError_t attr = [] {
@@ -1136,14 +1136,16 @@ constexpr bool kBlockVariant = sizeof(R) == 4 && RB == 4;
 template <typename R, int RB>
 static hipError_t fused_attr()
 {
-    hipError_t e = fused_attr_one<R, RB, false, false, false>();
-    if (e == hipSuccess) e = fused_attr_one<R, RB, true, false, false>();
-    if (e == hipSuccess) e = fused_attr_one<R, RB, false, false, true>();
-    if (e == hipSuccess) e = fused_attr_one<R, RB, true, false, true>();
+    hipError_t e = fused_attr_one<R, RB, false, false, 0>();
+    if (e == hipSuccess) e = fused_attr_one<R, RB, true, false, 0>();
+    if (e == hipSuccess) e = fused_attr_one<R, RB, false, false, 1>();
+    if (e == hipSuccess) e = fused_attr_one<R, RB, true, false, 1>();
+    if (e == hipSuccess) e = fused_attr_one<R, RB, false, false, 2>();
+    if (e == hipSuccess) e = fused_attr_one<R, RB, true, false, 2>();
     if constexpr (kBlockVariant<R, RB>) {
         // block rounds replace the op-by-op loop: no zero-input paths there
-        if (e == hipSuccess) e = fused_attr_one<R, RB, false, true, false>();
-        if (e == hipSuccess) e = fused_attr_one<R, RB, true, true, false>();
+        if (e == hipSuccess) e = fused_attr_one<R, RB, false, true, 0>();
+        if (e == hipSuccess) e = fused_attr_one<R, RB, true, true, 0>();
     }
     return e;
 }
@@ -1181,18 +1183,21 @@ static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_ind
                        (const cxf<R> *)rec, (const cxf<R> *)wtab, otab, ovl, slot_base, slots)
     if constexpr (kBlockVariant<R, RB>) {
         if (h.blocks) {
-            if (h.uni_kernel) QS_FUSED_LAUNCH(true, true, false);
-            else QS_FUSED_LAUNCH(false, true, false);
+            if (h.uni_kernel) QS_FUSED_LAUNCH(true, true, 0);
+            else QS_FUSED_LAUNCH(false, true, 0);
             return hipGetLastError();
         }
     }
     if (h.blocks) return hipErrorInvalidValue;   // no block-round variant for this tile shape
-    if (h.zin_ops) {
-        if (h.uni_kernel) QS_FUSED_LAUNCH(true, false, true);
-        else QS_FUSED_LAUNCH(false, false, true);
+    if (h.zin_ops == 2) {
+        if (h.uni_kernel) QS_FUSED_LAUNCH(true, false, 2);
+        else QS_FUSED_LAUNCH(false, false, 2);
+    } else if (h.zin_ops == 1) {
+        if (h.uni_kernel) QS_FUSED_LAUNCH(true, false, 1);
+        else QS_FUSED_LAUNCH(false, false, 1);
     } else {
-        if (h.uni_kernel) QS_FUSED_LAUNCH(true, false, false);
-        else QS_FUSED_LAUNCH(false, false, false);
+        if (h.uni_kernel) QS_FUSED_LAUNCH(true, false, 0);
+        else QS_FUSED_LAUNCH(false, false, 0);
     }
 #undef QS_FUSED_LAUNCH
     return hipGetLastError();

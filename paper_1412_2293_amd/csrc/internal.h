@@ -97,8 +97,8 @@ struct PassDesc {
                                   // bits in the thread id, else the load layout
     int32_t blocks;               // some round of the pass runs as a dense block (matrix cores)
     uint64_t store_off[16];       // store layout: physical index bits of register r
-    int32_t zin_ops;              // some one-qubit op of the pass acts on a target that still holds
-                                  // its basis bit (the kernel variant with the zero-input updates)
+    int32_t zin_ops;              // one-qubit ops of the pass acting on a target that still holds
+                                  // its basis bit (zero-input updates): 0 none, 1 some, 2 all
     int32_t reserved_;
 };
 

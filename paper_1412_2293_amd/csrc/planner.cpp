@@ -635,10 +635,17 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                 for (int ri = pd.round_begin; ri < pd.round_end; ++ri) P.rounds[ri].block_rec = -1;
             pd.blocks = all ? 1 : 0;
         }
-        // whether any one-qubit op of the pass finds its target untouched (zero-input updates)
-        pd.zin_ops = 0;
-        for (int oi = pd.op_begin; oi < (int)P.ops.size(); ++oi)
-            if (P.ops[oi].type == OP_U1 && ((P.ops[oi].creg >> P.ops[oi].p0) & 1u)) pd.zin_ops = 1;
+        // which one-qubit ops of the pass find their target untouched (zero-input updates):
+        // 0 none, 1 some, 2 all
+        {
+            int u1 = 0, zin = 0;
+            for (int oi = pd.op_begin; oi < (int)P.ops.size(); ++oi)
+                if (P.ops[oi].type == OP_U1) {
+                    ++u1;
+                    zin += ((P.ops[oi].creg >> P.ops[oi].p0) & 1u) != 0;
+                }
+            pd.zin_ops = zin == 0 ? 0 : (zin == u1 ? 2 : 1);
+        }
         pd.op_end = (int)P.ops.size();
         pd.job_end = (int)P.jobs.size();
         pd.rec_size = rec;
