@@ -1171,6 +1171,7 @@ qs_status qs_plan_describe(const qs_gate *gates, int n_gates, int n, qs_dtype dt
         I("zero_fill", pd.zero_fill);
         I("uni_kernel", pd.uni_kernel);
         I("zin_ops", pd.zin_ops);
+        I("mixed_ops", pd.mixed_ops);
         I("rec_size", pd.rec_size);
         I("load_round", pd.load_round);
         I("load_reg_mask", P.rounds[pd.load_round].reg_mask);

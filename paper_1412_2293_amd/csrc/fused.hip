@@ -664,7 +664,10 @@ constexpr int kMinWaves = (sizeof(R) == 4 && RB == 4) ? 4 : 1;
 // ZV: which one-qubit ops act on a target that still holds its basis bit (the zero-input
 // updates): 0 none, 1 some, 2 all.  Variants 0 and 2 leave out the code paths they cannot take
 // (the op dispatch of variant 1 is the largest; without it random layers measured 2-3% faster).
-template <typename R, int RB, bool UNI, bool BLK, int ZV>
+// MIX: whether the pass has ops other than one-qubit gates (dense two-qubit gates, diagonal
+// patterns left standalone); without them the op loop holds only the one-qubit paths (QFT
+// and random-layer passes 1-2% faster).
+template <typename R, int RB, bool UNI, bool BLK, int ZV, bool MIX>
 __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     __attribute__((amdgpu_waves_per_eu(kMinWaves<R, RB>, 8))) k_fused(R *__restrict__ psi, int n, int S, int pass_index,
                                                   int rec_cap, int64_t init, int64_t basis, uint32_t blocal,
@@ -925,12 +928,12 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                     load_phases<R, RB>(post, rec + postr, rec + postr, postr >= 0, true,
                                        UNI && (flags & OPF_POST_UNI) != 0, postj, wout, tid);
                     dispatch_u1<R, RB>(op->p0, (flags & OPF_REAL) != 0, prekind, zin, a, m, pre, post);
-                } else if (type == OP_U2) {
+                } else if (MIX && type == OP_U2) {
                     cxf<R> m[16];
 #pragma unroll
                     for (int k = 0; k < 16; ++k) m[k] = orec[k];
                     dispatch_u2<R, RB>(op->p0, op->p1, (op->flags & OPF_REAL) != 0, a, m);
-                } else {
+                } else if (MIX) {
                     // no early exit when the tile-number condition fails: a pass-through path
                     // would make the register tile move between registers
                     const bool ohit = (outer & op->omask) == op->ovalue;
@@ -1114,19 +1117,27 @@ hipError_t launch_pass_jobs(qs_dtype dt, int n, int S, const PassDesc *h, Progra
 }
 
 // thread-safe one-time opt-in to the full 160 KiB of LDS
-template <typename R, int RB, bool UNI, bool BLK, int ZV>
+template <typename R, int RB, bool UNI, bool BLK, int ZV, bool MIX>
 static hipError_t fused_attr_one()
 {
     static const hipError_t attr = [] {
         // the kernel addresses its tile at LDS address 0: it must have no static LDS
         hipFuncAttributes fa;
-        hipError_t e = hipFuncGetAttributes(&fa, (const void *)k_fused<R, RB, UNI, BLK, ZV>);
+        hipError_t e = hipFuncGetAttributes(&fa, (const void *)k_fused<R, RB, UNI, BLK, ZV, MIX>);
         if (e != hipSuccess) return e;
         if (fa.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
-        return hipFuncSetAttribute((const void *)k_fused<R, RB, UNI, BLK, ZV>,
+        return hipFuncSetAttribute((const void *)k_fused<R, RB, UNI, BLK, ZV, MIX>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     }();
     return attr;
+}
+
+template <typename R, int RB, bool UNI, int ZV>
+static hipError_t fused_attr_mix()
+{
+    hipError_t e = fused_attr_one<R, RB, UNI, false, ZV, false>();
+    if (e == hipSuccess) e = fused_attr_one<R, RB, UNI, false, ZV, true>();
+    return e;
 }
 
 // the block-round variants (matrix-core rounds) exist for complex<float> with 16 registers only
@@ -1136,16 +1147,16 @@ constexpr bool kBlockVariant = sizeof(R) == 4 && RB == 4;
 template <typename R, int RB>
 static hipError_t fused_attr()
 {
-    hipError_t e = fused_attr_one<R, RB, false, false, 0>();
-    if (e == hipSuccess) e = fused_attr_one<R, RB, true, false, 0>();
-    if (e == hipSuccess) e = fused_attr_one<R, RB, false, false, 1>();
-    if (e == hipSuccess) e = fused_attr_one<R, RB, true, false, 1>();
-    if (e == hipSuccess) e = fused_attr_one<R, RB, false, false, 2>();
-    if (e == hipSuccess) e = fused_attr_one<R, RB, true, false, 2>();
+    hipError_t e = fused_attr_mix<R, RB, false, 0>();
+    if (e == hipSuccess) e = fused_attr_mix<R, RB, true, 0>();
+    if (e == hipSuccess) e = fused_attr_mix<R, RB, false, 1>();
+    if (e == hipSuccess) e = fused_attr_mix<R, RB, true, 1>();
+    if (e == hipSuccess) e = fused_attr_mix<R, RB, false, 2>();
+    if (e == hipSuccess) e = fused_attr_mix<R, RB, true, 2>();
     if constexpr (kBlockVariant<R, RB>) {
         // block rounds replace the op-by-op loop: no zero-input paths there
-        if (e == hipSuccess) e = fused_attr_one<R, RB, false, true, 0>();
-        if (e == hipSuccess) e = fused_attr_one<R, RB, true, true, 0>();
+        if (e == hipSuccess) e = fused_attr_one<R, RB, false, true, 0, true>();
+        if (e == hipSuccess) e = fused_attr_one<R, RB, true, true, 0, true>();
     }
     return e;
 }
@@ -1177,10 +1188,15 @@ static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_ind
     uint32_t blocal = 0;
     for (int j = 0; j < h.K; ++j)
         if (((uint64_t)basis >> h.q_pos[j]) & 1ull) blocal |= 1u << j;
-#define QS_FUSED_LAUNCH(UNI, BLK, ZV)                                                                          \
-    hipLaunchKernelGGL((k_fused<R, RB, UNI, BLK, ZV>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index,   \
+#define QS_FUSED_LAUNCH_M(UNI, BLK, ZV, MIX)                                                                   \
+    hipLaunchKernelGGL((k_fused<R, RB, UNI, BLK, ZV, MIX>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index, \
                        rec_cap, init, basis, blocal, dyn, prog.passes, prog.stages, prog.rounds, prog.ops,         \
                        (const cxf<R> *)rec, (const cxf<R> *)wtab, otab, ovl, slot_base, slots)
+#define QS_FUSED_LAUNCH(UNI, BLK, ZV)                                                                          \
+    do {                                                                                                       \
+        if (BLK || h.mixed_ops) QS_FUSED_LAUNCH_M(UNI, BLK, ZV, true);                                         \
+        else QS_FUSED_LAUNCH_M(UNI, BLK, ZV, false);                                                           \
+    } while (0)
     if constexpr (kBlockVariant<R, RB>) {
         if (h.blocks) {
             if (h.uni_kernel) QS_FUSED_LAUNCH(true, true, 0);
@@ -1200,6 +1216,7 @@ static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_ind
         else QS_FUSED_LAUNCH(false, false, 0);
     }
 #undef QS_FUSED_LAUNCH
+#undef QS_FUSED_LAUNCH_M
     return hipGetLastError();
 }
 

@@ -99,7 +99,7 @@ struct PassDesc {
     uint64_t store_off[16];       // store layout: physical index bits of register r
     int32_t zin_ops;              // one-qubit ops of the pass acting on a target that still holds
                                   // its basis bit (zero-input updates): 0 none, 1 some, 2 all
-    int32_t reserved_;
+    int32_t mixed_ops;            // the pass has ops other than one-qubit gates
 };
 
 // A stage: consecutive rounds whose records, outer jobs and outer bits stay within the

@@ -645,6 +645,7 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                     zin += ((P.ops[oi].creg >> P.ops[oi].p0) & 1u) != 0;
                 }
             pd.zin_ops = zin == 0 ? 0 : (zin == u1 ? 2 : 1);
+            pd.mixed_ops = u1 < (int)P.ops.size() - pd.op_begin ? 1 : 0;
         }
         pd.op_end = (int)P.ops.size();
         pd.job_end = (int)P.jobs.size();
