@@ -366,6 +366,31 @@ def test_classical_bits_are_the_untouched_tile_number_bits(plan):
             touched |= pass_targets(pas)
 
 
+def test_pass_kernel_variant_flags():
+    """The per-pass flags that pick a kernel variant agree with the pass's ops: zin_ops says
+    whether none (0), some (1) or all (2) of its one-qubit ops find their target untouched, and
+    mixed_ops whether it holds any other op (a variant without those paths must never run one)."""
+    seen = set()
+    for c in circuits():
+        for plan in PLANS:
+            if plan.get("tile_bits", 12) > c.n and plan.get("reg_bits", 3) > c.n:
+                continue
+            prog = q.plan_describe(c.gates, c.n, q.C64, plan)
+            for pas in prog["passes"]:
+                ops = [op for st in pas["stages"] for rd in st["rounds"] for op in rd["ops"]]
+                u1 = [op for op in ops if op["type"] == 0]
+                zin = sum((op["creg"] >> op["p0"]) & 1 for op in u1)
+                assert pas["zin_ops"] == (0 if zin == 0 else 2 if zin == len(u1) else 1), (c.name, plan)
+                assert pas["mixed_ops"] == (1 if len(u1) < len(ops) else 0), (c.name, plan)
+                seen.add((pas["zin_ops"], pas["mixed_ops"]))
+    assert {0, 1, 2} <= {z for z, _ in seen} and {0, 1} <= {m for _, m in seen}
+    # every pass of a QFT from a basis state holds only one-qubit ops on untouched targets
+    c = qft(14, seed=6)
+    for pas in q.plan_describe(c.gates, c.n, q.C64, {"fuse": 1, "tile_bits": 6, "reg_bits": 2,
+                                                     "run_bits": 2})["passes"]:
+        assert (pas["zin_ops"], pas["mixed_ops"]) == (2, 0)
+
+
 def test_qft_second_pass_has_a_support_bound():
     """On a QFT from a basis state the low qubits are transformed last, so the second pass still
     has classical tile-number bits: most of its tiles hold zeros and are left alone."""
