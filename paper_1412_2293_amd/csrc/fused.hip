@@ -1192,28 +1192,29 @@ static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_ind
     hipLaunchKernelGGL((k_fused<R, RB, UNI, BLK, ZV, MIX>), dim3(blocks), dim3(threads), lds, st, psi, n, S, pass_index, \
                        rec_cap, init, basis, blocal, dyn, prog.passes, prog.stages, prog.rounds, prog.ops,         \
                        (const cxf<R> *)rec, (const cxf<R> *)wtab, otab, ovl, slot_base, slots)
-#define QS_FUSED_LAUNCH(UNI, BLK, ZV)                                                                          \
+#define QS_FUSED_LAUNCH(UNI, ZV)                                                                               \
     do {                                                                                                       \
-        if (BLK || h.mixed_ops) QS_FUSED_LAUNCH_M(UNI, BLK, ZV, true);                                         \
-        else QS_FUSED_LAUNCH_M(UNI, BLK, ZV, false);                                                           \
+        if (h.mixed_ops) QS_FUSED_LAUNCH_M(UNI, false, ZV, true);                                              \
+        else QS_FUSED_LAUNCH_M(UNI, false, ZV, false);                                                         \
     } while (0)
     if constexpr (kBlockVariant<R, RB>) {
         if (h.blocks) {
-            if (h.uni_kernel) QS_FUSED_LAUNCH(true, true, 0);
-            else QS_FUSED_LAUNCH(false, true, 0);
+            // block rounds: one variant, every op path kept
+            if (h.uni_kernel) QS_FUSED_LAUNCH_M(true, true, 0, true);
+            else QS_FUSED_LAUNCH_M(false, true, 0, true);
             return hipGetLastError();
         }
     }
     if (h.blocks) return hipErrorInvalidValue;   // no block-round variant for this tile shape
     if (h.zin_ops == 2) {
-        if (h.uni_kernel) QS_FUSED_LAUNCH(true, false, 2);
-        else QS_FUSED_LAUNCH(false, false, 2);
+        if (h.uni_kernel) QS_FUSED_LAUNCH(true, 2);
+        else QS_FUSED_LAUNCH(false, 2);
     } else if (h.zin_ops == 1) {
-        if (h.uni_kernel) QS_FUSED_LAUNCH(true, false, 1);
-        else QS_FUSED_LAUNCH(false, false, 1);
+        if (h.uni_kernel) QS_FUSED_LAUNCH(true, 1);
+        else QS_FUSED_LAUNCH(false, 1);
     } else {
-        if (h.uni_kernel) QS_FUSED_LAUNCH(true, false, 0);
-        else QS_FUSED_LAUNCH(false, false, 0);
+        if (h.uni_kernel) QS_FUSED_LAUNCH(true, 0);
+        else QS_FUSED_LAUNCH(false, 0);
     }
 #undef QS_FUSED_LAUNCH
 #undef QS_FUSED_LAUNCH_M
