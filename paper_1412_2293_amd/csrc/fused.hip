@@ -992,14 +992,25 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
     if (ovl) {
         // This tile's share of <psi_0|psi_slot> and <psi_slot|psi_slot> in FP64: the same sums
         // as the separate overlap reduction, one partial per (slot, tile).
+        // Each product is one multiply-add into the running sum (for complex<float> the products
+        // are exact in FP64, so this rounds once per term); the choice of reference is uniform,
+        // so it is a branch rather than a select per amplitude.
         double v[3] = {0.0, 0.0, 0.0};
+        if (pre_ref) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const tv<R> e = pre_ref ? refv[r] : a[r];
-            const double ar = e.x, ai = e.y, br = a[r].x, bi = a[r].y;
-            v[0] += ar * br + ai * bi;
-            v[1] += ar * bi - ai * br;
-            v[2] += br * br + bi * bi;
+            for (int r = 0; r < NR; ++r) {
+                const double ar = refv[r].x, ai = refv[r].y, br = a[r].x, bi = a[r].y;
+                v[0] = __builtin_fma(ai, bi, __builtin_fma(ar, br, v[0]));
+                v[1] = __builtin_fma(-ai, br, __builtin_fma(ar, bi, v[1]));
+                v[2] = __builtin_fma(bi, bi, __builtin_fma(br, br, v[2]));
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const double br = a[r].x, bi = a[r].y;
+                v[2] = __builtin_fma(bi, bi, __builtin_fma(br, br, v[2]));
+            }
+            v[0] = v[2];
         }
         // Block sums.  With more than one wave, every thread leaves its three sums in the LDS
         // (the tile's LDS, free once every wave has left the last exchange, holds three doubles
