@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <queue>
 
 #include "internal.h"
 
@@ -39,6 +40,113 @@ struct PassBuild {
     std::vector<int> targets;    // physical qubits touched non-diagonally
     int high = 0;                // targets outside the low run bits
 };
+
+// Qubits a gate acts on (a pattern gate: every qubit of its mask).
+static void gate_qubits(const PG &x, int n, std::vector<int> &qs)
+{
+    qs.clear();
+    if (x.kind == QS_G_FLIP || x.kind == QS_G_DIAG) {
+        for (int q = 0; q < n; ++q)
+            if ((x.mask >> q) & 1ull) qs.push_back(q);
+        return;
+    }
+    qs.push_back(x.a);
+    if (x.b >= 0) qs.push_back(x.b);
+}
+
+// Gate order for the passes.  Two gates commute when they act on disjoint qubits or are both
+// diagonal, so the circuit fixes only a partial order: each gate follows the last non-diagonal
+// gate on each of its qubits, and a non-diagonal gate also follows the diagonal gates on its
+// qubits since then.  The passes are filled by list scheduling over that order: a pass takes,
+// lowest circuit index first, every gate whose predecessors are placed and whose targets still
+// fit the tile (targets among the low run bits are free), and a new pass starts only when no
+// such gate is left.  Taken strictly in circuit order a pass ends at the first gate that does
+// not fit, which costs a Grover iteration twice the passes and a layer of a random circuit on
+// 30 qubits about three times.  The result is the same list in the new order; the order of
+// the gates on each qubit, and of a diagonal gate with respect to the non-diagonal gates on
+// its qubits, is kept, so the program computes the same state.
+static void schedule_for_passes(std::vector<PG> &pg, int n, int max_targets, int run_bits, bool whole)
+{
+    const int m = (int)pg.size();
+    std::vector<std::vector<int>> succ(m);
+    std::vector<int> npred(m, 0), mark(m, -1), last_nd(n, -1);
+    std::vector<std::vector<int>> diag_since(n);
+    std::vector<int> qs;
+    for (int i = 0; i < m; ++i) {
+        const PG &x = pg[i];
+        const bool nd = x.nondiag();
+        gate_qubits(x, n, qs);
+        auto dep = [&](int p) {
+            if (p >= 0 && mark[p] != i) {
+                mark[p] = i;
+                succ[p].push_back(i);
+                ++npred[i];
+            }
+        };
+        for (int q : qs) {
+            dep(last_nd[q]);
+            if (nd)
+                for (int d : diag_since[q]) dep(d);
+        }
+        for (int q : qs) {
+            if (nd) {
+                last_nd[q] = i;
+                diag_since[q].clear();
+            } else {
+                diag_since[q].push_back(i);
+            }
+        }
+    }
+    std::priority_queue<int, std::vector<int>, std::greater<int>> ready;
+    for (int i = 0; i < m; ++i)
+        if (npred[i] == 0) ready.push(i);
+    std::vector<PG> out;
+    out.reserve(m);
+    std::vector<char> in_pass(n, 0);
+    std::vector<int> pass_targets, skipped;
+    while ((int)out.size() < m) {
+        for (int q : pass_targets) in_pass[q] = 0;
+        pass_targets.clear();
+        int high = 0;
+        bool progress = true;
+        while (progress) {
+            // targets only grow within a pass, so a gate passed over may fit once others have
+            // added its qubits: scan again until nothing more is placed
+            progress = false;
+            skipped.clear();
+            while (!ready.empty()) {
+                const int i = ready.top();
+                ready.pop();
+                const PG &x = pg[i];
+                int need[2], nn = 0;
+                if (x.kind == QS_G_U1) need[nn++] = x.a;
+                else if (x.kind == QS_G_U2 || x.kind == QS_G_CNOT) {
+                    need[nn++] = x.a;
+                    need[nn++] = x.b;
+                }
+                int extra = 0;
+                for (int k = 0; k < nn; ++k)
+                    if (!in_pass[need[k]] && (whole || need[k] >= run_bits)) ++extra;
+                if (high + extra > max_targets) {
+                    skipped.push_back(i);
+                    continue;
+                }
+                for (int k = 0; k < nn; ++k)
+                    if (!in_pass[need[k]]) {
+                        in_pass[need[k]] = 1;
+                        pass_targets.push_back(need[k]);
+                        if (whole || need[k] >= run_bits) ++high;
+                    }
+                out.push_back(x);
+                progress = true;
+                for (int sc : succ[i])
+                    if (--npred[sc] == 0) ready.push(sc);
+            }
+            for (int i : skipped) ready.push(i);
+        }
+    }
+    pg.swap(out);
+}
 
 // Register offsets (plain and swizzled) and thread-id deposit tables of a round whose
 // registers hold tile-local bits m.
@@ -137,6 +245,7 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         pg.push_back(x);
     }
     P.layout = perm;
+    schedule_for_passes(pg, n, max_targets, run_bits, whole);
 
     // 1b. phase chains.  A unitary 2x2 matrix factors as M = e^{i phi} diag(1, e^{i beta}) R
     // diag(1, e^{i delta}) with R real.  The output factor diag(1, e^{i beta}) commutes with

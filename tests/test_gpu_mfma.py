@@ -35,7 +35,7 @@ def block_rounds(c, plan):
 
 
 CASES = [("random14", lambda: random_layers(14, 5, seed=31, pairing="random")),
-         ("brick13", lambda: random_layers(13, 4, seed=32)),
+         ("brick13", lambda: random_layers(13, 3, seed=32)),
          ("mixed14", lambda: random_mixed_circuit(14, 200, seed=33)),
          ("qft13", lambda: qft(13, seed=34))]
 
