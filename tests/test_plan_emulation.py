@@ -458,3 +458,69 @@ def test_stage_records_fit_the_lds_stage(dtype):
                         for op in rd["ops"]:
                             size = {0: 5 if op["flags"] & 4 else 4, 1: 16, 2: 1}[op["type"]]
                             assert st["rec_begin"] <= op["rec"] and op["rec"] + size <= st["rec_end"]
+
+
+def _in_order_passes(circuit, K, run_bits):
+    """Passes the planner's target rule gives when gates are taken strictly in circuit order
+    (a pass ends at the first gate whose targets do not fit)."""
+    n = circuit.n
+    whole = n == K
+    cap = K if whole else K - run_bits
+    perm = list(range(n))
+    passes, targets, high = 1, set(), 0
+    for g in circuit.gates:
+        if g.kind == SWAP:
+            perm[g.q0], perm[g.q1] = perm[g.q1], perm[g.q0]
+            continue
+        need = []
+        if g.kind == U1:
+            need = [perm[g.q0]]
+        elif g.kind in (U2, CNOT):
+            need = [perm[g.q0], perm[g.q1]]
+        extra = sum(1 for x in need if x not in targets and (whole or x >= run_bits))
+        if high + extra > cap:
+            passes, targets, high = passes + 1, set(), 0
+        for x in need:
+            if x not in targets:
+                targets.add(x)
+                high += whole or x >= run_bits
+    return passes
+
+
+@pytest.mark.parametrize("make,plan", [
+    (lambda: grover(10, seed=4, iterations=6), {"fuse": 1, "tile_bits": 7, "reg_bits": 3, "run_bits": 2}),
+    (lambda: random_layers(12, 6, seed=5, pairing="brickwork"), {"fuse": 1, "tile_bits": 6, "reg_bits": 2,
+                                                                  "run_bits": 2}),
+    (lambda: random_mixed_circuit(11, 160, seed=8), {"fuse": 1, "tile_bits": 6, "reg_bits": 3, "run_bits": 1}),
+], ids=["grover10", "brick12", "mixed11"])
+def test_passes_are_list_scheduled(make, plan):
+    """Gates that commute (disjoint qubits, or both diagonal) may change order so that a pass
+    keeps taking gates that fit: fewer passes than taking the circuit strictly in order (a Grover
+    iteration in two passes), every qubit's non-diagonal gates still in circuit order, and the
+    program's state equal to the oracle's."""
+    c = make()
+    prog = q.plan_describe(c.gates, c.n, q.C64, plan)
+    npass = len(prog["passes"])
+    assert npass < _in_order_passes(c, plan["tile_bits"], plan["run_bits"])
+    if c.name.startswith("grover"):
+        assert npass <= 2 * 6 + 2
+    # per physical qubit, the non-diagonal ops appear in increasing gate index
+    last = {}
+    for pas in prog["passes"]:
+        K = len(pas["q_pos"])
+        for st in pas["stages"]:
+            for rd in st["rounds"]:
+                regbits = [j for j in range(K) if (rd["reg_mask"] >> j) & 1]
+                for op in rd["ops"]:
+                    if op["type"] == 2:
+                        continue
+                    qbs = [pas["q_pos"][regbits[op["p0"]]]]
+                    if op["type"] == 1:
+                        qbs.append(pas["q_pos"][regbits[op["p1"]]])
+                    for qb in qbs:
+                        assert op["gate"] > last.get(qb, -1), (qb, op["gate"])
+                        last[qb] = op["gate"]
+    for e, traj in ((0.0, 0), (0.2, 3)):
+        psi, layout = emulate(c, prog, e, seed=7, traj=traj)
+        ref = oracle.sv_run(c, e, seed=7, traj=traj)
+        assert np.linalg.norm(unpermute(psi, layout, c.n) - ref) < 1e-12
