@@ -685,7 +685,7 @@ double model_cost_unfused(const qs_gate *gates, int n_gates, int n, qs_dtype dt,
 static const int kCandC64[][3] = {{12, 4, 4}, {12, 4, 5}, {12, 3, 5}, {12, 3, 4}, {12, 3, 3}, {11, 3, 4},
                                   {11, 2, 3}, {10, 2, 3}};
 static const int kCandC128[][3] = {{11, 3, 4}, {11, 3, 3}, {11, 2, 4}, {11, 2, 3}, {10, 2, 3}, {10, 1, 3},
-                                   {12, 4, 3}, {12, 4, 4}};
+                                   {12, 4, 4}, {12, 4, 3}};
 
 qs_status autotune_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, int S, Plan &out,
                         double *cost_out)
@@ -968,7 +968,7 @@ static qs_status enqueue_compute(const TrajPrep &prep, const TrajLayout &L, char
             const int64_t init = p == 0 ? (int64_t)init_index : -1;
             uint64_t *otab = (uint64_t *)(B + L.wtab);
             char *wtab = B + L.wtab + align256((size_t(1) << (n > P.K ? n - P.K : 0)) * sizeof(uint64_t));
-            QS_HIP(launch_pass_prep(dt, S, &P.passes[p], pdv, tab, gdev, B + L.rec, st));
+            QS_HIP(launch_pass_prep(dt, S, &P.passes[p], pdv, tab, gdev, B + L.rec, (int64_t)init_index, dyn, st));
             bool blocks = false;
             for (int ri = P.passes[p].round_begin; ri < P.passes[p].round_end; ++ri)
                 blocks = blocks || P.rounds[ri].block_rec >= 0;

@@ -135,16 +135,22 @@ __device__ constexpr int quad_base(int k)
 }
 
 // PRE: input phase kind (0 none, 1 one factor per thread, 2 with register-bit factors); POST:
-// whether the folded output block is present.  ZIN: which input of every pair is known to be
+// the folded output block (0 none, 1 one factor per thread, 2 with register-bit factors; with
+// one factor it joins the |1> row of the matrix once per op instead of a product per pair).  ZIN: which input of every pair is known to be
 // zero (0 neither; 1 the |1> input, 2 the |0> input) -- the target qubit has not been touched by
 // any earlier gate of the run and still holds the basis bit 0 (1), so that half of the tile is
 // exactly zero and its products are left out (the result is the same: a product with zero
 // added to a value leaves the value).  They are uniform per op, so each combination is its own
 // straight-line code behind a scalar branch, with no work for an absent block.
-template <typename R, int RB, int P, int PRE, bool POST, int ZIN>
-__device__ __forceinline__ void apply_u1(tv<R> (&a)[1 << RB], const cxf<R> (&m)[4],
+template <typename R, int RB, int P, int PRE, int POST, int ZIN>
+__device__ __forceinline__ void apply_u1(tv<R> (&a)[1 << RB], const cxf<R> (&m0)[4],
                                          const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
+    cxf<R> m[4] = {m0[0], m0[1], m0[2], m0[3]};
+    if constexpr (POST == 1) {
+        m[2] = mul(post.w, m[2]);
+        m[3] = mul(post.w, m[3]);
+    }
 #pragma unroll
     for (int k = 0; k < (1 << (RB - 1)); ++k) {
         const int r = pair_base<P>(k);
@@ -164,18 +170,24 @@ __device__ __forceinline__ void apply_u1(tv<R> (&a)[1 << RB], const cxf<R> (&m)[
                 y1 = fma_c(m[3], x1, mul(m[2], x0));
             }
         }
-        if constexpr (POST) y1 = mul(pair_phase<R, RB, P, true>(post, r), y1);
+        if constexpr (POST == 2) y1 = mul(pair_phase<R, RB, P, true>(post, r), y1);
         a[r] = tvec(y0);
         a[r1] = tvec(y1);
     }
 }
 
-// The same update with a real matrix (m[k].im == 0): half the multiplications.
-template <typename R, int RB, int P, int PRE, bool POST, int ZIN>
+// The same update with a real matrix (m[k].im == 0): half the multiplications.  A one-factor
+// output block makes the |1> row complex (m2 w, m3 w).
+template <typename R, int RB, int P, int PRE, int POST, int ZIN>
 __device__ __forceinline__ void apply_u1_real(tv<R> (&a)[1 << RB], const cxf<R> (&m)[4],
                                               const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
     const R m0 = m[0].re, m1 = m[1].re, m2 = m[2].re, m3 = m[3].re;
+    cxf<R> m2w, m3w;
+    if constexpr (POST == 1) {
+        m2w = {m2 * post.w.re, m2 * post.w.im};
+        m3w = {m3 * post.w.re, m3 * post.w.im};
+    }
 #pragma unroll
     for (int k = 0; k < (1 << (RB - 1)); ++k) {
         const int r = pair_base<P>(k);
@@ -184,18 +196,21 @@ __device__ __forceinline__ void apply_u1_real(tv<R> (&a)[1 << RB], const cxf<R> 
         cxf<R> y0, y1;
         if constexpr (ZIN == 1) {
             y0 = {m0 * x0.re, m0 * x0.im};
-            y1 = {m2 * x0.re, m2 * x0.im};
+            if constexpr (POST == 1) y1 = mul(m2w, x0);
+            else y1 = {m2 * x0.re, m2 * x0.im};
         } else {
             if constexpr (PRE > 0) x1 = mul(pair_phase<R, RB, P, PRE == 2>(pre, r), x1);
             if constexpr (ZIN == 2) {
                 y0 = {m1 * x1.re, m1 * x1.im};
-                y1 = {m3 * x1.re, m3 * x1.im};
+                if constexpr (POST == 1) y1 = mul(m3w, x1);
+                else y1 = {m3 * x1.re, m3 * x1.im};
             } else {
                 y0 = {m0 * x0.re + m1 * x1.re, m0 * x0.im + m1 * x1.im};
-                y1 = {m2 * x0.re + m3 * x1.re, m2 * x0.im + m3 * x1.im};
+                if constexpr (POST == 1) y1 = fma_c(m3w, x1, mul(m2w, x0));
+                else y1 = {m2 * x0.re + m3 * x1.re, m2 * x0.im + m3 * x1.im};
             }
         }
-        if constexpr (POST) y1 = mul(pair_phase<R, RB, P, true>(post, r), y1);
+        if constexpr (POST == 2) y1 = mul(pair_phase<R, RB, P, true>(post, r), y1);
         a[r] = tvec(y0);
         a[r1] = tvec(y1);
     }
@@ -236,7 +251,7 @@ __device__ __forceinline__ void apply_u2(tv<R> (&a)[1 << RB], const cxf<R> (&m)[
 // Dispatch on the target register bit.  There is no pass-through branch (the last position
 // is the fall-back): every path rewrites the register tile, which lets the register allocator
 // keep the tile in the same registers across ops instead of copying it at each merge.
-template <typename R, int RB, int PRE, bool POST, int ZIN>
+template <typename R, int RB, int PRE, int POST, int ZIN>
 __device__ __forceinline__ void dispatch_u1_pp(int p, bool real, tv<R> (&a)[1 << RB], const cxf<R> (&m)[4],
                                                const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
@@ -254,34 +269,34 @@ __device__ __forceinline__ void dispatch_u1_pp(int p, bool real, tv<R> (&a)[1 <<
 }
 
 // zin: 0 general, 1 the |1> inputs are zero (no input phase to apply), 2 the |0> inputs are zero.
+// postkind: 0 no output block, 1 one factor per thread, 2 with register-bit factors.
+template <typename R, int RB, int PRE, int ZIN>
+__device__ __forceinline__ void dispatch_u1_post(int p, bool real, int postkind, tv<R> (&a)[1 << RB],
+                                                 const cxf<R> (&m)[4], const PhaseSet<R, RB> &pre,
+                                                 const PhaseSet<R, RB> &post)
+{
+    if (postkind == 2) dispatch_u1_pp<R, RB, PRE, 2, ZIN>(p, real, a, m, pre, post);
+    else if (postkind == 1) dispatch_u1_pp<R, RB, PRE, 1, ZIN>(p, real, a, m, pre, post);
+    else dispatch_u1_pp<R, RB, PRE, 0, ZIN>(p, real, a, m, pre, post);
+}
+
 template <typename R, int RB>
-__device__ __forceinline__ void dispatch_u1(int p, bool real, int prekind, int zin, tv<R> (&a)[1 << RB],
-                                            const cxf<R> (&m)[4], const PhaseSet<R, RB> &pre,
-                                            const PhaseSet<R, RB> &post)
+__device__ __forceinline__ void dispatch_u1(int p, bool real, int prekind, int zin, int postkind,
+                                            tv<R> (&a)[1 << RB], const cxf<R> (&m)[4],
+                                            const PhaseSet<R, RB> &pre, const PhaseSet<R, RB> &post)
 {
     if (zin == 1) {
-        if (post.any) dispatch_u1_pp<R, RB, 0, true, 1>(p, real, a, m, pre, post);
-        else dispatch_u1_pp<R, RB, 0, false, 1>(p, real, a, m, pre, post);
+        dispatch_u1_post<R, RB, 0, 1>(p, real, postkind, a, m, pre, post);
     } else if (zin == 2) {
-        if (prekind == 2) {
-            if (post.any) dispatch_u1_pp<R, RB, 2, true, 2>(p, real, a, m, pre, post);
-            else dispatch_u1_pp<R, RB, 2, false, 2>(p, real, a, m, pre, post);
-        } else if (prekind == 1) {
-            if (post.any) dispatch_u1_pp<R, RB, 1, true, 2>(p, real, a, m, pre, post);
-            else dispatch_u1_pp<R, RB, 1, false, 2>(p, real, a, m, pre, post);
-        } else {
-            if (post.any) dispatch_u1_pp<R, RB, 0, true, 2>(p, real, a, m, pre, post);
-            else dispatch_u1_pp<R, RB, 0, false, 2>(p, real, a, m, pre, post);
-        }
+        if (prekind == 2) dispatch_u1_post<R, RB, 2, 2>(p, real, postkind, a, m, pre, post);
+        else if (prekind == 1) dispatch_u1_post<R, RB, 1, 2>(p, real, postkind, a, m, pre, post);
+        else dispatch_u1_post<R, RB, 0, 2>(p, real, postkind, a, m, pre, post);
     } else if (prekind == 2) {
-        if (post.any) dispatch_u1_pp<R, RB, 2, true, 0>(p, real, a, m, pre, post);
-        else dispatch_u1_pp<R, RB, 2, false, 0>(p, real, a, m, pre, post);
+        dispatch_u1_post<R, RB, 2, 0>(p, real, postkind, a, m, pre, post);
     } else if (prekind == 1) {
-        if (post.any) dispatch_u1_pp<R, RB, 1, true, 0>(p, real, a, m, pre, post);
-        else dispatch_u1_pp<R, RB, 1, false, 0>(p, real, a, m, pre, post);
+        dispatch_u1_post<R, RB, 1, 0>(p, real, postkind, a, m, pre, post);
     } else {
-        if (post.any) dispatch_u1_pp<R, RB, 0, true, 0>(p, real, a, m, pre, post);
-        else dispatch_u1_pp<R, RB, 0, false, 0>(p, real, a, m, pre, post);
+        dispatch_u1_post<R, RB, 0, 0>(p, real, postkind, a, m, pre, post);
     }
 }
 
@@ -578,10 +593,12 @@ __global__ void k_pass_jobs(int S, int n_jobs, int tiles_log, uint64_t walk, uin
 
 template <typename R>
 __global__ void k_pass_prep(int S, int op_begin, int n_ops, int rec_size, ProgramDev prog,
-                            const double *tab, const qs_gate *gates, cxf<R> *rec_all)
+                            const double *tab, const qs_gate *gates, cxf<R> *rec_all, uint64_t basis,
+                            const RunParams *dyn)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)n_ops * S) return;
+    if (dyn) basis = dyn->init;
     const int slot = (int)(i / n_ops), ol = (int)(i % n_ops);
     const OpDesc op = prog.ops[op_begin + ol];
     cxf<R> *blk = rec_all + (size_t)slot * rec_size;
@@ -608,6 +625,7 @@ __global__ void k_pass_prep(int S, int op_begin, int n_ops, int rec_size, Progra
             int block = post ? op.post_rec : op.pre_rec;
             if (block < 0) continue;
             double2 preg[kMaxRegBits], ptid[9];
+            double2 ubas = make_double2(1.0, 0.0);     // the block's basis-conditioned factors
             for (int k = 0; k < kMaxRegBits; ++k) preg[k] = make_double2(1.0, 0.0);
             for (int k = 0; k < 9; ++k) ptid[k] = make_double2(1.0, 0.0);
             for (int k = op.pref_begin; k < op.pref_end; ++k) {
@@ -616,12 +634,14 @@ __global__ void k_pass_prep(int S, int op_begin, int n_ops, int rec_size, Progra
                 double2 ph = tabc(pr.gate);
                 if (pr.kind == PR_REG) preg[pr.bit] = dmul(preg[pr.bit], ph);
                 else if (pr.kind == PR_THREAD) ptid[pr.bit] = dmul(ptid[pr.bit], ph);
-                else put(blk + pr.slot_entry, ph);
+                else if (pr.kind == PR_BASIS) {
+                    if ((basis >> pr.bit) & 1ull) ubas = dmul(ubas, ph);
+                } else put(blk + pr.slot_entry, ph);
             }
             cxf<R> *b = blk + block;
             for (int k = 0; k < 4; ++k) put(b + k, k < kMaxRegBits ? preg[k] : make_double2(1.0, 0.0));
             for (int x = 0; x < 32; ++x) {
-                double2 w = post ? make_double2(1.0, 0.0) : uni;
+                double2 w = dmul(ubas, post ? make_double2(1.0, 0.0) : uni);
                 for (int k = 0; k < 5; ++k)
                     if ((x >> k) & 1) w = dmul(w, ptid[k]);
                 put(b + 4 + x, w);
@@ -925,9 +945,12 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                                            UNI && (flags & OPF_PRE_UNI) != 0, prej, wout, tid);
                         prekind = prer < 0 ? 0 : bits ? 2 : 1;
                     }
-                    load_phases<R, RB>(post, rec + postr, rec + postr, postr >= 0, true,
+                    const bool postbits = !(flags & OPF_POSTW);
+                    load_phases<R, RB>(post, rec + postr, rec + postr, postr >= 0, postbits,
                                        UNI && (flags & OPF_POST_UNI) != 0, postj, wout, tid);
-                    dispatch_u1<R, RB>(op->p0, (flags & OPF_REAL) != 0, prekind, zin, a, m, pre, post);
+                    const int postkind = postr < 0 ? 0 : postbits ? 2 : 1;
+                    dispatch_u1<R, RB>(op->p0, (flags & OPF_REAL) != 0, prekind, zin, postkind, a, m, pre,
+                                       post);
                 } else if (MIX && type == OP_U2) {
                     cxf<R> m[16];
 #pragma unroll
@@ -1076,7 +1099,8 @@ size_t fused_lds_bytes(qs_dtype dt, int K)
 }
 
 hipError_t launch_pass_prep(qs_dtype dt, int S, const PassDesc *h, ProgramDev prog,
-                            const double *tab, const qs_gate *gates_dev, void *rec, hipStream_t st)
+                            const double *tab, const qs_gate *gates_dev, void *rec, int64_t basis,
+                            const RunParams *dyn, hipStream_t st)
 {
     const int n_ops = h->op_end - h->op_begin;
     const uint64_t tot = (uint64_t)n_ops * S;
@@ -1085,10 +1109,10 @@ hipError_t launch_pass_prep(qs_dtype dt, int S, const PassDesc *h, ProgramDev pr
     unsigned blocks = (unsigned)((tot + 127) / 128);
     if (dt == QS_C64)
         hipLaunchKernelGGL(k_pass_prep<float>, dim3(blocks), dim3(128), 0, st, S, h->op_begin, n_ops,
-                           h->rec_size, prog, tab, gates_dev, (cxf<float> *)rec);
+                           h->rec_size, prog, tab, gates_dev, (cxf<float> *)rec, (uint64_t)basis, dyn);
     else
         hipLaunchKernelGGL(k_pass_prep<double>, dim3(blocks), dim3(128), 0, st, S, h->op_begin, n_ops,
-                           h->rec_size, prog, tab, gates_dev, (cxf<double> *)rec);
+                           h->rec_size, prog, tab, gates_dev, (cxf<double> *)rec, (uint64_t)basis, dyn);
     return hipGetLastError();
 }
 

@@ -121,7 +121,7 @@ constexpr int kStageObits = 512;  // outer condition bits per stage
 
 enum OpType : int32_t { OP_U1 = 0, OP_U2 = 1, OP_DIAG = 2 };
 enum DiagKind : int32_t { DIAG_NEGATE = 0, DIAG_PHASE = 1 };
-enum PrepKind : int32_t { PR_REG = 0, PR_THREAD = 1, PR_OUTER = 2 };
+enum PrepKind : int32_t { PR_REG = 0, PR_THREAD = 1, PR_OUTER = 2, PR_BASIS = 3 };
 
 // OPF_REAL: the one-qubit matrix the kernel applies is real in every slot (for a two-qubit op:
 // its 4 x 4 matrix is real).  OPF_CHAIN: the gate
@@ -131,8 +131,11 @@ enum PrepKind : int32_t { PR_REG = 0, PR_THREAD = 1, PR_OUTER = 2 };
 // on register bits (a per-thread or uniform factor only).
 // OPF_PRE_UNI / OPF_POST_UNI: the folded input / output block has no phase conditioned on a
 // thread-id bit, so its per-thread factor is the same for every thread of a block.
+// OPF_POSTW: the folded output block has no phase conditioned on a register bit (one factor
+// for all the registers of a thread).
 enum OpFlags : int32_t {
-    OPF_REAL = 1, OPF_CHAIN = 2, OPF_UPHASE = 4, OPF_PREW = 8, OPF_PRE_UNI = 16, OPF_POST_UNI = 32
+    OPF_REAL = 1, OPF_CHAIN = 2, OPF_UPHASE = 4, OPF_PREW = 8, OPF_PRE_UNI = 16, OPF_POST_UNI = 32,
+    OPF_POSTW = 64
 };
 
 struct OpDesc {
@@ -155,7 +158,11 @@ struct OpDesc {
 
 // A controlled phase folded into a one-qubit op: the phase of gate `gate` (noise table) when
 // the condition bit is 1.  kind PR_REG: register bit `bit`; PR_THREAD: thread-id bit `bit`;
-// PR_OUTER: stored at record entry `slot_entry`, conditioned per tile by an OuterJob.
+// PR_OUTER: stored at record entry `slot_entry`, conditioned per tile by an OuterJob;
+// PR_BASIS: a tile-local condition qubit (physical bit `bit`) that no non-diagonal gate has
+// touched yet, so every amplitude that can be nonzero holds the run's basis bit there: the
+// phase is one factor for the whole block when that bit is 1 and none when it is 0 (the
+// amplitudes it would otherwise reach are zero).
 struct PrepRef {
     int32_t kind;
     int32_t post;
@@ -261,7 +268,8 @@ struct ProgramDev {
 
 // Records of pass `pass_host` for all S slots into rec (S * rec_size complex entries).
 hipError_t launch_pass_prep(qs_dtype dt, int S, const PassDesc *pass_host, ProgramDev prog,
-                            const double *tab, const qs_gate *gates_dev, void *rec, hipStream_t st);
+                            const double *tab, const qs_gate *gates_dev, void *rec, int64_t basis,
+                            const RunParams *dyn, hipStream_t st);
 // Sets the fused kernels' LDS limit (done by the first launch otherwise); call before capturing
 // a graph.
 hipError_t fused_prepare_attributes();

@@ -359,6 +359,19 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         };
         int na = next_of(x.a), nb = next_of(x.b);
         int nx = (na < 0) ? nb : (nb < 0 ? na : std::min(na, nb));
+        {
+            // one qubit untouched so far (no non-diagonal gate before this one), the other's last
+            // gate a one-qubit gate: fold as that gate's output phase conditioned on the untouched
+            // qubit, which still holds the run's basis bit there, so the phase is one factor for
+            // the whole tile (or none) instead of a per-amplitude input phase of the later gate
+            const int pa = prev_of(x.a), pb = prev_of(x.b);
+            const int pt = pa >= 0 && pb < 0 ? pa : (pb >= 0 && pa < 0 ? pb : -1);
+            if (pt >= 0 && pg[pt].kind == QS_G_U1) {
+                const int cond = (pg[pt].a == x.a) ? x.b : x.a;
+                post_att[pt].push_back({cond, x.gate});
+                continue;
+            }
+        }
         if (nx >= 0 && pg[nx].kind == QS_G_U1) {
             int cond = (pg[nx].a == x.a) ? x.b : x.a;
             pre_att[nx].push_back({cond, x.gate});
@@ -601,6 +614,9 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                                 pr.bit = at.cond;
                                 pr.slot_entry = block + kPhaseTable + outer_k++;
                                 P.obits.push_back(at.cond);
+                            } else if ((lcls >> j) & 1u) {
+                                pr.kind = PR_BASIS;
+                                pr.bit = at.cond;
                             } else if (reg_index[j] >= 0) {
                                 pr.kind = PR_REG;
                                 pr.bit = reg_index[j];
@@ -610,16 +626,17 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                             }
                             P.prefs.push_back(pr);
                         }
-                        if (!post) {
-                            bool reg = false;
-                            for (auto &at : att)
-                                if (local_of[at.cond] >= 0 && reg_index[local_of[at.cond]] >= 0) reg = true;
-                            if (!reg) op.flags |= OPF_PREW;
-                        }
                         {
-                            bool thr = false;
-                            for (auto &at : att)
-                                if (local_of[at.cond] >= 0 && reg_index[local_of[at.cond]] < 0) thr = true;
+                            // which factors stay conditioned per register or per thread (the
+                            // others: outer bits per tile, basis bits once per block)
+                            bool reg = false, thr = false;
+                            for (auto &at : att) {
+                                const int j = local_of[at.cond];
+                                if (j < 0 || ((lcls >> j) & 1u)) continue;
+                                if (reg_index[j] >= 0) reg = true;
+                                else thr = true;
+                            }
+                            if (!reg) op.flags |= post ? OPF_POSTW : OPF_PREW;
                             if (!thr) op.flags |= post ? OPF_POST_UNI : OPF_PRE_UNI;
                         }
                         if (n_outer > 0) {

@@ -66,7 +66,7 @@ def chain_operators(ops, chains):
     return out
 
 
-def block_round(v, rnd, regbits, tbits, ar, outer, ops):
+def block_round(v, rnd, regbits, tbits, ar, outer, basis, ops):
     """A round run as one dense block (the kernel's matrix-core path): every op's phases
     conditioned outside the registers on its target's |1> states first, then the ops in order with
     their phases conditioned on register bits (the block), then the outside output phases."""
@@ -75,6 +75,8 @@ def block_round(v, rnd, regbits, tbits, ar, outer, ops):
             return (idx >> regbits[bit]) & 1
         if kind == 1:
             return (idx >> tbits[bit]) & 1
+        if kind == 3:
+            return np.full(idx.size, (basis >> bit) & 1)
         return np.full(idx.size, (outer >> bit) & 1)
 
     def phases(v, op, post, inside):
@@ -159,7 +161,7 @@ def emulate(circuit, prog, e=0.0, seed=0, traj=0):
                     regbits = [j for j in range(K) if (m >> j) & 1]
                     tbits = [j for j in range(K) if not (m >> j) & 1]
                     if rnd.get("block_rec", -1) >= 0:
-                        v = block_round(v, rnd, regbits, tbits, ar, outer, ops)
+                        v = block_round(v, rnd, regbits, tbits, ar, outer, b, ops)
                         continue
                     for op in rnd["ops"]:
                         if op["type"] == 0:
@@ -178,14 +180,25 @@ def emulate(circuit, prog, e=0.0, seed=0, traj=0):
                                     cond = (l0 >> regbits[bit]) & 1
                                 elif kind == 1:
                                     cond = (l0 >> tbits[bit]) & 1
+                                elif kind == 3:
+                                    # a basis-bit condition: the tile-local qubit is untouched,
+                                    # so the amplitudes that disagree with the basis there are
+                                    # zero (the phase is one factor, or none, for the block)
+                                    jl = qpos.index(bit)
+                                    off = ((ar ^ blocal) >> jl) & 1 == 1
+                                    assert np.all(v[off] == 0), (pi, "basis condition")
+                                    cond = np.full(l0.size, (b >> bit) & 1)
                                 else:
                                     cond = np.full(l0.size, (outer >> bit) & 1)
                                 w[post] = w[post] * np.where(cond == 1, ops[cpg], 1.0)
                             M = ops[op["gate"]]
-                            # a block flagged uniform has no thread-conditioned phase
+                            # a block flagged uniform has no thread-conditioned phase; one flagged
+                            # one-factor (64) no register-conditioned output phase
                             for post, flag in ((0, 16), (1, 32)):
                                 if op["flags"] & flag:
                                     assert not any(ph[0] == 1 and ph[1] == post for ph in op["phases"])
+                            if op["flags"] & 64:
+                                assert not any(ph[0] == 0 and ph[1] == 1 for ph in op["phases"])
                             assert bool(op["flags"] & 2) == isinstance(M, tuple)
                             if op["flags"] & 2:
                                 # inner chain member: a real matrix after a uniform input phase
