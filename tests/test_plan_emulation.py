@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import paper_1412_2293_amd as q
-from workloads import (CNOT, CP, FLIP, NOISE_PHASE, NOISE_ROT, SWAP, U1, U2, chain_heavy_circuit, grover,
+from workloads import (CNOT, CP, FLIP, NOISE_PHASE, NOISE_ROT, SWAP, U1, U2, Circuit, chain_heavy_circuit, grover,
                        qft, random_layers, random_mixed_circuit)
 
 CNOT4 = np.array([[1, 0, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0], [0, 1, 0, 0]], np.complex128)
@@ -537,3 +537,30 @@ def test_passes_are_list_scheduled(make, plan):
         psi, layout = emulate(c, prog, e, seed=7, traj=traj)
         ref = oracle.sv_run(c, e, seed=7, traj=traj)
         assert np.linalg.norm(unpermute(psi, layout, c.n) - ref) < 1e-12
+
+
+def test_qft_phases_fold_on_basis_bits():
+    """A QFT from a basis state meets every controlled phase while its control is still untouched:
+    each is folded into the target's Hadamard as an output phase conditioned on the basis bit
+    (kind 3) or on a tile-number bit, so no block has a per-register or per-thread factor, and
+    the program still gives the oracle's state for inputs with many and few ones."""
+    for n, plan in ((12, {"fuse": 1, "tile_bits": 6, "reg_bits": 2, "run_bits": 2}),
+                    (13, {"fuse": 1, "tile_bits": 8, "reg_bits": 3, "run_bits": 2})):
+        c = qft(n, seed=2)
+        prog = q.plan_describe(c.gates, n, q.C64, plan)
+        kinds = set()
+        for pas in prog["passes"]:
+            for st in pas["stages"]:
+                for rd in st["rounds"]:
+                    for op in rd["ops"]:
+                        kinds |= {ph[0] for ph in op["phases"]}
+                        if any(ph[1] == 1 for ph in op["phases"]):
+                            assert op["flags"] & 64 and op["flags"] & 32
+                        assert not any(ph[1] == 0 for ph in op["phases"])
+        assert 3 in kinds and not kinds & {0, 1}
+        for init in (c.init_index, (1 << n) - 1, 1):
+            ci = Circuit(n, c.gates, name=c.name, init_index=init)
+            for e, traj in ((0.0, 0), (0.1, 2)):
+                psi, layout = emulate(ci, prog, e, seed=3, traj=traj)
+                ref = oracle.sv_run(ci, e, seed=3, traj=traj)
+                assert np.linalg.norm(unpermute(psi, layout, n) - ref) < 1e-12
