@@ -54,26 +54,26 @@ static void gate_qubits(const PG &x, int n, std::vector<int> &qs)
     if (x.b >= 0) qs.push_back(x.b);
 }
 
-// Gate order for the passes.  Two gates commute when they act on disjoint qubits or are both
-// diagonal, so the circuit fixes only a partial order: each gate follows the last non-diagonal
-// gate on each of its qubits, and a non-diagonal gate also follows the diagonal gates on its
-// qubits since then.  The passes are filled by list scheduling over that order: a pass takes,
-// lowest circuit index first, every gate whose predecessors are placed and whose targets still
-// fit the tile (targets among the low run bits are free), and a new pass starts only when no
-// such gate is left.  Taken strictly in circuit order a pass ends at the first gate that does
-// not fit, which costs a Grover iteration twice the passes and a layer of a random circuit on
-// 30 qubits about three times.  The result is the same list in the new order; the order of
-// the gates on each qubit, and of a diagonal gate with respect to the non-diagonal gates on
-// its qubits, is kept, so the program computes the same state.
-static void schedule_for_passes(std::vector<PG> &pg, int n, int max_targets, int run_bits, bool whole)
+// List scheduling of the gates sel (indices into pg, in an order that respects the circuit)
+// into groups.  Two gates commute when they act on disjoint qubits or are both diagonal, so
+// the circuit fixes only a partial order: each gate follows the last non-diagonal gate on each
+// of its qubits, and a non-diagonal gate also follows the diagonal gates on its qubits since
+// then.  A group takes, lowest position in sel first, every gate whose predecessors are placed
+// and whose targets still fit (at most cap targets for which counts(q) holds); a new group
+// starts only when no such gate is left.  Appends the gates in the new order to order and the
+// position where each group starts to starts.  The order of the gates on each qubit, and of a
+// diagonal gate with respect to the non-diagonal gates on its qubits, is kept.
+template <typename Counts>
+static void list_schedule(const std::vector<PG> &pg, const std::vector<int> &sel, int n, int cap, Counts counts,
+                          std::vector<int> &order, std::vector<int> &starts)
 {
-    const int m = (int)pg.size();
+    const int m = (int)sel.size();
     std::vector<std::vector<int>> succ(m);
     std::vector<int> npred(m, 0), mark(m, -1), last_nd(n, -1);
     std::vector<std::vector<int>> diag_since(n);
     std::vector<int> qs;
     for (int i = 0; i < m; ++i) {
-        const PG &x = pg[i];
+        const PG &x = pg[sel[i]];
         const bool nd = x.nondiag();
         gate_qubits(x, n, qs);
         auto dep = [&](int p) {
@@ -100,24 +100,24 @@ static void schedule_for_passes(std::vector<PG> &pg, int n, int max_targets, int
     std::priority_queue<int, std::vector<int>, std::greater<int>> ready;
     for (int i = 0; i < m; ++i)
         if (npred[i] == 0) ready.push(i);
-    std::vector<PG> out;
-    out.reserve(m);
-    std::vector<char> in_pass(n, 0);
-    std::vector<int> pass_targets, skipped;
-    while ((int)out.size() < m) {
-        for (int q : pass_targets) in_pass[q] = 0;
-        pass_targets.clear();
-        int high = 0;
+    std::vector<char> in_group(n, 0);
+    std::vector<int> group_targets, skipped;
+    int placed = 0;
+    while (placed < m) {
+        starts.push_back((int)order.size());
+        for (int q : group_targets) in_group[q] = 0;
+        group_targets.clear();
+        int used = 0;
         bool progress = true;
         while (progress) {
-            // targets only grow within a pass, so a gate passed over may fit once others have
+            // targets only grow within a group, so a gate passed over may fit once others have
             // added its qubits: scan again until nothing more is placed
             progress = false;
             skipped.clear();
             while (!ready.empty()) {
                 const int i = ready.top();
                 ready.pop();
-                const PG &x = pg[i];
+                const PG &x = pg[sel[i]];
                 int need[2], nn = 0;
                 if (x.kind == QS_G_U1) need[nn++] = x.a;
                 else if (x.kind == QS_G_U2 || x.kind == QS_G_CNOT) {
@@ -126,18 +126,19 @@ static void schedule_for_passes(std::vector<PG> &pg, int n, int max_targets, int
                 }
                 int extra = 0;
                 for (int k = 0; k < nn; ++k)
-                    if (!in_pass[need[k]] && (whole || need[k] >= run_bits)) ++extra;
-                if (high + extra > max_targets) {
+                    if (!in_group[need[k]] && counts(need[k])) ++extra;
+                if (used + extra > cap) {
                     skipped.push_back(i);
                     continue;
                 }
                 for (int k = 0; k < nn; ++k)
-                    if (!in_pass[need[k]]) {
-                        in_pass[need[k]] = 1;
-                        pass_targets.push_back(need[k]);
-                        if (whole || need[k] >= run_bits) ++high;
+                    if (!in_group[need[k]]) {
+                        in_group[need[k]] = 1;
+                        group_targets.push_back(need[k]);
+                        if (counts(need[k])) ++used;
                     }
-                out.push_back(x);
+                order.push_back(sel[i]);
+                ++placed;
                 progress = true;
                 for (int sc : succ[i])
                     if (--npred[sc] == 0) ready.push(sc);
@@ -145,6 +146,38 @@ static void schedule_for_passes(std::vector<PG> &pg, int n, int max_targets, int
             for (int i : skipped) ready.push(i);
         }
     }
+}
+
+// Gate order for the passes and their register rounds, by list scheduling over the circuit's
+// partial order: first into passes (at most max_targets targets outside the low run bits,
+// which every tile holds), then each pass's gates into rounds of at most RB target qubits.
+// Taken strictly in circuit order a pass or a round ends at the first gate that does not fit,
+// which costs a Grover iteration twice the passes, a layer of a random circuit on 30 qubits
+// about three times the passes, and random layers twice the register rounds (each one more
+// exchange through LDS).  The planner below cuts passes and rounds greedily in the new order,
+// which reproduces these groups; the program computes the same state.  Plans with block rounds
+// keep each pass in pass order: a block round needs every op's phases conditioned outside the
+// registers to sit before the first or after the last op on its target, which rounds that span
+// several layers of the same qubits rarely meet.
+static void schedule_for_passes(std::vector<PG> &pg, int n, int max_targets, int run_bits, bool whole, int RB,
+                                bool rounds)
+{
+    const int m = (int)pg.size();
+    std::vector<int> all(m), by_pass, pass_starts;
+    for (int i = 0; i < m; ++i) all[i] = i;
+    list_schedule(pg, all, n, max_targets, [&](int q) { return whole || q >= run_bits; }, by_pass, pass_starts);
+    pass_starts.push_back(m);
+    std::vector<int> order, round_starts, seg;
+    order.reserve(m);
+    if (!rounds) order = by_pass;
+    else
+        for (size_t p = 0; p + 1 < pass_starts.size(); ++p) {
+            seg.assign(by_pass.begin() + pass_starts[p], by_pass.begin() + pass_starts[p + 1]);
+            list_schedule(pg, seg, n, RB, [](int) { return true; }, order, round_starts);
+        }
+    std::vector<PG> out;
+    out.reserve(m);
+    for (int i : order) out.push_back(pg[i]);
     pg.swap(out);
 }
 
@@ -245,7 +278,7 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
         pg.push_back(x);
     }
     P.layout = perm;
-    schedule_for_passes(pg, n, max_targets, run_bits, whole);
+    schedule_for_passes(pg, n, max_targets, run_bits, whole, RB, !mfma);
 
     // 1b. phase chains.  A unitary 2x2 matrix factors as M = e^{i phi} diag(1, e^{i beta}) R
     // diag(1, e^{i delta}) with R real.  The output factor diag(1, e^{i beta}) commutes with

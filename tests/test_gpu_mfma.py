@@ -60,8 +60,9 @@ def test_block_rounds_full_states(name, make, plan):
 
 
 def test_block_rounds_equal_their_graph_replay():
-    c = random_layers(12, 6, seed=35, pairing="random")
+    c = random_layers(12, 4, seed=35, pairing="random")
     plan = {"fuse": 1, "mfma": 1}
+    assert block_rounds(c, plan) >= 1
     with q.TrajGraph(c.gates, c.n, q.C64, 4, plan=plan) as g:
         for init in (0, 77):
             a = g.launch(init, e=0.05, seed=3)
