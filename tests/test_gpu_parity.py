@@ -154,6 +154,33 @@ def test_qft_states_and_fidelities(n, plan, dtype):
 
 
 @pytest.mark.parametrize("dtype", [q.C128, q.C64])
+@pytest.mark.parametrize("plan", [{"fuse": 1}, {"fuse": 1, "tile_bits": 8, "reg_bits": 3, "run_bits": 2},
+                                  {"fuse": 1, "tile_bits": 6, "reg_bits": 2, "run_bits": 2}],
+                         ids=["default", "t8r3", "t6r2"])
+def test_qft_basis_folded_phases_every_input(dtype, plan):
+    """The QFT's controlled phases fold into the target's Hadamard as one factor per tile taken
+    from the run's basis bits (the control is still untouched there): inputs with no ones, all
+    ones, alternating bits and a random index, every amplitude of every trajectory against the
+    oracle."""
+    n = 13
+    c0 = qft(n, seed=8)
+    d = q.plan_describe(c0.gates, n, dtype, plan)
+    assert any(ph[0] == 3 for p in d["passes"] for st in p["stages"] for rd in st["rounds"]
+               for op in rd["ops"] for ph in op["phases"])
+    T, e, seed = 3, 0.08, 13
+    for x in (0, (1 << n) - 1, 0x0AAA, 0x1555, c0.init_index):
+        c = Circuit(n, c0.gates, name=c0.name, init_index=x)
+        res = q.run_trajectories(c.gates, n, x, dtype, T, e=e, seed=seed, plan=plan)
+        F_ref, _, ideal, states = oracle.run_trajectories(c, e, seed, range(T), keep_states=True)
+        st = q.trajectory_states(res, n, dtype, T).cpu().numpy().astype(np.complex128)
+        tol = 1e-12 if dtype == q.C128 else 3e-5
+        assert rel_err(unpermute(st[0], res["layout"], n), ideal) <= tol, x
+        for t in range(T):
+            assert rel_err(unpermute(st[t + 1], res["layout"], n), states[t]) <= tol, (x, t)
+        assert np.max(np.abs(res["F"] - F_ref)) <= TOL[dtype], x
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
 def test_random_layers_against_oracle(dtype):
     c = random_layers(12, 6, seed=5, pairing="random")
     T = 4
