@@ -684,6 +684,8 @@ constexpr int kMinWaves = (sizeof(R) == 4 && RB == 4) ? 4 : 1;
 // ZV: which one-qubit ops act on a target that still holds its basis bit (the zero-input
 // updates): 0 none, 1 some, 2 all.  Variants 0 and 2 leave out the code paths they cannot take
 // (the op dispatch of variant 1 is the largest; without it random layers measured 2-3% faster).
+// ZV 3: as 2, and every one-qubit op has a real matrix, no input phase and at most a uniform
+// output factor (the QFT's passes), so the op loop holds only those paths.
 // MIX: whether the pass has ops other than one-qubit gates (dense two-qubit gates, diagonal
 // patterns left standalone); without them the op loop holds only the one-qubit paths (QFT
 // and random-layer passes 1-2% faster).
@@ -917,7 +919,22 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                 const OpDesc *op = prog.ops + oi;
                 const int type = op->type;
                 const cxf<R> *__restrict__ orec = rec + op->rec;
-                if (type == OP_U1) {
+                if (ZV == 3 && type == OP_U1) {
+                    // every one-qubit op of the pass: real matrix, target still untouched, no
+                    // input phase, output phase at most one uniform factor
+                    cxf<R> m[4] = {orec[0], orec[1], orec[2], orec[3]};
+                    PhaseSet<R, RB> pre, post;
+                    pre.any = false;
+                    const int postr = op->post_rec, postj = op->post_job;
+                    post.any = postr >= 0;
+                    if (post.any) {
+                        post.w = rec[postr + 4];
+                        if (postj >= 0) post.w = mul(post.w, wout[postj]);
+                    }
+                    const bool bit1 = (blocal & prog.rounds[cur_ri].roff[1 << op->p0]) != 0;
+                    if (bit1) dispatch_u1_post<R, RB, 0, 2>(op->p0, true, post.any ? 1 : 0, a, m, pre, post);
+                    else dispatch_u1_post<R, RB, 0, 1>(op->p0, true, post.any ? 1 : 0, a, m, pre, post);
+                } else if (type == OP_U1) {
                     cxf<R> m[4] = {orec[0], orec[1], orec[2], orec[3]};
                     PhaseSet<R, RB> pre, post;
                     const int flags = op->flags;
@@ -926,7 +943,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                     // a target qubit no earlier gate has touched holds the basis bit: when that
                     // bit is 0 every |1> input is zero (and its input phase has nothing to do),
                     // when it is 1 every |0> input
-                    const bool untouched = ZV == 2 || (ZV == 1 && ((op->creg >> op->p0) & 1u) != 0);
+                    const bool untouched = ZV >= 2 || (ZV == 1 && ((op->creg >> op->p0) & 1u) != 0);
                     const bool bit1 = (blocal & prog.rounds[cur_ri].roff[1 << op->p0]) != 0;
                     const bool zero_in = untouched && !bit1;
                     const int zin = untouched ? (bit1 ? 2 : 1) : 0;
@@ -1188,6 +1205,7 @@ static hipError_t fused_attr()
     if (e == hipSuccess) e = fused_attr_mix<R, RB, true, 1>();
     if (e == hipSuccess) e = fused_attr_mix<R, RB, false, 2>();
     if (e == hipSuccess) e = fused_attr_mix<R, RB, true, 2>();
+    if (e == hipSuccess) e = fused_attr_one<R, RB, true, false, 3, false>();
     if constexpr (kBlockVariant<R, RB>) {
         // block rounds replace the op-by-op loop: no zero-input paths there
         if (e == hipSuccess) e = fused_attr_one<R, RB, false, true, 0, true>();
@@ -1241,7 +1259,9 @@ static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_ind
         }
     }
     if (h.blocks) return hipErrorInvalidValue;   // no block-round variant for this tile shape
-    if (h.zin_ops == 2) {
+    if (h.zin_ops == 3) {
+        QS_FUSED_LAUNCH_M(true, false, 3, false);
+    } else if (h.zin_ops == 2) {
         if (h.uni_kernel) QS_FUSED_LAUNCH(true, 2);
         else QS_FUSED_LAUNCH(false, 2);
     } else if (h.zin_ops == 1) {

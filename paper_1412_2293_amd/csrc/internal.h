@@ -98,7 +98,9 @@ struct PassDesc {
     int32_t blocks;               // some round of the pass runs as a dense block (matrix cores)
     uint64_t store_off[16];       // store layout: physical index bits of register r
     int32_t zin_ops;              // one-qubit ops of the pass acting on a target that still holds
-                                  // its basis bit (zero-input updates): 0 none, 1 some, 2 all
+                                  // its basis bit (zero-input updates): 0 none, 1 some, 2 all,
+                                  // 3 all, each with a real matrix, no input phase and at most
+                                  // a uniform output factor
     int32_t mixed_ops;            // the pass has ops other than one-qubit gates
 };
 

@@ -805,6 +805,18 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                 }
             pd.zin_ops = zin == 0 ? 0 : (zin == u1 ? 2 : 1);
             pd.mixed_ops = u1 < (int)P.ops.size() - pd.op_begin ? 1 : 0;
+            // 3: as 2, with only real matrices, no input phases and uniform output factors
+            if (pd.zin_ops == 2 && !pd.mixed_ops && !pd.blocks) {
+                bool simple = true;
+                for (int oi = pd.op_begin; oi < (int)P.ops.size() && simple; ++oi) {
+                    const OpDesc &o = P.ops[oi];
+                    const int need = OPF_POSTW | OPF_POST_UNI;
+                    if (!(o.flags & OPF_REAL) || (o.flags & (OPF_CHAIN | OPF_UPHASE)) || o.pre_rec >= 0 ||
+                        (o.post_rec >= 0 && (o.flags & need) != need))
+                        simple = false;
+                }
+                if (simple) pd.zin_ops = 3;
+            }
         }
         pd.op_end = (int)P.ops.size();
         pd.job_end = (int)P.jobs.size();

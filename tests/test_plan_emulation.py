@@ -393,15 +393,24 @@ def test_pass_kernel_variant_flags():
                 ops = [op for st in pas["stages"] for rd in st["rounds"] for op in rd["ops"]]
                 u1 = [op for op in ops if op["type"] == 0]
                 zin = sum((op["creg"] >> op["p0"]) & 1 for op in u1)
-                assert pas["zin_ops"] == (0 if zin == 0 else 2 if zin == len(u1) else 1), (c.name, plan)
+                expect = 0 if zin == 0 else 2 if zin == len(u1) else 1
+                # 3: all untouched, and every op real (1), no chain (2, 4), no input phases, any
+                # output phases one uniform factor (64, 32)
+                simple = all(op["flags"] & 1 and not op["flags"] & 6 and not any(ph[1] == 0 for ph in op["phases"])
+                             and (not any(ph[1] == 1 for ph in op["phases"]) or (op["flags"] & 96) == 96)
+                             for op in u1)
+                if expect == 2 and simple and len(u1) == len(ops) and not pas["blocks"]:
+                    expect = 3
+                assert pas["zin_ops"] == expect, (c.name, plan)
                 assert pas["mixed_ops"] == (1 if len(u1) < len(ops) else 0), (c.name, plan)
                 seen.add((pas["zin_ops"], pas["mixed_ops"]))
-    assert {0, 1, 2} <= {z for z, _ in seen} and {0, 1} <= {m for _, m in seen}
-    # every pass of a QFT from a basis state holds only one-qubit ops on untouched targets
+    assert {0, 1, 3} <= {z for z, _ in seen} and {0, 1} <= {m for _, m in seen}
+    # every pass of a QFT from a basis state holds only real one-qubit ops on untouched targets
+    # with uniform output factors
     c = qft(14, seed=6)
     for pas in q.plan_describe(c.gates, c.n, q.C64, {"fuse": 1, "tile_bits": 6, "reg_bits": 2,
                                                      "run_bits": 2})["passes"]:
-        assert (pas["zin_ops"], pas["mixed_ops"]) == (2, 0)
+        assert (pas["zin_ops"], pas["mixed_ops"]) == (3, 0)
 
 
 def test_qft_second_pass_has_a_support_bound():
