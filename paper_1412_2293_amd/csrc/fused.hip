@@ -685,7 +685,8 @@ constexpr int kMinWaves = (sizeof(R) == 4 && RB == 4) ? 4 : 1;
 // updates): 0 none, 1 some, 2 all.  Variants 0 and 2 leave out the code paths they cannot take
 // (the op dispatch of variant 1 is the largest; without it random layers measured 2-3% faster).
 // ZV 3: as 2, and every one-qubit op has a real matrix, no input phase and at most a uniform
-// output factor (the QFT's passes), so the op loop holds only those paths.
+// output factor (the QFT's passes), so the op loop holds only those paths.  ZV 4: as 0, and
+// every one-qubit op has a real matrix and no folded phase (Grover's Hadamard layers).
 // MIX: whether the pass has ops other than one-qubit gates (dense two-qubit gates, diagonal
 // patterns left standalone); without them the op loop holds only the one-qubit paths (QFT
 // and random-layer passes 1-2% faster).
@@ -919,7 +920,14 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                 const OpDesc *op = prog.ops + oi;
                 const int type = op->type;
                 const cxf<R> *__restrict__ orec = rec + op->rec;
-                if (ZV == 3 && type == OP_U1) {
+                if (ZV == 4 && type == OP_U1) {
+                    // every one-qubit op of the pass: real matrix, no folded phase, target
+                    // already touched (the general pair update)
+                    cxf<R> m[4] = {orec[0], orec[1], orec[2], orec[3]};
+                    PhaseSet<R, RB> none;
+                    none.any = false;
+                    dispatch_u1_pp<R, RB, 0, 0, 0>(op->p0, true, a, m, none, none);
+                } else if (ZV == 3 && type == OP_U1) {
                     // every one-qubit op of the pass: real matrix, target still untouched, no
                     // input phase, output phase at most one uniform factor
                     cxf<R> m[4] = {orec[0], orec[1], orec[2], orec[3]};
@@ -1206,6 +1214,7 @@ static hipError_t fused_attr()
     if (e == hipSuccess) e = fused_attr_mix<R, RB, false, 2>();
     if (e == hipSuccess) e = fused_attr_mix<R, RB, true, 2>();
     if (e == hipSuccess) e = fused_attr_one<R, RB, true, false, 3, false>();
+    if (e == hipSuccess) e = fused_attr_mix<R, RB, false, 4>();
     if constexpr (kBlockVariant<R, RB>) {
         // block rounds replace the op-by-op loop: no zero-input paths there
         if (e == hipSuccess) e = fused_attr_one<R, RB, false, true, 0, true>();
@@ -1261,6 +1270,8 @@ static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_ind
     if (h.blocks) return hipErrorInvalidValue;   // no block-round variant for this tile shape
     if (h.zin_ops == 3) {
         QS_FUSED_LAUNCH_M(true, false, 3, false);
+    } else if (h.zin_ops == 4) {
+        QS_FUSED_LAUNCH(false, 4);
     } else if (h.zin_ops == 2) {
         if (h.uni_kernel) QS_FUSED_LAUNCH(true, 2);
         else QS_FUSED_LAUNCH(false, 2);

@@ -100,7 +100,8 @@ struct PassDesc {
     int32_t zin_ops;              // one-qubit ops of the pass acting on a target that still holds
                                   // its basis bit (zero-input updates): 0 none, 1 some, 2 all,
                                   // 3 all, each with a real matrix, no input phase and at most
-                                  // a uniform output factor
+                                  // a uniform output factor; 4 none, each with a real matrix and
+                                  // no folded phase
     int32_t mixed_ops;            // the pass has ops other than one-qubit gates
 };
 

@@ -817,6 +817,18 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                 }
                 if (simple) pd.zin_ops = 3;
             }
+            // 4: as 0, with only real matrices and no folded phases
+            if (pd.zin_ops == 0 && !pd.blocks && u1 > 0) {
+                bool plain = true;
+                for (int oi = pd.op_begin; oi < (int)P.ops.size() && plain; ++oi) {
+                    const OpDesc &o = P.ops[oi];
+                    if (o.type != OP_U1) continue;
+                    if (!(o.flags & OPF_REAL) || (o.flags & (OPF_CHAIN | OPF_UPHASE)) || o.pre_rec >= 0 ||
+                        o.post_rec >= 0)
+                        plain = false;
+                }
+                if (plain) pd.zin_ops = 4;
+            }
         }
         pd.op_end = (int)P.ops.size();
         pd.job_end = (int)P.jobs.size();

@@ -401,6 +401,10 @@ def test_pass_kernel_variant_flags():
                              for op in u1)
                 if expect == 2 and simple and len(u1) == len(ops) and not pas["blocks"]:
                     expect = 3
+                # 4: none untouched, every one-qubit op real, no chain, no folded phase
+                plain = all(op["flags"] & 1 and not op["flags"] & 6 and not op["phases"] for op in u1)
+                if expect == 0 and plain and u1 and not pas["blocks"]:
+                    expect = 4
                 assert pas["zin_ops"] == expect, (c.name, plan)
                 assert pas["mixed_ops"] == (1 if len(u1) < len(ops) else 0), (c.name, plan)
                 seen.add((pas["zin_ops"], pas["mixed_ops"]))
