@@ -685,7 +685,7 @@ double model_cost_unfused(const qs_gate *gates, int n_gates, int n, qs_dtype dt,
 static const int kCandC64[][3] = {{12, 4, 4}, {12, 4, 5}, {12, 3, 5}, {12, 3, 4}, {12, 3, 3}, {11, 3, 4},
                                   {11, 2, 3}, {10, 2, 3}};
 static const int kCandC128[][3] = {{11, 3, 4}, {11, 3, 3}, {11, 2, 4}, {11, 2, 3}, {10, 2, 3}, {10, 1, 3},
-                                   {12, 4, 4}, {12, 4, 3}};
+                                   {12, 4, 3}, {12, 4, 4}};
 
 qs_status autotune_plan(const qs_gate *gates, int n_gates, int n, qs_dtype dt, int S, Plan &out,
                         double *cost_out)

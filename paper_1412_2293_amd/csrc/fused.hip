@@ -686,7 +686,9 @@ constexpr int kMinWaves = (sizeof(R) == 4 && RB == 4) ? 4 : 1;
 // (the op dispatch of variant 1 is the largest; without it random layers measured 2-3% faster).
 // ZV 3: as 2, and every one-qubit op has a real matrix, no input phase and at most a uniform
 // output factor (the QFT's passes), so the op loop holds only those paths.  ZV 4: as 0, and
-// every one-qubit op has a real matrix and no folded phase (Grover's Hadamard layers).
+// every one-qubit op has a real matrix and no folded phase (Grover's Hadamard layers).  ZV 5:
+// no one-qubit op at all (density-matrix passes of dense two-qubit superoperators and diagonal
+// patterns).
 // MIX: whether the pass has ops other than one-qubit gates (dense two-qubit gates, diagonal
 // patterns left standalone); without them the op loop holds only the one-qubit paths (QFT
 // and random-layer passes 1-2% faster).
@@ -942,7 +944,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                     const bool bit1 = (blocal & prog.rounds[cur_ri].roff[1 << op->p0]) != 0;
                     if (bit1) dispatch_u1_post<R, RB, 0, 2>(op->p0, true, post.any ? 1 : 0, a, m, pre, post);
                     else dispatch_u1_post<R, RB, 0, 1>(op->p0, true, post.any ? 1 : 0, a, m, pre, post);
-                } else if (type == OP_U1) {
+                } else if (ZV != 5 && type == OP_U1) {
                     cxf<R> m[4] = {orec[0], orec[1], orec[2], orec[3]};
                     PhaseSet<R, RB> pre, post;
                     const int flags = op->flags;
@@ -1215,6 +1217,7 @@ static hipError_t fused_attr()
     if (e == hipSuccess) e = fused_attr_mix<R, RB, true, 2>();
     if (e == hipSuccess) e = fused_attr_one<R, RB, true, false, 3, false>();
     if (e == hipSuccess) e = fused_attr_mix<R, RB, false, 4>();
+    if (e == hipSuccess) e = fused_attr_one<R, RB, false, false, 5, true>();
     if constexpr (kBlockVariant<R, RB>) {
         // block rounds replace the op-by-op loop: no zero-input paths there
         if (e == hipSuccess) e = fused_attr_one<R, RB, false, true, 0, true>();
@@ -1272,6 +1275,8 @@ static hipError_t launch_t(R *psi, int n, int S, const PassDesc &h, int pass_ind
         QS_FUSED_LAUNCH_M(true, false, 3, false);
     } else if (h.zin_ops == 4) {
         QS_FUSED_LAUNCH(false, 4);
+    } else if (h.zin_ops == 5) {
+        QS_FUSED_LAUNCH_M(false, false, 5, true);
     } else if (h.zin_ops == 2) {
         if (h.uni_kernel) QS_FUSED_LAUNCH(true, 2);
         else QS_FUSED_LAUNCH(false, 2);

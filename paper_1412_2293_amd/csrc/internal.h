@@ -101,7 +101,7 @@ struct PassDesc {
                                   // its basis bit (zero-input updates): 0 none, 1 some, 2 all,
                                   // 3 all, each with a real matrix, no input phase and at most
                                   // a uniform output factor; 4 none, each with a real matrix and
-                                  // no folded phase
+                                  // no folded phase; 5 the pass has no one-qubit op
     int32_t mixed_ops;            // the pass has ops other than one-qubit gates
 };
 

@@ -829,6 +829,8 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                 }
                 if (plain) pd.zin_ops = 4;
             }
+            // 5: no one-qubit op at all
+            if (u1 == 0 && pd.mixed_ops && !pd.blocks) pd.zin_ops = 5;
         }
         pd.op_end = (int)P.ops.size();
         pd.job_end = (int)P.jobs.size();

@@ -405,6 +405,8 @@ def test_pass_kernel_variant_flags():
                 plain = all(op["flags"] & 1 and not op["flags"] & 6 and not op["phases"] for op in u1)
                 if expect == 0 and plain and u1 and not pas["blocks"]:
                     expect = 4
+                if not u1 and ops and not pas["blocks"]:
+                    expect = 5
                 assert pas["zin_ops"] == expect, (c.name, plan)
                 assert pas["mixed_ops"] == (1 if len(u1) < len(ops) else 0), (c.name, plan)
                 seen.add((pas["zin_ops"], pas["mixed_ops"]))
