@@ -747,6 +747,11 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
         slot = (int)(blockIdx.x >> tiles_log);
         tile = (uint64_t)blockIdx.x & ((1ull << tiles_log) - 1ull);
     }
+    // uniform by construction; the division above runs on the vector ALUs, so say so, and the
+    // record and table pointers derived from them stay in scalar registers
+    slot = __builtin_amdgcn_readfirstlane(slot);
+    tile = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(tile >> 32)) << 32) |
+           (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)tile);
     const uint64_t bidx = ((uint64_t)slot << tiles_log) | tile;
     const uint32_t tid = threadIdx.x, nthr = blockDim.x;
     const cxf<R> *__restrict__ rec = rec_all + (size_t)slot * pd->rec_size;
