@@ -938,17 +938,20 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                     // every one-qubit op of the pass: real matrix, target still untouched, no
                     // input phase, output phase at most one uniform factor
                     cxf<R> m[4] = {orec[0], orec[1], orec[2], orec[3]};
+                    // an op without an output block takes the factor 1: one update path per
+                    // target and input instead of two
                     PhaseSet<R, RB> pre, post;
                     pre.any = false;
+                    post.any = true;
                     const int postr = op->post_rec, postj = op->post_job;
-                    post.any = postr >= 0;
-                    if (post.any) {
+                    post.w = cxf<R>{(R)1, (R)0};
+                    if (postr >= 0) {
                         post.w = rec[postr + 4];
                         if (postj >= 0) post.w = mul(post.w, wout[postj]);
                     }
                     const bool bit1 = (blocal & prog.rounds[cur_ri].roff[1 << op->p0]) != 0;
-                    if (bit1) dispatch_u1_post<R, RB, 0, 2>(op->p0, true, post.any ? 1 : 0, a, m, pre, post);
-                    else dispatch_u1_post<R, RB, 0, 1>(op->p0, true, post.any ? 1 : 0, a, m, pre, post);
+                    if (bit1) dispatch_u1_pp<R, RB, 0, 1, 2>(op->p0, true, a, m, pre, post);
+                    else dispatch_u1_pp<R, RB, 0, 1, 1>(op->p0, true, a, m, pre, post);
                 } else if (ZV != 5 && type == OP_U1) {
                     cxf<R> m[4] = {orec[0], orec[1], orec[2], orec[3]};
                     PhaseSet<R, RB> pre, post;
