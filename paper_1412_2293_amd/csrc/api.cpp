@@ -1201,6 +1201,7 @@ qs_status qs_plan_describe(const qs_gate *gates, int n_gates, int n, qs_dtype dt
                 o += ri != sd.round_begin ? ",{" : "{";
                 I("reg_mask", rd.reg_mask);
                 I("block_rec", rd.block_rec);
+                I("seq", rd.seq);
                 o += "\"ops\":[";
                 for (int oi = rd.op_begin; oi < rd.op_end; ++oi) {
                     const OpDesc &op = P.ops[oi];

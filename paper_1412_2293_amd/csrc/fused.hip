@@ -9,6 +9,8 @@
 // sign flips are diagonal: a controlled phase is folded into the neighbouring one-qubit gate
 // on one of its qubits as a phase on that gate's |1> input or output, conditioned on the other
 // qubit, which is a tile-constant, thread-constant or register bit here.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace qs {
@@ -213,6 +215,22 @@ __device__ __forceinline__ void apply_u1_real(tv<R> (&a)[1 << RB], const cxf<R> 
         if constexpr (POST == 2) y1 = mul(pair_phase<R, RB, P, true>(post, r), y1);
         a[r] = tvec(y0);
         a[r1] = tvec(y1);
+    }
+}
+
+// A one-qubit update on a target that still holds its basis bit, with a real matrix and one
+// uniform output factor: one input of every pair is exactly zero (which one is the basis bit),
+// so their sum is the other; the |0> output is A times it (A real), the |1> output B times it.
+template <typename R, int RB, int P>
+__device__ __forceinline__ void apply_u1_untouched(tv<R> (&a)[1 << RB], R A, cxf<R> B)
+{
+#pragma unroll
+    for (int k = 0; k < (1 << (RB - 1)); ++k) {
+        const int r = pair_base<P>(k);
+        const int r1 = r | (1 << P);
+        const cxf<R> x = {a[r].x + a[r1].x, a[r].y + a[r1].y};
+        a[r] = tv<R>{A * x.re, A * x.im};
+        a[r1] = tvec(mul(B, x));
     }
 }
 
@@ -922,6 +940,45 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                     }
                 }
             } else {
+            if constexpr (ZV == 3 && sizeof(R) == 4 && RB == 4) {
+                // a round of untouched-target updates on register bits k-1, ..., 0: straight-line,
+                // no per-op dispatch (its merges copy the register tile)
+                const int seq = rd->seq;
+                if (seq > 0) {
+                    auto step = [&](int oi, auto pc) {
+                        constexpr int PP = decltype(pc)::value;
+                        const OpDesc *op = prog.ops + oi;
+                        const cxf<R> *__restrict__ orec = rec + op->rec;
+                        const int postr = op->post_rec, postj = op->post_job;
+                        cxf<R> w = cxf<R>{(R)1, (R)0};
+                        if (postr >= 0) {
+                            w = rec[postr + 4];
+                            if (postj >= 0) w = mul(w, wout[postj]);
+                        }
+                        const bool bit1 = (blocal & prog.rounds[cur_ri].roff[1 << PP]) != 0;
+                        const R A = bit1 ? orec[1].re : orec[0].re;
+                        const R Bm = bit1 ? orec[3].re : orec[2].re;
+                        apply_u1_untouched<R, RB, PP>(a, A, cxf<R>{Bm * w.re, Bm * w.im});
+                    };
+                    const int ob = rd->op_begin;
+                    if (seq == 4) {
+                        step(ob, std::integral_constant<int, 3>{});
+                        step(ob + 1, std::integral_constant<int, 2>{});
+                        step(ob + 2, std::integral_constant<int, 1>{});
+                        step(ob + 3, std::integral_constant<int, 0>{});
+                    } else if (seq == 3) {
+                        step(ob, std::integral_constant<int, 2>{});
+                        step(ob + 1, std::integral_constant<int, 1>{});
+                        step(ob + 2, std::integral_constant<int, 0>{});
+                    } else if (seq == 2) {
+                        step(ob, std::integral_constant<int, 1>{});
+                        step(ob + 1, std::integral_constant<int, 0>{});
+                    } else {
+                        step(ob, std::integral_constant<int, 0>{});
+                    }
+                    continue;
+                }
+            }
             const int oe = rd->op_end;
             for (int oi = rd->op_begin; oi < oe; ++oi) {
                 const OpDesc *op = prog.ops + oi;

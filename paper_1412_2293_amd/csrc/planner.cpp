@@ -817,6 +817,18 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                 }
                 if (simple) pd.zin_ops = 3;
             }
+            // rounds of such a pass whose ops target register bits k-1, ..., 0 in turn run as one
+            // straight-line sequence
+            for (int ri = pd.round_begin; ri < pd.round_end; ++ri) {
+                RoundDesc &rd = P.rounds[ri];
+                rd.seq = 0;
+                const int k = rd.op_end - rd.op_begin;
+                if (pd.zin_ops != 3 || k < 1 || k > RB) continue;
+                bool ok = true;
+                for (int i = 0; i < k; ++i)
+                    if (P.ops[rd.op_begin + i].type != OP_U1 || P.ops[rd.op_begin + i].p0 != k - 1 - i) ok = false;
+                if (ok) rd.seq = k;
+            }
             // 4: as 0, with only real matrices and no folded phases
             if (pd.zin_ops == 0 && !pd.blocks && u1 > 0) {
                 bool plain = true;

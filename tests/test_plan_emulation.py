@@ -419,6 +419,27 @@ def test_pass_kernel_variant_flags():
         assert (pas["zin_ops"], pas["mixed_ops"]) == (3, 0)
 
 
+def test_straight_line_rounds():
+    """A round is marked for the straight-line path (seq = k) exactly when its pass is of the
+    simple untouched-target kind and its k ops are one-qubit ops on register bits k-1, ..., 0 in
+    that order; the QFT's rounds all are."""
+    marked = 0
+    for c in list(circuits()) + [qft(26, seed=1)]:
+        for plan in PLANS[:1] + [{"fuse": 1, "tile_bits": 12, "reg_bits": 4, "run_bits": 4}]:
+            if plan.get("tile_bits", 12) > c.n:
+                continue
+            for pas in q.plan_describe(c.gates, c.n, q.C64, plan)["passes"]:
+                for st in pas["stages"]:
+                    for rd in st["rounds"]:
+                        ops = rd["ops"]
+                        k = len(ops)
+                        want = k if (pas["zin_ops"] == 3 and 0 < k <= 4
+                                     and all(op["type"] == 0 and op["p0"] == k - 1 - i for i, op in enumerate(ops))) else 0
+                        assert rd["seq"] == want, (c.name, plan)
+                        marked += rd["seq"] > 0
+    assert marked >= 7
+
+
 def test_qft_second_pass_has_a_support_bound():
     """On a QFT from a basis state the low qubits are transformed last, so the second pass still
     has classical tile-number bits: most of its tiles hold zeros and are left alone."""
