@@ -979,6 +979,55 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                     continue;
                 }
             }
+            if constexpr (ZV == 4 && sizeof(R) == 4 && RB == 4) {
+                // rounds of real updates of touched targets on register bits 0, ..., k-1 in turn
+                // (seq = k), or two such runs of four around one diagonal pattern (seq = 9):
+                // straight-line, the target bits fixed at compile time
+                const int seq = rd->seq;
+                if (seq > 0) {
+                    PhaseSet<R, RB> none;
+                    none.any = false;
+                    auto step = [&](int oi, auto pc) {
+                        constexpr int PP = decltype(pc)::value;
+                        const cxf<R> *__restrict__ orec = rec + prog.ops[oi].rec;
+                        const cxf<R> m[4] = {orec[0], orec[1], orec[2], orec[3]};
+                        apply_u1_real<R, RB, PP, 0, 0, 0>(a, m, none, none);
+                    };
+                    auto run4 = [&](int ob) {
+                        step(ob, std::integral_constant<int, 0>{});
+                        step(ob + 1, std::integral_constant<int, 1>{});
+                        step(ob + 2, std::integral_constant<int, 2>{});
+                        step(ob + 3, std::integral_constant<int, 3>{});
+                    };
+                    const int ob = rd->op_begin;
+                    if (seq == 9) {
+                        run4(ob);
+                        const OpDesc *op = prog.ops + ob + 4;
+                        const bool ohit = (outer & op->omask) == op->ovalue;
+                        const uint32_t lmask = op->lmask, lvalue = op->lvalue;
+                        const cxf<R> f = rec[op->rec];
+#pragma unroll
+                        for (int r = 0; r < NR; ++r) {
+                            bool hit = ohit && ((lthr | prog.rounds[cur_ri].roff[r]) & lmask) == lvalue;
+                            const tv<R> y = tvec(mul(f, cx<R>(a[r])));
+                            a[r] = hit ? y : a[r];
+                        }
+                        run4(ob + 5);
+                    } else if (seq == 4) {
+                        run4(ob);
+                    } else if (seq == 3) {
+                        step(ob, std::integral_constant<int, 0>{});
+                        step(ob + 1, std::integral_constant<int, 1>{});
+                        step(ob + 2, std::integral_constant<int, 2>{});
+                    } else if (seq == 2) {
+                        step(ob, std::integral_constant<int, 0>{});
+                        step(ob + 1, std::integral_constant<int, 1>{});
+                    } else {
+                        step(ob, std::integral_constant<int, 0>{});
+                    }
+                    continue;
+                }
+            }
             const int oe = rd->op_end;
             for (int oi = rd->op_begin; oi < oe; ++oi) {
                 const OpDesc *op = prog.ops + oi;

@@ -55,8 +55,10 @@ struct RoundDesc {
     uint32_t sroff[16];           // lds_swizzle(roff[r])
     uint16_t tlo[32];             // tile-local bits of thread-id bits 0..4, indexed by tid & 31
     uint16_t thi[16];             // tile-local bits of thread-id bits 5..8, indexed by tid >> 5
-    int32_t seq;                  // k > 0: the round is k one-qubit ops on register bits k-1, ..., 0
-                                  // in that order (in a pass of the simple untouched-target kind)
+    int32_t seq;                  // straight-line round: in a pass of the simple untouched-target
+                                  // kind, k > 0 one-qubit ops on register bits k-1, ..., 0 in that
+                                  // order; in a pass of the plain kind, on bits 0, ..., k-1, or
+                                  // (9) two runs on bits 0..3 around one diagonal pattern
     int32_t reserved_;
 };
 

@@ -817,18 +817,6 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
                 }
                 if (simple) pd.zin_ops = 3;
             }
-            // rounds of such a pass whose ops target register bits k-1, ..., 0 in turn run as one
-            // straight-line sequence
-            for (int ri = pd.round_begin; ri < pd.round_end; ++ri) {
-                RoundDesc &rd = P.rounds[ri];
-                rd.seq = 0;
-                const int k = rd.op_end - rd.op_begin;
-                if (pd.zin_ops != 3 || k < 1 || k > RB) continue;
-                bool ok = true;
-                for (int i = 0; i < k; ++i)
-                    if (P.ops[rd.op_begin + i].type != OP_U1 || P.ops[rd.op_begin + i].p0 != k - 1 - i) ok = false;
-                if (ok) rd.seq = k;
-            }
             // 4: as 0, with only real matrices and no folded phases
             if (pd.zin_ops == 0 && !pd.blocks && u1 > 0) {
                 bool plain = true;
@@ -843,6 +831,33 @@ qs_status plan_fused(const qs_gate *gates, int n_gates, int n, int K, int RB, in
             }
             // 5: no one-qubit op at all
             if (u1 == 0 && pd.mixed_ops && !pd.blocks) pd.zin_ops = 5;
+            // rounds that run as one straight-line sequence: in a pass of kind 3, k ops on
+            // register bits k-1, ..., 0 in turn; of kind 4, on bits 0, ..., k-1, or two runs on
+            // bits 0..3 around one diagonal pattern (seq = 9)
+            for (int ri = pd.round_begin; ri < pd.round_end; ++ri) {
+                RoundDesc &rd = P.rounds[ri];
+                rd.seq = 0;
+                const int k = rd.op_end - rd.op_begin;
+                auto u1_at = [&](int i, int p) {
+                    const OpDesc &o = P.ops[rd.op_begin + i];
+                    return o.type == OP_U1 && o.p0 == p;
+                };
+                if (pd.zin_ops == 3 && k >= 1 && k <= RB) {
+                    bool ok = true;
+                    for (int i = 0; i < k; ++i) ok = ok && u1_at(i, k - 1 - i);
+                    if (ok) rd.seq = k;
+                } else if (pd.zin_ops == 4 && RB == 4) {
+                    bool ok = k >= 1 && k <= RB;
+                    for (int i = 0; ok && i < k; ++i) ok = u1_at(i, i);
+                    if (ok) {
+                        rd.seq = k;
+                    } else if (k == 9 && P.ops[rd.op_begin + 4].type == OP_DIAG) {
+                        ok = true;
+                        for (int i = 0; i < 4; ++i) ok = ok && u1_at(i, i) && u1_at(5 + i, i);
+                        if (ok) rd.seq = 9;
+                    }
+                }
+            }
         }
         pd.op_end = (int)P.ops.size();
         pd.job_end = (int)P.jobs.size();

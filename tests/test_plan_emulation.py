@@ -424,20 +424,30 @@ def test_straight_line_rounds():
     simple untouched-target kind and its k ops are one-qubit ops on register bits k-1, ..., 0 in
     that order; the QFT's rounds all are."""
     marked = 0
-    for c in list(circuits()) + [qft(26, seed=1)]:
+    for c in list(circuits()) + [qft(26, seed=1), grover(16, seed=2, iterations=4)]:
         for plan in PLANS[:1] + [{"fuse": 1, "tile_bits": 12, "reg_bits": 4, "run_bits": 4}]:
             if plan.get("tile_bits", 12) > c.n:
                 continue
-            for pas in q.plan_describe(c.gates, c.n, q.C64, plan)["passes"]:
+            prog = q.plan_describe(c.gates, c.n, q.C64, plan)
+            for pas in prog["passes"]:
                 for st in pas["stages"]:
                     for rd in st["rounds"]:
                         ops = rd["ops"]
                         k = len(ops)
-                        want = k if (pas["zin_ops"] == 3 and 0 < k <= 4
-                                     and all(op["type"] == 0 and op["p0"] == k - 1 - i for i, op in enumerate(ops))) else 0
+                        want = 0
+                        if pas["zin_ops"] == 3 and 0 < k <= 4:
+                            if all(op["type"] == 0 and op["p0"] == k - 1 - i for i, op in enumerate(ops)):
+                                want = k
+                        elif pas["zin_ops"] == 4 and prog["RB"] == 4:
+                            if 0 < k <= 4 and all(op["type"] == 0 and op["p0"] == i for i, op in enumerate(ops)):
+                                want = k
+                            elif (k == 9 and ops[4]["type"] == 2
+                                  and all(ops[i]["type"] == 0 and ops[i]["p0"] == i and ops[5 + i]["type"] == 0
+                                          and ops[5 + i]["p0"] == i for i in range(4))):
+                                want = 9
                         assert rd["seq"] == want, (c.name, plan)
                         marked += rd["seq"] > 0
-    assert marked >= 7
+    assert marked >= 12
 
 
 def test_qft_second_pass_has_a_support_bound():
