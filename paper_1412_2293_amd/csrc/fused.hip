@@ -826,15 +826,26 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
         // with the basis index on the tile-local classical bits (thread part per lane, register
         // part uniform)
         const uint32_t lc = pd->lclassical;
-        const bool tok = ((lthr0 ^ blocal) & lc & ~load_mask) == 0;
-        const RoundDesc *ld = prog.rounds + pd->load_round;
+        if (lc == 0) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const bool rok = ((ld->roff[r] ^ blocal) & lc & load_mask) == 0;
-            a[r] = tv<R>{(R)0, (R)0};
-            if (rok && tok) {
-                const uint64_t i = gthr | greg[r];
-                a[r] = __builtin_nontemporal_load(reinterpret_cast<const tv<R> *>(base + 2 * i));
+            for (int r = 0; r < NR; ++r)
+                a[r] = __builtin_nontemporal_load(reinterpret_cast<const tv<R> *>(base + 2 * (gthr | greg[r])));
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) a[r] = tv<R>{(R)0, (R)0};
+            // only lanes whose thread part agrees with the basis read anything, so a wave with
+            // none of them (most waves when few tile bits are touched) skips the loads
+            const bool tok = ((lthr0 ^ blocal) & lc & ~load_mask) == 0;
+            if (tok) {
+                const RoundDesc *ld = prog.rounds + pd->load_round;
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const bool rok = ((ld->roff[r] ^ blocal) & lc & load_mask) == 0;
+                    if (rok) {
+                        const uint64_t i = gthr | greg[r];
+                        a[r] = __builtin_nontemporal_load(reinterpret_cast<const tv<R> *>(base + 2 * i));
+                    }
+                }
             }
         }
     }
