@@ -658,7 +658,16 @@ double model_cost_fused(const Program &P, int n, qs_dtype dt, int S, int run_bit
         const double mem = (pi == 0 ? 1.0 : 2.0) * N * amp / (kModelHbm * eff);
         const double alu = N * per_amp * wide / kModelValu;
         // the two overlap only in part: a pass waits on both its loads and its arithmetic
-        total += std::max(mem, alu) + 0.5 * std::min(mem, alu);
+        double pass = std::max(mem, alu) + 0.5 * std::min(mem, alu);
+        if (dt == QS_C128 && pd.zin_ops == 5) {
+            // a pass without one-qubit ops holds few registers, so its occupancy is set by the
+            // LDS its tile takes: a 64 KiB tile leaves two waves per SIMD, which measured 10 %
+            // slower than smaller tiles at four or more (density-matrix superoperator passes)
+            const int blocks = (int)((160u * 1024u) / ((size_t(1) << pd.K) * 16u));
+            const int waves = blocks * (1 << (pd.K - pd.RB)) / 64 / 4;
+            if (waves < 4) pass /= waves <= 2 ? 0.85 : 0.92;
+        }
+        total += pass;
     }
     return total + kModelLaunch * (double)P.passes.size() / std::max(S, 1);
 }
