@@ -906,6 +906,25 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
         for (int r = 0; r < NR; ++r) a[r] = tvec(lds_get(sw ^ (rd->sroff[r] * CXS)));
     };
 
+    // A diagonal-pattern op: its tile-local condition splits into the lane's thread bits (one
+    // compare per lane) and the register bits (the same for every lane), so only the registers
+    // whose bits match are multiplied (a Grover sign flip on all qubits touches one of 16).
+    auto diag_op = [&](const OpDesc *op) {
+        const bool ohit = (outer & op->omask) == op->ovalue;
+        const uint32_t lmask = op->lmask, lvalue = op->lvalue;
+        const uint32_t rm = prog.rounds[cur_ri].reg_mask;
+        const bool thit = ohit && (lthr & lmask) == (lvalue & ~rm);
+        const uint32_t rmask = lmask & rm, rval = lvalue & rm;
+        const cxf<R> f = rec[op->rec];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if ((prog.rounds[cur_ri].roff[r] & rmask) == rval) {
+                const tv<R> y = tvec(mul(f, cx<R>(a[r])));
+                a[r] = thit ? y : a[r];
+            }
+        }
+    };
+
     for (int si = pd->stage_begin; si < pd->stage_end; ++si) {
         const StageDesc sd = prog.stages[si];
         for (int ri = sd.round_begin; ri < sd.round_end; ++ri) {
@@ -1013,16 +1032,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                     const int ob = rd->op_begin;
                     if (seq == 9) {
                         run4(ob);
-                        const OpDesc *op = prog.ops + ob + 4;
-                        const bool ohit = (outer & op->omask) == op->ovalue;
-                        const uint32_t lmask = op->lmask, lvalue = op->lvalue;
-                        const cxf<R> f = rec[op->rec];
-#pragma unroll
-                        for (int r = 0; r < NR; ++r) {
-                            bool hit = ohit && ((lthr | prog.rounds[cur_ri].roff[r]) & lmask) == lvalue;
-                            const tv<R> y = tvec(mul(f, cx<R>(a[r])));
-                            a[r] = hit ? y : a[r];
-                        }
+                        diag_op(prog.ops + ob + 4);
                         run4(ob + 5);
                     } else if (seq == 4) {
                         run4(ob);
@@ -1109,17 +1119,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                     for (int k = 0; k < 16; ++k) m[k] = orec[k];
                     dispatch_u2<R, RB>(op->p0, op->p1, (op->flags & OPF_REAL) != 0, a, m);
                 } else if (MIX) {
-                    // no early exit when the tile-number condition fails: a pass-through path
-                    // would make the register tile move between registers
-                    const bool ohit = (outer & op->omask) == op->ovalue;
-                    const uint32_t lmask = op->lmask, lvalue = op->lvalue;
-                    const cxf<R> f = orec[0];
-#pragma unroll
-                    for (int r = 0; r < NR; ++r) {
-                        bool hit = ohit && ((lthr | prog.rounds[cur_ri].roff[r]) & lmask) == lvalue;
-                        const tv<R> y = tvec(mul(f, cx<R>(a[r])));
-                        a[r] = hit ? y : a[r];
-                    }
+                    diag_op(op);
                 }
             }
             }
