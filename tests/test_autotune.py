@@ -73,3 +73,18 @@ def test_cache_lookup_and_fallback(tmp_path):
     assert autotune.lookup(c.gates, c.n, q.C128, path, arch="gfx950") is None
     assert autotune.lookup(c.gates, 17, q.C64, path, arch="gfx950") is None
     assert autotune.lookup(c.gates, c.n, q.C64, path, arch="gfx942") is None
+
+
+def test_density_matrix_passes_priced_by_occupancy():
+    """complex<double> passes without one-qubit ops (the density-matrix superoperator passes) hold
+    few registers, so LDS sets their occupancy: the model prices 64 KiB tiles (two waves per SIMD)
+    above 32 KiB ones and picks 2^11-amplitude tiles for them, while circuits with one-qubit ops
+    keep 2^12-amplitude tiles."""
+    c = grover(13, seed=5)
+    sg = q.dm_superop(c.gates, 13, 0.02)
+    p, _ = q.plan_choose(sg, 26, q.C128)
+    assert (p["tile_bits"], p["reg_bits"]) == (11, 3)
+    p, _ = q.plan_choose(sg, 26, q.C64)
+    assert (p["tile_bits"], p["reg_bits"]) == (12, 4)
+    p, _ = q.plan_choose(qft(20, 3).gates, 20, q.C128)
+    assert (p["tile_bits"], p["reg_bits"]) == (12, 4)
