@@ -970,7 +970,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                     }
                 }
             } else {
-            if constexpr (ZV == 3 && sizeof(R) == 4 && RB == 4) {
+            if constexpr (ZV == 3 && RB == 4) {
                 // a round of untouched-target updates on register bits k-1, ..., 0: straight-line,
                 // no per-op dispatch (its merges copy the register tile)
                 const int seq = rd->seq;
@@ -1009,7 +1009,7 @@ __global__ void __launch_bounds__((kWideTile<R, RB>) ? 256 : 512)
                     continue;
                 }
             }
-            if constexpr (ZV == 4 && sizeof(R) == 4 && RB == 4) {
+            if constexpr (ZV == 4 && RB == 4) {
                 // rounds of real updates of touched targets on register bits 0, ..., k-1 in turn
                 // (seq = k), or two such runs of four around one diagonal pattern (seq = 9):
                 // straight-line, the target bits fixed at compile time

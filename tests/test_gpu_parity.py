@@ -185,23 +185,25 @@ def test_qft_basis_folded_phases_every_input(dtype, plan):
                                     (16, {"fuse": 1, "tile_bits": 12, "reg_bits": 4, "run_bits": 4}),
                                     (18, {"fuse": 1, "tile_bits": 10, "reg_bits": 4, "run_bits": 2})],
                          ids=["n13t12", "n14t8", "n16t12", "n18t10"])
-def test_straight_line_rounds_full_states(n, plan):
-    """complex<float> 16-register tiles run the rounds of the QFT's passes (untouched targets,
-    register bits 3..0) and of Grover's (touched targets, bits 0..3, and at n = 16 and 18 two such
-    runs around the oracle's or the diffusion's sign flip) straight-line: every amplitude of
-    every trajectory against the oracle."""
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+def test_straight_line_rounds_full_states(n, plan, dtype):
+    """16-register tiles run the rounds of the QFT's passes (untouched targets, register bits
+    3..0) and of Grover's (touched targets, bits 0..3, and at n = 16 and 18 two such runs around
+    the oracle's or the diffusion's sign flip) straight-line: every amplitude of every trajectory
+    against the oracle."""
     seqs = set()
+    tol = 1e-12 if dtype == q.C128 else 3e-5
     for c in (qft(n, seed=n + 20), grover(n, seed=n + 20, iterations=3)):
-        d = q.plan_describe(c.gates, n, q.C64, plan)
+        d = q.plan_describe(c.gates, n, dtype, plan)
         seqs |= {rd["seq"] for p in d["passes"] for st in p["stages"] for rd in st["rounds"]}
         T, e, seed = 3, 0.1, 31
-        res = q.run_trajectories(c.gates, n, c.init_index, q.C64, T, e=e, seed=seed, plan=plan)
+        res = q.run_trajectories(c.gates, n, c.init_index, dtype, T, e=e, seed=seed, plan=plan)
         F_ref, _, ideal, states = oracle.run_trajectories(c, e, seed, range(T), keep_states=True)
-        st = q.trajectory_states(res, n, q.C64, T).cpu().numpy().astype(np.complex128)
-        assert rel_err(unpermute(st[0], res["layout"], n), ideal) <= 3e-5, c.name
+        st = q.trajectory_states(res, n, dtype, T).cpu().numpy().astype(np.complex128)
+        assert rel_err(unpermute(st[0], res["layout"], n), ideal) <= tol, c.name
         for t in range(T):
-            assert rel_err(unpermute(st[t + 1], res["layout"], n), states[t]) <= 3e-5, (c.name, t)
-        assert np.max(np.abs(res["F"] - F_ref)) <= TOL[q.C64], c.name
+            assert rel_err(unpermute(st[t + 1], res["layout"], n), states[t]) <= tol, (c.name, t)
+        assert np.max(np.abs(res["F"] - F_ref)) <= TOL[dtype], c.name
     assert 4 in seqs and (n < 16 or 9 in seqs)
 
 
