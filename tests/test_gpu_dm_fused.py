@@ -65,6 +65,7 @@ PLANS = {
     "fused": {"fuse": 1},
     "t8": {"fuse": 1, "tile_bits": 8, "reg_bits": 3, "run_bits": 2},
     "t9r2": {"fuse": 1, "tile_bits": 9, "reg_bits": 2, "run_bits": 3},
+    "t11r3": {"fuse": 1, "tile_bits": 11, "reg_bits": 3, "run_bits": 3},
     "unfused": {"fuse": 0},
     "auto": None,
 }
