@@ -208,6 +208,58 @@ def test_straight_line_rounds_full_states(n, plan, dtype):
 
 
 @pytest.mark.parametrize("dtype", [q.C128, q.C64])
+def test_grover20_full_size(dtype):
+    """Grover n = 20 with its full 804 iterations through the fused passes (two per iteration,
+    list-scheduled; rounds straight-line around the sign flips): the ideal slot's probabilities
+    against the closed form sin^2((2j+1)asin 2^-n/2) on the marked index and its complement
+    spread evenly over the others; the noisy trajectories' fidelities and marked probabilities
+    against the same circuit as per-gate sweeps (complex<double>), and against the complex<double>
+    fused run (complex<float>).  The bounds are those of 33,788 gate updates in sequence: about
+    that many roundings of the working precision (2e-11 for complex<double>, where one gate's
+    bound is 1e-12).  In complex<float> the norm drifts by about 1e-3 over the run (one rounding
+    of each Hadamard's 1/sqrt(2) per gate, accumulating in one direction), so its probabilities are
+    compared after normalising the state, as the fidelities already are."""
+    from paper_forms import grover_p_ideal
+    n = 20
+    c = grover(n, seed=2)
+    j = (len(c.gates) - n) // (2 * n + 2)
+    N = 1 << n
+    T, e, seed = 3, 0.01, 41
+    print(f"[grover20] dtype={dtype}", flush=True)
+    res = q.run_trajectories(c.gates, n, 0, dtype, T, e=e, seed=seed, marked=c.marked)
+    st = q.trajectory_states(res, n, dtype, T)
+    prob = (st[0].abs() ** 2).cpu().numpy().astype(np.float64)
+    norm = float(prob.sum())
+    print(f"[grover20] ideal slot norm^2 {norm:.9f}", flush=True)
+    if dtype == q.C64:
+        assert abs(norm - 1.0) <= 5e-3
+        prob /= norm
+    phys = 0
+    for qb in range(n):
+        phys |= ((c.marked >> qb) & 1) << int(res["layout"][qb])
+    p = grover_p_ideal(n, j)
+    tol = 2e-11 if dtype == q.C128 else 2e-5
+    print(f"[grover20] |dp| {abs(prob[phys] - p):.3e}", flush=True)
+    assert abs(prob[phys] - p) <= tol, (prob[phys], p)
+    rest = np.delete(prob, phys)
+    print(f"[grover20] rest max |d| {np.max(np.abs(rest - (1.0 - p) / (N - 1))):.3e}", flush=True)
+    assert np.max(np.abs(rest - (1.0 - p) / (N - 1))) <= tol / N * 8
+    del st
+    if dtype == q.C128:
+        ref = q.run_trajectories(c.gates, n, 0, q.C128, T, e=e, seed=seed, marked=c.marked, plan={"fuse": 0})
+        print(f"[grover20] fused vs sweeps max rel dF {np.max(np.abs(res['F'] - ref['F']) / ref['F']):.3e}", flush=True)
+        assert np.max(np.abs(res["F"] - ref["F"]) / ref["F"]) <= 2e-11
+        assert np.max(np.abs(res["p"] - ref["p"]) / ref["p"]) <= 2e-11
+    else:
+        ref = q.run_trajectories(c.gates, n, 0, q.C128, T, e=e, seed=seed, marked=c.marked)
+        print(f"[grover20] c64 vs c128 max |dF| {np.max(np.abs(res['F'] - ref['F'])):.3e}", flush=True)
+        assert np.max(np.abs(res["F"] - ref["F"])) <= 1e-5
+        # p is the unnormalised marked probability, so it carries the norm drift
+        assert np.max(np.abs(res["p"] - ref["p"])) <= 5e-3 * np.max(ref["p"])
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
 def test_random_layers_against_oracle(dtype):
     c = random_layers(12, 6, seed=5, pairing="random")
     T = 4
