@@ -259,6 +259,29 @@ def test_grover20_full_size(dtype):
     torch.cuda.empty_cache()
 
 
+def test_random_layers_n28_full_size_fused_against_sweeps():
+    """Eight random layers at n = 28 (brickwork CZ, noisy one-qubit gates and CZ phases): the
+    fused run, whose passes and register rounds are list-scheduled out of circuit order, against
+    the same circuit as per-gate sweeps in complex<double> (fidelities and norms, 1e-12 relative),
+    and the complex<float> fused run against both within the single-precision bound."""
+    n = 28
+    c = random_layers(n, 8, seed=12, pairing="brickwork")
+    T, e, seed = 2, 0.02, 17
+    print("[random28] fused c128", flush=True)
+    f128 = q.run_trajectories(c.gates, n, c.init_index, q.C128, T, e=e, seed=seed)
+    torch.cuda.empty_cache()
+    print("[random28] sweeps c128", flush=True)
+    s128 = q.run_trajectories(c.gates, n, c.init_index, q.C128, T, e=e, seed=seed, plan={"fuse": 0})
+    torch.cuda.empty_cache()
+    print("[random28] fused c64", flush=True)
+    f64 = q.run_trajectories(c.gates, n, c.init_index, q.C64, T, e=e, seed=seed)
+    torch.cuda.empty_cache()
+    assert np.max(np.abs(f128["F"] - s128["F"]) / s128["F"]) <= 1e-12
+    assert np.max(np.abs(f128["norm"] - s128["norm"])) <= 1e-12
+    assert np.max(np.abs(f64["F"] - f128["F"])) <= 1e-5
+    assert np.all(np.abs(f64["norm"] - 1.0) <= 1e-4)
+
+
 @pytest.mark.parametrize("dtype", [q.C128, q.C64])
 def test_random_layers_against_oracle(dtype):
     c = random_layers(12, 6, seed=5, pairing="random")
