@@ -262,7 +262,10 @@ qs_status qs_noise_draw(uint64_t seed, uint32_t request, uint32_t stream,
  * run as one batch, with the fidelity of each noisy state to the ideal one.
  * ---------------------------------------------------------------------------------------- */
 
-/* Bytes of dev_buf needed by qs_run_trajectories for this circuit and plan. */
+/* Bytes of dev_buf needed by qs_run_trajectories for this circuit and plan; 0 on a rejected
+ * argument (qs_last_error says which).  Plans the circuit as qs_run_trajectories does and keeps
+ * the result in the library's small cache of recent circuits, so the run that follows (or a
+ * repeated query) does not plan again.  No device work. */
 size_t qs_traj_bytes_required(const qs_gate *gates, int n_gates, int n_qubits, qs_dtype dt,
                               int n_traj, const qs_plan *plan);
 

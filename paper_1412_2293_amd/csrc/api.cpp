@@ -836,8 +836,8 @@ std::string prep_key(const qs_gate *gates, int n_gates, int n, qs_dtype dt, cons
 }
 }  // namespace
 
-qs_status traj_prepare(const qs_gate *gates, int n_gates, int n, qs_dtype dt, const qs_plan *plan,
-                       TrajPrep &prep)
+qs_status traj_prepare_shared(const qs_gate *gates, int n_gates, int n, qs_dtype dt, const qs_plan *plan,
+                              std::shared_ptr<const TrajPrep> &prep)
 {
     if (n < 1 || n > 34) return fail(QS_EINVAL, "run_trajectories: n_qubits must be in 1..34");
     if (dt != QS_C64 && dt != QS_C128) return fail(QS_EINVAL, "run_trajectories: unknown dtype");
@@ -849,19 +849,31 @@ qs_status traj_prepare(const qs_gate *gates, int n_gates, int n, qs_dtype dt, co
         std::lock_guard<std::mutex> lk(c.mu);
         for (auto &e : c.entries)
             if (e.first == key) {
-                prep = *e.second;
+                prep = e.second;
                 return QS_OK;
             }
     }
-    v = traj_prepare_uncached(gates, n_gates, n, dt, plan, prep);
+    auto fresh = std::make_shared<TrajPrep>();
+    v = traj_prepare_uncached(gates, n_gates, n, dt, plan, *fresh);
     if (v != QS_OK) return v;
-    auto shared = std::make_shared<const TrajPrep>(prep);
+    prep = fresh;
     PrepCache &c = prep_cache();
     std::lock_guard<std::mutex> lk(c.mu);
     if (c.entries.size() >= PrepCache::kMax) c.entries.erase(c.entries.begin());
-    c.entries.emplace_back(key, std::move(shared));
+    c.entries.emplace_back(key, prep);
     return QS_OK;
 }
+
+qs_status traj_prepare(const qs_gate *gates, int n_gates, int n, qs_dtype dt, const qs_plan *plan,
+                       TrajPrep &prep)
+{
+    std::shared_ptr<const TrajPrep> sp;
+    qs_status v = traj_prepare_shared(gates, n_gates, n, dt, plan, sp);
+    if (v == QS_OK) prep = *sp;
+    return v;
+}
+
+static void build_prog_image(TrajPrep &prep);
 
 qs_status traj_prepare_uncached(const qs_gate *gates, int n_gates, int n, qs_dtype dt, const qs_plan *plan,
                                 TrajPrep &prep)
@@ -881,6 +893,7 @@ qs_status traj_prepare_uncached(const qs_gate *gates, int n_gates, int n, qs_dty
         if (g.kind == QS_G_CNOT) std::memcpy(g.m, kCnot4, sizeof kCnot4);
     prep.layout.resize(n);
     for (int q = 0; q < n; ++q) prep.layout[q] = prep.fused ? prep.prog.layout[q] : q;
+    if (prep.fused) build_prog_image(prep);
     return QS_OK;
 }
 
@@ -909,34 +922,43 @@ size_t traj_prep_bytes(const TrajPrep &prep, int T)
     return T < 1 ? 0 : prep_layout(prep, T).total;
 }
 
-// Host-to-device copies of the gates and the fused program (the host arrays stay in prep).
+// The fused program's tables (passes, stages, rounds, ops, input-phase references, outer jobs,
+// outer bits, phase chains) laid out as in the run buffer from L.passes on, padding zeroed.
+static size_t prog_image_end(const TrajPrep &prep, const TrajLayout &L)
+{
+    const Program &P = prep.prog;
+    return L.chains + sizeof(int32_t) * (P.chain_off.size() + P.chain_gates.size());
+}
+
+static void build_prog_image(TrajPrep &prep)
+{
+    const TrajLayout L = prep_layout(prep, 1);
+    const Program &P = prep.prog;
+    prep.prog_image.assign(prog_image_end(prep, L) - L.passes, 0);
+    char *I = prep.prog_image.data() - L.passes;
+    auto put = [&](size_t at, const void *src, size_t bytes) {
+        if (bytes) std::memcpy(I + at, src, bytes);
+    };
+    put(L.passes, P.passes.data(), sizeof(PassDesc) * P.passes.size());
+    put(L.stages, P.stages.data(), sizeof(StageDesc) * P.stages.size());
+    put(L.rounds, P.rounds.data(), sizeof(RoundDesc) * P.rounds.size());
+    put(L.ops, P.ops.data(), sizeof(OpDesc) * P.ops.size());
+    put(L.prefs, P.prefs.data(), sizeof(PrepRef) * P.prefs.size());
+    put(L.jobs, P.jobs.data(), sizeof(OuterJob) * P.jobs.size());
+    put(L.obits, P.obits.data(), sizeof(int32_t) * P.obits.size());
+    put(L.chains, P.chain_off.data(), sizeof(int32_t) * P.chain_off.size());
+    put(L.chains + sizeof(int32_t) * P.chain_off.size(), P.chain_gates.data(), sizeof(int32_t) * P.chain_gates.size());
+}
+
+// Host-to-device copies of the gates and the fused program (the host arrays stay in prep): two
+// copies, the gates and the program image, whatever the number of tables.
 static qs_status upload_program(const TrajPrep &prep, const TrajLayout &L, char *B, hipStream_t st)
 {
     const int n_gates = (int)prep.hg.size();
     if (n_gates > 0)
         QS_HIP(hipMemcpyAsync(B + L.gates, prep.hg.data(), sizeof(qs_gate) * n_gates, hipMemcpyHostToDevice, st));
-    const Program &P = prep.prog;
     if (!prep.fused) return QS_OK;
-    if (!P.passes.empty())
-        QS_HIP(hipMemcpyAsync(B + L.passes, P.passes.data(), sizeof(PassDesc) * P.passes.size(), hipMemcpyHostToDevice, st));
-    if (!P.stages.empty())
-        QS_HIP(hipMemcpyAsync(B + L.stages, P.stages.data(), sizeof(StageDesc) * P.stages.size(), hipMemcpyHostToDevice, st));
-    if (!P.rounds.empty())
-        QS_HIP(hipMemcpyAsync(B + L.rounds, P.rounds.data(), sizeof(RoundDesc) * P.rounds.size(), hipMemcpyHostToDevice, st));
-    if (!P.ops.empty())
-        QS_HIP(hipMemcpyAsync(B + L.ops, P.ops.data(), sizeof(OpDesc) * P.ops.size(), hipMemcpyHostToDevice, st));
-    if (!P.prefs.empty())
-        QS_HIP(hipMemcpyAsync(B + L.prefs, P.prefs.data(), sizeof(PrepRef) * P.prefs.size(), hipMemcpyHostToDevice, st));
-    if (!P.jobs.empty())
-        QS_HIP(hipMemcpyAsync(B + L.jobs, P.jobs.data(), sizeof(OuterJob) * P.jobs.size(), hipMemcpyHostToDevice, st));
-    if (!P.obits.empty())
-        QS_HIP(hipMemcpyAsync(B + L.obits, P.obits.data(), sizeof(int32_t) * P.obits.size(), hipMemcpyHostToDevice, st));
-    if (!P.chain_off.empty()) {
-        QS_HIP(hipMemcpyAsync(B + L.chains, P.chain_off.data(), sizeof(int32_t) * P.chain_off.size(),
-                              hipMemcpyHostToDevice, st));
-        QS_HIP(hipMemcpyAsync(B + L.chains + sizeof(int32_t) * P.chain_off.size(), P.chain_gates.data(),
-                              sizeof(int32_t) * P.chain_gates.size(), hipMemcpyHostToDevice, st));
-    }
+    QS_HIP(hipMemcpyAsync(B + L.passes, prep.prog_image.data(), prep.prog_image.size(), hipMemcpyHostToDevice, st));
     return QS_OK;
 }
 
@@ -1086,10 +1108,10 @@ size_t qs_traj_bytes_required(const qs_gate *gates, int n_gates, int n, qs_dtype
                               const qs_plan *plan)
 {
     if (n < 1 || n > 34 || T < 1 || (dt != QS_C64 && dt != QS_C128)) return 0;
-    if (check_circuit(gates, n_gates, n) != QS_OK) return 0;
-    Plan pl;
-    if (resolve_plan(gates, n_gates, n, dt, T, plan, pl) != QS_OK) return 0;
-    return traj_layout(n, dt, T, n_gates, pl).total;
+    // the run's own (cached) preparation: a repeated call neither plans nor prices the shapes again
+    std::shared_ptr<const TrajPrep> prep;
+    if (traj_prepare_shared(gates, n_gates, n, dt, plan, prep) != QS_OK) return 0;
+    return traj_prep_bytes(*prep, T);
 }
 
 qs_status qs_traj_layout(const qs_gate *gates, int n_gates, int n, qs_dtype dt, int T, const qs_plan *plan,
@@ -1099,11 +1121,10 @@ qs_status qs_traj_layout(const qs_gate *gates, int n_gates, int n, qs_dtype dt, 
     if (!out) return fail(QS_EINVAL, "traj_layout: out is NULL");
     if (n < 1 || n > 34 || T < 1 || (dt != QS_C64 && dt != QS_C128))
         return fail(QS_EINVAL, "traj_layout: bad size or dtype");
-    qs_status v = check_circuit(gates, n_gates, n);
+    std::shared_ptr<const TrajPrep> prep;
+    qs_status v = traj_prepare_shared(gates, n_gates, n, dt, plan, prep);
     if (v != QS_OK) return v;
-    Plan pl;
-    if ((v = resolve_plan(gates, n_gates, n, dt, T, plan, pl)) != QS_OK) return v;
-    TrajLayout L = traj_layout(n, dt, T, n_gates, pl);
+    TrajLayout L = prep_layout(*prep, T);
     size_t vals[17] = {L.states, L.tab, L.gates, L.edev, L.passes, L.stages, L.rounds, L.ops, L.prefs,
                        L.jobs, L.obits, L.chains, L.wtab, L.rec, L.partials, L.out, L.total};
     for (int i = 0; i < 17; ++i) out[i] = vals[i];
@@ -1261,15 +1282,15 @@ qs_status qs_run_trajectories(const qs_gate *gates, int n_gates, int n, uint64_t
     if (!fid_out) return fail(QS_EINVAL, "run_trajectories: fid_out is NULL");
     if (p_out && marked < 0) return fail(QS_EINVAL, "run_trajectories: p_out needs marked >= 0");
     if (T < 1) return fail(QS_EINVAL, "run_trajectories: n_traj must be >= 1");
-    qs::TrajPrep prep;
-    qs_status v = qs::traj_prepare(gates, n_gates, n, dt, plan, prep);
+    std::shared_ptr<const qs::TrajPrep> prep;   // keeps the host arrays alive until the copies are done
+    qs_status v = qs::traj_prepare_shared(gates, n_gates, n, dt, plan, prep);
     if (v != QS_OK) return v;
     qs::TrajRun run;
-    if ((v = qs::traj_launch(prep, init_index, nz, T, marked, dev_buf, buf_bytes, (hipStream_t)hip_stream,
+    if ((v = qs::traj_launch(*prep, init_index, nz, T, marked, dev_buf, buf_bytes, (hipStream_t)hip_stream,
                              nullptr, run)) != QS_OK)
         return v;
     QS_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
-    qs::traj_finalize(prep, run, fid_out, p_out, norm_out, layout_out);
+    qs::traj_finalize(*prep, run, fid_out, p_out, norm_out, layout_out);
     return QS_OK;
 }
 
@@ -1536,10 +1557,10 @@ qs_status qs_traj_graph_bytes_required(const qs_gate *gates, int n_gates, int n,
     clear_error();
     if (!bytes) return fail(QS_EINVAL, "traj_graph_bytes_required: bytes is NULL");
     if (T < 1) return fail(QS_EINVAL, "traj_graph_bytes_required: n_traj must be >= 1");
-    qs::TrajPrep prep;
-    qs_status v = qs::traj_prepare(gates, n_gates, n, dt, plan, prep);
+    std::shared_ptr<const qs::TrajPrep> prep;
+    qs_status v = qs::traj_prepare_shared(gates, n_gates, n, dt, plan, prep);
     if (v != QS_OK) return v;
-    *bytes = qs::traj_prep_bytes(prep, T);
+    *bytes = qs::traj_prep_bytes(*prep, T);
     return QS_OK;
 }
 

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -376,6 +377,10 @@ struct TrajPrep {
     Program prog;
     std::vector<qs_gate> hg;       // device image of the gates (CNOT carries its 4x4 matrix)
     std::vector<int32_t> layout;   // logical qubit -> physical bit after the SWAP relabelling
+    // host image of the fused program's tables (passes through chains) as they lie in the run
+    // buffer: their offsets from the first table depend only on the table sizes, so one copy
+    // uploads them all
+    std::vector<char> prog_image;
 };
 // Validate and plan a trajectory run (cached per circuit, dtype and plan request);
 // traj_prepare_uncached always plans.
@@ -393,6 +398,9 @@ struct TrajRun {
 
 qs_status traj_prepare(const qs_gate *gates, int n_gates, int n, qs_dtype dt, const qs_plan *plan,
                        TrajPrep &prep);
+// The same without a copy: the cached preparation itself (kept alive by the pointer).
+qs_status traj_prepare_shared(const qs_gate *gates, int n_gates, int n, qs_dtype dt, const qs_plan *plan,
+                              std::shared_ptr<const TrajPrep> &prep);
 size_t traj_prep_bytes(const TrajPrep &prep, int T);
 qs_status traj_launch(const TrajPrep &prep, uint64_t init_index, const qs_noise *nz, int T, int64_t marked,
                       void *dev_buf, size_t buf_bytes, hipStream_t st, double *host_out, TrajRun &run);
