@@ -1011,8 +1011,21 @@ static qs_status enqueue_compute(const TrajPrep &prep, const TrajLayout &L, char
                                          B + L.rec, wtab, otab, st, dyn));
                 continue;
             }
-            // the last pass also forms the overlaps with slot 0: slot 0 first, then the others
             double *part = (double *)(B + L.partials);
+            // Small states whose last pass covers few tiles per slot: slot 0 alone would keep a
+            // handful of workgroups busy for the whole pass while the rest of the chip idles, so
+            // every slot runs in one launch and the overlaps are summed from the stored states
+            // (at most 64 KiB per slot).  The choice depends on n and the plan only, never on the
+            // number of slots, so a trajectory's results do not depend on its batch.
+            const size_t slot_bytes = ((size_t)1 << n) * (dt == QS_C64 ? 8 : 16);
+            if (S > 1 && fused_walked_bits(n, &P.passes[p], init) < 8 && slot_bytes <= (64u << 10)) {
+                QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (int)p, init, (int64_t)init_index, pdv,
+                                         B + L.rec, wtab, otab, st, dyn));
+                QS_HIP(launch_overlaps(psi, 0, psi, dt, n, S, pmarked, part, (double *)(B + L.out), st, dyn));
+                return QS_OK;
+            }
+            // otherwise the last pass also forms the overlaps with slot 0: slot 0 first, then the
+            // others
             QS_HIP(launch_fused_pass(psi, dt, n, S, &P.passes[p], (int)p, init, (int64_t)init_index, pdv, B + L.rec,
                                      wtab, otab, st, dyn, part, 0, 1));
             if (S > 1)
