@@ -857,3 +857,29 @@ def test_fused_last_pass_overlaps_edge_cases(dtype, T):
             norms = [np.vdot(s, s).real for s in states]
             assert np.max(np.abs(res["norm"] - norms)) <= TOL[dtype] * 10, (c.name, fuse)
         assert np.max(np.abs(out[1]["F"] - out[0]["F"])) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [q.C128, q.C64])
+@pytest.mark.parametrize("n", [10, 14])
+def test_trajectory_results_do_not_depend_on_the_batch(n, dtype):
+    """A trajectory's fidelity, marked probability and norm are the same bits whether it runs in
+    a batch of 64 or of 5: its noise comes from its own counter, and the overlap sums of a slot do
+    not depend on how many slots share the launch.  n = 10 (one 2^10-amplitude tile per slot)
+    runs every slot's last pass in one launch and sums the overlaps from the stored states;
+    n = 14 in complex<float> (128 KiB per slot) forms them inside the last pass, after slot 0."""
+    c = grover(n, seed=3, iterations=3)
+    e, seed = 0.02, 21
+    full = q.run_trajectories(c.gates, n, c.init_index, dtype, 64, e=e, seed=seed, marked=c.marked)
+    for base, T in ((0, 5), (37, 5), (63, 1)):
+        part = q.run_trajectories(c.gates, n, c.init_index, dtype, T, e=e, seed=seed, marked=c.marked,
+                                  traj_base=base)
+        for key in ("F", "p", "norm"):
+            assert np.array_equal(part[key], full[key][base:base + T]), (key, base, T)
+    # and the batch agrees with the oracle on its first eight trajectories
+    F_ref, p_ref = oracle.run_trajectories(c, e, seed, range(8))
+    if dtype == q.C128:
+        assert np.allclose(full["F"][:8], F_ref, rtol=1e-12, atol=0)
+        assert np.allclose(full["p"][:8], p_ref, rtol=1e-12, atol=1e-15)
+    else:
+        assert np.max(np.abs(full["F"][:8] - F_ref)) <= 1e-5
+        assert np.max(np.abs(full["p"][:8] - p_ref)) <= 1e-5
