@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import paper_1412_2293_amd as q
-from workloads import grover, qft
+from workloads import grover, qft, random_layers
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -213,3 +213,26 @@ def test_fused_plan_limits():
     from workloads import U1, Gate, haar_2x2
     g = [Gate(U1, q0=0, m=haar_2x2(np.random.default_rng(0)))]
     assert q.traj_bytes_required(g, 1, q.C64, 2, {"fuse": 1}) > 0
+
+
+def test_size_query_is_cached_and_program_offsets_do_not_depend_on_the_batch():
+    """The size query and the layout come from the run's cached preparation: repeated queries, and
+    queries for other batch sizes, agree with the layout's total; the program tables' offsets
+    from the first table are the same for every batch size (the run uploads them as one image
+    planned once per circuit); rejected arguments still give 0."""
+    c = random_layers(12, 4, seed=5, pairing="random")
+    prog = ["passes", "stages", "rounds", "ops", "prefs", "jobs", "obits", "chains"]
+    for dt in (q.C64, q.C128):
+        for plan in (None, {"fuse": 0}, {"fuse": 1}, {"fuse": 1, "tile_bits": 8, "reg_bits": 3, "run_bits": 2}):
+            rel = None
+            for T in (1, 5, 64, 5):
+                need = q.traj_bytes_required(c.gates, 12, dt, T, plan)
+                lay = q.traj_layout(c.gates, 12, dt, T, plan)
+                assert need == lay["total"] > 0
+                offs = [int(lay[k]) for k in prog]
+                assert all(o % 256 == 0 for o in offs) and offs == sorted(offs)
+                r = [o - offs[0] for o in offs]
+                rel = r if rel is None else rel
+                assert r == rel, (dt, plan, T)
+    assert q.traj_bytes_required(c.gates, 12, q.C64, 0, None) == 0
+    assert q.traj_bytes_required(c.gates, 12, q.C64, 4, {"fuse": 2}) == 0
